@@ -1,0 +1,379 @@
+/*
+ * CPU FP64 oracle for finite-horizon inversion of matrix-valued sequences and
+ * the Markov renewal quantities built on it.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the
+ * benchmark's CPU-baseline leg may load this library.  It shares no code,
+ * header, table or helper with the GPU library, and never calls it.
+ *
+ * Every routine is the plain definition from the paper, written out in double
+ * precision with no blocking, fusion or reordering beyond what the definition
+ * states.  Sequences are time-major: X[k][i][j] at X[(k*rows + i)*cols + j].
+ *
+ * Paper references (Kordalis & Trevezas, "Algebraic and FFT-Based Methods for
+ * Discrete-Time Matrix Convolutions with Applications to Semi-Markov Models"):
+ *   convolution ............ Section 2, eq. (convolution)
+ *   inverse recursion ...... Section 2.2, eq. (inverse-recursion) and the
+ *                            two-sided inverse of Theorem 2.1
+ *   finite-horizon inverse . Proposition 2.3
+ *   survival sequence Hbar . Section 4.1
+ *   transition matrix ...... Section 4.1, eq. (transition-discrete): P = psi*Hbar
+ *   first entrance ......... Section 4.1, eqs. (first-entrance-mass, -cdf)
+ *   occupation/availability  Section 4.1, A_B(k) = alpha P(k) 1_{E,B}
+ *   resolvent identity ..... Proposition 2.5 (basis of the adjoint)
+ *
+ * OpenMP parallelises only over independent output entries.
+ */
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define IDX3(k, i, j, r, c) ((((size_t)(k)) * (size_t)(r) + (size_t)(i)) * (size_t)(c) + (size_t)(j))
+
+/* ------------------------------------------------------------------------- */
+/* Gauss-Jordan inverse of a constant d x d matrix with partial pivoting.     */
+/* Returns 0 on success, 1 if a pivot is exactly zero or below               */
+/* d * 2^-53 * max|A| (singular to working precision).                       */
+/* ------------------------------------------------------------------------- */
+int orc_gj_inverse(const double *A, int d, double *Ainv)
+{
+    double *W = (double *)malloc(sizeof(double) * (size_t)d * 2 * d);
+    if (!W) return 2;
+    double amax = 0.0;
+    for (int i = 0; i < d; ++i) {
+        for (int j = 0; j < d; ++j) {
+            W[i * 2 * d + j] = A[i * d + j];
+            W[i * 2 * d + d + j] = (i == j) ? 1.0 : 0.0;
+            if (fabs(A[i * d + j]) > amax) amax = fabs(A[i * d + j]);
+        }
+    }
+    const double tol = d * ldexp(1.0, -53) * amax;
+    for (int c = 0; c < d; ++c) {
+        int piv = c;
+        for (int r = c + 1; r < d; ++r)
+            if (fabs(W[r * 2 * d + c]) > fabs(W[piv * 2 * d + c])) piv = r;
+        if (!(fabs(W[piv * 2 * d + c]) > tol)) { free(W); return 1; }
+        if (piv != c)
+            for (int j = 0; j < 2 * d; ++j) {
+                double t = W[c * 2 * d + j]; W[c * 2 * d + j] = W[piv * 2 * d + j]; W[piv * 2 * d + j] = t;
+            }
+        double inv = 1.0 / W[c * 2 * d + c];
+        for (int j = 0; j < 2 * d; ++j) W[c * 2 * d + j] *= inv;
+        for (int r = 0; r < d; ++r) {
+            if (r == c) continue;
+            double f = W[r * 2 * d + c];
+            if (f == 0.0) continue;
+            for (int j = 0; j < 2 * d; ++j) W[r * 2 * d + j] -= f * W[c * 2 * d + j];
+        }
+    }
+    for (int i = 0; i < d; ++i)
+        for (int j = 0; j < d; ++j) Ainv[i * d + j] = W[i * 2 * d + d + j];
+    free(W);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Left (column-decoupled) coefficient recursion.  From the order-k          */
+/* coefficient of A*X = e0:  X(0) = A(0)^-1 and, for k >= 1,                 */
+/*     X(k) = -A(0)^-1 sum_{l=1..k} A(l) X(k-l).                             */
+/* Column c of X depends only on column c of earlier X, so only the columns   */
+/* listed in cols[0..nc) are produced: X is [n][d][nc].                      */
+/* Returns 0 on success, 1 if A(0) is singular.                              */
+/* ------------------------------------------------------------------------- */
+int orc_inverse_left_cols(const double *A, int d, long n, const int *cols, int nc, double *X)
+{
+    double *A0inv = (double *)malloc(sizeof(double) * (size_t)d * d);
+    if (orc_gj_inverse(A, d, A0inv)) { free(A0inv); return 1; }
+    for (int i = 0; i < d; ++i)
+        for (int c = 0; c < nc; ++c) X[IDX3(0, i, c, d, nc)] = A0inv[i * d + cols[c]];
+    double *S = (double *)malloc(sizeof(double) * (size_t)d * nc);
+    for (long k = 1; k < n; ++k) {
+        /* S = sum_{l=1..k} A(l) X(k-l) */
+#pragma omp parallel for schedule(static) collapse(2) if ((double)k * d * d * nc > 2e5)
+        for (int r = 0; r < d; ++r)
+            for (int c = 0; c < nc; ++c) {
+                double s = 0.0;
+                for (long l = 1; l <= k; ++l)
+                    for (int t = 0; t < d; ++t)
+                        s += A[IDX3(l, r, t, d, d)] * X[IDX3(k - l, t, c, d, nc)];
+                S[r * nc + c] = s;
+            }
+        for (int i = 0; i < d; ++i)
+            for (int c = 0; c < nc; ++c) {
+                double s = 0.0;
+                for (int r = 0; r < d; ++r) s += A0inv[i * d + r] * S[r * nc + c];
+                X[IDX3(k, i, c, d, nc)] = -s;
+            }
+    }
+    free(S);
+    free(A0inv);
+    return 0;
+}
+
+int orc_inverse_left(const double *A, int d, long n, double *X)
+{
+    int *cols = (int *)malloc(sizeof(int) * (size_t)d);
+    for (int c = 0; c < d; ++c) cols[c] = c;
+    int rc = orc_inverse_left_cols(A, d, n, cols, d, X);
+    free(cols);
+    return rc;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Right (row-decoupled) recursion, the paper's own form:                    */
+/*     X(0) = A(0)^-1,   X(k) = -sum_{l=0..k-1} X(l) A(k-l) A(0)^-1.          */
+/* Row i of X depends only on row i of earlier X.  orc_inverse_row returns   */
+/* the row vector r(k) = alpha X(k) for a given alpha (length d): r is [n][d].*/
+/* ------------------------------------------------------------------------- */
+int orc_inverse_row(const double *A, int d, long n, const double *alpha, double *r)
+{
+    double *A0inv = (double *)malloc(sizeof(double) * (size_t)d * d);
+    if (orc_gj_inverse(A, d, A0inv)) { free(A0inv); return 1; }
+    for (int j = 0; j < d; ++j) {
+        double s = 0.0;
+        for (int i = 0; i < d; ++i) s += alpha[i] * A0inv[i * d + j];
+        r[j] = s;
+    }
+    double *S = (double *)malloc(sizeof(double) * (size_t)d);
+    for (long k = 1; k < n; ++k) {
+        /* S = sum_{l=0..k-1} r(l) A(k-l) */
+#pragma omp parallel for schedule(static) if ((double)k * d * d > 2e5)
+        for (int t = 0; t < d; ++t) {
+            double s = 0.0;
+            for (long l = 0; l < k; ++l)
+                for (int u = 0; u < d; ++u) s += r[(size_t)l * d + u] * A[IDX3(k - l, u, t, d, d)];
+            S[t] = s;
+        }
+        for (int j = 0; j < d; ++j) {
+            double s = 0.0;
+            for (int t = 0; t < d; ++t) s += S[t] * A0inv[t * d + j];
+            r[(size_t)k * d + j] = -s;
+        }
+    }
+    free(S);
+    free(A0inv);
+    return 0;
+}
+
+int orc_inverse_right(const double *A, int d, long n, double *X)
+{
+    /* Row i of X is alpha = e_i pushed through the right recursion. */
+    double *alpha = (double *)calloc((size_t)d, sizeof(double));
+    double *r = (double *)malloc(sizeof(double) * (size_t)n * d);
+    int rc = 0;
+    for (int i = 0; i < d && rc == 0; ++i) {
+        memset(alpha, 0, sizeof(double) * (size_t)d);
+        alpha[i] = 1.0;
+        rc = orc_inverse_row(A, d, n, alpha, r);
+        for (long k = 0; k < n && rc == 0; ++k)
+            for (int j = 0; j < d; ++j) X[IDX3(k, i, j, d, d)] = r[(size_t)k * d + j];
+    }
+    free(r);
+    free(alpha);
+    return rc;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Truncated convolution (A*B)(k) = sum_{l=0..k} A(l) B(k-l), k < n.         */
+/* A is [n][ra][m], B is [n][m][cb], C is [n][ra][cb].                       */
+/* ------------------------------------------------------------------------- */
+void orc_conv(const double *A, const double *B, int ra, int m, int cb, long n, double *C)
+{
+#pragma omp parallel for schedule(dynamic, 16)
+    for (long k = 0; k < n; ++k)
+        for (int i = 0; i < ra; ++i)
+            for (int j = 0; j < cb; ++j) {
+                double s = 0.0;
+                for (long l = 0; l <= k; ++l)
+                    for (int t = 0; t < m; ++t) s += A[IDX3(l, i, t, ra, m)] * B[IDX3(k - l, t, j, m, cb)];
+                C[IDX3(k, i, j, ra, cb)] = s;
+            }
+}
+
+/* ------------------------------------------------------------------------- */
+/* Survival sequence: hb[k][i] = 1 - sum_j sum_{l=1..k} q_ij(l).             */
+/* ------------------------------------------------------------------------- */
+void orc_hbar(const double *q, int d, long n, double *hb)
+{
+    for (int i = 0; i < d; ++i) {
+        double acc = 0.0;
+        hb[i] = 1.0;
+        for (long k = 1; k < n; ++k) {
+            for (int j = 0; j < d; ++j) acc += q[IDX3(k, i, j, d, d)];
+            hb[(size_t)k * d + i] = 1.0 - acc;
+        }
+    }
+}
+
+/* ------------------------------------------------------------------------- */
+/* Transition matrix P = psi * Hbar with Hbar diagonal:                      */
+/*     P(k)[i][j] = sum_{l=0..k} psi(l)[i][j] hb[k-l][j].                    */
+/* ------------------------------------------------------------------------- */
+void orc_transition(const double *psi, const double *q, int d, long n, double *P)
+{
+    double *hb = (double *)malloc(sizeof(double) * (size_t)n * d);
+    orc_hbar(q, d, n, hb);
+#pragma omp parallel for schedule(dynamic, 16)
+    for (long k = 0; k < n; ++k)
+        for (int i = 0; i < d; ++i)
+            for (int j = 0; j < d; ++j) {
+                double s = 0.0;
+                for (long l = 0; l <= k; ++l) s += psi[IDX3(l, i, j, d, d)] * hb[(size_t)(k - l) * d + j];
+                P[IDX3(k, i, j, d, d)] = s;
+            }
+    free(hb);
+}
+
+/* ------------------------------------------------------------------------- */
+/* Occupation probability A_B(k) = alpha P(k) 1_B computed from the row      */
+/* vector r = alpha psi (right recursion on e0 - q):                          */
+/*     A_B(k) = sum_{j in B} sum_{l=0..k} r(l)_j hb[k-l][j].                  */
+/* inB is a 0/1 mask of length d.  Out is [n].                                */
+/* ------------------------------------------------------------------------- */
+int orc_availability(const double *q, int d, long n, const double *alpha, const int *inB, double *out)
+{
+    size_t nd2 = (size_t)n * d * d;
+    double *A = (double *)malloc(sizeof(double) * nd2);
+    for (size_t t = 0; t < nd2; ++t) A[t] = -q[t];
+    for (int i = 0; i < d; ++i) A[IDX3(0, i, i, d, d)] += 1.0;
+    double *r = (double *)malloc(sizeof(double) * (size_t)n * d);
+    int rc = orc_inverse_row(A, d, n, alpha, r);
+    free(A);
+    if (rc) { free(r); return rc; }
+    double *hb = (double *)malloc(sizeof(double) * (size_t)n * d);
+    orc_hbar(q, d, n, hb);
+#pragma omp parallel for schedule(dynamic, 64)
+    for (long k = 0; k < n; ++k) {
+        double s = 0.0;
+        for (int j = 0; j < d; ++j) {
+            if (!inB[j]) continue;
+            for (long l = 0; l <= k; ++l) s += r[(size_t)l * d + j] * hb[(size_t)(k - l) * d + j];
+        }
+        out[k] = s;
+    }
+    free(hb);
+    free(r);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* First entrance into D (mask inD, C = complement), initial law alpha on E   */
+/* (entries outside C ignored).  g_D = (e0^C - q_CC)^-1 * q_CD; the scalar     */
+/* mass ga(k) = alpha_C g_D(k) 1_D and F(k) = sum_{l<=k} ga(l).              */
+/* alpha_C psi_C is taken from the right recursion on e0^C - q_CC.            */
+/* ------------------------------------------------------------------------- */
+int orc_first_entrance(const double *q, int d, long n, const int *inD, const double *alpha,
+                       double *ga, double *F)
+{
+    int nc = 0, nd = 0;
+    int *ci = (int *)malloc(sizeof(int) * (size_t)d), *di = (int *)malloc(sizeof(int) * (size_t)d);
+    for (int i = 0; i < d; ++i) { if (inD[i]) di[nd++] = i; else ci[nc++] = i; }
+    if (nc == 0) {
+        /* Already in D at time 0: the entrance time is 0. */
+        for (long k = 0; k < n; ++k) { ga[k] = (k == 0) ? 1.0 : 0.0; F[k] = 1.0; }
+        free(ci); free(di);
+        return 0;
+    }
+    size_t ncc = (size_t)nc * nc;
+    double *A = (double *)malloc(sizeof(double) * (size_t)n * ncc);
+    for (long k = 0; k < n; ++k)
+        for (int a = 0; a < nc; ++a)
+            for (int b = 0; b < nc; ++b)
+                A[IDX3(k, a, b, nc, nc)] = (k == 0 && a == b ? 1.0 : 0.0) - q[IDX3(k, ci[a], ci[b], d, d)];
+    double *al = (double *)malloc(sizeof(double) * (size_t)nc);
+    for (int a = 0; a < nc; ++a) al[a] = alpha[ci[a]];
+    double *r = (double *)malloc(sizeof(double) * (size_t)n * nc);
+    int rc = orc_inverse_row(A, nc, n, al, r);
+    free(A);
+    if (rc == 0) {
+        /* v(l)_a = sum_{j in D} q(l)[C_a][j] */
+        double *v = (double *)malloc(sizeof(double) * (size_t)n * nc);
+        for (long l = 0; l < n; ++l)
+            for (int a = 0; a < nc; ++a) {
+                double s = 0.0;
+                for (int b = 0; b < nd; ++b) s += q[IDX3(l, ci[a], di[b], d, d)];
+                v[(size_t)l * nc + a] = s;
+            }
+#pragma omp parallel for schedule(dynamic, 64)
+        for (long k = 0; k < n; ++k) {
+            double s = 0.0;
+            for (long l = 0; l <= k; ++l)
+                for (int a = 0; a < nc; ++a) s += r[(size_t)l * nc + a] * v[(size_t)(k - l) * nc + a];
+            ga[k] = s;
+        }
+        double acc = 0.0;
+        for (long k = 0; k < n; ++k) { acc += ga[k]; F[k] = acc; }
+        free(v);
+    }
+    free(r); free(al); free(ci); free(di);
+    return rc;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Adjoint of psi = (e0 - q)^-1 on the horizon.  Linearising the resolvent    */
+/* identity gives dpsi = psi * dq * psi, so for a cotangent psibar            */
+/*     qbar(b) = sum_{a + b + c < n} psi(a)^T psibar(a+b+c) psi(c)^T,         */
+/* evaluated in two correlation stages:                                      */
+/*     V(j)    = sum_{c=0..n-1-j} psibar(j+c) psi(c)^T                        */
+/*     qbar(b) = sum_{a=0..n-1-b} psi(a)^T V(a+b).                            */
+/* ------------------------------------------------------------------------- */
+void orc_adjoint(const double *psi, const double *psibar, int d, long n, double *qbar)
+{
+    size_t d2 = (size_t)d * d;
+    double *V = (double *)calloc((size_t)n * d2, sizeof(double));
+#pragma omp parallel for schedule(dynamic, 16)
+    for (long j = 0; j < n; ++j)
+        for (int i = 0; i < d; ++i)
+            for (int t = 0; t < d; ++t) {
+                double s = 0.0;
+                for (long c = 0; c + j < n; ++c)
+                    for (int u = 0; u < d; ++u)
+                        s += psibar[IDX3(j + c, i, u, d, d)] * psi[IDX3(c, t, u, d, d)];
+                V[IDX3(j, i, t, d, d)] = s;
+            }
+#pragma omp parallel for schedule(dynamic, 16)
+    for (long b = 0; b < n; ++b)
+        for (int i = 0; i < d; ++i)
+            for (int t = 0; t < d; ++t) {
+                double s = 0.0;
+                for (long a = 0; a + b < n; ++a)
+                    for (int u = 0; u < d; ++u)
+                        s += psi[IDX3(a, u, i, d, d)] * V[IDX3(a + b, u, t, d, d)];
+                qbar[IDX3(b, i, t, d, d)] = s;
+            }
+    free(V);
+}
+
+/* ------------------------------------------------------------------------- */
+/* Forward-mode derivative of the renewal equation psi = e0 + q*psi:         */
+/*     dpsi(0) = 0,  dpsi(k) = sum_{l=1..k} [dq(l) psi(k-l) + q(l) dpsi(k-l)] */
+/* (q(0) = dq(0) = 0).                                                       */
+/* ------------------------------------------------------------------------- */
+void orc_forward_mode(const double *q, const double *psi, const double *dq, int d, long n, double *dpsi)
+{
+    size_t d2 = (size_t)d * d;
+    memset(dpsi, 0, sizeof(double) * d2);
+    for (long k = 1; k < n; ++k) {
+#pragma omp parallel for schedule(static) collapse(2) if ((double)k * d2 * d > 2e5)
+        for (int i = 0; i < d; ++i)
+            for (int j = 0; j < d; ++j) {
+                double s = 0.0;
+                for (long l = 1; l <= k; ++l)
+                    for (int t = 0; t < d; ++t)
+                        s += dq[IDX3(l, i, t, d, d)] * psi[IDX3(k - l, t, j, d, d)]
+                           + q[IDX3(l, i, t, d, d)] * dpsi[IDX3(k - l, t, j, d, d)];
+                dpsi[IDX3(k, i, j, d, d)] = s;
+            }
+    }
+}
+
+/* Number of OpenMP threads the oracle will use (1 without OpenMP). */
+int orc_num_threads(void)
+{
+#ifdef _OPENMP
+    extern int omp_get_max_threads(void);
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}

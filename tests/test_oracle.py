@@ -1,0 +1,315 @@
+"""Pins of the CPU FP64 oracle against facts fixed by the paper and by
+mathematics, independent of the oracle's own formulas.
+
+Each test names what pins it: a brute-force enumeration, a closed form, an
+exact identity, a library routine, or a worked example printed in the paper.
+"""
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import smk_inputs as si
+from oracle import exact
+
+
+def _rand_series(rng, n, d, a0_scale=1.0):
+    A = rng.standard_normal((n, d, d)) / (d * np.arange(1, n + 1)[:, None, None])
+    A[0] = np.eye(d) * 2.0 + a0_scale * rng.standard_normal((d, d)) * 0.3
+    return A
+
+
+def test_gj_inverse_matches_library(orc):
+    rng = np.random.default_rng(10)
+    for d in (1, 2, 5, 17, 64):
+        A = rng.standard_normal((d, d)) + d * np.eye(d) * 0.1
+        assert np.allclose(orc.gj_inverse(A), np.linalg.inv(A), rtol=1e-10, atol=1e-12)
+
+
+def test_gj_singular_detected(orc):
+    A = np.diag([1.0, 0.0, 2.0])
+    with pytest.raises(orc.SingularError):
+        orc.gj_inverse(A)
+    S = np.zeros((4, 3, 3))
+    S[0] = A
+    with pytest.raises(orc.SingularError):
+        orc.series_inverse_left(S)
+
+
+def test_left_and_right_recursions_agree(orc):
+    """Left recursion (from A*X = e0) and the paper's right recursion (from
+    X*A = e0) are two definitions of the unique two-sided inverse (Thm 2.1)."""
+    rng = np.random.default_rng(1)
+    for d, n in ((1, 30), (3, 50), (6, 40)):
+        A = _rand_series(rng, n, d)
+        L = orc.series_inverse_left(A)
+        R = orc.series_inverse_right(A)
+        assert np.max(np.abs(L - R)) <= 1e-13 * max(1.0, np.max(np.abs(L)))
+
+
+@pytest.mark.parametrize("d,n", [(1, 9), (2, 8), (3, 7)])
+def test_exact_path_enumeration(orc, d, n):
+    """psi = sum_m q^(m), enumerated over state paths and compositions in
+    exact rationals (Theorem 2.1 Neumann form / renewal-sequence identity)."""
+    rng = np.random.default_rng(100 + d)
+    qf = exact.random_rational_kernel(d, n, rng)
+    ex = exact.psi_paths(qf)
+    q = np.array([[[float(x) for x in row] for row in mat] for mat in qf])
+    got = orc.psi(q)
+    exf = np.array([[[float(x) for x in row] for row in mat] for mat in ex])
+    assert np.max(np.abs(got - exf)) <= 1e-15
+
+
+def test_exact_enumeration_small_hand_case():
+    """Hand check of the enumerator itself: d = 1, q(1) = 1/2, q(2) = 1/3.
+    psi(1) = 1/2, psi(2) = q(2) + q(1)^2 = 1/3 + 1/4."""
+    q = [[[Fraction(0)]], [[Fraction(1, 2)]], [[Fraction(1, 3)]]]
+    ps = exact.psi_paths(q)
+    assert ps[1][0][0] == Fraction(1, 2)
+    assert ps[2][0][0] == Fraction(7, 12)
+
+
+def test_geometric_closed_form(orc):
+    """Geometric sojourns make the process a Markov chain with one-step matrix
+    M = diag(a) + diag(1-a) p.  Then P(k) = M^k and psi(k) = M^(k-1)(M - diag(a))
+    for k >= 1 (a jump lands at time k), psi(0) = I."""
+    d, n = 5, 80
+    k = si.geometric_kernel(d, n, 2)
+    q = k.q.numpy()
+    M, a = k.params["M"], k.params["a"]
+    ps = orc.psi(q)
+    ref = np.empty((n, d, d))
+    ref[0] = np.eye(d)
+    Mk = np.eye(d)
+    for t in range(1, n):
+        ref[t] = Mk @ (M - np.diag(a))
+        Mk = Mk @ M
+    assert np.max(np.abs(ps - ref)) <= 1e-14
+    P = orc.transition(ps, q)
+    Pref = np.array([np.linalg.matrix_power(M, t) for t in range(n)])
+    assert np.max(np.abs(P - Pref)) <= 1e-13
+
+
+def test_geometric_functionals_closed_form(orc):
+    """Markov case: availability alpha M^k 1_U, reliability alpha_U M_UU^k 1_U,
+    first entrance F_D(k) = 1 - alpha_C M_CC^k 1_C."""
+    d, n = 6, 70
+    k = si.geometric_kernel(d, n, 7)
+    q = k.q.numpy()
+    M = k.params["M"]
+    up = np.array([1, 1, 1, 0, 0, 0])
+    alpha = np.zeros(d)
+    alpha[0] = 1.0
+    A = orc.availability(q, up, alpha)
+    Aref = np.array([alpha @ np.linalg.matrix_power(M, t) @ up for t in range(n)])
+    assert np.max(np.abs(A - Aref)) <= 1e-13
+    R = orc.reliability(q, up, alpha)
+    MUU = M[:3, :3]
+    Rref = np.array([alpha[:3] @ np.linalg.matrix_power(MUU, t) @ np.ones(3) for t in range(n)])
+    assert np.max(np.abs(R - Rref)) <= 1e-13
+    inD = np.zeros(d, dtype=int)
+    inD[d - 1] = 1
+    _, F = orc.first_entrance(q, inD, alpha)
+    MCC = M[: d - 1, : d - 1]
+    Fref = np.array([1 - alpha[: d - 1] @ np.linalg.matrix_power(MCC, t) @ np.ones(d - 1) for t in range(n)])
+    assert np.max(np.abs(F - Fref)) <= 1e-13
+
+
+def test_scalar_geometric(orc):
+    """d = 1, f(k) = (1-a)a^(k-1): every step is a renewal with probability 1-a."""
+    a, n = 0.7, 50
+    q = np.zeros((n, 1, 1))
+    q[1:, 0, 0] = (1 - a) * a ** np.arange(n - 1)
+    ps = orc.psi(q)
+    assert abs(ps[0, 0, 0] - 1.0) == 0.0
+    assert np.max(np.abs(ps[1:, 0, 0] - (1 - a))) <= 1e-15
+
+
+def test_unit_sojourn_gives_matrix_powers(orc):
+    """q(k) = 0 except q(1) = B: psi = sum_m q^(m) has psi(k) = B^k."""
+    rng = np.random.default_rng(3)
+    d, n = 4, 25
+    B = rng.uniform(0, 0.3, (d, d))
+    q = np.zeros((n, d, d))
+    q[1] = B
+    ps = orc.psi(q)
+    ref = np.array([np.linalg.matrix_power(B, t) for t in range(n)])
+    assert np.max(np.abs(ps - ref)) <= 1e-15
+
+
+def test_conv_against_library_convolve(orc):
+    """(A*B)_ij = sum_t convolve(A_it, B_tj)[:n] (numpy.convolve per entry)."""
+    rng = np.random.default_rng(4)
+    n, ra, m, cb = 37, 3, 4, 2
+    A = rng.standard_normal((n, ra, m))
+    B = rng.standard_normal((n, m, cb))
+    C = orc.conv(A, B)
+    ref = np.zeros((n, ra, cb))
+    for i in range(ra):
+        for j in range(cb):
+            for t in range(m):
+                ref[:, i, j] += np.convolve(A[:, i, t], B[:, t, j])[:n]
+    assert np.max(np.abs(C - ref)) <= 1e-12
+
+
+def test_transition_row_sums_exact_identity(orc):
+    """P 1 = s0 * psi * (e0 - q) 1 = 1 for ANY q with q(0) = 0 (Section 4.1):
+    pins Hbar and the convolution P = psi * Hbar together."""
+    rng = np.random.default_rng(5)
+    n, d = 60, 4
+    q = rng.uniform(0, 0.05, (n, d, d))
+    q[0] = 0
+    ps = orc.psi(q)
+    P = orc.transition(ps, q)
+    assert np.max(np.abs(P.sum(axis=2) - 1.0)) <= 1e-12
+    assert np.array_equal(P[0], np.eye(d))
+
+
+def test_renewal_equation_and_transition_equation(orc):
+    """psi = e0 + q*psi and P = Hbar + q*P (eqs. renewal-sequence and
+    transition-discrete) hold for the oracle's outputs."""
+    k = si.weibull_kernel(4, 120, 11)
+    q = k.q.numpy()
+    ps = orc.psi(q)
+    E = np.zeros_like(ps)
+    E[0] = np.eye(4)
+    assert np.max(np.abs(ps - (E + orc.conv(q, ps)))) <= 1e-14
+    P = orc.transition(ps, q)
+    H = np.zeros_like(ps)
+    hb = orc.hbar(q)
+    for t in range(q.shape[0]):
+        H[t] = np.diag(hb[t])
+    assert np.max(np.abs(P - (H + orc.conv(q, P)))) <= 1e-13
+
+
+def test_finite_horizon_exactness(orc):
+    """Proposition 2.3: the first n' coefficients depend only on q(0..n'-1)."""
+    k = si.weibull_kernel(3, 100, 12)
+    q = k.q.numpy()
+    full = orc.psi(q)
+    pre = orc.psi(q[:40])
+    assert np.array_equal(full[:40], pre)
+    q2 = q.copy()
+    q2[40:] *= 0.5
+    assert np.array_equal(orc.psi(q2)[:40], full[:40])
+
+
+def test_nonnegative_and_substochastic(orc):
+    """psi >= 0, and for k >= 1 at most one renewal happens at time k, so each
+    row of psi(k) sums to <= 1; P is a stochastic matrix."""
+    for fam in ("weibull", "lognormal"):
+        k = si.family_kernel(fam, 5, 200, 21)
+        q = k.q.numpy()
+        ps = orc.psi(q)
+        assert ps.min() >= -1e-15
+        assert ps[1:].sum(axis=2).max() <= 1 + 1e-13
+        P = orc.transition(ps, q)
+        assert P.min() >= -1e-15
+
+
+def test_transpose_symmetry(orc):
+    """(e0 - q^T)^-1 = ((e0 - q)^-1)^T coefficientwise: catches a swapped
+    product order in any one-sided formula."""
+    k = si.weibull_kernel(5, 90, 13)
+    q = k.q.numpy()
+    a = orc.psi(q)
+    b = orc.psi(np.ascontiguousarray(q.transpose(0, 2, 1)))
+    assert np.max(np.abs(a - b.transpose(0, 2, 1))) <= 1e-14
+
+
+def test_residual_bound_proposition(orc):
+    """Proposition 2.6 on a perturbed inverse: ||psi - X||_{1,N} <=
+    ||rho||/(1-||rho||) ||X||_{1,N} whenever ||rho||_{1,N} < 1."""
+    k = si.weibull_kernel(3, 64, 14)
+    q = k.q.numpy()
+    ps = orc.psi(q)
+    rng = np.random.default_rng(0)
+    X = ps + 1e-6 * rng.standard_normal(ps.shape)
+    A = orc.e0_minus(q)
+    rL, rR = orc.residuals(A, X)
+    err = orc.norm_1N(ps - X)
+    for r in (rL, rR):
+        nr = orc.norm_1N(r)
+        assert nr < 1
+        assert err <= nr / (1 - nr) * orc.norm_1N(X) * (1 + 1e-12)
+
+
+def test_paper_first_entrance_worked_example(orc):
+    """Section 5.1 first-restoration example (Poisson 8, 5, 10, 7; D = {1},
+    C = {2, 3}, alpha_C = (1, 0), N = 128).  From the degraded state the chain
+    either returns directly (prob 1/5, 1 + Poisson(5) steps) or goes through
+    shutdown (prob 4/5, 2 + Poisson(10) + Poisson(7) = 2 + Poisson(17) steps),
+    so the mass has a closed form; the paper reports that the cumulative
+    probability at the last time is one to the displayed precision."""
+    from scipy.stats import poisson
+    n = 128
+    k = si.paper_three_state_poisson(n)
+    q = k.q.numpy()
+    inD = np.array([1, 0, 0])
+    alpha = np.array([0.0, 1.0, 0.0])
+    ga, F = orc.first_entrance(q, inD, alpha)
+    t = np.arange(n)
+    ref = 0.2 * np.where(t >= 1, poisson.pmf(t - 1, 5.0), 0) + 0.8 * np.where(t >= 2, poisson.pmf(t - 2, 17.0), 0)
+    assert np.max(np.abs(ga - ref)) <= 1e-15
+    assert abs(F[-1] - 1.0) <= 1e-14
+
+
+def test_adjoint_matches_forward_mode(orc):
+    """<qbar, dq> = <psibar, dpsi>: the adjoint (linearised resolvent identity,
+    Prop. 2.5) against forward mode on the renewal equation psi = e0 + q*psi."""
+    rng = np.random.default_rng(6)
+    k = si.weibull_kernel(4, 48, 15)
+    q = k.q.numpy()
+    ps = orc.psi(q)
+    pb = rng.standard_normal(ps.shape)
+    qb = orc.adjoint(ps, pb)
+    for _ in range(3):
+        dq = rng.standard_normal(q.shape)
+        dq[0] = 0
+        dps = orc.forward_mode(q, ps, dq)
+        lhs = np.sum(qb[1:] * dq[1:])
+        rhs = np.sum(pb * dps)
+        assert abs(lhs - rhs) <= 1e-11 * max(1.0, abs(rhs))
+
+
+def test_forward_mode_matches_central_difference(orc):
+    """Forward mode against a central finite difference of the oracle itself."""
+    rng = np.random.default_rng(7)
+    k = si.weibull_kernel(3, 40, 16)
+    q = k.q.numpy()
+    ps = orc.psi(q)
+    dq = rng.standard_normal(q.shape)
+    dq[0] = 0
+    h = 1e-6
+    fd = (orc.psi(q + h * dq) - orc.psi(q - h * dq)) / (2 * h)
+    dps = orc.forward_mode(q, ps, dq)
+    assert np.max(np.abs(fd - dps)) <= 1e-7 * max(1.0, np.max(np.abs(dps)))
+
+
+def test_row_recursion_matches_full(orc):
+    rng = np.random.default_rng(8)
+    A = _rand_series(rng, 30, 5)
+    al = rng.standard_normal(5)
+    r = orc.series_inverse_row(A, al)
+    X = orc.series_inverse_left(A)
+    assert np.max(np.abs(r - np.einsum("i,kij->kj", al, X))) <= 1e-13
+
+
+def test_column_subset_matches_full(orc):
+    rng = np.random.default_rng(9)
+    A = _rand_series(rng, 30, 6)
+    X = orc.series_inverse_left(A)
+    cols = [0, 3, 5]
+    Xc = orc.series_inverse_left(A, cols)
+    assert np.array_equal(Xc, X[:, :, cols])
+
+
+def test_paper_residual_orders(orc):
+    """Horizon-scaling model at N = 128: the recursion's own residuals are far
+    below the FFT-Newton residuals the paper reports (5.71e-15 / 5.91e-15)."""
+    k = si.paper_three_state_gamma(128)
+    q = k.q.numpy()
+    ps = orc.psi(q)
+    rL, rR = orc.residuals(orc.e0_minus(q), ps)
+    assert orc.norm_1N(rL) < 5.71e-15 * 10
+    assert orc.norm_1N(rR) < 5.91e-15 * 10
