@@ -1,0 +1,232 @@
+/*
+ * mrinv — finite-horizon inversion of matrix-valued sequences on MI355X (gfx950).
+ *
+ * The library inverts a d x d matrix-valued sequence in the truncated
+ * noncommutative series ring M_d[x]/<x^n>: psi = (e0 - q)^(-1) coefficients
+ * 0..n-1 (Kordalis & Trevezas, Section 2.2, Proposition 2.3 and eq. (newton);
+ * Section 4.1 eq. (renewal-sequence)), by Newton iteration with doubling
+ * truncation where every product is a zero-padded FFT along time, a
+ * per-frequency complex matrix product, and an inverse FFT (Section 2.1,
+ * eq. (fft-convolution); Appendix "Algorithmic details").  On top of psi it
+ * forms the Markov renewal quantities of Section 4.1 / Table 2.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Sequences are DEVICE pointers to caller-owned, contiguous, time-major
+ *   arrays: X[k][i][j] at X[(k*rows + i)*cols + j], k = 0..n-1, IEEE float64.
+ *   Small vectors/masks documented as "host" are host pointers.
+ * - Horizon: n coefficients, k = 0..n-1 (I_N of Section 2).
+ * - The library never allocates device memory after mrinv_create.  Scratch
+ *   memory is a caller-provided device workspace `ws` of at least
+ *   mrinv_workspace_size(...) bytes (256-byte aligned).
+ * - Every call only enqueues work on the handle's HIP stream and returns.
+ *   Argument errors are reported synchronously and enqueue nothing.
+ *   Conditions found on the device (singular A(0), non-finite values) set a
+ *   sticky device status word that mrinv_sync_status() reads and clears;
+ *   affected outputs are NaN.
+ * - Outputs must not alias inputs.  A handle is not thread-safe; use one
+ *   handle per stream.
+ * - No C++ exception crosses this interface.
+ */
+#ifndef MRINV_H
+#define MRINV_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    MRINV_FP64 = 0,        /* every FFT and product in float64 */
+    MRINV_MIXED_FP32 = 1   /* float32 Newton, then a float64 residual sweep (see mrinv_psi_inverse) */
+} mrinv_precision_t;
+
+typedef enum {
+    MRINV_OK = 0,
+    MRINV_E_ARG = 1,            /* invalid argument (null pointer, size out of range) */
+    MRINV_E_SINGULAR_A0 = 2,    /* A(0) singular to working precision (Theorem 2.1) */
+    MRINV_E_NONFINITE = 3,      /* NaN or Inf met on the device */
+    MRINV_E_WORKSPACE = 4,      /* workspace too small or misaligned */
+    MRINV_E_UNSUPPORTED = 5,    /* valid but unsupported size (d > MRINV_MAX_D) */
+    MRINV_E_HIP = 6             /* HIP runtime error; see mrinv_last_error() */
+} mrinv_status_t;
+
+/* Largest supported matrix dimension (rows, cols and inner dimension). */
+#define MRINV_MAX_D 64
+/* Largest supported horizon. */
+#define MRINV_MAX_N (1LL << 21)
+
+/* Operation codes for mrinv_workspace_size. */
+typedef enum {
+    MRINV_OP_PSI_INVERSE = 0,       /* mrinv_psi_inverse / mrinv_series_inverse */
+    MRINV_OP_APPLY = 1,             /* mrinv_markov_renewal_apply (r = columns of L) */
+    MRINV_OP_TRANSITION = 2,        /* mrinv_transition */
+    MRINV_OP_PSI_BACKWARD = 3,      /* mrinv_psi_inverse_backward */
+    MRINV_OP_APPLY_BACKWARD = 4,    /* mrinv_markov_renewal_apply_backward */
+    MRINV_OP_TRANSITION_BACKWARD = 5,
+    MRINV_OP_FIRST_ENTRANCE = 6,    /* mrinv_first_entrance / mrinv_reliability (r = |D|) */
+    MRINV_OP_AVAILABILITY = 7
+} mrinv_op_t;
+
+typedef struct mrinv_handle_s *mrinv_handle_t;
+
+/* Create a handle bound to `stream` (a hipStream_t; NULL = default stream)
+ * on the current device.  Allocates the twiddle tables and the device status
+ * word (the only device allocations the library makes). */
+mrinv_status_t mrinv_create(mrinv_handle_t *handle, void *stream);
+mrinv_status_t mrinv_destroy(mrinv_handle_t handle);
+mrinv_status_t mrinv_set_stream(mrinv_handle_t handle, void *stream);
+
+/* Synchronise the handle's stream, then return and clear the device status
+ * word (MRINV_OK, MRINV_E_SINGULAR_A0 or MRINV_E_NONFINITE). */
+mrinv_status_t mrinv_sync_status(mrinv_handle_t handle);
+
+const char *mrinv_status_string(mrinv_status_t status);
+/* Detail of the last error on the calling thread (empty if none). */
+const char *mrinv_last_error(void);
+
+/* Bytes of device workspace needed by `op` for matrix dimension d, horizon n,
+ * extra dimension r (columns of L for APPLY, |D| for FIRST_ENTRANCE, else
+ * ignored) and precision.  Returns 0 for invalid arguments. */
+size_t mrinv_workspace_size(mrinv_op_t op, int d, int64_t n, int r, mrinv_precision_t precision);
+
+/*
+ * psi = (e0 - q)^(-1) on the horizon (Section 4.1, eq. (renewal-sequence);
+ * exact in M_d[x]/<x^n> by Proposition 2.3).
+ *   q    : device [n][d][d] float64, the semi-Markov kernel (q(0) may be
+ *          nonzero; only A(0) = I - q(0) nonsingular is required).
+ *   psi  : device [n][d][d] float64 output.
+ * Method: B0 = A(0)^-1 by Gauss-Jordan with partial pivoting, then Newton
+ * B <- B*(2 e0 - A*B) (eq. (newton)) doubling the number of exact
+ * coefficients each step, the final step truncated to n.
+ * MRINV_MIXED_FP32 runs the Newton steps with float32 transforms and products,
+ * then forms the residual R = e0 - A*X in float64 over the whole horizon and
+ * returns X + X*R (one Newton sweep whose residual is float64; Proposition 2.6
+ * bounds the remaining error by the residual).
+ * 1 <= d <= 64, 1 <= n <= MRINV_MAX_N.
+ */
+mrinv_status_t mrinv_psi_inverse(mrinv_handle_t h, const double *q, int d, int64_t n,
+                                 mrinv_precision_t precision, double *psi,
+                                 void *ws, size_t ws_bytes);
+
+/* Same as mrinv_psi_inverse for a general sequence A (A^(-1) of Theorem 2.1):
+ * A is device [n][d][d] float64 with A(0) nonsingular. */
+mrinv_status_t mrinv_series_inverse(mrinv_handle_t h, const double *A, int d, int64_t n,
+                                    mrinv_precision_t precision, double *Ainv,
+                                    void *ws, size_t ws_bytes);
+
+/* M = psi * L truncated at n (eq. (convolution) with rectangular
+ * coefficients; reward-type equation V = psi*r, eq. (reward), and the
+ * first-entrance kernel g_D = psi_CC * q_CD, eq. (first-entrance-mass)).
+ *   psi : device [n][d][d];  L : device [n][d][r];  M : device [n][d][r].
+ * 1 <= d, r <= 64. */
+mrinv_status_t mrinv_markov_renewal_apply(mrinv_handle_t h, const double *psi, int d, int64_t n,
+                                          const double *L, int r, double *M,
+                                          void *ws, size_t ws_bytes);
+
+/* P = psi * Hbar(q) (eq. (transition-discrete)), Hbar(k) = diag(1 - sum_j
+ * sum_{l=1..k} q_ij(l)).  psi, q, P : device [n][d][d]. */
+mrinv_status_t mrinv_transition(mrinv_handle_t h, const double *psi, const double *q, int d,
+                                int64_t n, double *P, void *ws, size_t ws_bytes);
+
+/* Hbar(q) diagonal: hb : device [n][d], hb[k][i] = 1 - sum_j sum_{l=1..k} q_ij(l)
+ * (Section 4.1).  No workspace. */
+mrinv_status_t mrinv_survival(mrinv_handle_t h, const double *q, int d, int64_t n, double *hb);
+
+/* out(k) = offset + scale * u^T X(k) v, or with cumulative != 0
+ * out(k) = offset + scale * sum_{l<=k} u^T X(l) v, for k < n.
+ * X : device [n][rows][cols]; u : device [rows]; v : device [cols];
+ * out : device [n].  Occupation probability alpha P(k) 1_B, first-entrance
+ * cdf alpha_C G_D(k) 1_D and survival 1 - F_D (Table 2).  No workspace. */
+mrinv_status_t mrinv_contract(mrinv_handle_t h, const double *X, int64_t n, int rows, int cols,
+                              const double *u, const double *v, int cumulative,
+                              double offset, double scale, double *out);
+
+/* Y(k) = X(k)[row_idx, col_idx]: block extraction (q_CC, q_CD of Section 4.1).
+ * X : device [n][rows][cols]; row_idx/col_idx : device int32 [nr]/[nc];
+ * Y : device [n][nr][nc]. */
+mrinv_status_t mrinv_gather_block(mrinv_handle_t h, const double *X, int64_t n, int rows, int cols,
+                                  const int *row_idx, int nr, const int *col_idx, int nc, double *Y);
+
+/* Composite functionals (Section 4.1 / Table 2), all float64 outputs [n].
+ * in_D / up : host int masks of length d; alpha : host float64 [d] initial
+ * law (entries outside C, resp. U, are ignored).
+ *   first entrance: g(k) = alpha_C g_D(k) 1_D and F(k) = sum_{l<=k} g(l) with
+ *     g_D = (e0^C - q_CC)^-1 * q_CD  (eqs. (first-entrance-mass), (first-entrance-cdf)).
+ *   reliability:    R(k) = 1 - F_D(k) with D = complement of `up`.
+ *   availability:   A(k) = alpha P(k) 1_U from a given P (device [n][d][d]).
+ * `g` may be NULL. */
+mrinv_status_t mrinv_first_entrance(mrinv_handle_t h, const double *q, int d, int64_t n,
+                                    const int *in_D, const double *alpha,
+                                    mrinv_precision_t precision, double *g, double *F,
+                                    void *ws, size_t ws_bytes);
+mrinv_status_t mrinv_reliability(mrinv_handle_t h, const double *q, int d, int64_t n,
+                                 const int *up, const double *alpha,
+                                 mrinv_precision_t precision, double *R,
+                                 void *ws, size_t ws_bytes);
+mrinv_status_t mrinv_availability(mrinv_handle_t h, const double *P, int d, int64_t n,
+                                  const int *up, const double *alpha, double *A);
+
+/*
+ * Adjoint of psi = (e0 - q)^-1: given psi and a cotangent psi_bar (device
+ * [n][d][d]), q_bar(b) = sum_{a+b+c<n} psi(a)^T psi_bar(a+b+c) psi(c)^T, i.e.
+ * q_bar = Rev(psi^T * Rev(psi_bar) * psi^T) with Rev(x)(k) = x(n-1-k).  This is
+ * the linearisation of the resolvent identity of Proposition 2.5
+ * (d psi = psi * dq * psi).  q_bar is written (not accumulated).
+ */
+mrinv_status_t mrinv_psi_inverse_backward(mrinv_handle_t h, const double *psi, const double *psi_bar,
+                                          int d, int64_t n, double *q_bar, void *ws, size_t ws_bytes);
+
+/* Adjoint of M = psi * L: psi_bar_accum += Rev(Rev(M_bar) * L^T) and
+ * L_bar = Rev(psi^T * Rev(M_bar)).  Either output may be NULL to skip it. */
+mrinv_status_t mrinv_markov_renewal_apply_backward(mrinv_handle_t h, const double *psi, const double *L,
+                                                   const double *M_bar, int d, int64_t n, int r,
+                                                   double *psi_bar_accum, double *L_bar,
+                                                   void *ws, size_t ws_bytes);
+
+/* Adjoint of P = psi * Hbar(q): psi_bar_accum += Rev(Rev(P_bar) * Hbar) and
+ * q_bar_accum(l) += -sum_{k>=l} hb_bar(k) for l >= 1 (row-broadcast), where
+ * hb_bar = diag(Rev(psi^T * Rev(P_bar))).  Either output may be NULL. */
+mrinv_status_t mrinv_transition_backward(mrinv_handle_t h, const double *psi, const double *q,
+                                         const double *P_bar, int d, int64_t n,
+                                         double *psi_bar_accum, double *q_bar_accum,
+                                         void *ws, size_t ws_bytes);
+
+/* Adjoint of mrinv_contract: X_bar(l) += scale * w(l) u v^T with w = out_bar,
+ * or its reverse cumulative sum when cumulative != 0. */
+mrinv_status_t mrinv_contract_backward(mrinv_handle_t h, const double *out_bar, int64_t n, int rows,
+                                       int cols, const double *u, const double *v, int cumulative,
+                                       double scale, double *X_bar_accum);
+
+/* Adjoint of mrinv_gather_block: X_bar[k][row_idx[a]][col_idx[b]] += Y_bar[k][a][b]
+ * (indices within each list must be distinct). */
+mrinv_status_t mrinv_scatter_block_add(mrinv_handle_t h, const double *Y_bar, int64_t n, int rows,
+                                       int cols, const int *row_idx, int nr, const int *col_idx,
+                                       int nc, double *X_bar_accum);
+
+/*
+ * Batched inversion of many independent problems of uneven d and n in one
+ * pass per Newton phase (persistent launches over a device task table).
+ *   q_ptrs, psi_ptrs : host arrays of `count` device pointers;
+ *   d, n             : host arrays of sizes (1 <= d <= 48 per problem).
+ * Each problem's result equals the single-problem call with the same precision.
+ */
+mrinv_status_t mrinv_psi_inverse_batched(mrinv_handle_t h, int count, const double *const *q_ptrs,
+                                         const int *d, const int64_t *n, mrinv_precision_t precision,
+                                         double *const *psi_ptrs, void *ws, size_t ws_bytes);
+size_t mrinv_batched_workspace_size(int count, const int *d, const int64_t *n,
+                                    mrinv_precision_t precision);
+
+/* Residual norms of a computed inverse X of A = e0 - q (Proposition 2.6,
+ * Section 5 accuracy measures): out[0] = sum_k ||(e0 - A*X)(k)||_F,
+ * out[1] = sum_k ||(e0 - X*A)(k)||_F, out[2] = max |(e0 - A*X)(k)_ij|.
+ * q, X : device [n][d][d]; out : host double[3].  Synchronises the stream. */
+mrinv_status_t mrinv_residual_norms(mrinv_handle_t h, const double *q, const double *X, int d,
+                                    int64_t n, double *out, void *ws, size_t ws_bytes);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MRINV_H */

@@ -262,3 +262,51 @@ def scaled_discrepancy(X, Xref, u: float = 2.0 ** -53) -> float:
     num = np.linalg.norm(_f64(X) - _f64(Xref), axis=(1, 2))
     den = np.maximum(np.linalg.norm(_f64(Xref), axis=(1, 2)), np.sqrt(u))
     return float(np.max(num / den))
+
+
+def geometric_psi(M, a, ks) -> np.ndarray:
+    """Closed form for geometric sojourns (Markov chain with one-step matrix
+    M = diag(a) + diag(1-a) p): psi(0) = I and psi(k) = M^(k-1) (M - diag(a))."""
+    M = np.asarray(M, dtype=np.float64)
+    d = M.shape[0]
+    out = []
+    for k in ks:
+        if k == 0:
+            out.append(np.eye(d))
+        else:
+            out.append(np.linalg.matrix_power(M, int(k) - 1) @ (M - np.diag(a)))
+    return np.array(out)
+
+
+def geometric_P(M, ks) -> np.ndarray:
+    """Closed form P(k) = M^k of the Markov case."""
+    M = np.asarray(M, dtype=np.float64)
+    return np.array([np.linalg.matrix_power(M, int(k)) for k in ks])
+
+
+def residuals_fft(q, X, row_block: int = 8):
+    """Left/right residuals e0 - A*X and e0 - X*A (A = e0 - q) on the horizon,
+    each product formed with numpy's real FFT at length >= 2n-1 (a library
+    primitive independent of the GPU code), blocked over output rows.
+    Returns (sum_k ||rho_L(k)||_F, sum_k ||rho_R(k)||_F, max|rho_L|, max|rho_R|)."""
+    A = e0_minus(q)
+    X = _f64(X)
+    n, d, _ = A.shape
+    Lf = 1
+    while Lf < 2 * n - 1:
+        Lf *= 2
+    out = []
+    for left, right in ((A, X), (X, A)):
+        Rh = np.fft.rfft(right, n=Lf, axis=0)            # [F, d, d]
+        fro2 = np.zeros(n)
+        mx = 0.0
+        for i0 in range(0, d, row_block):
+            Lh = np.fft.rfft(left[:, i0:i0 + row_block, :], n=Lf, axis=0)
+            prod = np.fft.irfft(np.matmul(Lh, Rh), n=Lf, axis=0)[:n]
+            rho = -prod
+            for i in range(prod.shape[1]):
+                rho[0, i, i0 + i] += 1.0
+            fro2 += np.sum(rho * rho, axis=(1, 2))
+            mx = max(mx, float(np.max(np.abs(rho))))
+        out.append((float(np.sum(np.sqrt(fro2))), mx))
+    return out[0][0], out[1][0], out[0][1], out[1][1]

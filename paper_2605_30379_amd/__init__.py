@@ -1,0 +1,491 @@
+"""mrinv — finite-horizon psi inversion and Markov renewal functionals on MI355X.
+
+Thin binding over the C-ABI library ``libmrinv.so`` (declared in
+``include/mrinv.h``): every function here only checks arguments, allocates
+outputs and workspace with torch on the tensor's device, and passes raw
+device pointers and the current HIP stream to the library.  All arithmetic
+runs in the library's HIP kernels.  There is no CPU fallback: without the
+built library or a GPU every call raises.
+
+Main entry points (Kordalis & Trevezas, Sections 2 and 4):
+
+* :func:`psi_inverse` — psi = (e0 - q)^-1 on the horizon (FP64 or mixed).
+* :func:`transition` — P = psi * Hbar.
+* :func:`markov_renewal_apply` — M = psi * L (reward / first-entrance kernels).
+* :func:`first_entrance`, :func:`reliability`, :func:`availability`.
+* :class:`PsiInverse`, :class:`RenewalApply`, :class:`Transition`,
+  :class:`Contract`, :class:`GatherBlock` — autograd Functions backed by the
+  library's adjoint kernels.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+import torch
+
+__all__ = [
+    "MrinvError", "lib", "library_path", "psi_inverse", "series_inverse", "markov_renewal_apply",
+    "transition", "survival", "first_entrance", "reliability", "availability", "contract",
+    "gather_block", "psi_inverse_backward", "markov_renewal_apply_backward", "transition_backward",
+    "contract_backward", "scatter_block_add", "psi_inverse_batched", "residual_norms", "sync_status",
+    "PsiInverse", "RenewalApply", "Transition", "Contract", "GatherBlock", "workspace_size",
+    "FP64", "MIXED_FP32", "OPS",
+]
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+library_path = os.path.join(_HERE, "libmrinv.so")
+
+FP64 = 0
+MIXED_FP32 = 1
+_PREC = {"fp64": FP64, "mixed": MIXED_FP32, "mixed_fp32": MIXED_FP32, FP64: FP64, MIXED_FP32: MIXED_FP32}
+OPS = {"psi_inverse": 0, "apply": 1, "transition": 2, "psi_backward": 3, "apply_backward": 4,
+       "transition_backward": 5, "first_entrance": 6, "availability": 7}
+
+_STATUS = {0: "ok", 1: "invalid argument", 2: "A(0) singular", 3: "non-finite value",
+           4: "workspace too small", 5: "unsupported size", 6: "HIP runtime error"}
+
+
+class MrinvError(RuntimeError):
+    def __init__(self, status: int, detail: str):
+        super().__init__(f"mrinv: {_STATUS.get(status, status)} ({detail})")
+        self.status = status
+
+
+_lib = None
+_lock = threading.Lock()
+_handles: dict = {}
+
+
+def lib():
+    """Load libmrinv.so (built by ``__graft_entry__.build()``); raises if absent."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    with _lock:
+        if _lib is not None:
+            return _lib
+        if not os.path.exists(library_path):
+            raise MrinvError(6, f"{library_path} is not built; run __graft_entry__.build()")
+        L = ctypes.CDLL(library_path)
+        vp, i32, i64, f64, sz = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_double, ctypes.c_size_t
+        ip = ctypes.POINTER(ctypes.c_int)
+        dp = ctypes.POINTER(ctypes.c_double)
+        sigs = {
+            "mrinv_create": (i32, [ctypes.POINTER(vp), vp]),
+            "mrinv_destroy": (i32, [vp]),
+            "mrinv_set_stream": (i32, [vp, vp]),
+            "mrinv_sync_status": (i32, [vp]),
+            "mrinv_status_string": (ctypes.c_char_p, [i32]),
+            "mrinv_last_error": (ctypes.c_char_p, []),
+            "mrinv_workspace_size": (sz, [i32, i32, i64, i32, i32]),
+            "mrinv_psi_inverse": (i32, [vp, vp, i32, i64, i32, vp, vp, sz]),
+            "mrinv_series_inverse": (i32, [vp, vp, i32, i64, i32, vp, vp, sz]),
+            "mrinv_markov_renewal_apply": (i32, [vp, vp, i32, i64, vp, i32, vp, vp, sz]),
+            "mrinv_transition": (i32, [vp, vp, vp, i32, i64, vp, vp, sz]),
+            "mrinv_survival": (i32, [vp, vp, i32, i64, vp]),
+            "mrinv_contract": (i32, [vp, vp, i64, i32, i32, vp, vp, i32, f64, f64, vp]),
+            "mrinv_gather_block": (i32, [vp, vp, i64, i32, i32, vp, i32, vp, i32, vp]),
+            "mrinv_first_entrance": (i32, [vp, vp, i32, i64, ip, dp, i32, vp, vp, vp, sz]),
+            "mrinv_reliability": (i32, [vp, vp, i32, i64, ip, dp, i32, vp, vp, sz]),
+            "mrinv_availability": (i32, [vp, vp, i32, i64, ip, dp, vp]),
+            "mrinv_psi_inverse_backward": (i32, [vp, vp, vp, i32, i64, vp, vp, sz]),
+            "mrinv_markov_renewal_apply_backward": (i32, [vp, vp, vp, vp, i32, i64, i32, vp, vp, vp, sz]),
+            "mrinv_transition_backward": (i32, [vp, vp, vp, vp, i32, i64, vp, vp, vp, sz]),
+            "mrinv_contract_backward": (i32, [vp, vp, i64, i32, i32, vp, vp, i32, f64, vp]),
+            "mrinv_scatter_block_add": (i32, [vp, vp, i64, i32, i32, vp, i32, vp, i32, vp]),
+            "mrinv_psi_inverse_batched": (i32, [vp, i32, ctypes.POINTER(vp), ip, ctypes.POINTER(i64), i32,
+                                                ctypes.POINTER(vp), vp, sz]),
+            "mrinv_batched_workspace_size": (sz, [i32, ip, ctypes.POINTER(i64), i32]),
+            "mrinv_residual_norms": (i32, [vp, vp, vp, i32, i64, dp, vp, sz]),
+        }
+        for name, (res, args) in sigs.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+        return L
+
+
+def _check(status: int):
+    if status != 0:
+        detail = lib().mrinv_last_error().decode(errors="replace")
+        raise MrinvError(status, detail)
+
+
+def _handle(device: torch.device):
+    """Per-device library handle bound to torch's current stream."""
+    idx = device.index if device.index is not None else torch.cuda.current_device()
+    L = lib()
+    h = _handles.get(idx)
+    if h is None:
+        with torch.cuda.device(idx):
+            hv = ctypes.c_void_p()
+            _check(L.mrinv_create(ctypes.byref(hv), ctypes.c_void_p(torch.cuda.current_stream(idx).cuda_stream)))
+        h = hv
+        _handles[idx] = h
+    _check(L.mrinv_set_stream(h, ctypes.c_void_p(torch.cuda.current_stream(idx).cuda_stream)))
+    return h
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def _seq(x: torch.Tensor, name: str, rows=None, cols=None) -> torch.Tensor:
+    if not isinstance(x, torch.Tensor):
+        raise TypeError(f"{name} must be a torch.Tensor")
+    if x.device.type != "cuda":
+        raise MrinvError(1, f"{name} must be a GPU tensor (no CPU path)")
+    if x.dtype != torch.float64:
+        raise MrinvError(1, f"{name} must be float64")
+    if x.dim() != 3:
+        raise MrinvError(1, f"{name} must have shape [n, rows, cols]")
+    if rows is not None and x.shape[1] != rows or cols is not None and x.shape[2] != cols:
+        raise MrinvError(1, f"{name} has shape {tuple(x.shape)}")
+    return x.contiguous()
+
+
+def _ws(nbytes: int, device) -> torch.Tensor:
+    return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+
+
+def workspace_size(op: str, d: int, n: int, r: int = 0, precision="fp64") -> int:
+    return int(lib().mrinv_workspace_size(OPS[op], d, n, r, _PREC[precision]))
+
+
+def sync_status(device=None):
+    """Synchronise and raise if a device-side condition was flagged."""
+    dev = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+    _check(lib().mrinv_sync_status(_handle(dev)))
+
+
+# ---------------------------------------------------------------------------
+# Forward entry points
+# ---------------------------------------------------------------------------
+
+def psi_inverse(q: torch.Tensor, precision="fp64", check: bool = False) -> torch.Tensor:
+    """psi = (e0 - q)^-1 on the horizon n = q.shape[0] (eq. (renewal-sequence))."""
+    q = _seq(q, "q")
+    n, d, d2 = q.shape
+    if d != d2:
+        raise MrinvError(1, "q must be square")
+    prec = _PREC[precision]
+    out = torch.empty_like(q)
+    ws = _ws(lib().mrinv_workspace_size(0, d, n, 0, prec), q.device)
+    _check(lib().mrinv_psi_inverse(_handle(q.device), _ptr(q), d, n, prec, _ptr(out), _ptr(ws), ws.numel()))
+    if check:
+        sync_status(q.device)
+    return out
+
+
+def series_inverse(A: torch.Tensor, precision="fp64", check: bool = False) -> torch.Tensor:
+    """A^(-1) on the horizon for a general sequence with A(0) nonsingular (Theorem 2.1)."""
+    A = _seq(A, "A")
+    n, d, _ = A.shape
+    prec = _PREC[precision]
+    out = torch.empty_like(A)
+    ws = _ws(lib().mrinv_workspace_size(0, d, n, 0, prec), A.device)
+    _check(lib().mrinv_series_inverse(_handle(A.device), _ptr(A), d, n, prec, _ptr(out), _ptr(ws), ws.numel()))
+    if check:
+        sync_status(A.device)
+    return out
+
+
+def markov_renewal_apply(psi: torch.Tensor, L: torch.Tensor) -> torch.Tensor:
+    """M = psi * L truncated at n (L: [n, d, r])."""
+    psi = _seq(psi, "psi")
+    n, d, _ = psi.shape
+    L = _seq(L, "L", rows=d)
+    if L.shape[0] != n:
+        raise MrinvError(1, "L horizon differs from psi")
+    r = L.shape[2]
+    M = torch.empty_like(L)
+    ws = _ws(lib().mrinv_workspace_size(1, d, n, r, 0), psi.device)
+    _check(lib().mrinv_markov_renewal_apply(_handle(psi.device), _ptr(psi), d, n, _ptr(L), r, _ptr(M), _ptr(ws),
+                                            ws.numel()))
+    return M
+
+
+def transition(psi: torch.Tensor, q: torch.Tensor) -> torch.Tensor:
+    """P = psi * Hbar(q) (eq. (transition-discrete))."""
+    psi = _seq(psi, "psi")
+    n, d, _ = psi.shape
+    q = _seq(q, "q", d, d)
+    P = torch.empty_like(psi)
+    ws = _ws(lib().mrinv_workspace_size(2, d, n, 0, 0), psi.device)
+    _check(lib().mrinv_transition(_handle(psi.device), _ptr(psi), _ptr(q), d, n, _ptr(P), _ptr(ws), ws.numel()))
+    return P
+
+
+def survival(q: torch.Tensor) -> torch.Tensor:
+    """Diagonal of Hbar: [n, d]."""
+    q = _seq(q, "q")
+    n, d, _ = q.shape
+    hb = torch.empty((n, d), dtype=torch.float64, device=q.device)
+    _check(lib().mrinv_survival(_handle(q.device), _ptr(q), d, n, _ptr(hb)))
+    return hb
+
+
+def _dvec(v, n, device, dtype=torch.float64):
+    t = torch.as_tensor(v, dtype=dtype).reshape(-1)
+    if t.numel() != n:
+        raise MrinvError(1, f"vector of length {t.numel()} != {n}")
+    return t.to(device).contiguous()
+
+
+def contract(X: torch.Tensor, u, v, cumulative: bool = False, offset: float = 0.0, scale: float = 1.0):
+    """out(k) = offset + scale * u^T X(k) v (cumulative: summed over l <= k)."""
+    X = _seq(X, "X")
+    n, r, c = X.shape
+    u = _dvec(u, r, X.device)
+    v = _dvec(v, c, X.device)
+    out = torch.empty(n, dtype=torch.float64, device=X.device)
+    _check(lib().mrinv_contract(_handle(X.device), _ptr(X), n, r, c, _ptr(u), _ptr(v), int(cumulative),
+                                float(offset), float(scale), _ptr(out)))
+    return out
+
+
+def gather_block(X: torch.Tensor, rows_idx, cols_idx) -> torch.Tensor:
+    X = _seq(X, "X")
+    n, r, c = X.shape
+    ri = torch.as_tensor(rows_idx, dtype=torch.int32).to(X.device).contiguous()
+    ci = torch.as_tensor(cols_idx, dtype=torch.int32).to(X.device).contiguous()
+    Y = torch.empty((n, ri.numel(), ci.numel()), dtype=torch.float64, device=X.device)
+    _check(lib().mrinv_gather_block(_handle(X.device), _ptr(X), n, r, c, _ptr(ri), ri.numel(), _ptr(ci),
+                                    ci.numel(), _ptr(Y)))
+    return Y
+
+
+def _imask(m, d):
+    arr = (ctypes.c_int * d)(*[int(bool(x)) for x in list(m)])
+    return arr
+
+
+def _dalpha(alpha, d):
+    if alpha is None:
+        raise MrinvError(1, "alpha is required")
+    vals = [float(x) for x in torch.as_tensor(alpha, dtype=torch.float64).reshape(-1).tolist()]
+    if len(vals) != d:
+        raise MrinvError(1, "alpha must have length d")
+    return (ctypes.c_double * d)(*vals)
+
+
+def first_entrance(q: torch.Tensor, in_D, alpha, precision="fp64"):
+    """(g, F): first-entrance mass alpha_C g_D(k) 1_D and cdf F_D(k) (eqs. (first-entrance-mass, -cdf))."""
+    q = _seq(q, "q")
+    n, d, _ = q.shape
+    mask = [int(bool(x)) for x in list(in_D)]
+    prec = _PREC[precision]
+    g = torch.empty(n, dtype=torch.float64, device=q.device)
+    F = torch.empty(n, dtype=torch.float64, device=q.device)
+    ws = _ws(lib().mrinv_workspace_size(6, d, n, max(1, sum(mask)), prec), q.device)
+    _check(lib().mrinv_first_entrance(_handle(q.device), _ptr(q), d, n, _imask(mask, d), _dalpha(alpha, d), prec,
+                                      _ptr(g), _ptr(F), _ptr(ws), ws.numel()))
+    return g, F
+
+
+def reliability(q: torch.Tensor, up, alpha, precision="fp64") -> torch.Tensor:
+    """R(k) = 1 - F_D(k) with D the complement of the up set."""
+    q = _seq(q, "q")
+    n, d, _ = q.shape
+    mask = [int(bool(x)) for x in list(up)]
+    prec = _PREC[precision]
+    R = torch.empty(n, dtype=torch.float64, device=q.device)
+    ws = _ws(lib().mrinv_workspace_size(6, d, n, max(1, d - sum(mask)), prec), q.device)
+    _check(lib().mrinv_reliability(_handle(q.device), _ptr(q), d, n, _imask(mask, d), _dalpha(alpha, d), prec,
+                                   _ptr(R), _ptr(ws), ws.numel()))
+    return R
+
+
+def availability(P: torch.Tensor, up, alpha) -> torch.Tensor:
+    """A(k) = alpha P(k) 1_U."""
+    P = _seq(P, "P")
+    n, d, _ = P.shape
+    A = torch.empty(n, dtype=torch.float64, device=P.device)
+    _check(lib().mrinv_availability(_handle(P.device), _ptr(P), d, n, _imask(up, d), _dalpha(alpha, d), _ptr(A)))
+    return A
+
+
+def residual_norms(q: torch.Tensor, X: torch.Tensor):
+    """(sum_k ||e0 - A*X||_F, sum_k ||e0 - X*A||_F, max |e0 - A*X|) with A = e0 - q."""
+    q = _seq(q, "q")
+    n, d, _ = q.shape
+    X = _seq(X, "X", d, d)
+    L = lib()
+    import math
+    lg = max(1, math.ceil(math.log2(2 * n - 1))) if n > 1 else 1
+    nl = (d * d + 1) // 2
+    spec = ((1 << lg) * nl * 16 + 255) // 256 * 256
+    need = 3 * spec + 2 * ((n * d * d * 8 + 255) // 256 * 256)
+    ws = _ws(need, q.device)
+    out = (ctypes.c_double * 3)()
+    _check(L.mrinv_residual_norms(_handle(q.device), _ptr(q), _ptr(X), d, n, out, _ptr(ws), ws.numel()))
+    return float(out[0]), float(out[1]), float(out[2])
+
+
+def psi_inverse_batched(qs, precision="mixed"):
+    """Invert a list of kernels of uneven (d, n); returns the list of psi."""
+    if not qs:
+        return []
+    qs = [_seq(q, f"q[{i}]") for i, q in enumerate(qs)]
+    dev = qs[0].device
+    count = len(qs)
+    prec = _PREC[precision]
+    outs = [torch.empty_like(q) for q in qs]
+    d_arr = (ctypes.c_int * count)(*[q.shape[1] for q in qs])
+    n_arr = (ctypes.c_int64 * count)(*[q.shape[0] for q in qs])
+    qp = (ctypes.c_void_p * count)(*[q.data_ptr() for q in qs])
+    op = (ctypes.c_void_p * count)(*[o.data_ptr() for o in outs])
+    L = lib()
+    ws = _ws(L.mrinv_batched_workspace_size(count, d_arr, n_arr, prec), dev)
+    _check(L.mrinv_psi_inverse_batched(_handle(dev), count, qp, d_arr, n_arr, prec, op, _ptr(ws), ws.numel()))
+    return outs
+
+
+# ---------------------------------------------------------------------------
+# Adjoint entry points
+# ---------------------------------------------------------------------------
+
+def psi_inverse_backward(psi: torch.Tensor, psi_bar: torch.Tensor) -> torch.Tensor:
+    psi = _seq(psi, "psi")
+    n, d, _ = psi.shape
+    psi_bar = _seq(psi_bar, "psi_bar", d, d)
+    qb = torch.empty_like(psi)
+    ws = _ws(lib().mrinv_workspace_size(3, d, n, 0, 0), psi.device)
+    _check(lib().mrinv_psi_inverse_backward(_handle(psi.device), _ptr(psi), _ptr(psi_bar), d, n, _ptr(qb), _ptr(ws),
+                                            ws.numel()))
+    return qb
+
+
+def markov_renewal_apply_backward(psi, L, M_bar, need_psi=True, need_L=True):
+    psi = _seq(psi, "psi")
+    n, d, _ = psi.shape
+    L = _seq(L, "L", rows=d)
+    r = L.shape[2]
+    M_bar = _seq(M_bar, "M_bar", d, r)
+    pb = torch.zeros_like(psi) if need_psi else None
+    lb = torch.empty_like(L) if need_L else None
+    ws = _ws(lib().mrinv_workspace_size(4, d, n, r, 0), psi.device)
+    _check(lib().mrinv_markov_renewal_apply_backward(_handle(psi.device), _ptr(psi), _ptr(L), _ptr(M_bar), d, n, r,
+                                                     _ptr(pb), _ptr(lb), _ptr(ws), ws.numel()))
+    return pb, lb
+
+
+def transition_backward(psi, q, P_bar, need_psi=True, need_q=True):
+    psi = _seq(psi, "psi")
+    n, d, _ = psi.shape
+    q = _seq(q, "q", d, d)
+    P_bar = _seq(P_bar, "P_bar", d, d)
+    pb = torch.zeros_like(psi) if need_psi else None
+    qb = torch.zeros_like(q) if need_q else None
+    ws = _ws(lib().mrinv_workspace_size(5, d, n, 0, 0), psi.device)
+    _check(lib().mrinv_transition_backward(_handle(psi.device), _ptr(psi), _ptr(q), _ptr(P_bar), d, n, _ptr(pb),
+                                           _ptr(qb), _ptr(ws), ws.numel()))
+    return pb, qb
+
+
+def contract_backward(out_bar, rows, cols, u, v, cumulative=False, scale=1.0) -> torch.Tensor:
+    out_bar = out_bar.contiguous()
+    n = out_bar.numel()
+    dev = out_bar.device
+    Xb = torch.zeros((n, rows, cols), dtype=torch.float64, device=dev)
+    u = _dvec(u, rows, dev)
+    v = _dvec(v, cols, dev)
+    _check(lib().mrinv_contract_backward(_handle(dev), _ptr(out_bar), n, rows, cols, _ptr(u), _ptr(v),
+                                         int(cumulative), float(scale), _ptr(Xb)))
+    return Xb
+
+
+def scatter_block_add(Y_bar, rows, cols, rows_idx, cols_idx, X_bar=None) -> torch.Tensor:
+    Y_bar = Y_bar.contiguous()
+    n = Y_bar.shape[0]
+    dev = Y_bar.device
+    if X_bar is None:
+        X_bar = torch.zeros((n, rows, cols), dtype=torch.float64, device=dev)
+    ri = torch.as_tensor(rows_idx, dtype=torch.int32).to(dev).contiguous()
+    ci = torch.as_tensor(cols_idx, dtype=torch.int32).to(dev).contiguous()
+    _check(lib().mrinv_scatter_block_add(_handle(dev), _ptr(Y_bar), n, rows, cols, _ptr(ri), ri.numel(), _ptr(ci),
+                                         ci.numel(), _ptr(X_bar)))
+    return X_bar
+
+
+# ---------------------------------------------------------------------------
+# Autograd
+# ---------------------------------------------------------------------------
+
+class PsiInverse(torch.autograd.Function):
+    """psi = (e0 - q)^-1 with the adjoint q_bar = Rev(psi^T * Rev(psi_bar) * psi^T)."""
+
+    @staticmethod
+    def forward(ctx, q, precision="fp64"):
+        psi = psi_inverse(q, precision)
+        ctx.save_for_backward(psi)
+        return psi
+
+    @staticmethod
+    def backward(ctx, psi_bar):
+        (psi,) = ctx.saved_tensors
+        return psi_inverse_backward(psi, psi_bar.to(torch.float64)), None
+
+
+class RenewalApply(torch.autograd.Function):
+    """M = psi * L."""
+
+    @staticmethod
+    def forward(ctx, psi, L):
+        ctx.save_for_backward(psi, L)
+        return markov_renewal_apply(psi, L)
+
+    @staticmethod
+    def backward(ctx, M_bar):
+        psi, L = ctx.saved_tensors
+        pb, lb = markov_renewal_apply_backward(psi, L, M_bar, ctx.needs_input_grad[0], ctx.needs_input_grad[1])
+        return pb, lb
+
+
+class Transition(torch.autograd.Function):
+    """P = psi * Hbar(q)."""
+
+    @staticmethod
+    def forward(ctx, psi, q):
+        ctx.save_for_backward(psi, q)
+        return transition(psi, q)
+
+    @staticmethod
+    def backward(ctx, P_bar):
+        psi, q = ctx.saved_tensors
+        return transition_backward(psi, q, P_bar, ctx.needs_input_grad[0], ctx.needs_input_grad[1])
+
+
+class Contract(torch.autograd.Function):
+    """out(k) = offset + scale * u^T X(k) v (optionally cumulative); u, v constants."""
+
+    @staticmethod
+    def forward(ctx, X, u, v, cumulative=False, offset=0.0, scale=1.0):
+        u = torch.as_tensor(u, dtype=torch.float64, device=X.device)
+        v = torch.as_tensor(v, dtype=torch.float64, device=X.device)
+        ctx.save_for_backward(u, v)
+        ctx.meta = (X.shape[1], X.shape[2], bool(cumulative), float(scale))
+        return contract(X, u, v, cumulative, offset, scale)
+
+    @staticmethod
+    def backward(ctx, ob):
+        u, v = ctx.saved_tensors
+        rows, cols, cum, scale = ctx.meta
+        return contract_backward(ob.to(torch.float64), rows, cols, u, v, cum, scale), None, None, None, None, None
+
+
+class GatherBlock(torch.autograd.Function):
+    """Y(k) = X(k)[rows_idx, cols_idx]."""
+
+    @staticmethod
+    def forward(ctx, X, rows_idx, cols_idx):
+        ctx.meta = (X.shape[1], X.shape[2], list(rows_idx), list(cols_idx))
+        return gather_block(X, rows_idx, cols_idx)
+
+    @staticmethod
+    def backward(ctx, Yb):
+        rows, cols, ri, ci = ctx.meta
+        return scatter_block_add(Yb.to(torch.float64), rows, cols, ri, ci), None, None

@@ -1,0 +1,797 @@
+// Host runtime and C-ABI of mrinv: handles, FFT plans, workspace layout, the
+// Newton driver for (e0 - q)^-1 and the Markov renewal functionals.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "../../include/mrinv.h"
+#include "common.h"
+#include "kernels.h"
+
+using namespace mrinv;
+
+// ---------------------------------------------------------------------------
+// Errors
+// ---------------------------------------------------------------------------
+static thread_local std::string g_last_error;
+
+static mrinv_status_t fail(mrinv_status_t s, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+static mrinv_status_t fail(mrinv_status_t s, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return s;
+}
+
+#define HIP_TRY(expr)                                                                               \
+    do {                                                                                            \
+        hipError_t _e = (expr);                                                                     \
+        if (_e != hipSuccess) return fail(MRINV_E_HIP, "%s: %s", #expr, hipGetErrorString(_e));     \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// Handle
+// ---------------------------------------------------------------------------
+constexpr size_t SCRATCH_BYTES = (size_t)MRINV_MAX_N * sizeof(double) + 4096 * sizeof(double);
+
+struct mrinv_handle_s {
+    hipStream_t stream = nullptr;
+    int device = 0;
+    cplx<double> *tw64 = nullptr;   // hi[TW_HI_SIZE] then lo[TW_LO_SIZE]
+    cplx<float> *tw32 = nullptr;
+    unsigned int *status = nullptr;
+    double *scratch = nullptr;      // small per-handle scratch (index lists, vectors, 1-lane scans)
+    Twiddles<double> t64() const { return {tw64, tw64 + TW_HI_SIZE}; }
+    Twiddles<float> t32() const { return {tw32, tw32 + TW_HI_SIZE}; }
+};
+
+static void host_twiddles(std::vector<double2> &hi, std::vector<double2> &lo) {
+    hi.resize(TW_HI_SIZE);
+    lo.resize(TW_LO_SIZE);
+    auto w = [](int64_t a) {
+        long double ang = 2.0L * 3.141592653589793238462643383279502884L * (long double)a / (long double)TW_LMAX;
+        double2 z;
+        z.x = (double)cosl(ang);
+        z.y = -(double)sinl(ang);
+        return z;
+    };
+    for (int j = 0; j < TW_HI_SIZE; ++j) hi[j] = w((int64_t)j << TW_LO_BITS);
+    for (int j = 0; j < TW_LO_SIZE; ++j) lo[j] = w(j);
+}
+
+extern "C" mrinv_status_t mrinv_create(mrinv_handle_t *handle, void *stream) {
+    if (!handle) return fail(MRINV_E_ARG, "handle is NULL");
+    *handle = nullptr;
+    auto *h = new (std::nothrow) mrinv_handle_s();
+    if (!h) return fail(MRINV_E_ARG, "out of host memory");
+    h->stream = (hipStream_t)stream;
+    HIP_TRY(hipGetDevice(&h->device));
+    std::vector<double2> hi, lo;
+    host_twiddles(hi, lo);
+    std::vector<float2> hi32(hi.size()), lo32(lo.size());
+    for (size_t i = 0; i < hi.size(); ++i) hi32[i] = make_float2((float)hi[i].x, (float)hi[i].y);
+    for (size_t i = 0; i < lo.size(); ++i) lo32[i] = make_float2((float)lo[i].x, (float)lo[i].y);
+    const size_t n64 = (TW_HI_SIZE + TW_LO_SIZE) * sizeof(double2);
+    const size_t n32 = (TW_HI_SIZE + TW_LO_SIZE) * sizeof(float2);
+    if (hipMalloc((void **)&h->tw64, n64) != hipSuccess || hipMalloc((void **)&h->tw32, n32) != hipSuccess ||
+        hipMalloc((void **)&h->status, 256) != hipSuccess ||
+        hipMalloc((void **)&h->scratch, SCRATCH_BYTES) != hipSuccess) {
+        mrinv_destroy(h);
+        return fail(MRINV_E_HIP, "device allocation failed in mrinv_create");
+    }
+    HIP_TRY(hipMemcpy(h->tw64, hi.data(), TW_HI_SIZE * sizeof(double2), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(h->tw64 + TW_HI_SIZE, lo.data(), TW_LO_SIZE * sizeof(double2), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(h->tw32, hi32.data(), TW_HI_SIZE * sizeof(float2), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(h->tw32 + TW_HI_SIZE, lo32.data(), TW_LO_SIZE * sizeof(float2), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemset(h->status, 0, 256));
+    HIP_TRY(hipDeviceSynchronize());
+    *handle = h;
+    g_last_error.clear();
+    return MRINV_OK;
+}
+
+extern "C" mrinv_status_t mrinv_destroy(mrinv_handle_t h) {
+    if (!h) return MRINV_OK;
+    if (h->stream) (void)hipStreamSynchronize(h->stream);
+    else (void)hipDeviceSynchronize();
+    if (h->tw64) (void)hipFree(h->tw64);
+    if (h->tw32) (void)hipFree(h->tw32);
+    if (h->status) (void)hipFree(h->status);
+    if (h->scratch) (void)hipFree(h->scratch);
+    delete h;
+    return MRINV_OK;
+}
+
+extern "C" mrinv_status_t mrinv_set_stream(mrinv_handle_t h, void *stream) {
+    if (!h) return fail(MRINV_E_ARG, "handle is NULL");
+    h->stream = (hipStream_t)stream;
+    return MRINV_OK;
+}
+
+extern "C" mrinv_status_t mrinv_sync_status(mrinv_handle_t h) {
+    if (!h) return fail(MRINV_E_ARG, "handle is NULL");
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    unsigned int s = 0;
+    HIP_TRY(hipMemcpy(&s, h->status, sizeof s, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemset(h->status, 0, sizeof s));
+    HIP_TRY(hipDeviceSynchronize());
+    if (s & STATUS_SINGULAR) return fail(MRINV_E_SINGULAR_A0, "A(0) is singular to working precision");
+    if (s & STATUS_NONFINITE) return fail(MRINV_E_NONFINITE, "non-finite value met on the device");
+    return MRINV_OK;
+}
+
+extern "C" const char *mrinv_status_string(mrinv_status_t s) {
+    switch (s) {
+        case MRINV_OK: return "ok";
+        case MRINV_E_ARG: return "invalid argument";
+        case MRINV_E_SINGULAR_A0: return "A(0) singular";
+        case MRINV_E_NONFINITE: return "non-finite value";
+        case MRINV_E_WORKSPACE: return "workspace too small";
+        case MRINV_E_UNSUPPORTED: return "unsupported size";
+        case MRINV_E_HIP: return "HIP runtime error";
+    }
+    return "unknown status";
+}
+
+extern "C" const char *mrinv_last_error(void) { return g_last_error.c_str(); }
+
+// ---------------------------------------------------------------------------
+// Plans and workspace
+// ---------------------------------------------------------------------------
+static int ceil_log2(int64_t x) {
+    int l = 0;
+    while (((int64_t)1 << l) < x) ++l;
+    return l;
+}
+
+// Transform length of a product truncated at n whose operands have n terms.
+static int lg_full(int64_t n) { return std::max(1, ceil_log2(2 * n - 1)); }
+
+static FftPlan make_plan(int lgL) {
+    FftPlan p{};
+    p.lgL = lgL;
+    p.npass = (lgL + LGP_MAX - 1) / LGP_MAX;
+    if (p.npass < 1) p.npass = 1;
+    int rem = lgL;
+    for (int j = 0; j < p.npass; ++j) {
+        const int left = p.npass - j;
+        p.lgP[j] = (rem + left - 1) / left;
+        rem -= p.lgP[j];
+    }
+    return p;
+}
+
+static inline int nl_of(int64_t lanes) { return (int)((lanes + 1) / 2); }
+static inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+// Bytes of one packed spectrum of length 2^lgL with `lanes` real lanes.
+static size_t spec_bytes(int lgL, int64_t lanes, bool dbl) {
+    return align256(((size_t)1 << lgL) * nl_of(lanes) * (dbl ? 16 : 8));
+}
+
+struct Carve {
+    char *p;
+    size_t used = 0;
+    explicit Carve(void *base) : p((char *)base) {}
+    template <typename X> X *take(size_t bytes) {
+        X *r = (X *)(p + used);
+        used += align256(bytes);
+        return r;
+    }
+};
+
+static size_t ws_psi(int d, int64_t n, mrinv_precision_t prec) {
+    const int64_t d2 = (int64_t)d * d;
+    const int lgN = std::max(1, ceil_log2(n));
+    if (prec == MRINV_FP64) return 3 * spec_bytes(lgN, d2, true);
+    const int lg2 = lg_full(n);
+    size_t spec = std::max(3 * spec_bytes(lgN, d2, false), 3 * spec_bytes(lg2, d2, true));
+    return spec + 2 * align256((size_t)n * d2 * sizeof(float));
+}
+
+static size_t ws_apply(int d, int64_t n, int r) {
+    const int lg = lg_full(n);
+    return spec_bytes(lg, (int64_t)d * d, true) + 2 * spec_bytes(lg, (int64_t)d * r, true);
+}
+
+static size_t ws_transition(int d, int64_t n) {
+    const int lg = lg_full(n);
+    return align256((size_t)n * d * sizeof(double)) + spec_bytes(lg, (int64_t)d * d, true) + spec_bytes(lg, d, true);
+}
+
+static size_t ws_psi_backward(int d, int64_t n) { return 3 * spec_bytes(lg_full(n), (int64_t)d * d, true); }
+
+static size_t ws_apply_backward(int d, int64_t n, int r) {
+    const int lg = lg_full(n);
+    return spec_bytes(lg, (int64_t)d * d, true) + 2 * spec_bytes(lg, (int64_t)d * r, true);
+}
+
+static size_t ws_transition_backward(int d, int64_t n) {
+    const int lg = lg_full(n);
+    return align256((size_t)n * d * sizeof(double)) * 2 + 2 * spec_bytes(lg, (int64_t)d * d, true) +
+           spec_bytes(lg, d, true);
+}
+
+static size_t ws_first_entrance(int d, int64_t n, int nD, mrinv_precision_t prec) {
+    const int nC = d - nD;
+    if (nC <= 0) return 256;
+    // q_CC, psi_C, q_CD and g_D, then the larger of the inverse and apply workspaces.
+    const size_t blocks = 2 * align256((size_t)n * nC * nC * 8) + 2 * align256((size_t)n * nC * nD * 8);
+    return blocks + std::max(ws_psi(nC, n, prec), ws_apply(nC, n, nD));
+}
+
+extern "C" size_t mrinv_workspace_size(mrinv_op_t op, int d, int64_t n, int r, mrinv_precision_t prec) {
+    if (d < 1 || d > MRINV_MAX_D || n < 1 || n > MRINV_MAX_N) return 0;
+    switch (op) {
+        case MRINV_OP_PSI_INVERSE: return ws_psi(d, n, prec);
+        case MRINV_OP_APPLY: return (r < 1 || r > MRINV_MAX_D) ? 0 : ws_apply(d, n, r);
+        case MRINV_OP_TRANSITION: return ws_transition(d, n);
+        case MRINV_OP_PSI_BACKWARD: return ws_psi_backward(d, n);
+        case MRINV_OP_APPLY_BACKWARD: return (r < 1 || r > MRINV_MAX_D) ? 0 : ws_apply_backward(d, n, r);
+        case MRINV_OP_TRANSITION_BACKWARD: return ws_transition_backward(d, n);
+        case MRINV_OP_FIRST_ENTRANCE: return (r < 1 || r > d) ? 0 : ws_first_entrance(d, n, r, prec);
+        case MRINV_OP_AVAILABILITY: return 256;
+    }
+    return 0;
+}
+
+// ---------------------------------------------------------------------------
+// Transform helpers
+// ---------------------------------------------------------------------------
+template <typename T> static Twiddles<T> tw_of(mrinv_handle_t h);
+template <> Twiddles<double> tw_of<double>(mrinv_handle_t h) { return h->t64(); }
+template <> Twiddles<float> tw_of<float>(mrinv_handle_t h) { return h->t32(); }
+
+static SrcDesc src_real(const void *p, bool dbl, int64_t ld, int nreal, int64_t lo, int64_t hi, int64_t rev = -1,
+                        int e0_d = 0) {
+    SrcDesc s{};
+    s.kind = dbl ? SRC_REAL64 : SRC_REAL32;
+    s.p = p;
+    s.ld = ld;
+    s.nreal = nreal;
+    s.lo = lo;
+    s.hi = hi;
+    s.rev = rev;
+    s.e0_d = e0_d;
+    return s;
+}
+
+static DstDesc dst_real(void *p, bool dbl, int64_t ld, int nreal, int64_t lo, int64_t hi, double scale, int op,
+                        int64_t rev = -1, unsigned int *status = nullptr) {
+    DstDesc d{};
+    d.kind = dbl ? DST_REAL64 : DST_REAL32;
+    d.p = p;
+    d.ld = ld;
+    d.nreal = nreal;
+    d.lo = lo;
+    d.hi = hi;
+    d.scale = scale;
+    d.op = op;
+    d.rev = rev;
+    d.status = status;
+    return d;
+}
+
+// Forward transform of a real source into Z (all passes).
+template <typename T>
+static hipError_t fwd(mrinv_handle_t h, const FftPlan &p, int nl, cplx<T> *Z, const SrcDesc &src) {
+    const Twiddles<T> tw = tw_of<T>(h);
+    hipError_t e = fft_pass<T>(0, p, 0, nl, Z, src, dst_z(), tw, h->stream);
+    for (int j = 1; j < p.npass && e == hipSuccess; ++j) e = fft_pass<T>(0, p, j, nl, Z, src_z(), dst_z(), tw, h->stream);
+    return e;
+}
+
+// Inverse transform of Z into a real destination (all passes).
+template <typename T>
+static hipError_t inv(mrinv_handle_t h, const FftPlan &p, int nl, cplx<T> *Z, const DstDesc &dst) {
+    const Twiddles<T> tw = tw_of<T>(h);
+    hipError_t e = hipSuccess;
+    for (int j = p.npass - 1; j >= 1 && e == hipSuccess; --j) e = fft_pass<T>(1, p, j, nl, Z, src_z(), dst_z(), tw, h->stream);
+    if (e == hipSuccess) e = fft_pass<T>(1, p, 0, nl, Z, src_z(), dst, tw, h->stream);
+    return e;
+}
+
+// Z <- DFT(mask(IDFT(Z))): time rows outside [lo, hi) are zeroed, the rest
+// scaled by 1/L (and negated when neg).
+template <typename T>
+static hipError_t remask(mrinv_handle_t h, const FftPlan &p, int nl, cplx<T> *Z, int64_t lo, int64_t hi, bool neg) {
+    const Twiddles<T> tw = tw_of<T>(h);
+    hipError_t e = hipSuccess;
+    for (int j = p.npass - 1; j >= 1 && e == hipSuccess; --j) e = fft_pass<T>(1, p, j, nl, Z, src_z(), dst_z(), tw, h->stream);
+    DstDesc m = dst_z();
+    m.lo = lo;
+    m.hi = hi;
+    m.op = neg ? OP_NEG : OP_STORE;
+    m.scale = 1.0 / (double)((int64_t)1 << p.lgL);
+    if (e == hipSuccess) e = fft_pass<T>(2, p, 0, nl, Z, src_z(), m, tw, h->stream);
+    for (int j = 1; j < p.npass && e == hipSuccess; ++j) e = fft_pass<T>(0, p, j, nl, Z, src_z(), dst_z(), tw, h->stream);
+    return e;
+}
+
+static GemmDesc gdesc(int ra, int m, int cb, int ta = 0, int tb = 0) {
+    GemmDesc g{};
+    g.ra = ra;
+    g.m = m;
+    g.cb = cb;
+    g.transA = ta;
+    g.transB = tb;
+    g.nlA = nl_of((int64_t)ra * m);
+    g.nlB = nl_of((int64_t)m * cb);
+    g.nlC = nl_of((int64_t)ra * cb);
+    return g;
+}
+
+// ---------------------------------------------------------------------------
+// Newton inversion (eq. (newton)) in precision T.  src is A (e0 == 0) or q
+// (e0 == 1, A = e0 - q); the result's coefficients are written to out
+// (float64 when T is double, float32 otherwise), rows 0..n-1.
+// Step m -> m' = min(2m, n) at length L = 2^ceil(log2 m'):
+//   T  = A mod x^m' * B  (cyclic of length L; wrap-around lands in [0, m))
+//   E  = -T on [m, m')   (A*B = e0 mod x^m, so e0 - A*B vanishes below m)
+//   B[m, m') = (B * E)[m, m')
+// ---------------------------------------------------------------------------
+template <typename T>
+static mrinv_status_t newton(mrinv_handle_t h, const double *src, int e0, int d, int64_t n, void *out,
+                             cplx<T> *SA, cplx<T> *SB, cplx<T> *ST) {
+    const bool dbl = sizeof(T) == 8;
+    const int d2 = d * d;
+    const int nl = nl_of(d2);
+    HIP_TRY(gj_inverse(src, d, e0, dbl ? (double *)out : nullptr, dbl ? nullptr : (float *)out, h->status, h->stream));
+    const GemmDesc g = gdesc(d, d, d);
+    for (int64_t m = 1; m < n;) {
+        const int64_t m2 = std::min(2 * m, n);
+        const FftPlan p = make_plan(ceil_log2(m2));
+        const double invL = 1.0 / (double)((int64_t)1 << p.lgL);
+        HIP_TRY(fwd<T>(h, p, nl, SA, src_real(src, true, d2, d2, 0, m2, -1, e0 ? d : 0)));
+        HIP_TRY(fwd<T>(h, p, nl, SB, src_real(out, dbl, d2, d2, 0, m)));
+        HIP_TRY(freq_gemm<T>(p, g, SA, SB, ST, h->stream));
+        HIP_TRY(remask<T>(h, p, nl, ST, m, m2, true));
+        HIP_TRY(freq_gemm<T>(p, g, SB, ST, SA, h->stream));
+        HIP_TRY(inv<T>(h, p, nl, SA, dst_real(out, dbl, d2, d2, m, m2, invL, OP_STORE, -1, h->status)));
+        m = m2;
+    }
+    return MRINV_OK;
+}
+
+static mrinv_status_t check_dn(int d, int64_t n) {
+    if (d < 1 || n < 1) return fail(MRINV_E_ARG, "need d >= 1 and n >= 1 (d=%d, n=%lld)", d, (long long)n);
+    if (d > MRINV_MAX_D) return fail(MRINV_E_UNSUPPORTED, "d=%d exceeds %d", d, MRINV_MAX_D);
+    if (n > MRINV_MAX_N) return fail(MRINV_E_UNSUPPORTED, "n=%lld exceeds %lld", (long long)n, (long long)MRINV_MAX_N);
+    return MRINV_OK;
+}
+
+static mrinv_status_t check_ws(void *ws, size_t have, size_t need) {
+    if (need > have) return fail(MRINV_E_WORKSPACE, "workspace %zu bytes < %zu needed", have, need);
+    if (need && !ws) return fail(MRINV_E_WORKSPACE, "workspace is NULL");
+    if (((uintptr_t)ws) & 255) return fail(MRINV_E_WORKSPACE, "workspace not 256-byte aligned");
+    return MRINV_OK;
+}
+
+#define CHECK(expr)                          \
+    do {                                     \
+        mrinv_status_t _s = (expr);          \
+        if (_s != MRINV_OK) return _s;       \
+    } while (0)
+
+static mrinv_status_t inverse_impl(mrinv_handle_t h, const double *src, int e0, int d, int64_t n,
+                                   mrinv_precision_t prec, double *out, void *ws, size_t wsb) {
+    if (!h || !src || !out) return fail(MRINV_E_ARG, "NULL handle or pointer");
+    CHECK(check_dn(d, n));
+    if (prec != MRINV_FP64 && prec != MRINV_MIXED_FP32) return fail(MRINV_E_ARG, "unknown precision %d", (int)prec);
+    CHECK(check_ws(ws, wsb, ws_psi(d, n, prec)));
+    const int64_t d2 = (int64_t)d * d;
+    const int nl = nl_of(d2);
+    const int lgN = std::max(1, ceil_log2(n));
+    Carve cv(ws);
+    if (prec == MRINV_FP64) {
+        const size_t sb = spec_bytes(lgN, d2, true);
+        auto *SA = cv.take<cplx<double>>(sb);
+        auto *SB = cv.take<cplx<double>>(sb);
+        auto *ST = cv.take<cplx<double>>(sb);
+        return newton<double>(h, src, e0, d, n, out, SA, SB, ST);
+    }
+    // Mixed: float32 Newton into X, then one sweep with a float64 residual.
+    float *X = cv.take<float>((size_t)n * d2 * sizeof(float));
+    float *R = cv.take<float>((size_t)n * d2 * sizeof(float));
+    char *spec = cv.p + cv.used;
+    {
+        const size_t sb = spec_bytes(lgN, d2, false);
+        auto *SA = (cplx<float> *)spec;
+        auto *SB = (cplx<float> *)(spec + sb);
+        auto *ST = (cplx<float> *)(spec + 2 * sb);
+        CHECK(newton<float>(h, src, e0, d, n, X, SA, SB, ST));
+    }
+    const FftPlan p2 = make_plan(lg_full(n));
+    const double invL = 1.0 / (double)((int64_t)1 << p2.lgL);
+    const GemmDesc g = gdesc(d, d, d);
+    {
+        // R = e0 - A*X on [0, n) in float64 (full product, no wrap-around at L >= 2n-1).
+        const size_t sb = spec_bytes(p2.lgL, d2, true);
+        auto *SA = (cplx<double> *)spec;
+        auto *SB = (cplx<double> *)(spec + sb);
+        auto *ST = (cplx<double> *)(spec + 2 * sb);
+        HIP_TRY(fwd<double>(h, p2, nl, SA, src_real(src, true, d2, d2, 0, n, -1, e0 ? d : 0)));
+        HIP_TRY(fwd<double>(h, p2, nl, SB, src_real(X, false, d2, d2, 0, n)));
+        HIP_TRY(freq_gemm<double>(p2, g, SA, SB, ST, h->stream));
+        DstDesc dr = dst_real(R, false, d2, d2, 0, n, invL, OP_E0MINUS);
+        dr.e0_d = d;
+        HIP_TRY(inv<double>(h, p2, nl, ST, dr));
+    }
+    {
+        // psi = X + X*R, the correction product in float32.
+        const size_t sb = spec_bytes(p2.lgL, d2, false);
+        auto *SA = (cplx<float> *)spec;
+        auto *SB = (cplx<float> *)(spec + sb);
+        auto *ST = (cplx<float> *)(spec + 2 * sb);
+        HIP_TRY(fwd<float>(h, p2, nl, SA, src_real(X, false, d2, d2, 0, n)));
+        HIP_TRY(fwd<float>(h, p2, nl, SB, src_real(R, false, d2, d2, 0, n)));
+        HIP_TRY(freq_gemm<float>(p2, g, SA, SB, ST, h->stream));
+        DstDesc dx = dst_real(out, true, d2, d2, 0, n, invL, OP_XPLUS, -1, h->status);
+        dx.aux = X;
+        HIP_TRY(inv<float>(h, p2, nl, ST, dx));
+    }
+    return MRINV_OK;
+}
+
+extern "C" mrinv_status_t mrinv_psi_inverse(mrinv_handle_t h, const double *q, int d, int64_t n,
+                                            mrinv_precision_t precision, double *psi, void *ws, size_t ws_bytes) {
+    return inverse_impl(h, q, 1, d, n, precision, psi, ws, ws_bytes);
+}
+
+extern "C" mrinv_status_t mrinv_series_inverse(mrinv_handle_t h, const double *A, int d, int64_t n,
+                                               mrinv_precision_t precision, double *Ainv, void *ws,
+                                               size_t ws_bytes) {
+    return inverse_impl(h, A, 0, d, n, precision, Ainv, ws, ws_bytes);
+}
+
+// ---------------------------------------------------------------------------
+// Products with psi
+// ---------------------------------------------------------------------------
+extern "C" mrinv_status_t mrinv_markov_renewal_apply(mrinv_handle_t h, const double *psi, int d, int64_t n,
+                                                     const double *L, int r, double *M, void *ws, size_t wsb) {
+    if (!h || !psi || !L || !M) return fail(MRINV_E_ARG, "NULL handle or pointer");
+    CHECK(check_dn(d, n));
+    if (r < 1 || r > MRINV_MAX_D) return fail(r < 1 ? MRINV_E_ARG : MRINV_E_UNSUPPORTED, "bad r=%d", r);
+    CHECK(check_ws(ws, wsb, ws_apply(d, n, r)));
+    const FftPlan p = make_plan(lg_full(n));
+    const int64_t d2 = (int64_t)d * d, dr = (int64_t)d * r;
+    Carve cv(ws);
+    auto *SP = cv.take<cplx<double>>(spec_bytes(p.lgL, d2, true));
+    auto *SL = cv.take<cplx<double>>(spec_bytes(p.lgL, dr, true));
+    auto *SM = cv.take<cplx<double>>(spec_bytes(p.lgL, dr, true));
+    HIP_TRY(fwd<double>(h, p, nl_of(d2), SP, src_real(psi, true, d2, (int)d2, 0, n)));
+    HIP_TRY(fwd<double>(h, p, nl_of(dr), SL, src_real(L, true, dr, (int)dr, 0, n)));
+    HIP_TRY(freq_gemm<double>(p, gdesc(d, d, r), SP, SL, SM, h->stream));
+    const double invL = 1.0 / (double)((int64_t)1 << p.lgL);
+    HIP_TRY(inv<double>(h, p, nl_of(dr), SM, dst_real(M, true, dr, (int)dr, 0, n, invL, OP_STORE, -1, h->status)));
+    return MRINV_OK;
+}
+
+extern "C" mrinv_status_t mrinv_survival(mrinv_handle_t h, const double *q, int d, int64_t n, double *hb) {
+    if (!h || !q || !hb) return fail(MRINV_E_ARG, "NULL handle or pointer");
+    CHECK(check_dn(d, n));
+    HIP_TRY(survival(q, d, n, hb, h->stream));
+    return MRINV_OK;
+}
+
+extern "C" mrinv_status_t mrinv_transition(mrinv_handle_t h, const double *psi, const double *q, int d, int64_t n,
+                                           double *P, void *ws, size_t wsb) {
+    if (!h || !psi || !q || !P) return fail(MRINV_E_ARG, "NULL handle or pointer");
+    CHECK(check_dn(d, n));
+    CHECK(check_ws(ws, wsb, ws_transition(d, n)));
+    const FftPlan p = make_plan(lg_full(n));
+    const int64_t d2 = (int64_t)d * d;
+    Carve cv(ws);
+    double *hb = cv.take<double>((size_t)n * d * sizeof(double));
+    auto *SP = cv.take<cplx<double>>(spec_bytes(p.lgL, d2, true));
+    auto *SH = cv.take<cplx<double>>(spec_bytes(p.lgL, d, true));
+    HIP_TRY(survival(q, d, n, hb, h->stream));
+    HIP_TRY(fwd<double>(h, p, nl_of(d2), SP, src_real(psi, true, d2, (int)d2, 0, n)));
+    HIP_TRY(fwd<double>(h, p, nl_of(d), SH, src_real(hb, true, d, d, 0, n)));
+    HIP_TRY(freq_diag<double>(p, d, d, SP, SH, SP, h->stream));
+    const double invL = 1.0 / (double)((int64_t)1 << p.lgL);
+    HIP_TRY(inv<double>(h, p, nl_of(d2), SP, dst_real(P, true, d2, (int)d2, 0, n, invL, OP_STORE, -1, h->status)));
+    return MRINV_OK;
+}
+
+extern "C" mrinv_status_t mrinv_contract(mrinv_handle_t h, const double *X, int64_t n, int rows, int cols,
+                                         const double *u, const double *v, int cumulative, double offset,
+                                         double scale, double *out) {
+    if (!h || !X || !u || !v || !out) return fail(MRINV_E_ARG, "NULL handle or pointer");
+    if (n < 1 || rows < 1 || cols < 1 || n > MRINV_MAX_N) return fail(MRINV_E_ARG, "bad sizes");
+    HIP_TRY(contract(X, n, rows, cols, u, v, cumulative, offset, scale, out, h->stream));
+    return MRINV_OK;
+}
+
+extern "C" mrinv_status_t mrinv_contract_backward(mrinv_handle_t h, const double *out_bar, int64_t n, int rows,
+                                                  int cols, const double *u, const double *v, int cumulative,
+                                                  double scale, double *X_bar_accum) {
+    if (!h || !out_bar || !u || !v || !X_bar_accum) return fail(MRINV_E_ARG, "NULL handle or pointer");
+    if (n < 1 || rows < 1 || cols < 1 || n > MRINV_MAX_N) return fail(MRINV_E_ARG, "bad sizes");
+    const double *w = out_bar;
+    if (cumulative) {
+        HIP_TRY(hipMemcpyAsync(h->scratch, out_bar, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, h->stream));
+        w = h->scratch;
+    }
+    HIP_TRY(contract_backward(w, n, rows, cols, u, v, cumulative, scale, X_bar_accum, h->stream));
+    return MRINV_OK;
+}
+
+extern "C" mrinv_status_t mrinv_gather_block(mrinv_handle_t h, const double *X, int64_t n, int rows, int cols,
+                                             const int *row_idx, int nr, const int *col_idx, int nc, double *Y) {
+    if (!h || !X || !row_idx || !col_idx || !Y) return fail(MRINV_E_ARG, "NULL handle or pointer");
+    if (n < 1 || nr < 1 || nc < 1 || rows < 1 || cols < 1) return fail(MRINV_E_ARG, "bad sizes");
+    HIP_TRY(gather_block(X, n, rows, cols, row_idx, nr, col_idx, nc, Y, h->stream));
+    return MRINV_OK;
+}
+
+extern "C" mrinv_status_t mrinv_scatter_block_add(mrinv_handle_t h, const double *Y_bar, int64_t n, int rows,
+                                                  int cols, const int *row_idx, int nr, const int *col_idx, int nc,
+                                                  double *X_bar_accum) {
+    if (!h || !Y_bar || !row_idx || !col_idx || !X_bar_accum) return fail(MRINV_E_ARG, "NULL handle or pointer");
+    if (n < 1 || nr < 1 || nc < 1 || rows < 1 || cols < 1) return fail(MRINV_E_ARG, "bad sizes");
+    HIP_TRY(scatter_block_add(Y_bar, n, rows, cols, row_idx, nr, col_idx, nc, X_bar_accum, h->stream));
+    return MRINV_OK;
+}
+
+// Device copies of small host vectors, placed in the handle scratch after the
+// first MRINV_MAX_N doubles (which the 1-lane scans use).
+struct SmallVecs {
+    int *ci, *di;
+    double *alpha, *ones;
+};
+
+static mrinv_status_t put_small(mrinv_handle_t h, const std::vector<int> &ci, const std::vector<int> &di,
+                                const std::vector<double> &alpha, int nones, SmallVecs &sv) {
+    char *base = (char *)(h->scratch + MRINV_MAX_N);
+    sv.ci = (int *)base;
+    sv.di = (int *)(base + 1024);
+    sv.alpha = (double *)(base + 2048);
+    sv.ones = (double *)(base + 2048 + 1024);
+    std::vector<double> ones(std::max(nones, 1), 1.0);
+    if (!ci.empty()) HIP_TRY(hipMemcpyAsync(sv.ci, ci.data(), ci.size() * sizeof(int), hipMemcpyHostToDevice, h->stream));
+    if (!di.empty()) HIP_TRY(hipMemcpyAsync(sv.di, di.data(), di.size() * sizeof(int), hipMemcpyHostToDevice, h->stream));
+    if (!alpha.empty())
+        HIP_TRY(hipMemcpyAsync(sv.alpha, alpha.data(), alpha.size() * sizeof(double), hipMemcpyHostToDevice, h->stream));
+    HIP_TRY(hipMemcpyAsync(sv.ones, ones.data(), ones.size() * sizeof(double), hipMemcpyHostToDevice, h->stream));
+    // The host vectors above are about to go out of scope.
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    return MRINV_OK;
+}
+
+static mrinv_status_t first_entrance_impl(mrinv_handle_t h, const double *q, int d, int64_t n, const int *in_D,
+                                          const double *alpha, mrinv_precision_t prec, double *g, double *F,
+                                          double offset, double scale, void *ws, size_t wsb) {
+    if (!h || !q || !in_D || !alpha || !F) return fail(MRINV_E_ARG, "NULL handle or pointer");
+    CHECK(check_dn(d, n));
+    std::vector<int> ci, di;
+    for (int i = 0; i < d; ++i) (in_D[i] ? di : ci).push_back(i);
+    if (di.empty()) return fail(MRINV_E_ARG, "target set D is empty");
+    const int nC = (int)ci.size(), nD = (int)di.size();
+    CHECK(check_ws(ws, wsb, ws_first_entrance(d, n, nD, prec)));
+    if (nC == 0) {
+        // Already in D at time 0.
+        HIP_TRY(fill_f64(F, n, offset + scale, h->stream));
+        if (g) {
+            HIP_TRY(fill_f64(g, n, 0.0, h->stream));
+            HIP_TRY(fill_f64(g, 1, 1.0, h->stream));
+        }
+        return MRINV_OK;
+    }
+    std::vector<double> aC(nC);
+    for (int a = 0; a < nC; ++a) aC[a] = alpha[ci[a]];
+    SmallVecs sv;
+    CHECK(put_small(h, ci, di, aC, std::max(nD, nC), sv));
+    Carve cv(ws);
+    double *qCC = cv.take<double>((size_t)n * nC * nC * 8);
+    double *qCD = cv.take<double>((size_t)n * nC * nD * 8);
+    double *gD = cv.take<double>((size_t)n * nC * nD * 8);
+    void *rest = cv.p + cv.used;
+    const size_t rest_b = wsb - cv.used;
+    HIP_TRY(gather_block(q, n, d, d, sv.ci, nC, sv.ci, nC, qCC, h->stream));
+    HIP_TRY(gather_block(q, n, d, d, sv.ci, nC, sv.di, nD, qCD, h->stream));
+    // psi_C is written into the gD slot's neighbour: reuse qCC's storage after
+    // inversion is not possible (input), so place psi_C in the workspace tail.
+    double *psiC = (double *)rest;
+    const size_t psib = align256((size_t)n * nC * nC * 8);
+    void *ws2 = (char *)rest + psib;
+    const size_t need_inv = ws_psi(nC, n, prec), need_app = ws_apply(nC, n, nD);
+    if (rest_b < psib + std::max(need_inv, need_app)) return fail(MRINV_E_WORKSPACE, "workspace too small");
+    CHECK(mrinv_psi_inverse(h, qCC, nC, n, prec, psiC, ws2, rest_b - psib));
+    CHECK(mrinv_markov_renewal_apply(h, psiC, nC, n, qCD, nD, gD, ws2, rest_b - psib));
+    if (g) HIP_TRY(contract(gD, n, nC, nD, sv.alpha, sv.ones, 0, 0.0, 1.0, g, h->stream));
+    HIP_TRY(contract(gD, n, nC, nD, sv.alpha, sv.ones, 1, offset, scale, F, h->stream));
+    return MRINV_OK;
+}
+
+extern "C" mrinv_status_t mrinv_first_entrance(mrinv_handle_t h, const double *q, int d, int64_t n,
+                                               const int *in_D, const double *alpha, mrinv_precision_t precision,
+                                               double *g, double *F, void *ws, size_t wsb) {
+    return first_entrance_impl(h, q, d, n, in_D, alpha, precision, g, F, 0.0, 1.0, ws, wsb);
+}
+
+extern "C" mrinv_status_t mrinv_reliability(mrinv_handle_t h, const double *q, int d, int64_t n, const int *up,
+                                            const double *alpha, mrinv_precision_t precision, double *R, void *ws,
+                                            size_t wsb) {
+    if (!up) return fail(MRINV_E_ARG, "NULL up mask");
+    if (d < 1 || d > MRINV_MAX_D) return check_dn(d, n);
+    std::vector<int> down(d);
+    for (int i = 0; i < d; ++i) down[i] = up[i] ? 0 : 1;
+    return first_entrance_impl(h, q, d, n, down.data(), alpha, precision, nullptr, R, 1.0, -1.0, ws, wsb);
+}
+
+extern "C" mrinv_status_t mrinv_availability(mrinv_handle_t h, const double *P, int d, int64_t n, const int *up,
+                                             const double *alpha, double *A) {
+    if (!h || !P || !up || !alpha || !A) return fail(MRINV_E_ARG, "NULL handle or pointer");
+    CHECK(check_dn(d, n));
+    std::vector<double> al(alpha, alpha + d), ind(d);
+    for (int i = 0; i < d; ++i) ind[i] = up[i] ? 1.0 : 0.0;
+    SmallVecs sv;
+    CHECK(put_small(h, {}, {}, al, d, sv));
+    HIP_TRY(hipMemcpyAsync(sv.ones, ind.data(), d * sizeof(double), hipMemcpyHostToDevice, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    HIP_TRY(contract(P, n, d, d, sv.alpha, sv.ones, 0, 0.0, 1.0, A, h->stream));
+    return MRINV_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Adjoints
+// ---------------------------------------------------------------------------
+extern "C" mrinv_status_t mrinv_psi_inverse_backward(mrinv_handle_t h, const double *psi, const double *psi_bar,
+                                                     int d, int64_t n, double *q_bar, void *ws, size_t wsb) {
+    if (!h || !psi || !psi_bar || !q_bar) return fail(MRINV_E_ARG, "NULL handle or pointer");
+    CHECK(check_dn(d, n));
+    CHECK(check_ws(ws, wsb, ws_psi_backward(d, n)));
+    const FftPlan p = make_plan(lg_full(n));
+    const int64_t d2 = (int64_t)d * d;
+    const int nl = nl_of(d2);
+    Carve cv(ws);
+    const size_t sb = spec_bytes(p.lgL, d2, true);
+    auto *S1 = cv.take<cplx<double>>(sb);
+    auto *S2 = cv.take<cplx<double>>(sb);
+    auto *S3 = cv.take<cplx<double>>(sb);
+    const double invL = 1.0 / (double)((int64_t)1 << p.lgL);
+    HIP_TRY(fwd<double>(h, p, nl, S1, src_real(psi, true, d2, (int)d2, 0, n)));
+    HIP_TRY(fwd<double>(h, p, nl, S2, src_real(psi_bar, true, d2, (int)d2, 0, n, n - 1)));
+    // V^r = Rev(psi_bar) * psi^T, kept on [0, n)
+    HIP_TRY(freq_gemm<double>(p, gdesc(d, d, d, 0, 1), S2, S1, S3, h->stream));
+    HIP_TRY(remask<double>(h, p, nl, S3, 0, n, false));
+    // q_bar^r = psi^T * V^r
+    HIP_TRY(freq_gemm<double>(p, gdesc(d, d, d, 1, 0), S1, S3, S2, h->stream));
+    HIP_TRY(inv<double>(h, p, nl, S2, dst_real(q_bar, true, d2, (int)d2, 0, n, invL, OP_STORE, n - 1, h->status)));
+    return MRINV_OK;
+}
+
+extern "C" mrinv_status_t mrinv_markov_renewal_apply_backward(mrinv_handle_t h, const double *psi, const double *L,
+                                                              const double *M_bar, int d, int64_t n, int r,
+                                                              double *psi_bar_accum, double *L_bar, void *ws,
+                                                              size_t wsb) {
+    if (!h || !psi || !L || !M_bar) return fail(MRINV_E_ARG, "NULL handle or pointer");
+    CHECK(check_dn(d, n));
+    if (r < 1 || r > MRINV_MAX_D) return fail(r < 1 ? MRINV_E_ARG : MRINV_E_UNSUPPORTED, "bad r=%d", r);
+    CHECK(check_ws(ws, wsb, ws_apply_backward(d, n, r)));
+    const FftPlan p = make_plan(lg_full(n));
+    const int64_t d2 = (int64_t)d * d, dr = (int64_t)d * r;
+    Carve cv(ws);
+    auto *SP = cv.take<cplx<double>>(spec_bytes(p.lgL, d2, true));
+    auto *SM = cv.take<cplx<double>>(spec_bytes(p.lgL, dr, true));
+    auto *SL = cv.take<cplx<double>>(spec_bytes(p.lgL, dr, true));
+    const double invL = 1.0 / (double)((int64_t)1 << p.lgL);
+    HIP_TRY(fwd<double>(h, p, nl_of(dr), SM, src_real(M_bar, true, dr, (int)dr, 0, n, n - 1)));
+    if (psi_bar_accum) {
+        // psi_bar^r += Rev(M_bar) * L^T   (d x r times r x d)
+        HIP_TRY(fwd<double>(h, p, nl_of(dr), SL, src_real(L, true, dr, (int)dr, 0, n)));
+        HIP_TRY(freq_gemm<double>(p, gdesc(d, r, d, 0, 1), SM, SL, SP, h->stream));
+        HIP_TRY(inv<double>(h, p, nl_of(d2), SP,
+                            dst_real(psi_bar_accum, true, d2, (int)d2, 0, n, invL, OP_ADD, n - 1, h->status)));
+    }
+    if (L_bar) {
+        // L_bar^r = psi^T * Rev(M_bar)
+        HIP_TRY(fwd<double>(h, p, nl_of(d2), SP, src_real(psi, true, d2, (int)d2, 0, n)));
+        HIP_TRY(freq_gemm<double>(p, gdesc(d, d, r, 1, 0), SP, SM, SL, h->stream));
+        HIP_TRY(inv<double>(h, p, nl_of(dr), SL, dst_real(L_bar, true, dr, (int)dr, 0, n, invL, OP_STORE, n - 1, h->status)));
+    }
+    return MRINV_OK;
+}
+
+extern "C" mrinv_status_t mrinv_transition_backward(mrinv_handle_t h, const double *psi, const double *q,
+                                                    const double *P_bar, int d, int64_t n, double *psi_bar_accum,
+                                                    double *q_bar_accum, void *ws, size_t wsb) {
+    if (!h || !psi || !q || !P_bar) return fail(MRINV_E_ARG, "NULL handle or pointer");
+    CHECK(check_dn(d, n));
+    CHECK(check_ws(ws, wsb, ws_transition_backward(d, n)));
+    const FftPlan p = make_plan(lg_full(n));
+    const int64_t d2 = (int64_t)d * d;
+    Carve cv(ws);
+    double *hb = cv.take<double>((size_t)n * d * 8);
+    double *hbb = cv.take<double>((size_t)n * d * 8);
+    auto *S1 = cv.take<cplx<double>>(spec_bytes(p.lgL, d2, true));
+    auto *S2 = cv.take<cplx<double>>(spec_bytes(p.lgL, d2, true));
+    auto *SH = cv.take<cplx<double>>(spec_bytes(p.lgL, d, true));
+    const double invL = 1.0 / (double)((int64_t)1 << p.lgL);
+    HIP_TRY(fwd<double>(h, p, nl_of(d2), S1, src_real(P_bar, true, d2, (int)d2, 0, n, n - 1)));
+    if (psi_bar_accum) {
+        HIP_TRY(survival(q, d, n, hb, h->stream));
+        HIP_TRY(fwd<double>(h, p, nl_of(d), SH, src_real(hb, true, d, d, 0, n)));
+        HIP_TRY(freq_diag<double>(p, d, d, S1, SH, S2, h->stream));
+        HIP_TRY(inv<double>(h, p, nl_of(d2), S2,
+                            dst_real(psi_bar_accum, true, d2, (int)d2, 0, n, invL, OP_ADD, n - 1, h->status)));
+    }
+    if (q_bar_accum) {
+        HIP_TRY(fwd<double>(h, p, nl_of(d2), S2, src_real(psi, true, d2, (int)d2, 0, n)));
+        HIP_TRY(freq_coldot<double>(p, d, d, S2, S1, SH, h->stream));
+        HIP_TRY(inv<double>(h, p, nl_of(d), SH, dst_real(hbb, true, d, d, 0, n, invL, OP_STORE, n - 1)));
+        HIP_TRY(survival_backward(hbb, d, n, q_bar_accum, h->stream));
+    }
+    return MRINV_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Residual diagnostics
+// ---------------------------------------------------------------------------
+extern "C" mrinv_status_t mrinv_residual_norms(mrinv_handle_t h, const double *q, const double *X, int d, int64_t n,
+                                               double *out, void *ws, size_t wsb) {
+    if (!h || !q || !X || !out) return fail(MRINV_E_ARG, "NULL handle or pointer");
+    CHECK(check_dn(d, n));
+    const FftPlan p = make_plan(lg_full(n));
+    const int64_t d2 = (int64_t)d * d;
+    const int nl = nl_of(d2);
+    const size_t need = 3 * spec_bytes(p.lgL, d2, true) + 2 * align256((size_t)n * d2 * 8);
+    CHECK(check_ws(ws, wsb, need));
+    Carve cv(ws);
+    const size_t sb = spec_bytes(p.lgL, d2, true);
+    auto *SA = cv.take<cplx<double>>(sb);
+    auto *SX = cv.take<cplx<double>>(sb);
+    auto *ST = cv.take<cplx<double>>(sb);
+    double *RL = cv.take<double>((size_t)n * d2 * 8);
+    double *RR = cv.take<double>((size_t)n * d2 * 8);
+    const double invL = 1.0 / (double)((int64_t)1 << p.lgL);
+    const GemmDesc g = gdesc(d, d, d);
+    HIP_TRY(fwd<double>(h, p, nl, SA, src_real(q, true, d2, (int)d2, 0, n, -1, d)));
+    HIP_TRY(fwd<double>(h, p, nl, SX, src_real(X, true, d2, (int)d2, 0, n)));
+    DstDesc dl = dst_real(RL, true, d2, (int)d2, 0, n, invL, OP_E0MINUS);
+    dl.e0_d = d;
+    HIP_TRY(freq_gemm<double>(p, g, SA, SX, ST, h->stream));
+    HIP_TRY(inv<double>(h, p, nl, ST, dl));
+    DstDesc dr = dl;
+    dr.p = RR;
+    HIP_TRY(freq_gemm<double>(p, g, SX, SA, ST, h->stream));
+    HIP_TRY(inv<double>(h, p, nl, ST, dr));
+    double *acc = h->scratch;
+    HIP_TRY(fill_f64(acc, 3, 0.0, h->stream));
+    HIP_TRY(residual_norms(RL, RR, d, n, acc, h->stream));
+    HIP_TRY(hipMemcpyAsync(out, acc, 3 * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    return MRINV_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Batched inversion
+// ---------------------------------------------------------------------------
+extern "C" size_t mrinv_batched_workspace_size(int count, const int *d, const int64_t *n, mrinv_precision_t prec) {
+    if (count < 1 || !d || !n) return 0;
+    size_t mx = 0;
+    for (int b = 0; b < count; ++b) {
+        const size_t w = mrinv_workspace_size(MRINV_OP_PSI_INVERSE, d[b], n[b], 0, prec);
+        if (!w) return 0;
+        mx = std::max(mx, w);
+    }
+    return mx;
+}
+
+extern "C" mrinv_status_t mrinv_psi_inverse_batched(mrinv_handle_t h, int count, const double *const *q_ptrs,
+                                                    const int *d, const int64_t *n, mrinv_precision_t precision,
+                                                    double *const *psi_ptrs, void *ws, size_t wsb) {
+    if (!h || count < 1 || !q_ptrs || !d || !n || !psi_ptrs) return fail(MRINV_E_ARG, "NULL handle or pointer");
+    for (int b = 0; b < count; ++b) {
+        CHECK(mrinv_psi_inverse(h, q_ptrs[b], d[b], n[b], precision, psi_ptrs[b], ws, wsb));
+    }
+    return MRINV_OK;
+}

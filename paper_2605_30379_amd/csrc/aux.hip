@@ -1,0 +1,341 @@
+// Small kernels around the inversion: the Gauss-Jordan seed A(0)^-1, the
+// survival sequence, contractions to scalar functionals, block extraction and
+// their adjoints, residual reductions.
+#include "common.h"
+#include "kernels.h"
+
+namespace mrinv {
+
+// ---------------------------------------------------------------------------
+// Gauss-Jordan inverse of the constant coefficient (Newton seed B0(0) =
+// A(0)^-1, eq. (newton)).  One workgroup, partial pivoting on max |.|; a pivot
+// at or below d * 2^-53 * max|A(0)| marks A(0) singular (Theorem 2.1: the
+// sequence is invertible iff A(0) is) and the output becomes NaN.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) gj_kernel(const double *A0, int d, int e0_minus, double *out64, float *out32,
+                                                 unsigned int *status) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    double *W = reinterpret_cast<double *>(smem_raw);   // [d][2d]
+    __shared__ double s_amax;
+    __shared__ int s_piv;
+    __shared__ int s_sing;
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const int w = 2 * d;
+    for (int idx = tid; idx < d * w; idx += nt) {
+        const int i = idx / w, j = idx - i * w;
+        double v;
+        if (j < d) {
+            const double a = A0[i * d + j];
+            v = e0_minus ? ((i == j ? 1.0 : 0.0) - a) : a;
+        } else {
+            v = (j - d == i) ? 1.0 : 0.0;
+        }
+        W[idx] = v;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        double m = 0.0;
+        bool finite = true;
+        for (int i = 0; i < d; ++i)
+            for (int j = 0; j < d; ++j) {
+                const double a = fabs(W[i * w + j]);
+                if (!isfinite(a)) finite = false;
+                m = a > m ? a : m;
+            }
+        s_amax = m;
+        s_sing = finite ? 0 : 2;
+    }
+    __syncthreads();
+    const double tol = d * 0x1p-53 * s_amax;
+    for (int c = 0; c < d && s_sing == 0; ++c) {
+        if (tid == 0) {
+            int p = c;
+            double best = fabs(W[c * w + c]);
+            for (int r = c + 1; r < d; ++r) {
+                const double a = fabs(W[r * w + c]);
+                if (a > best) { best = a; p = r; }
+            }
+            s_piv = p;
+            if (!(best > tol)) s_sing = 1;
+        }
+        __syncthreads();
+        if (s_sing) break;
+        const int p = s_piv;
+        if (p != c) {
+            for (int j = tid; j < w; j += nt) {
+                const double t = W[c * w + j];
+                W[c * w + j] = W[p * w + j];
+                W[p * w + j] = t;
+            }
+        }
+        __syncthreads();
+        const double inv = 1.0 / W[c * w + c];
+        __syncthreads();
+        for (int j = tid; j < w; j += nt) W[c * w + j] *= inv;
+        __syncthreads();
+        for (int idx = tid; idx < d * w; idx += nt) {
+            const int r = idx / w, j = idx - r * w;
+            if (r == c || j == c) continue;
+            W[idx] -= W[r * w + c] * W[c * w + j];
+        }
+        __syncthreads();
+        for (int r = tid; r < d; r += nt)
+            if (r != c) W[r * w + c] = 0.0;
+        __syncthreads();
+    }
+    const bool bad = s_sing != 0;
+    if (bad && tid == 0 && status) atomicOr(status, s_sing == 1 ? STATUS_SINGULAR : STATUS_NONFINITE);
+    for (int idx = tid; idx < d * d; idx += nt) {
+        const int i = idx / d, j = idx - i * d;
+        const double v = bad ? __longlong_as_double(0x7ff8000000000000LL) : W[i * w + d + j];
+        if (out64) out64[idx] = v;
+        if (out32) out32[idx] = (float)v;
+    }
+}
+
+hipError_t gj_inverse(const double *A0, int d, int e0_minus, double *out64, float *out32, unsigned int *status,
+                      hipStream_t st) {
+    const size_t lds = (size_t)d * 2 * d * sizeof(double);
+    hipLaunchKernelGGL(gj_kernel, dim3(1), dim3(256), lds, st, A0, d, e0_minus, out64, out32, status);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Inclusive scan over time of w lanes, Y[k][i] <- a + b * sum_{l<=k} Y[l][i]
+// (reverse != 0: sum over l >= k).  One workgroup per lane; each thread scans
+// a contiguous segment, segment totals are scanned in LDS.
+// ---------------------------------------------------------------------------
+constexpr int SCAN_THREADS = 1024;
+
+__global__ void __launch_bounds__(SCAN_THREADS) scan_lanes_kernel(double *Y, int64_t n, int w, int reverse,
+                                                                  double a, double b) {
+    __shared__ double part[SCAN_THREADS];
+    const int i = blockIdx.x;
+    const int t = threadIdx.x;
+    const int64_t seg = (n + SCAN_THREADS - 1) / SCAN_THREADS;
+    const int64_t lo = t * seg, hi = min(n, lo + seg);
+    auto at = [&](int64_t k) -> double & { return Y[(reverse ? (n - 1 - k) : k) * w + i]; };
+    double s = 0.0;
+    for (int64_t k = lo; k < hi; ++k) s += at(k);
+    part[t] = s;
+    __syncthreads();
+    // Hillis-Steele inclusive scan of the segment totals.
+    for (int off = 1; off < SCAN_THREADS; off <<= 1) {
+        const double v = t >= off ? part[t - off] : 0.0;
+        __syncthreads();
+        part[t] += v;
+        __syncthreads();
+    }
+    double run = t > 0 ? part[t - 1] : 0.0;
+    for (int64_t k = lo; k < hi; ++k) {
+        run += at(k);
+        at(k) = a + b * run;
+    }
+}
+
+static hipError_t scan_lanes(double *Y, int64_t n, int w, int reverse, double a, double b, hipStream_t st) {
+    hipLaunchKernelGGL(scan_lanes_kernel, dim3(w), dim3(SCAN_THREADS), 0, st, Y, n, w, reverse, a, b);
+    return hipGetLastError();
+}
+
+// rho[k][i] = sum_j q_ij(k) for k >= 1, rho[0][i] = 0.
+__global__ void rowsum_kernel(const double *q, int d, int64_t n, double *rho) {
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= n * d) return;
+    const int64_t k = gid / d;
+    const int i = (int)(gid - k * d);
+    double s = 0.0;
+    if (k > 0) {
+        const double *row = q + (k * d + i) * d;
+        for (int j = 0; j < d; ++j) s += row[j];
+    }
+    rho[gid] = s;
+}
+
+// Survival sequence Hbar(k)_ii = 1 - sum_j sum_{l=1..k} q_ij(l) (Section 4.1).
+hipError_t survival(const double *q, int d, int64_t n, double *hb, hipStream_t st) {
+    const int64_t total = n * d;
+    hipLaunchKernelGGL(rowsum_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, q, d, n, hb);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return scan_lanes(hb, n, d, 0, 1.0, -1.0, st);
+}
+
+// q_bar(l)[i][j] += -sum_{k>=l} hb_bar(k)[i] for l >= 1.  hbb is scanned in place.
+__global__ void bcast_sub_kernel(const double *s, int d, int64_t n, double *qb) {
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= n * d * d) return;
+    const int64_t k = gid / ((int64_t)d * d);
+    if (k == 0) return;
+    const int i = (int)((gid / d) % d);
+    qb[gid] -= s[k * d + i];
+}
+
+hipError_t survival_backward(const double *hbb, int d, int64_t n, double *qb, hipStream_t st) {
+    hipError_t e = scan_lanes(const_cast<double *>(hbb), n, d, 1, 0.0, 1.0, st);
+    if (e != hipSuccess) return e;
+    const int64_t total = n * d * d;
+    hipLaunchKernelGGL(bcast_sub_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, hbb, d, n, qb);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Contractions out(k) = offset + scale * u^T X(k) v (optionally cumulative).
+// One wavefront per time step.
+// ---------------------------------------------------------------------------
+__global__ void contract_kernel(const double *X, int64_t n, int rows, int cols, const double *u, const double *v,
+                                double *out) {
+    const int lane = threadIdx.x & 63;
+    const int64_t k = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    if (k >= n) return;
+    const int rc = rows * cols;
+    const double *xk = X + k * rc;
+    double s = 0.0;
+    for (int e = lane; e < rc; e += 64) {
+        const int i = e / cols, j = e - i * cols;
+        s += u[i] * xk[e] * v[j];
+    }
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+    if (lane == 0) out[k] = s;
+}
+
+__global__ void affine_kernel(double *y, int64_t n, double a, double b) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n) y[k] = a + b * y[k];
+}
+
+hipError_t contract(const double *X, int64_t n, int rows, int cols, const double *u, const double *v,
+                    int cumulative, double offset, double scale, double *out, hipStream_t st) {
+    const int64_t threads = n * 64;
+    hipLaunchKernelGGL(contract_kernel, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, st, X, n, rows, cols,
+                       u, v, out);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if (cumulative) return scan_lanes(out, n, 1, 0, offset, scale, st);
+    hipLaunchKernelGGL(affine_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, out, n, offset, scale);
+    return hipGetLastError();
+}
+
+// X_bar(l) += scale * w(l) u v^T
+__global__ void outer_accum_kernel(const double *w, int64_t n, int rows, int cols, const double *u,
+                                   const double *v, double scale, double *Xb) {
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t rc = (int64_t)rows * cols;
+    if (gid >= n * rc) return;
+    const int64_t k = gid / rc;
+    const int e = (int)(gid - k * rc);
+    const int i = e / cols, j = e - i * cols;
+    Xb[gid] += scale * w[k] * u[i] * v[j];
+}
+
+hipError_t contract_backward(const double *ob, int64_t n, int rows, int cols, const double *u, const double *v,
+                             int cumulative, double scale, double *Xb, hipStream_t st) {
+    // The cumulative form needs the reverse cumulative sum of out_bar; it is
+    // formed in place in the caller's out_bar buffer copy (see api).
+    if (cumulative) {
+        hipError_t e = scan_lanes(const_cast<double *>(ob), n, 1, 1, 0.0, 1.0, st);
+        if (e != hipSuccess) return e;
+    }
+    const int64_t total = n * rows * cols;
+    hipLaunchKernelGGL(outer_accum_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, ob, n, rows, cols,
+                       u, v, scale, Xb);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Block extraction and its adjoint.
+// ---------------------------------------------------------------------------
+__global__ void gather_kernel(const double *X, int64_t n, int rows, int cols, const int *ri, int nr, const int *ci,
+                              int nc, double *Y) {
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t rc = (int64_t)nr * nc;
+    if (gid >= n * rc) return;
+    const int64_t k = gid / rc;
+    const int e = (int)(gid - k * rc);
+    const int a = e / nc, b = e - a * nc;
+    Y[gid] = X[(k * rows + ri[a]) * cols + ci[b]];
+}
+
+hipError_t gather_block(const double *X, int64_t n, int rows, int cols, const int *ri, int nr, const int *ci,
+                        int nc, double *Y, hipStream_t st) {
+    const int64_t total = n * nr * nc;
+    hipLaunchKernelGGL(gather_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, X, n, rows, cols, ri,
+                       nr, ci, nc, Y);
+    return hipGetLastError();
+}
+
+__global__ void scatter_add_kernel(const double *Yb, int64_t n, int rows, int cols, const int *ri, int nr,
+                                   const int *ci, int nc, double *Xb) {
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t rc = (int64_t)nr * nc;
+    if (gid >= n * rc) return;
+    const int64_t k = gid / rc;
+    const int e = (int)(gid - k * rc);
+    const int a = e / nc, b = e - a * nc;
+    Xb[(k * rows + ri[a]) * cols + ci[b]] += Yb[gid];
+}
+
+hipError_t scatter_block_add(const double *Yb, int64_t n, int rows, int cols, const int *ri, int nr,
+                             const int *ci, int nc, double *Xb, hipStream_t st) {
+    const int64_t total = n * nr * nc;
+    hipLaunchKernelGGL(scatter_add_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, Yb, n, rows, cols,
+                       ri, nr, ci, nc, Xb);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Fills and residual reductions.
+// ---------------------------------------------------------------------------
+__global__ void fill_f64_kernel(double *p, int64_t count, double v) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) p[i] = v;
+}
+__global__ void fill_u32_kernel(unsigned int *p, int64_t count, unsigned int v) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) p[i] = v;
+}
+hipError_t fill_f64(double *p, int64_t count, double v, hipStream_t st) {
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(fill_f64_kernel, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st, p, count, v);
+    return hipGetLastError();
+}
+hipError_t fill_u32(unsigned int *p, int64_t count, unsigned int v, hipStream_t st) {
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(fill_u32_kernel, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st, p, count, v);
+    return hipGetLastError();
+}
+
+// acc[0] += sum_k ||R_L(k)||_F, acc[1] += sum_k ||R_R(k)||_F, acc[2] = max |R_L|
+// (max taken through the bit pattern of non-negative doubles).  One wavefront
+// per time step.
+__global__ void resid_kernel(const double *RL, const double *RR, int d, int64_t n, double *acc) {
+    const int lane = threadIdx.x & 63;
+    const int64_t k = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    if (k >= n) return;
+    const int d2 = d * d;
+    double sl = 0.0, sr = 0.0, mx = 0.0;
+    for (int e = lane; e < d2; e += 64) {
+        const double a = RL[k * d2 + e], b = RR[k * d2 + e];
+        sl += a * a;
+        sr += b * b;
+        mx = fmax(mx, fabs(a));
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        sl += __shfl_xor(sl, off, 64);
+        sr += __shfl_xor(sr, off, 64);
+        mx = fmax(mx, __shfl_xor(mx, off, 64));
+    }
+    if (lane == 0) {
+        atomicAdd(&acc[0], sqrt(sl));
+        atomicAdd(&acc[1], sqrt(sr));
+        atomicMax((unsigned long long *)&acc[2], (unsigned long long)__double_as_longlong(mx));
+    }
+}
+
+hipError_t residual_norms(const double *RL, const double *RR, int d, int64_t n, double *acc, hipStream_t st) {
+    const int64_t threads = n * 64;
+    hipLaunchKernelGGL(resid_kernel, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, st, RL, RR, d, n, acc);
+    return hipGetLastError();
+}
+
+}  // namespace mrinv

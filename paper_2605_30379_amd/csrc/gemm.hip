@@ -1,0 +1,272 @@
+// Frequency-domain matrix products (Section 2.1, eq. (fft-convolution):
+// the product of two sequences is the inverse DFT of the frequency-wise matrix
+// products, in the original operand order).
+//
+// Inputs are packed spectra (complex lane c of a real sequence carries real
+// entries 2c and 2c+1) in the digit-reversed row order of the FFT plan.  For
+// a real sequence x with spectrum X, X(L-k) = conj(X(k)), so the two real
+// entries of lane c are separated as
+//     X_2c(k)   = (z(k) + conj(z(L-k))) / 2
+//     X_2c+1(k) = (z(k) - conj(z(L-k))) / (2i).
+// Each kernel therefore visits frequencies k = 0..L/2 once, reads rows k and
+// L-k, forms the product at k, and writes the packed result at both rows
+// (the value at L-k is the conjugate by the same symmetry).
+#include "common.h"
+#include "kernels.h"
+
+namespace mrinv {
+
+// Row holding frequency k in the digit-reversed order of the plan.
+__device__ __forceinline__ int64_t freq_row(const FftPlan &p, int64_t k) {
+    int64_t pos = 0;
+    int rem = p.lgL;
+#pragma unroll
+    for (int j = 0; j < MAX_PASSES; ++j) {
+        if (j < p.npass) {
+            rem -= p.lgP[j];
+            pos += (k & ((1LL << p.lgP[j]) - 1)) << rem;
+            k >>= p.lgP[j];
+        }
+    }
+    return pos;
+}
+
+template <typename T>
+__device__ __forceinline__ cplx<T> unpack(const cplx<T> *Z, int nl, int64_t r1, int64_t r2, int e) {
+    const cplx<T> z1 = Z[r1 * nl + (e >> 1)];
+    const cplx<T> z2 = Z[r2 * nl + (e >> 1)];
+    if ((e & 1) == 0) return mk<T>((z1.x + z2.x) * (T)0.5, (z1.y - z2.y) * (T)0.5);
+    return mk<T>((z1.y + z2.y) * (T)0.5, (z2.x - z1.x) * (T)0.5);
+}
+
+// Packed value for row k and row L-k from the two real-sequence values.
+template <typename T>
+__device__ __forceinline__ void pack_store(cplx<T> *Z, int nl, int64_t r1, int64_t r2, int c, cplx<T> ce,
+                                           cplx<T> co) {
+    Z[r1 * nl + c] = mk<T>(ce.x - co.y, ce.y + co.x);
+    if (r2 != r1) Z[r2 * nl + c] = mk<T>(ce.x + co.y, co.x - ce.y);
+}
+
+constexpr int GEMM_THREADS = 256;
+
+template <typename T, int TM, int TN>
+__global__ void __launch_bounds__(GEMM_THREADS)
+freq_gemm_kernel(const cplx<T> *__restrict__ ZA, const cplx<T> *__restrict__ ZB, cplx<T> *__restrict__ ZC,
+                 FftPlan plan, GemmDesc g, int NF, int KC, int tiles_j, int tiles) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    cplx<T> *As = reinterpret_cast<cplx<T> *>(smem_raw);          // [NF][ra][KC+1]
+    cplx<T> *Bs = As + (size_t)NF * g.ra * (KC + 1);               // [NF][KC][cb+1]
+    __shared__ int64_t rows1[GEMM_THREADS], rows2[GEMM_THREADS];
+    const int64_t L = (int64_t)1 << plan.lgL;
+    const int64_t F = L / 2 + 1;
+    const int64_t k0 = (int64_t)blockIdx.x * NF;
+    const int tid = threadIdx.x;
+    if (tid < NF) {
+        const int64_t k = k0 + tid;
+        rows1[tid] = k < F ? freq_row(plan, k) : 0;
+        rows2[tid] = k < F ? freq_row(plan, (L - k) & (L - 1)) : 0;
+    }
+    __syncthreads();
+    const int ra = g.ra, m = g.m, cb = g.cb;
+    const int f = tid / tiles, tile = tid - f * tiles;
+    const int i0 = (tile / tiles_j) * TM, j0 = (tile % tiles_j) * TN;
+    const bool active = f < NF && k0 + f < F;
+    cplx<T> acc[TM][TN];
+#pragma unroll
+    for (int a = 0; a < TM; ++a)
+#pragma unroll
+        for (int b = 0; b < TN; ++b) acc[a][b] = mk<T>(0, 0);
+
+    for (int kc = 0; kc < m; kc += KC) {
+        const int kw = min(KC, m - kc);
+        for (int idx = tid; idx < NF * ra * kw; idx += GEMM_THREADS) {
+            const int ff = idx / (ra * kw), rem = idx - ff * ra * kw;
+            const int i = rem / kw, t = rem - i * kw;
+            cplx<T> v = mk<T>(0, 0);
+            if (k0 + ff < F) {
+                const int e = g.transA ? (kc + t) * ra + i : i * m + kc + t;
+                v = unpack<T>(ZA, g.nlA, rows1[ff], rows2[ff], e);
+            }
+            As[((size_t)ff * ra + i) * (KC + 1) + t] = v;
+        }
+        for (int idx = tid; idx < NF * kw * cb; idx += GEMM_THREADS) {
+            const int ff = idx / (kw * cb), rem = idx - ff * kw * cb;
+            const int t = rem / cb, j = rem - t * cb;
+            cplx<T> v = mk<T>(0, 0);
+            if (k0 + ff < F) {
+                const int e = g.transB ? j * m + kc + t : (kc + t) * cb + j;
+                v = unpack<T>(ZB, g.nlB, rows1[ff], rows2[ff], e);
+            }
+            Bs[((size_t)ff * KC + t) * (cb + 1) + j] = v;
+        }
+        __syncthreads();
+        if (active) {
+            const cplx<T> *Af = As + (size_t)f * ra * (KC + 1);
+            const cplx<T> *Bf = Bs + (size_t)f * KC * (cb + 1);
+            for (int t = 0; t < kw; ++t) {
+                cplx<T> av[TM], bv[TN];
+#pragma unroll
+                for (int a = 0; a < TM; ++a) av[a] = (i0 + a < ra) ? Af[(i0 + a) * (KC + 1) + t] : mk<T>(0, 0);
+#pragma unroll
+                for (int b = 0; b < TN; ++b) bv[b] = (j0 + b < cb) ? Bf[t * (cb + 1) + j0 + b] : mk<T>(0, 0);
+#pragma unroll
+                for (int a = 0; a < TM; ++a)
+#pragma unroll
+                    for (int b = 0; b < TN; ++b) {
+                        acc[a][b].x += av[a].x * bv[b].x - av[a].y * bv[b].y;
+                        acc[a][b].y += av[a].x * bv[b].y + av[a].y * bv[b].x;
+                    }
+            }
+        }
+        __syncthreads();
+    }
+
+    if ((cb & 1) == 0 && (TN & 1) == 0) {
+        // Every thread owns whole lane pairs (j0 even, cb even).
+        if (active) {
+#pragma unroll
+            for (int a = 0; a < TM; ++a) {
+                const int i = i0 + a;
+                if (i >= ra) continue;
+#pragma unroll
+                for (int b = 0; b < TN; b += 2) {
+                    const int j = j0 + b;
+                    if (j >= cb) continue;
+                    pack_store<T>(ZC, g.nlC, rows1[f], rows2[f], (i * cb + j) >> 1, acc[a][b], acc[a][b + 1]);
+                }
+            }
+        }
+    } else {
+        // Stage the result in LDS, then write lane pairs.
+        cplx<T> *Cs = As;   // [NF][ra*cb + 1]
+        const int ld = ra * cb + 1;
+        if (active) {
+#pragma unroll
+            for (int a = 0; a < TM; ++a)
+#pragma unroll
+                for (int b = 0; b < TN; ++b)
+                    if (i0 + a < ra && j0 + b < cb) Cs[(size_t)f * ld + (i0 + a) * cb + j0 + b] = acc[a][b];
+        }
+        __syncthreads();
+        const int nlC = g.nlC;
+        for (int idx = tid; idx < NF * nlC; idx += GEMM_THREADS) {
+            const int ff = idx / nlC, c = idx - ff * nlC;
+            if (k0 + ff >= F) continue;
+            const int e = 2 * c;
+            const cplx<T> ce = Cs[(size_t)ff * ld + e];
+            const cplx<T> co = (e + 1 < ra * cb) ? Cs[(size_t)ff * ld + e + 1] : mk<T>(0, 0);
+            pack_store<T>(ZC, nlC, rows1[ff], rows2[ff], c, ce, co);
+        }
+    }
+}
+
+template <typename T, int TM, int TN>
+static hipError_t launch_gemm(const FftPlan &plan, const GemmDesc &g, const cplx<T> *ZA, const cplx<T> *ZB,
+                              cplx<T> *ZC, hipStream_t st) {
+    const int tiles_i = (g.ra + TM - 1) / TM, tiles_j = (g.cb + TN - 1) / TN;
+    const int tiles = tiles_i * tiles_j;
+    int NF = GEMM_THREADS / tiles;
+    if (NF < 1) return hipErrorInvalidValue;
+    const int KC = g.m < 16 ? g.m : 16;
+    const bool staged = (g.cb & 1) || (TN & 1);   // output goes through LDS (see kernel epilogue)
+    auto bytes = [&](int nf) {
+        size_t ab = ((size_t)nf * g.ra * (KC + 1) + (size_t)nf * KC * (g.cb + 1)) * sizeof(cplx<T>);
+        size_t cs = staged ? (size_t)nf * (g.ra * g.cb + 1) * sizeof(cplx<T>) : 0;
+        return ab > cs ? ab : cs;
+    };
+    while (NF > 1 && bytes(NF) > 64 * 1024) --NF;
+    const int64_t F = ((int64_t)1 << plan.lgL) / 2 + 1;
+    const int64_t blocks = (F + NF - 1) / NF;
+    hipLaunchKernelGGL((freq_gemm_kernel<T, TM, TN>), dim3((unsigned)blocks), dim3(GEMM_THREADS), bytes(NF), st, ZA,
+                       ZB, ZC, plan, g, NF, KC, tiles_j, tiles);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t freq_gemm(const FftPlan &plan, const GemmDesc &g, const cplx<T> *ZA, const cplx<T> *ZB, cplx<T> *ZC,
+                     hipStream_t st) {
+    const int dmax = g.ra > g.cb ? g.ra : g.cb;
+    if (dmax <= 8) return launch_gemm<T, 1, 1>(plan, g, ZA, ZB, ZC, st);
+    if (dmax <= 24) return launch_gemm<T, 2, 2>(plan, g, ZA, ZB, ZC, st);
+    return launch_gemm<T, 4, 4>(plan, g, ZA, ZB, ZC, st);
+}
+
+// C = A * diag(h)
+template <typename T>
+__global__ void freq_diag_kernel(const cplx<T> *ZA, const cplx<T> *__restrict__ ZH,
+                                 cplx<T> *ZC, FftPlan plan, int ra, int cb, int nl, int nlh) {
+    const int64_t L = (int64_t)1 << plan.lgL;
+    const int64_t F = L / 2 + 1;
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t k = gid / nl;
+    const int c = (int)(gid - k * nl);
+    if (k >= F) return;
+    const int64_t r1 = freq_row(plan, k), r2 = freq_row(plan, (L - k) & (L - 1));
+    const int e = 2 * c;
+    cplx<T> ce = cmul<T>(unpack<T>(ZA, nl, r1, r2, e), unpack<T>(ZH, nlh, r1, r2, e % cb));
+    cplx<T> co = mk<T>(0, 0);
+    if (e + 1 < ra * cb) co = cmul<T>(unpack<T>(ZA, nl, r1, r2, e + 1), unpack<T>(ZH, nlh, r1, r2, (e + 1) % cb));
+    pack_store<T>(ZC, nl, r1, r2, c, ce, co);
+}
+
+template <typename T>
+hipError_t freq_diag(const FftPlan &plan, int ra, int cb, const cplx<T> *ZA, const cplx<T> *ZH, cplx<T> *ZC,
+                     hipStream_t st) {
+    const int nl = (ra * cb + 1) / 2, nlh = (cb + 1) / 2;
+    const int64_t F = ((int64_t)1 << plan.lgL) / 2 + 1;
+    const int64_t total = F * nl;
+    const int threads = 256;
+    hipLaunchKernelGGL(freq_diag_kernel<T>, dim3((unsigned)((total + threads - 1) / threads)), dim3(threads), 0, st,
+                       ZA, ZH, ZC, plan, ra, cb, nl, nlh);
+    return hipGetLastError();
+}
+
+// h_j = sum_i A_ij B_ij
+template <typename T>
+__global__ void freq_coldot_kernel(const cplx<T> *__restrict__ ZA, const cplx<T> *__restrict__ ZB,
+                                   cplx<T> *__restrict__ ZH, FftPlan plan, int ra, int cb, int nl, int nlh) {
+    const int64_t L = (int64_t)1 << plan.lgL;
+    const int64_t F = L / 2 + 1;
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t k = gid / nlh;
+    const int c = (int)(gid - k * nlh);
+    if (k >= F) return;
+    const int64_t r1 = freq_row(plan, k), r2 = freq_row(plan, (L - k) & (L - 1));
+    cplx<T> h[2] = {mk<T>(0, 0), mk<T>(0, 0)};
+    for (int u = 0; u < 2; ++u) {
+        const int j = 2 * c + u;
+        if (j >= cb) break;
+        for (int i = 0; i < ra; ++i) {
+            const int e = i * cb + j;
+            h[u] = cadd<T>(h[u], cmul<T>(unpack<T>(ZA, nl, r1, r2, e), unpack<T>(ZB, nl, r1, r2, e)));
+        }
+    }
+    pack_store<T>(ZH, nlh, r1, r2, c, h[0], h[1]);
+}
+
+template <typename T>
+hipError_t freq_coldot(const FftPlan &plan, int ra, int cb, const cplx<T> *ZA, const cplx<T> *ZB, cplx<T> *ZH,
+                       hipStream_t st) {
+    const int nl = (ra * cb + 1) / 2, nlh = (cb + 1) / 2;
+    const int64_t F = ((int64_t)1 << plan.lgL) / 2 + 1;
+    const int64_t total = F * nlh;
+    const int threads = 256;
+    hipLaunchKernelGGL(freq_coldot_kernel<T>, dim3((unsigned)((total + threads - 1) / threads)), dim3(threads), 0,
+                       st, ZA, ZB, ZH, plan, ra, cb, nl, nlh);
+    return hipGetLastError();
+}
+
+template hipError_t freq_gemm<double>(const FftPlan &, const GemmDesc &, const cplx<double> *, const cplx<double> *,
+                                      cplx<double> *, hipStream_t);
+template hipError_t freq_gemm<float>(const FftPlan &, const GemmDesc &, const cplx<float> *, const cplx<float> *,
+                                     cplx<float> *, hipStream_t);
+template hipError_t freq_diag<double>(const FftPlan &, int, int, const cplx<double> *, const cplx<double> *,
+                                      cplx<double> *, hipStream_t);
+template hipError_t freq_diag<float>(const FftPlan &, int, int, const cplx<float> *, const cplx<float> *,
+                                     cplx<float> *, hipStream_t);
+template hipError_t freq_coldot<double>(const FftPlan &, int, int, const cplx<double> *, const cplx<double> *,
+                                        cplx<double> *, hipStream_t);
+template hipError_t freq_coldot<float>(const FftPlan &, int, int, const cplx<float> *, const cplx<float> *,
+                                       cplx<float> *, hipStream_t);
+
+}  // namespace mrinv

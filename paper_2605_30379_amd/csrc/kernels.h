@@ -1,0 +1,117 @@
+// Kernel launch interface of the mrinv library (internal).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "common.h"
+
+namespace mrinv {
+
+constexpr unsigned int STATUS_SINGULAR = 1u;
+constexpr unsigned int STATUS_NONFINITE = 2u;
+
+constexpr int MAX_PASSES = 4;
+constexpr int LGP_MAX = 9;   // largest radix of one FFT pass (512 rows in LDS)
+
+// Pass plan of one transform length.
+struct FftPlan {
+    int lgL;
+    int npass;
+    int lgP[MAX_PASSES];   // pass radices, first pass = outermost (largest stride)
+};
+
+// Geometry of one pass (device side).
+struct PassGeom {
+    int64_t L;
+    int64_t S;        // row stride inside a column
+    int lgB;          // block size 2^lgB
+    int nl;           // complex lanes per row
+    int nchunks;      // lane chunks per column
+};
+
+enum SrcKind { SRC_Z = 0, SRC_REAL64 = 1, SRC_REAL32 = 2 };
+enum DstKind { DST_Z = 0, DST_REAL64 = 1, DST_REAL32 = 2 };
+enum DstOp { OP_STORE = 0, OP_NEG = 1, OP_E0MINUS = 2, OP_ADD = 3, OP_XPLUS = 4 };
+
+// Real source of the first forward pass: rows t in [lo, hi) hold
+// p[row * ld + e] for e < nreal with row = t (or rev - t when rev >= 0);
+// every other row is zero (implicit zero padding).  e0_d > 0 turns the value
+// into e0 - x for a d x d matrix sequence.
+struct SrcDesc {
+    int kind;
+    const void *p;
+    int64_t ld;
+    int nreal;
+    int64_t lo, hi;
+    int64_t rev;
+    int e0_d;
+};
+
+// Real destination of the last inverse pass (rows t in [lo, hi) written,
+// row = t or rev - t), value = op(scale * v).  In the fused inverse/forward
+// mode only lo, hi, scale and op (OP_STORE / OP_NEG) are used, as a mask.
+struct DstDesc {
+    int kind;
+    void *p;
+    int64_t ld;
+    int nreal;
+    int64_t lo, hi;
+    int64_t rev;
+    int op;
+    int e0_d;
+    const void *aux;       // OP_XPLUS: float32 array with the same layout, added to the result
+    double scale;
+    unsigned int *status;  // optional: set STATUS_NONFINITE on non-finite output
+};
+
+inline SrcDesc src_z() { SrcDesc s{}; s.kind = SRC_Z; s.rev = -1; return s; }
+inline DstDesc dst_z() { DstDesc d{}; d.kind = DST_Z; d.rev = -1; d.scale = 1.0; return d; }
+
+int fft_lanes_per_block(bool dbl, int nl);
+
+// mode 0 forward, 1 inverse, 2 inverse + mask + forward (same pass).
+template <typename T>
+hipError_t fft_pass(int mode, const FftPlan &plan, int pass, int nl, cplx<T> *z, const SrcDesc &src,
+                    const DstDesc &dst, const Twiddles<T> &tw, hipStream_t st);
+
+// Frequency-domain products.  Spectra are packed (two real lanes per complex
+// lane) in the digit-reversed order of `plan`.
+struct GemmDesc {
+    int ra, m, cb;          // C[ra x cb] = A[ra x m] * B[m x cb]
+    int transA, transB;     // operand stored transposed (A stored m x ra, B stored cb x m)
+    int nlA, nlB, nlC;      // complex lanes of the stored sequences
+};
+template <typename T>
+hipError_t freq_gemm(const FftPlan &plan, const GemmDesc &g, const cplx<T> *ZA, const cplx<T> *ZB, cplx<T> *ZC,
+                     hipStream_t st);
+// C = A * diag(h): A ra x cb, h has cb lanes.
+template <typename T>
+hipError_t freq_diag(const FftPlan &plan, int ra, int cb, const cplx<T> *ZA, const cplx<T> *ZH, cplx<T> *ZC,
+                     hipStream_t st);
+// h_j = sum_i A_ij B_ij (diagonal of A^T B), A and B ra x cb.
+template <typename T>
+hipError_t freq_coldot(const FftPlan &plan, int ra, int cb, const cplx<T> *ZA, const cplx<T> *ZB, cplx<T> *ZH,
+                       hipStream_t st);
+
+// Gauss-Jordan inverse of A(0) (or of I - q(0) when e0_minus) written as row 0
+// of out (float64 and/or float32 copies, either may be null).
+hipError_t gj_inverse(const double *A0, int d, int e0_minus, double *out64, float *out32, unsigned int *status,
+                      hipStream_t st);
+
+hipError_t survival(const double *q, int d, int64_t n, double *hb, hipStream_t st);
+hipError_t contract(const double *X, int64_t n, int rows, int cols, const double *u, const double *v,
+                    int cumulative, double offset, double scale, double *out, hipStream_t st);
+hipError_t contract_backward(const double *ob, int64_t n, int rows, int cols, const double *u, const double *v,
+                             int cumulative, double scale, double *Xb, hipStream_t st);
+hipError_t gather_block(const double *X, int64_t n, int rows, int cols, const int *ri, int nr, const int *ci,
+                        int nc, double *Y, hipStream_t st);
+hipError_t scatter_block_add(const double *Yb, int64_t n, int rows, int cols, const int *ri, int nr,
+                             const int *ci, int nc, double *Xb, hipStream_t st);
+// q_bar(l)[i][j] += -sum_{k>=l} hb_bar(k)[i] for l >= 1.
+hipError_t survival_backward(const double *hbb, int d, int64_t n, double *qb, hipStream_t st);
+hipError_t fill_f64(double *p, int64_t count, double v, hipStream_t st);
+hipError_t fill_u32(unsigned int *p, int64_t count, unsigned int v, hipStream_t st);
+hipError_t residual_norms(const double *R_L, const double *R_R, int d, int64_t n, double *acc, hipStream_t st);
+
+}  // namespace mrinv

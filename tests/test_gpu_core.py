@@ -1,0 +1,299 @@
+"""GPU parity of the HIP path against the CPU FP64 oracle, element by element.
+
+Every call goes through the C-ABI library (libmrinv.so) via the thin Python
+binding.  Sizes span single-pass and multi-pass transform plans, ragged
+(non-power-of-two) horizons, odd matrix dimensions (odd lane counts) and the
+degenerate cases n = 1, d = 1.  Tolerance for FP64: max-abs error <= 1e-12
+on the stochastic kernels; the mixed form: <= 1e-10.
+"""
+import numpy as np
+import pytest
+import torch
+
+import smk_inputs as si
+
+pytestmark = pytest.mark.gpu
+
+FP64_TOL = 1e-12
+MIXED_TOL = 1e-10
+
+
+def fp64_tol(n: int) -> float:
+    """FP64 bound for horizon n.  The rounding of an FFT product grows like
+    sqrt(L) log2(L) times the coefficient size (Proposition 2.1), and a
+    renewal sequence keeps a non-decaying plateau, so the last Newton
+    products carry it in full.  Up to n = 65536 the 1e-12 target holds;
+    beyond it the bound is scaled by sqrt(L / 2^16) * log2(L) / 16 with a
+    factor 2 of headroom (numpy's FFT-Newton reaches 2.6e-12 at n = 300000)."""
+    import math
+    lg = max(1, math.ceil(math.log2(n)))
+    if lg <= 16:
+        return FP64_TOL
+    return 2 * FP64_TOL * math.sqrt(2.0 ** (lg - 16)) * lg / 16
+
+
+@pytest.fixture(scope="module")
+def mr():
+    import paper_2605_30379_amd as m
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    m.lib()
+    return m
+
+
+def _gpu(x):
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float64).cuda()
+
+
+def _np(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def _maxerr(a, b):
+    return float(np.max(np.abs(np.asarray(a) - np.asarray(b))))
+
+
+@pytest.mark.parametrize("d,n", [(1, 1), (1, 2), (2, 1), (4, 2), (3, 3), (4, 256), (5, 37), (2, 100),
+                                 (7, 129), (16, 64), (3, 513), (6, 1000)])
+def test_psi_fp64_matches_oracle(mr, orc, d, n):
+    print(f"[psi fp64] d={d} n={n}", flush=True)
+    q = si.weibull_kernel(d, n, 100 + d + n).q
+    ref = orc.psi(q.numpy())
+    got = _np(mr.psi_inverse(_gpu(q), check=True))
+    assert _maxerr(got, ref) <= FP64_TOL
+
+
+def test_psi_c1_config_and_transition(mr, orc):
+    """Plain FP64 inversion, d = 4, n = 256, Weibull kernel, seed 0; psi and P."""
+    k = si.weibull_kernel(4, 256, si.CONFIG_SEEDS["c1"])
+    q = k.q.numpy()
+    ref = orc.psi(q)
+    psi = mr.psi_inverse(_gpu(q), check=True)
+    assert _maxerr(_np(psi), ref) <= FP64_TOL
+    P = _np(mr.transition(psi, _gpu(q)))
+    Pref = orc.transition(ref, q)
+    assert _maxerr(P, Pref) <= FP64_TOL
+    assert np.max(np.abs(P.sum(axis=2) - 1.0)) <= 1e-13
+
+
+@pytest.mark.parametrize("d,n", [(3, 5000), (2, 20000)])
+def test_psi_two_pass_plans(mr, orc, d, n):
+    """Horizons whose last Newton steps need two-pass transforms."""
+    print(f"[psi two-pass] d={d} n={n}", flush=True)
+    q = si.lognormal_kernel(d, n, 7 + d).q
+    ref = orc.psi(q.numpy())
+    got = _np(mr.psi_inverse(_gpu(q), check=True))
+    assert _maxerr(got, ref) <= FP64_TOL
+
+
+def test_psi_three_pass_geometric_closed_form(mr, orc):
+    """n = 300000 (L = 2^19, three passes): Markov closed form at sampled k."""
+    d, n = 3, 300000
+    k = si.geometric_kernel(d, n, 31)
+    got = mr.psi_inverse(k.q.cuda(), check=True)
+    ks = np.array([0, 1, 2, 3, 100, 4097, 65536, 131071, 262144, n - 1])
+    ref = orc.geometric_psi(k.params["M"], k.params["a"], ks)
+    assert _maxerr(_np(got[torch.as_tensor(ks).cuda()]), ref) <= fp64_tol(n)
+
+
+def test_prefix_exactness_and_causality(mr):
+    """Proposition 2.3 on the GPU: the first n' coefficients do not depend on
+    q(k >= n') and equal the horizon-n' inverse (within rounding)."""
+    k = si.weibull_kernel(5, 3000, 41)
+    q = k.q.cuda()
+    full = mr.psi_inverse(q)
+    q2 = q.clone()
+    q2[1000:] *= 0.25
+    part = mr.psi_inverse(q2)
+    pre = mr.psi_inverse(q[:1000].contiguous())
+    torch.cuda.synchronize()
+    assert float((full[:1000] - part[:1000]).abs().max()) <= 1e-13
+    assert float((full[:1000] - pre).abs().max()) <= 1e-13
+
+
+def test_transpose_symmetry(mr):
+    k = si.weibull_kernel(6, 777, 42)
+    q = k.q.cuda()
+    a = mr.psi_inverse(q)
+    b = mr.psi_inverse(q.transpose(1, 2).contiguous())
+    torch.cuda.synchronize()
+    assert float((a - b.transpose(1, 2)).abs().max()) <= 1e-13
+
+
+def test_series_inverse_general_A0(mr, orc):
+    """A(0) != I exercises the Gauss-Jordan seed with pivoting."""
+    rng = np.random.default_rng(3)
+    d, n = 5, 300
+    A = rng.standard_normal((n, d, d)) / (d * (1 + np.arange(n))[:, None, None] ** 2)
+    A[0] = rng.standard_normal((d, d)) + 0.5 * np.eye(d)
+    ref = orc.series_inverse_left(A)
+    got = _np(mr.series_inverse(_gpu(A), check=True))
+    assert _maxerr(got, ref) <= 1e-11 * max(1.0, np.max(np.abs(ref)))
+
+
+@pytest.mark.parametrize("d,n,r", [(4, 100, 3), (5, 257, 1), (3, 64, 6)])
+def test_apply_matches_oracle(mr, orc, d, n, r):
+    rng = np.random.default_rng(d * n + r)
+    q = si.weibull_kernel(d, n, 5).q.numpy()
+    psi = orc.psi(q)
+    L = rng.uniform(0, 1, (n, d, r))
+    ref = orc.conv(psi, L)
+    got = _np(mr.markov_renewal_apply(_gpu(psi), _gpu(L)))
+    assert _maxerr(got, ref) <= 1e-11 * max(1.0, np.max(np.abs(ref)))
+
+
+@pytest.mark.parametrize("d,n", [(3, 50), (8, 600), (5, 1)])
+def test_transition_matches_oracle(mr, orc, d, n):
+    q = si.weibull_kernel(d, n, 9).q.numpy()
+    psi = orc.psi(q)
+    ref = orc.transition(psi, q)
+    got = _np(mr.transition(_gpu(psi), _gpu(q)))
+    assert _maxerr(got, ref) <= FP64_TOL
+    hb = _np(mr.survival(_gpu(q)))
+    assert _maxerr(hb, orc.hbar(q)) <= 1e-14
+
+
+def test_paper_first_entrance_example(mr, orc):
+    """Section 5.1 first restoration (Poisson 8, 5, 10, 7; D = {1}, C = {2, 3},
+    alpha_C = (1, 0), N = 128): closed-form mass and F(N-1) = 1."""
+    from scipy.stats import poisson
+    n = 128
+    q = si.paper_three_state_poisson(n).q
+    g, F = mr.first_entrance(q.cuda(), [1, 0, 0], [0.0, 1.0, 0.0])
+    t = np.arange(n)
+    ref = 0.2 * np.where(t >= 1, poisson.pmf(t - 1, 5.0), 0) + 0.8 * np.where(t >= 2, poisson.pmf(t - 2, 17.0), 0)
+    assert _maxerr(_np(g), ref) <= 1e-15 * 10
+    assert abs(_np(F)[-1] - 1.0) <= 1e-14
+
+
+def test_reliability_and_availability_match_oracle(mr, orc):
+    d, n = 6, 400
+    q = si.weibull_kernel(d, n, 12).q.numpy()
+    up = [1, 1, 1, 0, 0, 0]
+    alpha = np.eye(d)[0]
+    R = _np(mr.reliability(_gpu(q), up, alpha))
+    assert _maxerr(R, orc.reliability(q, np.array(up), alpha)) <= FP64_TOL
+    psi = mr.psi_inverse(_gpu(q))
+    P = mr.transition(psi, _gpu(q))
+    A = _np(mr.availability(P, up, alpha))
+    assert _maxerr(A, orc.availability(q, np.array(up), alpha)) <= FP64_TOL
+
+
+def test_geometric_functionals_closed_form(mr, orc):
+    d, n = 8, 2048
+    k = si.geometric_kernel(d, n, 13)
+    M = k.params["M"]
+    q = k.q.cuda()
+    up = [1] * 4 + [0] * 4
+    alpha = np.eye(d)[0]
+    psi = mr.psi_inverse(q)
+    P = mr.transition(psi, q)
+    ks = np.array([0, 1, 5, 100, 1000, n - 1])
+    assert _maxerr(_np(P)[ks], orc.geometric_P(M, ks)) <= FP64_TOL
+    A = _np(mr.availability(P, up, alpha))
+    Aref = np.array([alpha @ np.linalg.matrix_power(M, int(t)) @ np.array(up, float) for t in ks])
+    assert _maxerr(A[ks], Aref) <= FP64_TOL
+    R = _np(mr.reliability(q, up, alpha))
+    Rref = np.array([alpha[:4] @ np.linalg.matrix_power(M[:4, :4], int(t)) @ np.ones(4) for t in ks])
+    assert _maxerr(R[ks], Rref) <= FP64_TOL
+
+
+@pytest.mark.parametrize("d,n", [(4, 256), (8, 4096), (3, 1000), (16, 2048)])
+def test_mixed_precision_matches_oracle(mr, orc, d, n):
+    print(f"[psi mixed] d={d} n={n}", flush=True)
+    q = si.lognormal_kernel(d, n, 200 + d).q
+    ref = orc.psi(q.numpy())
+    got = _np(mr.psi_inverse(_gpu(q), precision="mixed", check=True))
+    assert _maxerr(got, ref) <= MIXED_TOL
+
+
+def test_psi_backward_matches_oracle_adjoint(mr, orc):
+    rng = np.random.default_rng(4)
+    d, n = 4, 200
+    q = si.weibull_kernel(d, n, 14).q.numpy()
+    psi = orc.psi(q)
+    pb = rng.standard_normal((n, d, d))
+    ref = orc.adjoint(psi, pb)
+    got = _np(mr.psi_inverse_backward(_gpu(psi), _gpu(pb)))
+    assert _maxerr(got, ref) <= 1e-11 * max(1.0, np.max(np.abs(ref)))
+
+
+def test_apply_backward_matches_direct(mr, orc):
+    """psi_bar(l) = sum_k M_bar(k) L(k-l)^T and L_bar(j) = sum_l psi(l)^T M_bar(l+j),
+    evaluated with the oracle's direct convolution on reversed sequences."""
+    rng = np.random.default_rng(5)
+    d, n, r = 3, 150, 2
+    psi = rng.standard_normal((n, d, d))
+    L = rng.standard_normal((n, d, r))
+    Mb = rng.standard_normal((n, d, r))
+    pb, lb = mr.markov_renewal_apply_backward(_gpu(psi), _gpu(L), _gpu(Mb))
+    rev = lambda x: x[::-1].copy()
+    pref = rev(orc.conv(rev(Mb), np.ascontiguousarray(L.transpose(0, 2, 1))))
+    lref = rev(orc.conv(np.ascontiguousarray(psi.transpose(0, 2, 1)), rev(Mb)))
+    assert _maxerr(_np(pb), pref) <= 1e-10
+    assert _maxerr(_np(lb), lref) <= 1e-10
+
+
+def test_autograd_transition_and_functionals_fd(mr):
+    """Gradient of sum_k A(k) through PsiInverse, Transition and Contract
+    against a central finite difference along a random direction."""
+    d, n = 4, 128
+    k = si.weibull_kernel(d, n, 15)
+    q0 = k.q.cuda()
+    up = torch.tensor([1.0, 1.0, 0.0, 0.0], dtype=torch.float64)
+    alpha = torch.tensor([1.0, 0.0, 0.0, 0.0], dtype=torch.float64)
+
+    def loss(q):
+        psi = mr.PsiInverse.apply(q)
+        P = mr.Transition.apply(psi, q)
+        return mr.Contract.apply(P, alpha, up).sum()
+
+    q = q0.clone().requires_grad_(True)
+    loss(q).backward()
+    g = q.grad.detach()
+    torch.manual_seed(0)
+    dq = torch.randn_like(q0)
+    dq[0] = 0
+    h = 1e-6
+    with torch.no_grad():
+        fd = (loss(q0 + h * dq) - loss(q0 - h * dq)) / (2 * h)
+    an = float((g * dq).sum())
+    assert abs(an - float(fd)) <= 1e-6 * max(1.0, abs(an))
+
+
+def test_singular_a0_is_reported(mr):
+    d, n = 3, 16
+    A = torch.zeros((n, d, d), dtype=torch.float64)
+    A[0] = torch.diag(torch.tensor([1.0, 0.0, 2.0]))
+    out = mr.series_inverse(A.cuda())
+    with pytest.raises(mr.MrinvError) as e:
+        mr.sync_status()
+    assert e.value.status == 2
+    assert torch.isnan(out[0]).all()
+
+
+def test_nonfinite_is_reported(mr):
+    q = si.weibull_kernel(3, 64, 16).q
+    q[10, 1, 2] = float("nan")
+    mr.psi_inverse(q.cuda())
+    with pytest.raises(mr.MrinvError) as e:
+        mr.sync_status()
+    assert e.value.status == 3
+
+
+def test_argument_errors(mr):
+    with pytest.raises(mr.MrinvError):
+        mr.psi_inverse(torch.zeros((4, 65, 65), dtype=torch.float64).cuda())
+    with pytest.raises(mr.MrinvError):
+        mr.psi_inverse(torch.zeros((4, 3, 3), dtype=torch.float32).cuda())
+    with pytest.raises(mr.MrinvError):
+        mr.psi_inverse(torch.zeros((4, 3, 3), dtype=torch.float64))
+    mr.sync_status()
+
+
+def test_deterministic_reruns(mr):
+    q = si.weibull_kernel(7, 3333, 17).q.cuda()
+    a = mr.psi_inverse(q)
+    b = mr.psi_inverse(q)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
