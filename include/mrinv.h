@@ -226,6 +226,24 @@ size_t mrinv_batched_workspace_size(int count, const int *d, const int64_t *n,
 mrinv_status_t mrinv_residual_norms(mrinv_handle_t h, const double *q, const double *X, int d,
                                     int64_t n, double *out, void *ws, size_t ws_bytes);
 
+/* Per-kernel timing, a profiling aid that is off by default.  While enabled,
+ * every kernel launch of the library is bracketed by HIP events on the
+ * handle's stream and tagged with the algorithmic bytes (one read of each
+ * input element the launch needs, one write of each output element) and
+ * flops of that launch.  mrinv_set_timing also clears earlier records. */
+typedef struct {
+    char name[96];      /* kernel name with its template arguments */
+    int64_t launches;
+    double total_ms;    /* sum of event-measured launch durations */
+    double bytes;       /* sum of algorithmic bytes */
+    double flops;       /* sum of algorithmic flops (0 for pure data movement) */
+} mrinv_kernel_stat_t;
+
+mrinv_status_t mrinv_set_timing(mrinv_handle_t h, int enabled);
+/* Synchronises the stream; fills up to max_out entries, returns the number of
+ * distinct kernels recorded (or -1 on error). */
+int mrinv_kernel_stats(mrinv_handle_t h, mrinv_kernel_stat_t *out, int max_out);
+
 #ifdef __cplusplus
 }
 #endif

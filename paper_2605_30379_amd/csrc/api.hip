@@ -45,12 +45,13 @@ constexpr size_t SCRATCH_BYTES = (size_t)MRINV_MAX_N * sizeof(double) + 4096 * s
 struct mrinv_handle_s {
     hipStream_t stream = nullptr;
     int device = 0;
-    cplx<double> *tw64 = nullptr;   // hi[TW_HI_SIZE] then lo[TW_LO_SIZE]
-    cplx<float> *tw32 = nullptr;
+    cplx<double> *tw64 = nullptr;   // hi[TW_HI_SIZE] then lo[TW_LO_SIZE] (used by both precisions)
     unsigned int *status = nullptr;
     double *scratch = nullptr;      // small per-handle scratch (index lists, vectors, 1-lane scans)
+    void *timer = nullptr;          // launch timing records (mrinv_set_timing)
+    bool timing = false;
     Twiddles<double> t64() const { return {tw64, tw64 + TW_HI_SIZE}; }
-    Twiddles<float> t32() const { return {tw32, tw32 + TW_HI_SIZE}; }
+    Twiddles<float> t32() const { return {tw64, tw64 + TW_HI_SIZE}; }
 };
 
 static void host_twiddles(std::vector<double2> &hi, std::vector<double2> &lo) {
@@ -76,12 +77,8 @@ extern "C" mrinv_status_t mrinv_create(mrinv_handle_t *handle, void *stream) {
     HIP_TRY(hipGetDevice(&h->device));
     std::vector<double2> hi, lo;
     host_twiddles(hi, lo);
-    std::vector<float2> hi32(hi.size()), lo32(lo.size());
-    for (size_t i = 0; i < hi.size(); ++i) hi32[i] = make_float2((float)hi[i].x, (float)hi[i].y);
-    for (size_t i = 0; i < lo.size(); ++i) lo32[i] = make_float2((float)lo[i].x, (float)lo[i].y);
     const size_t n64 = (TW_HI_SIZE + TW_LO_SIZE) * sizeof(double2);
-    const size_t n32 = (TW_HI_SIZE + TW_LO_SIZE) * sizeof(float2);
-    if (hipMalloc((void **)&h->tw64, n64) != hipSuccess || hipMalloc((void **)&h->tw32, n32) != hipSuccess ||
+    if (hipMalloc((void **)&h->tw64, n64) != hipSuccess ||
         hipMalloc((void **)&h->status, 256) != hipSuccess ||
         hipMalloc((void **)&h->scratch, SCRATCH_BYTES) != hipSuccess) {
         mrinv_destroy(h);
@@ -89,8 +86,6 @@ extern "C" mrinv_status_t mrinv_create(mrinv_handle_t *handle, void *stream) {
     }
     HIP_TRY(hipMemcpy(h->tw64, hi.data(), TW_HI_SIZE * sizeof(double2), hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(h->tw64 + TW_HI_SIZE, lo.data(), TW_LO_SIZE * sizeof(double2), hipMemcpyHostToDevice));
-    HIP_TRY(hipMemcpy(h->tw32, hi32.data(), TW_HI_SIZE * sizeof(float2), hipMemcpyHostToDevice));
-    HIP_TRY(hipMemcpy(h->tw32 + TW_HI_SIZE, lo32.data(), TW_LO_SIZE * sizeof(float2), hipMemcpyHostToDevice));
     HIP_TRY(hipMemset(h->status, 0, 256));
     HIP_TRY(hipDeviceSynchronize());
     *handle = h;
@@ -103,9 +98,9 @@ extern "C" mrinv_status_t mrinv_destroy(mrinv_handle_t h) {
     if (h->stream) (void)hipStreamSynchronize(h->stream);
     else (void)hipDeviceSynchronize();
     if (h->tw64) (void)hipFree(h->tw64);
-    if (h->tw32) (void)hipFree(h->tw32);
     if (h->status) (void)hipFree(h->status);
     if (h->scratch) (void)hipFree(h->scratch);
+    if (h->timer) timer_destroy(h->timer);
     delete h;
     return MRINV_OK;
 }
@@ -142,6 +137,30 @@ extern "C" const char *mrinv_status_string(mrinv_status_t s) {
 }
 
 extern "C" const char *mrinv_last_error(void) { return g_last_error.c_str(); }
+
+// Activates launch timing for the duration of one entry point.
+struct TimerScope {
+    explicit TimerScope(mrinv_handle_t h) { timer_activate(h && h->timing ? h->timer : nullptr, h ? h->stream : nullptr); }
+    ~TimerScope() { timer_activate(nullptr, nullptr); }
+};
+
+extern "C" mrinv_status_t mrinv_set_timing(mrinv_handle_t h, int enabled) {
+    if (!h) return fail(MRINV_E_ARG, "handle is NULL");
+    if (h->stream) (void)hipStreamSynchronize(h->stream);
+    if (!h->timer) h->timer = timer_create();
+    timer_reset(h->timer);
+    h->timing = enabled != 0;
+    return MRINV_OK;
+}
+
+namespace mrinv {
+int timer_stats(void *t, hipStream_t st, mrinv_kernel_stat_t *out, int max_out);
+}
+
+extern "C" int mrinv_kernel_stats(mrinv_handle_t h, mrinv_kernel_stat_t *out, int max_out) {
+    if (!h || !h->timer) return -1;
+    return timer_stats(h->timer, h->stream, out, max_out);
+}
 
 // ---------------------------------------------------------------------------
 // Plans and workspace
@@ -380,6 +399,13 @@ static mrinv_status_t check_ws(void *ws, size_t have, size_t need) {
         if (_s != MRINV_OK) return _s;       \
     } while (0)
 
+// Residual sweeps of the mixed form.  Each one forms R = e0 - A*X in float64
+// over the whole horizon and applies X <- X + X*R, which squares the residual
+// (Appendix "Algorithmic details": e0 - A*B_{r+1} = (e0 - A*B_r)^2).  With the
+// float32 Newton error of long renewal horizons (about 1e-6), one sweep leaves
+// about 1e-10 and a second one reaches float64 rounding.
+constexpr int MIXED_SWEEPS = 2;
+
 static mrinv_status_t inverse_impl(mrinv_handle_t h, const double *src, int e0, int d, int64_t n,
                                    mrinv_precision_t prec, double *out, void *ws, size_t wsb) {
     if (!h || !src || !out) return fail(MRINV_E_ARG, "NULL handle or pointer");
@@ -411,43 +437,50 @@ static mrinv_status_t inverse_impl(mrinv_handle_t h, const double *src, int e0, 
     const FftPlan p2 = make_plan(lg_full(n));
     const double invL = 1.0 / (double)((int64_t)1 << p2.lgL);
     const GemmDesc g = gdesc(d, d, d);
-    {
-        // R = e0 - A*X on [0, n) in float64 (full product, no wrap-around at L >= 2n-1).
-        const size_t sb = spec_bytes(p2.lgL, d2, true);
-        auto *SA = (cplx<double> *)spec;
-        auto *SB = (cplx<double> *)(spec + sb);
-        auto *ST = (cplx<double> *)(spec + 2 * sb);
-        HIP_TRY(fwd<double>(h, p2, nl, SA, src_real(src, true, d2, d2, 0, n, -1, e0 ? d : 0)));
-        HIP_TRY(fwd<double>(h, p2, nl, SB, src_real(X, false, d2, d2, 0, n)));
-        HIP_TRY(freq_gemm<double>(p2, g, SA, SB, ST, h->stream));
-        DstDesc dr = dst_real(R, false, d2, d2, 0, n, invL, OP_E0MINUS);
-        dr.e0_d = d;
-        HIP_TRY(inv<double>(h, p2, nl, ST, dr));
-    }
-    {
-        // psi = X + X*R, the correction product in float32.
-        const size_t sb = spec_bytes(p2.lgL, d2, false);
-        auto *SA = (cplx<float> *)spec;
-        auto *SB = (cplx<float> *)(spec + sb);
-        auto *ST = (cplx<float> *)(spec + 2 * sb);
-        HIP_TRY(fwd<float>(h, p2, nl, SA, src_real(X, false, d2, d2, 0, n)));
-        HIP_TRY(fwd<float>(h, p2, nl, SB, src_real(R, false, d2, d2, 0, n)));
-        HIP_TRY(freq_gemm<float>(p2, g, SA, SB, ST, h->stream));
-        DstDesc dx = dst_real(out, true, d2, d2, 0, n, invL, OP_XPLUS, -1, h->status);
-        dx.aux = X;
-        HIP_TRY(inv<float>(h, p2, nl, ST, dx));
+    for (int sweep = 0; sweep < MIXED_SWEEPS; ++sweep) {
+        const bool last = sweep == MIXED_SWEEPS - 1;
+        {
+            // R = e0 - A*X on [0, n) in float64 (full product, no wrap-around at L >= 2n-1).
+            const size_t sb = spec_bytes(p2.lgL, d2, true);
+            auto *SA = (cplx<double> *)spec;
+            auto *SB = (cplx<double> *)(spec + sb);
+            auto *ST = (cplx<double> *)(spec + 2 * sb);
+            HIP_TRY(fwd<double>(h, p2, nl, SA, src_real(src, true, d2, d2, 0, n, -1, e0 ? d : 0)));
+            HIP_TRY(fwd<double>(h, p2, nl, SB, src_real(X, false, d2, d2, 0, n)));
+            HIP_TRY(freq_gemm<double>(p2, g, SA, SB, ST, h->stream));
+            DstDesc dr = dst_real(R, false, d2, d2, 0, n, invL, OP_E0MINUS);
+            dr.e0_d = d;
+            HIP_TRY(inv<double>(h, p2, nl, ST, dr));
+        }
+        {
+            // X <- X + X*R, the correction product in float32; the last sweep
+            // writes the float64 result, earlier ones update X in place.
+            const size_t sb = spec_bytes(p2.lgL, d2, false);
+            auto *SA = (cplx<float> *)spec;
+            auto *SB = (cplx<float> *)(spec + sb);
+            auto *ST = (cplx<float> *)(spec + 2 * sb);
+            HIP_TRY(fwd<float>(h, p2, nl, SA, src_real(X, false, d2, d2, 0, n)));
+            HIP_TRY(fwd<float>(h, p2, nl, SB, src_real(R, false, d2, d2, 0, n)));
+            HIP_TRY(freq_gemm<float>(p2, g, SA, SB, ST, h->stream));
+            DstDesc dx = last ? dst_real(out, true, d2, d2, 0, n, invL, OP_XPLUS, -1, h->status)
+                              : dst_real(X, false, d2, d2, 0, n, invL, OP_XPLUS);
+            dx.aux = X;
+            HIP_TRY(inv<float>(h, p2, nl, ST, dx));
+        }
     }
     return MRINV_OK;
 }
 
 extern "C" mrinv_status_t mrinv_psi_inverse(mrinv_handle_t h, const double *q, int d, int64_t n,
                                             mrinv_precision_t precision, double *psi, void *ws, size_t ws_bytes) {
+    TimerScope _ts(h);
     return inverse_impl(h, q, 1, d, n, precision, psi, ws, ws_bytes);
 }
 
 extern "C" mrinv_status_t mrinv_series_inverse(mrinv_handle_t h, const double *A, int d, int64_t n,
                                                mrinv_precision_t precision, double *Ainv, void *ws,
                                                size_t ws_bytes) {
+    TimerScope _ts(h);
     return inverse_impl(h, A, 0, d, n, precision, Ainv, ws, ws_bytes);
 }
 
@@ -456,6 +489,7 @@ extern "C" mrinv_status_t mrinv_series_inverse(mrinv_handle_t h, const double *A
 // ---------------------------------------------------------------------------
 extern "C" mrinv_status_t mrinv_markov_renewal_apply(mrinv_handle_t h, const double *psi, int d, int64_t n,
                                                      const double *L, int r, double *M, void *ws, size_t wsb) {
+    TimerScope _ts(h);
     if (!h || !psi || !L || !M) return fail(MRINV_E_ARG, "NULL handle or pointer");
     CHECK(check_dn(d, n));
     if (r < 1 || r > MRINV_MAX_D) return fail(r < 1 ? MRINV_E_ARG : MRINV_E_UNSUPPORTED, "bad r=%d", r);
@@ -475,6 +509,7 @@ extern "C" mrinv_status_t mrinv_markov_renewal_apply(mrinv_handle_t h, const dou
 }
 
 extern "C" mrinv_status_t mrinv_survival(mrinv_handle_t h, const double *q, int d, int64_t n, double *hb) {
+    TimerScope _ts(h);
     if (!h || !q || !hb) return fail(MRINV_E_ARG, "NULL handle or pointer");
     CHECK(check_dn(d, n));
     HIP_TRY(survival(q, d, n, hb, h->stream));
@@ -483,6 +518,7 @@ extern "C" mrinv_status_t mrinv_survival(mrinv_handle_t h, const double *q, int 
 
 extern "C" mrinv_status_t mrinv_transition(mrinv_handle_t h, const double *psi, const double *q, int d, int64_t n,
                                            double *P, void *ws, size_t wsb) {
+    TimerScope _ts(h);
     if (!h || !psi || !q || !P) return fail(MRINV_E_ARG, "NULL handle or pointer");
     CHECK(check_dn(d, n));
     CHECK(check_ws(ws, wsb, ws_transition(d, n)));
@@ -504,6 +540,7 @@ extern "C" mrinv_status_t mrinv_transition(mrinv_handle_t h, const double *psi, 
 extern "C" mrinv_status_t mrinv_contract(mrinv_handle_t h, const double *X, int64_t n, int rows, int cols,
                                          const double *u, const double *v, int cumulative, double offset,
                                          double scale, double *out) {
+    TimerScope _ts(h);
     if (!h || !X || !u || !v || !out) return fail(MRINV_E_ARG, "NULL handle or pointer");
     if (n < 1 || rows < 1 || cols < 1 || n > MRINV_MAX_N) return fail(MRINV_E_ARG, "bad sizes");
     HIP_TRY(contract(X, n, rows, cols, u, v, cumulative, offset, scale, out, h->stream));
@@ -513,6 +550,7 @@ extern "C" mrinv_status_t mrinv_contract(mrinv_handle_t h, const double *X, int6
 extern "C" mrinv_status_t mrinv_contract_backward(mrinv_handle_t h, const double *out_bar, int64_t n, int rows,
                                                   int cols, const double *u, const double *v, int cumulative,
                                                   double scale, double *X_bar_accum) {
+    TimerScope _ts(h);
     if (!h || !out_bar || !u || !v || !X_bar_accum) return fail(MRINV_E_ARG, "NULL handle or pointer");
     if (n < 1 || rows < 1 || cols < 1 || n > MRINV_MAX_N) return fail(MRINV_E_ARG, "bad sizes");
     const double *w = out_bar;
@@ -526,6 +564,7 @@ extern "C" mrinv_status_t mrinv_contract_backward(mrinv_handle_t h, const double
 
 extern "C" mrinv_status_t mrinv_gather_block(mrinv_handle_t h, const double *X, int64_t n, int rows, int cols,
                                              const int *row_idx, int nr, const int *col_idx, int nc, double *Y) {
+    TimerScope _ts(h);
     if (!h || !X || !row_idx || !col_idx || !Y) return fail(MRINV_E_ARG, "NULL handle or pointer");
     if (n < 1 || nr < 1 || nc < 1 || rows < 1 || cols < 1) return fail(MRINV_E_ARG, "bad sizes");
     HIP_TRY(gather_block(X, n, rows, cols, row_idx, nr, col_idx, nc, Y, h->stream));
@@ -535,6 +574,7 @@ extern "C" mrinv_status_t mrinv_gather_block(mrinv_handle_t h, const double *X, 
 extern "C" mrinv_status_t mrinv_scatter_block_add(mrinv_handle_t h, const double *Y_bar, int64_t n, int rows,
                                                   int cols, const int *row_idx, int nr, const int *col_idx, int nc,
                                                   double *X_bar_accum) {
+    TimerScope _ts(h);
     if (!h || !Y_bar || !row_idx || !col_idx || !X_bar_accum) return fail(MRINV_E_ARG, "NULL handle or pointer");
     if (n < 1 || nr < 1 || nc < 1 || rows < 1 || cols < 1) return fail(MRINV_E_ARG, "bad sizes");
     HIP_TRY(scatter_block_add(Y_bar, n, rows, cols, row_idx, nr, col_idx, nc, X_bar_accum, h->stream));
@@ -614,12 +654,14 @@ static mrinv_status_t first_entrance_impl(mrinv_handle_t h, const double *q, int
 extern "C" mrinv_status_t mrinv_first_entrance(mrinv_handle_t h, const double *q, int d, int64_t n,
                                                const int *in_D, const double *alpha, mrinv_precision_t precision,
                                                double *g, double *F, void *ws, size_t wsb) {
+    TimerScope _ts(h);
     return first_entrance_impl(h, q, d, n, in_D, alpha, precision, g, F, 0.0, 1.0, ws, wsb);
 }
 
 extern "C" mrinv_status_t mrinv_reliability(mrinv_handle_t h, const double *q, int d, int64_t n, const int *up,
                                             const double *alpha, mrinv_precision_t precision, double *R, void *ws,
                                             size_t wsb) {
+    TimerScope _ts(h);
     if (!up) return fail(MRINV_E_ARG, "NULL up mask");
     if (d < 1 || d > MRINV_MAX_D) return check_dn(d, n);
     std::vector<int> down(d);
@@ -629,6 +671,7 @@ extern "C" mrinv_status_t mrinv_reliability(mrinv_handle_t h, const double *q, i
 
 extern "C" mrinv_status_t mrinv_availability(mrinv_handle_t h, const double *P, int d, int64_t n, const int *up,
                                              const double *alpha, double *A) {
+    TimerScope _ts(h);
     if (!h || !P || !up || !alpha || !A) return fail(MRINV_E_ARG, "NULL handle or pointer");
     CHECK(check_dn(d, n));
     std::vector<double> al(alpha, alpha + d), ind(d);
@@ -646,6 +689,7 @@ extern "C" mrinv_status_t mrinv_availability(mrinv_handle_t h, const double *P, 
 // ---------------------------------------------------------------------------
 extern "C" mrinv_status_t mrinv_psi_inverse_backward(mrinv_handle_t h, const double *psi, const double *psi_bar,
                                                      int d, int64_t n, double *q_bar, void *ws, size_t wsb) {
+    TimerScope _ts(h);
     if (!h || !psi || !psi_bar || !q_bar) return fail(MRINV_E_ARG, "NULL handle or pointer");
     CHECK(check_dn(d, n));
     CHECK(check_ws(ws, wsb, ws_psi_backward(d, n)));
@@ -673,6 +717,7 @@ extern "C" mrinv_status_t mrinv_markov_renewal_apply_backward(mrinv_handle_t h, 
                                                               const double *M_bar, int d, int64_t n, int r,
                                                               double *psi_bar_accum, double *L_bar, void *ws,
                                                               size_t wsb) {
+    TimerScope _ts(h);
     if (!h || !psi || !L || !M_bar) return fail(MRINV_E_ARG, "NULL handle or pointer");
     CHECK(check_dn(d, n));
     if (r < 1 || r > MRINV_MAX_D) return fail(r < 1 ? MRINV_E_ARG : MRINV_E_UNSUPPORTED, "bad r=%d", r);
@@ -704,6 +749,7 @@ extern "C" mrinv_status_t mrinv_markov_renewal_apply_backward(mrinv_handle_t h, 
 extern "C" mrinv_status_t mrinv_transition_backward(mrinv_handle_t h, const double *psi, const double *q,
                                                     const double *P_bar, int d, int64_t n, double *psi_bar_accum,
                                                     double *q_bar_accum, void *ws, size_t wsb) {
+    TimerScope _ts(h);
     if (!h || !psi || !q || !P_bar) return fail(MRINV_E_ARG, "NULL handle or pointer");
     CHECK(check_dn(d, n));
     CHECK(check_ws(ws, wsb, ws_transition_backward(d, n)));
@@ -738,6 +784,7 @@ extern "C" mrinv_status_t mrinv_transition_backward(mrinv_handle_t h, const doub
 // ---------------------------------------------------------------------------
 extern "C" mrinv_status_t mrinv_residual_norms(mrinv_handle_t h, const double *q, const double *X, int d, int64_t n,
                                                double *out, void *ws, size_t wsb) {
+    TimerScope _ts(h);
     if (!h || !q || !X || !out) return fail(MRINV_E_ARG, "NULL handle or pointer");
     CHECK(check_dn(d, n));
     const FftPlan p = make_plan(lg_full(n));
@@ -789,6 +836,7 @@ extern "C" size_t mrinv_batched_workspace_size(int count, const int *d, const in
 extern "C" mrinv_status_t mrinv_psi_inverse_batched(mrinv_handle_t h, int count, const double *const *q_ptrs,
                                                     const int *d, const int64_t *n, mrinv_precision_t precision,
                                                     double *const *psi_ptrs, void *ws, size_t wsb) {
+    TimerScope _ts(h);
     if (!h || count < 1 || !q_ptrs || !d || !n || !psi_ptrs) return fail(MRINV_E_ARG, "NULL handle or pointer");
     for (int b = 0; b < count; ++b) {
         CHECK(mrinv_psi_inverse(h, q_ptrs[b], d[b], n[b], precision, psi_ptrs[b], ws, wsb));

@@ -96,7 +96,9 @@ __global__ void __launch_bounds__(256) gj_kernel(const double *A0, int d, int e0
 hipError_t gj_inverse(const double *A0, int d, int e0_minus, double *out64, float *out32, unsigned int *status,
                       hipStream_t st) {
     const size_t lds = (size_t)d * 2 * d * sizeof(double);
+    launch_begin("gj_kernel", (double)d * d * 8.0 * 2, 2.0 * d * d * d);
     hipLaunchKernelGGL(gj_kernel, dim3(1), dim3(256), lds, st, A0, d, e0_minus, out64, out32, status);
+    launch_end();
     return hipGetLastError();
 }
 
@@ -134,7 +136,9 @@ __global__ void __launch_bounds__(SCAN_THREADS) scan_lanes_kernel(double *Y, int
 }
 
 static hipError_t scan_lanes(double *Y, int64_t n, int w, int reverse, double a, double b, hipStream_t st) {
+    launch_begin("scan_lanes_kernel", 2.0 * n * w * 8.0, 0.0);
     hipLaunchKernelGGL(scan_lanes_kernel, dim3(w), dim3(SCAN_THREADS), 0, st, Y, n, w, reverse, a, b);
+    launch_end();
     return hipGetLastError();
 }
 
@@ -155,7 +159,9 @@ __global__ void rowsum_kernel(const double *q, int d, int64_t n, double *rho) {
 // Survival sequence Hbar(k)_ii = 1 - sum_j sum_{l=1..k} q_ij(l) (Section 4.1).
 hipError_t survival(const double *q, int d, int64_t n, double *hb, hipStream_t st) {
     const int64_t total = n * d;
+    launch_begin("rowsum_kernel", (double)n * d * (d + 1) * 8.0, 0.0);
     hipLaunchKernelGGL(rowsum_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, q, d, n, hb);
+    launch_end();
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     return scan_lanes(hb, n, d, 0, 1.0, -1.0, st);

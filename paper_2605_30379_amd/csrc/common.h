@@ -46,17 +46,19 @@ constexpr int TW_LO_BITS = 11;
 constexpr int TW_LO_SIZE = 1 << TW_LO_BITS;
 constexpr int TW_HI_SIZE = 1 << (TW_LG - TW_LO_BITS);
 
+// The tables are float64 for both precisions: a float32 twiddle is the
+// float64 product rounded once, so it is within half an ulp of the exact value.
 template <typename T> struct Twiddles {
-    const cplx<T> *hi;
-    const cplx<T> *lo;
+    const double2 *hi;
+    const double2 *lo;
 };
 
 // exp(-2 pi i * num / den) with den a power of two dividing TW_LMAX, num in [0, den).
 template <typename T, bool INV>
 __device__ __forceinline__ cplx<T> twiddle(const Twiddles<T> &tw, uint32_t num, int lg_den) {
     uint32_t a = num << (TW_LG - lg_den);
-    cplx<T> w = cmul<T>(tw.hi[a >> TW_LO_BITS], tw.lo[a & (TW_LO_SIZE - 1)]);
-    return INV ? cconj<T>(w) : w;
+    const double2 w = cmul<double>(tw.hi[a >> TW_LO_BITS], tw.lo[a & (TW_LO_SIZE - 1)]);
+    return mk<T>((T)w.x, INV ? -(T)w.y : (T)w.y);
 }
 
 // ---------------------------------------------------------------------------

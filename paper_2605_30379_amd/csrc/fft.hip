@@ -22,6 +22,8 @@
 // up to three register-radix stages (radix <= 16); the first stage reads global
 // memory directly, the last stage writes global memory directly, and LDS holds
 // the data between stages.
+#include <stdio.h>
+
 #include "common.h"
 #include "kernels.h"
 
@@ -226,6 +228,29 @@ fft_pass_kernel(cplx<T> *z, PassGeom g, SrcDesc src, DstDesc dst, Twiddles<T> tw
 // ---------------------------------------------------------------------------
 // Host-side launch: dispatch on (T, lgP, C, mode).
 // ---------------------------------------------------------------------------
+static double window_rows(int64_t L, int64_t lo, int64_t hi) {
+    const int64_t a = lo > 0 ? lo : 0, b = hi < L ? hi : L;
+    return b > a ? (double)(b - a) : 0.0;
+}
+
+// Algorithmic bytes of one pass: each input element the pass needs read once,
+// each output element written once.
+template <typename T>
+static double pass_bytes(int mode, const PassGeom &g, const SrcDesc &src, const DstDesc &dst) {
+    const double zc = (double)g.L * g.nl * sizeof(cplx<T>);
+    double rd = zc, wr = zc;
+    if (mode == 0 && src.kind != SRC_Z)
+        rd = window_rows(g.L, src.lo, src.hi) * src.nreal * (src.kind == SRC_REAL64 ? 8.0 : 4.0);
+    if (mode == 1 && dst.kind != DST_Z) {
+        const double rows = window_rows(g.L, dst.lo, dst.hi);
+        const double w = dst.kind == DST_REAL64 ? 8.0 : 4.0;
+        wr = rows * dst.nreal * w;
+        if (dst.op == OP_ADD) rd += rows * dst.nreal * w;
+        if (dst.op == OP_XPLUS) rd += rows * dst.nreal * 4.0;
+    }
+    return rd + wr;
+}
+
 template <typename T, int LGP, int C, int MODE>
 static hipError_t launch_pass_t(cplx<T> *z, const PassGeom &g, const SrcDesc &src, const DstDesc &dst,
                                 const Twiddles<T> &tw, hipStream_t st) {
@@ -240,7 +265,11 @@ static hipError_t launch_pass_t(cplx<T> *z, const PassGeom &g, const SrcDesc &sr
     }
     const int64_t cols = g.L >> LGP;
     const int64_t blocks = cols * g.nchunks;
+    char name[96];
+    snprintf(name, sizeof name, "fft_pass_kernel<%s, %d, %d, %d>", sizeof(T) == 8 ? "double" : "float", LGP, C, MODE);
+    launch_begin(name, pass_bytes<T>(MODE, g, src, dst), 0.0);
     hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(threads), lds, st, z, g, src, dst, tw);
+    launch_end();
     return hipGetLastError();
 }
 

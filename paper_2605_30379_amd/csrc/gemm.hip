@@ -11,6 +11,8 @@
 // Each kernel therefore visits frequencies k = 0..L/2 once, reads rows k and
 // L-k, forms the product at k, and writes the packed result at both rows
 // (the value at L-k is the conjugate by the same symmetry).
+#include <stdio.h>
+
 #include "common.h"
 #include "kernels.h"
 
@@ -177,8 +179,13 @@ static hipError_t launch_gemm(const FftPlan &plan, const GemmDesc &g, const cplx
     while (NF > 1 && bytes(NF) > 64 * 1024) --NF;
     const int64_t F = ((int64_t)1 << plan.lgL) / 2 + 1;
     const int64_t blocks = (F + NF - 1) / NF;
+    char name[96];
+    snprintf(name, sizeof name, "freq_gemm_kernel<%s, %d, %d>", sizeof(T) == 8 ? "double" : "float", TM, TN);
+    const double Lr = (double)((int64_t)1 << plan.lgL);
+    launch_begin(name, Lr * (g.nlA + g.nlB + g.nlC) * sizeof(cplx<T>), (double)F * 8.0 * g.ra * g.m * g.cb);
     hipLaunchKernelGGL((freq_gemm_kernel<T, TM, TN>), dim3((unsigned)blocks), dim3(GEMM_THREADS), bytes(NF), st, ZA,
                        ZB, ZC, plan, g, NF, KC, tiles_j, tiles);
+    launch_end();
     return hipGetLastError();
 }
 
@@ -216,8 +223,11 @@ hipError_t freq_diag(const FftPlan &plan, int ra, int cb, const cplx<T> *ZA, con
     const int64_t F = ((int64_t)1 << plan.lgL) / 2 + 1;
     const int64_t total = F * nl;
     const int threads = 256;
+    launch_begin(sizeof(T) == 8 ? "freq_diag_kernel<double>" : "freq_diag_kernel<float>",
+                 (double)((int64_t)1 << plan.lgL) * (2 * nl + nlh) * sizeof(cplx<T>), (double)F * ra * cb * 6.0);
     hipLaunchKernelGGL(freq_diag_kernel<T>, dim3((unsigned)((total + threads - 1) / threads)), dim3(threads), 0, st,
                        ZA, ZH, ZC, plan, ra, cb, nl, nlh);
+    launch_end();
     return hipGetLastError();
 }
 

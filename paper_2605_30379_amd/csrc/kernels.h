@@ -6,7 +6,18 @@
 
 #include "common.h"
 
+
+
 namespace mrinv {
+
+// Optional launch timing (see mrinv_set_timing).  launch_begin/launch_end
+// bracket one kernel launch; they do nothing unless a timer is active.
+void timer_activate(void *timer, hipStream_t st);
+void launch_begin(const char *name, double bytes, double flops);
+void launch_end();
+void *timer_create();
+void timer_destroy(void *t);
+void timer_reset(void *t);
 
 constexpr unsigned int STATUS_SINGULAR = 1u;
 constexpr unsigned int STATUS_NONFINITE = 2u;
