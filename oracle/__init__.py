@@ -24,7 +24,7 @@ _lib = None
 
 def build(verbose: bool = False) -> str:
     """Compile the oracle with gcc (-O2, OpenMP, IEEE semantics kept)."""
-    cmd = ["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-ffp-contract=off",
+    cmd = ["gcc", "-O3", "-fopenmp", "-fPIC", "-shared", "-ffp-contract=off",
            "-o", _LIB_PATH + ".tmp", _SRC, "-lm"]
     if verbose:
         print(" ".join(cmd))

@@ -27,6 +27,11 @@
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+int orc_num_threads(void);
 
 #define IDX3(k, i, j, r, c) ((((size_t)(k)) * (size_t)(r) + (size_t)(i)) * (size_t)(c) + (size_t)(j))
 
@@ -86,27 +91,53 @@ int orc_inverse_left_cols(const double *A, int d, long n, const int *cols, int n
     if (orc_gj_inverse(A, d, A0inv)) { free(A0inv); return 1; }
     for (int i = 0; i < d; ++i)
         for (int c = 0; c < nc; ++c) X[IDX3(0, i, c, d, nc)] = A0inv[i * d + cols[c]];
-    double *S = (double *)malloc(sizeof(double) * (size_t)d * nc);
-    for (long k = 1; k < n; ++k) {
-        /* S = sum_{l=1..k} A(l) X(k-l) */
-#pragma omp parallel for schedule(static) collapse(2) if ((double)k * d * d * nc > 2e5)
+    /* AT[l][t][r] = A(l)[r][t]: a plain transposed copy so the sums below
+       run over contiguous memory. */
+    double *AT = (double *)malloc(sizeof(double) * (size_t)n * d * d);
+    for (long l = 0; l < n; ++l)
         for (int r = 0; r < d; ++r)
-            for (int c = 0; c < nc; ++c) {
-                double s = 0.0;
-                for (long l = 1; l <= k; ++l)
-                    for (int t = 0; t < d; ++t)
-                        s += A[IDX3(l, r, t, d, d)] * X[IDX3(k - l, t, c, d, nc)];
-                S[r * nc + c] = s;
-            }
+            for (int t = 0; t < d; ++t) AT[IDX3(l, t, r, d, d)] = A[IDX3(l, r, t, d, d)];
+    int nth = orc_num_threads();
+    size_t blk = (size_t)nc * d;
+    double *part = (double *)malloc(sizeof(double) * blk * (size_t)nth);
+    double *S = (double *)malloc(sizeof(double) * blk);   /* S[c][r] */
+    for (long k = 1; k < n; ++k) {
+        /* S[c][r] = sum_{l=1..k} sum_t A(l)[r][t] X(k-l)[t][c], the l-range split
+           into one contiguous chunk per thread; chunks are added in thread order. */
+        int use = ((double)k * d * d * nc > 2e5) ? nth : 1;
+#pragma omp parallel num_threads(use)
+        {
+            int me = 0, cnt = 1;
+#ifdef _OPENMP
+            me = omp_get_thread_num();
+            cnt = omp_get_num_threads();
+#endif
+            double *P = part + (size_t)me * blk;
+            memset(P, 0, sizeof(double) * blk);
+            long lo = 1 + (k * me) / cnt, hi = 1 + (k * (me + 1)) / cnt;
+            for (long l = lo; l < hi; ++l)
+                for (int t = 0; t < d; ++t) {
+                    const double *at = AT + IDX3(l, t, 0, d, d);
+                    for (int c = 0; c < nc; ++c) {
+                        double x = X[IDX3(k - l, t, c, d, nc)];
+                        double *pc = P + (size_t)c * d;
+                        for (int r = 0; r < d; ++r) pc[r] += at[r] * x;
+                    }
+                }
+        }
+        for (size_t e = 0; e < blk; ++e) {
+            double s = 0.0;
+            for (int th = 0; th < use; ++th) s += part[(size_t)th * blk + e];
+            S[e] = s;
+        }
         for (int i = 0; i < d; ++i)
             for (int c = 0; c < nc; ++c) {
                 double s = 0.0;
-                for (int r = 0; r < d; ++r) s += A0inv[i * d + r] * S[r * nc + c];
+                for (int r = 0; r < d; ++r) s += A0inv[i * d + r] * S[(size_t)c * d + r];
                 X[IDX3(k, i, c, d, nc)] = -s;
             }
     }
-    free(S);
-    free(A0inv);
+    free(S); free(part); free(AT); free(A0inv);
     return 0;
 }
 
@@ -134,14 +165,32 @@ int orc_inverse_row(const double *A, int d, long n, const double *alpha, double 
         for (int i = 0; i < d; ++i) s += alpha[i] * A0inv[i * d + j];
         r[j] = s;
     }
+    int nth = orc_num_threads();
+    double *part = (double *)malloc(sizeof(double) * (size_t)d * nth);
     double *S = (double *)malloc(sizeof(double) * (size_t)d);
     for (long k = 1; k < n; ++k) {
-        /* S = sum_{l=0..k-1} r(l) A(k-l) */
-#pragma omp parallel for schedule(static) if ((double)k * d * d > 2e5)
+        /* S = sum_{l=0..k-1} r(l) A(k-l), l split into per-thread chunks added in order */
+        int use = ((double)k * d * d > 2e5) ? nth : 1;
+#pragma omp parallel num_threads(use)
+        {
+            int me = 0, cnt = 1;
+#ifdef _OPENMP
+            me = omp_get_thread_num();
+            cnt = omp_get_num_threads();
+#endif
+            double *P = part + (size_t)me * d;
+            memset(P, 0, sizeof(double) * (size_t)d);
+            long lo = (k * me) / cnt, hi = (k * (me + 1)) / cnt;
+            for (long l = lo; l < hi; ++l)
+                for (int u = 0; u < d; ++u) {
+                    const double a = r[(size_t)l * d + u];
+                    const double *row = A + IDX3(k - l, u, 0, d, d);
+                    for (int t = 0; t < d; ++t) P[t] += a * row[t];
+                }
+        }
         for (int t = 0; t < d; ++t) {
             double s = 0.0;
-            for (long l = 0; l < k; ++l)
-                for (int u = 0; u < d; ++u) s += r[(size_t)l * d + u] * A[IDX3(k - l, u, t, d, d)];
+            for (int th = 0; th < use; ++th) s += part[(size_t)th * d + t];
             S[t] = s;
         }
         for (int j = 0; j < d; ++j) {
@@ -150,8 +199,7 @@ int orc_inverse_row(const double *A, int d, long n, const double *alpha, double 
             r[(size_t)k * d + j] = -s;
         }
     }
-    free(S);
-    free(A0inv);
+    free(S); free(part); free(A0inv);
     return 0;
 }
 
@@ -180,14 +228,18 @@ int orc_inverse_right(const double *A, int d, long n, double *X)
 void orc_conv(const double *A, const double *B, int ra, int m, int cb, long n, double *C)
 {
 #pragma omp parallel for schedule(dynamic, 16)
-    for (long k = 0; k < n; ++k)
-        for (int i = 0; i < ra; ++i)
-            for (int j = 0; j < cb; ++j) {
-                double s = 0.0;
-                for (long l = 0; l <= k; ++l)
-                    for (int t = 0; t < m; ++t) s += A[IDX3(l, i, t, ra, m)] * B[IDX3(k - l, t, j, m, cb)];
-                C[IDX3(k, i, j, ra, cb)] = s;
-            }
+    for (long k = 0; k < n; ++k) {
+        double *ck = C + IDX3(k, 0, 0, ra, cb);
+        memset(ck, 0, sizeof(double) * (size_t)ra * cb);
+        for (long l = 0; l <= k; ++l)
+            for (int i = 0; i < ra; ++i)
+                for (int t = 0; t < m; ++t) {
+                    const double a = A[IDX3(l, i, t, ra, m)];
+                    const double *brow = B + IDX3(k - l, t, 0, m, cb);
+                    double *crow = ck + (size_t)i * cb;
+                    for (int j = 0; j < cb; ++j) crow[j] += a * brow[j];
+                }
+    }
 }
 
 /* ------------------------------------------------------------------------- */
@@ -214,13 +266,17 @@ void orc_transition(const double *psi, const double *q, int d, long n, double *P
     double *hb = (double *)malloc(sizeof(double) * (size_t)n * d);
     orc_hbar(q, d, n, hb);
 #pragma omp parallel for schedule(dynamic, 16)
-    for (long k = 0; k < n; ++k)
-        for (int i = 0; i < d; ++i)
-            for (int j = 0; j < d; ++j) {
-                double s = 0.0;
-                for (long l = 0; l <= k; ++l) s += psi[IDX3(l, i, j, d, d)] * hb[(size_t)(k - l) * d + j];
-                P[IDX3(k, i, j, d, d)] = s;
+    for (long k = 0; k < n; ++k) {
+        double *pk = P + IDX3(k, 0, 0, d, d);
+        memset(pk, 0, sizeof(double) * (size_t)d * d);
+        for (long l = 0; l <= k; ++l) {
+            const double *h = hb + (size_t)(k - l) * d;
+            for (int i = 0; i < d; ++i) {
+                const double *ps = psi + IDX3(l, i, 0, d, d);
+                for (int j = 0; j < d; ++j) pk[i * d + j] += ps[j] * h[j];
             }
+        }
+    }
     free(hb);
 }
 
@@ -321,26 +377,36 @@ void orc_adjoint(const double *psi, const double *psibar, int d, long n, double 
 {
     size_t d2 = (size_t)d * d;
     double *V = (double *)calloc((size_t)n * d2, sizeof(double));
+    double *PT = (double *)malloc(sizeof(double) * (size_t)n * d2);   /* PT[c][u][t] = psi(c)[t][u] */
+    for (long c = 0; c < n; ++c)
+        for (int t = 0; t < d; ++t)
+            for (int u = 0; u < d; ++u) PT[IDX3(c, u, t, d, d)] = psi[IDX3(c, t, u, d, d)];
+    /* V(j)[i][t] = sum_c sum_u psibar(j+c)[i][u] psi(c)[t][u] */
 #pragma omp parallel for schedule(dynamic, 16)
     for (long j = 0; j < n; ++j)
-        for (int i = 0; i < d; ++i)
-            for (int t = 0; t < d; ++t) {
-                double s = 0.0;
-                for (long c = 0; c + j < n; ++c)
-                    for (int u = 0; u < d; ++u)
-                        s += psibar[IDX3(j + c, i, u, d, d)] * psi[IDX3(c, t, u, d, d)];
-                V[IDX3(j, i, t, d, d)] = s;
-            }
+        for (long c = 0; c + j < n; ++c)
+            for (int i = 0; i < d; ++i)
+                for (int u = 0; u < d; ++u) {
+                    const double a = psibar[IDX3(j + c, i, u, d, d)];
+                    const double *pt = PT + IDX3(c, u, 0, d, d);
+                    double *v = V + IDX3(j, i, 0, d, d);
+                    for (int t = 0; t < d; ++t) v[t] += a * pt[t];
+                }
+    /* qbar(b)[i][t] = sum_a sum_u psi(a)[u][i] V(a+b)[u][t] */
 #pragma omp parallel for schedule(dynamic, 16)
-    for (long b = 0; b < n; ++b)
-        for (int i = 0; i < d; ++i)
-            for (int t = 0; t < d; ++t) {
-                double s = 0.0;
-                for (long a = 0; a + b < n; ++a)
-                    for (int u = 0; u < d; ++u)
-                        s += psi[IDX3(a, u, i, d, d)] * V[IDX3(a + b, u, t, d, d)];
-                qbar[IDX3(b, i, t, d, d)] = s;
-            }
+    for (long b = 0; b < n; ++b) {
+        double *qb = qbar + IDX3(b, 0, 0, d, d);
+        memset(qb, 0, sizeof(double) * d2);
+        for (long a = 0; a + b < n; ++a)
+            for (int u = 0; u < d; ++u)
+                for (int i = 0; i < d; ++i) {
+                    const double x = psi[IDX3(a, u, i, d, d)];
+                    const double *v = V + IDX3(a + b, u, 0, d, d);
+                    double *q = qb + (size_t)i * d;
+                    for (int t = 0; t < d; ++t) q[t] += x * v[t];
+                }
+    }
+    free(PT);
     free(V);
 }
 
@@ -354,16 +420,18 @@ void orc_forward_mode(const double *q, const double *psi, const double *dq, int 
     size_t d2 = (size_t)d * d;
     memset(dpsi, 0, sizeof(double) * d2);
     for (long k = 1; k < n; ++k) {
-#pragma omp parallel for schedule(static) collapse(2) if ((double)k * d2 * d > 2e5)
-        for (int i = 0; i < d; ++i)
-            for (int j = 0; j < d; ++j) {
-                double s = 0.0;
-                for (long l = 1; l <= k; ++l)
-                    for (int t = 0; t < d; ++t)
-                        s += dq[IDX3(l, i, t, d, d)] * psi[IDX3(k - l, t, j, d, d)]
-                           + q[IDX3(l, i, t, d, d)] * dpsi[IDX3(k - l, t, j, d, d)];
-                dpsi[IDX3(k, i, j, d, d)] = s;
-            }
+#pragma omp parallel for schedule(static) if ((double)k * d2 * d > 2e5)
+        for (int i = 0; i < d; ++i) {
+            double *out = dpsi + IDX3(k, i, 0, d, d);
+            memset(out, 0, sizeof(double) * (size_t)d);
+            for (long l = 1; l <= k; ++l)
+                for (int t = 0; t < d; ++t) {
+                    const double a = dq[IDX3(l, i, t, d, d)], b = q[IDX3(l, i, t, d, d)];
+                    const double *ps = psi + IDX3(k - l, t, 0, d, d);
+                    const double *dp = dpsi + IDX3(k - l, t, 0, d, d);
+                    for (int j = 0; j < d; ++j) out[j] += a * ps[j] + b * dp[j];
+                }
+        }
     }
 }
 
@@ -371,7 +439,6 @@ void orc_forward_mode(const double *q, const double *psi, const double *dq, int 
 int orc_num_threads(void)
 {
 #ifdef _OPENMP
-    extern int omp_get_max_threads(void);
     return omp_get_max_threads();
 #else
     return 1;

@@ -12,80 +12,61 @@ namespace mrinv {
 // at or below d * 2^-53 * max|A(0)| marks A(0) singular (Theorem 2.1: the
 // sequence is invertible iff A(0) is) and the output becomes NaN.
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) gj_kernel(const double *A0, int d, int e0_minus, double *out64, float *out32,
-                                                 unsigned int *status) {
+__global__ void __launch_bounds__(64) gj_kernel(const double *A0, int d, int e0_minus, double *out64, float *out32,
+                                                unsigned int *status) {
+    // One wavefront; lane r owns row r of W = [A(0) | I] (kept in LDS).
     extern __shared__ __align__(16) unsigned char smem_raw[];
     double *W = reinterpret_cast<double *>(smem_raw);   // [d][2d]
-    __shared__ double s_amax;
-    __shared__ int s_piv;
-    __shared__ int s_sing;
-    const int tid = threadIdx.x, nt = blockDim.x;
+    const int lane = threadIdx.x;
     const int w = 2 * d;
-    for (int idx = tid; idx < d * w; idx += nt) {
-        const int i = idx / w, j = idx - i * w;
-        double v;
-        if (j < d) {
-            const double a = A0[i * d + j];
-            v = e0_minus ? ((i == j ? 1.0 : 0.0) - a) : a;
-        } else {
-            v = (j - d == i) ? 1.0 : 0.0;
+    double amax = 0.0;
+    bool finite = true;
+    if (lane < d) {
+        for (int j = 0; j < d; ++j) {
+            const double a = A0[lane * d + j];
+            const double v = e0_minus ? ((lane == j ? 1.0 : 0.0) - a) : a;
+            W[lane * w + j] = v;
+            W[lane * w + d + j] = lane == j ? 1.0 : 0.0;
+            finite = finite && isfinite(v);
+            amax = fmax(amax, fabs(v));
         }
-        W[idx] = v;
     }
+    for (int off = 32; off > 0; off >>= 1) amax = fmax(amax, __shfl_xor(amax, off, 64));
+    int sing = __any(!finite) ? 2 : 0;
+    const double tol = d * 0x1p-53 * amax;
     __syncthreads();
-    if (tid == 0) {
-        double m = 0.0;
-        bool finite = true;
-        for (int i = 0; i < d; ++i)
-            for (int j = 0; j < d; ++j) {
-                const double a = fabs(W[i * w + j]);
-                if (!isfinite(a)) finite = false;
-                m = a > m ? a : m;
-            }
-        s_amax = m;
-        s_sing = finite ? 0 : 2;
-    }
-    __syncthreads();
-    const double tol = d * 0x1p-53 * s_amax;
-    for (int c = 0; c < d && s_sing == 0; ++c) {
-        if (tid == 0) {
-            int p = c;
-            double best = fabs(W[c * w + c]);
-            for (int r = c + 1; r < d; ++r) {
-                const double a = fabs(W[r * w + c]);
-                if (a > best) { best = a; p = r; }
-            }
-            s_piv = p;
-            if (!(best > tol)) s_sing = 1;
+    for (int c = 0; c < d && !sing; ++c) {
+        // Partial pivoting: argmax over rows c..d-1 of |W[r][c]| (lowest row on ties).
+        double best = (lane >= c && lane < d) ? fabs(W[lane * w + c]) : -1.0;
+        int piv = lane;
+        for (int off = 32; off > 0; off >>= 1) {
+            const double ob = __shfl_xor(best, off, 64);
+            const int op = __shfl_xor(piv, off, 64);
+            if (ob > best || (ob == best && op < piv)) { best = ob; piv = op; }
         }
-        __syncthreads();
-        if (s_sing) break;
-        const int p = s_piv;
-        if (p != c) {
-            for (int j = tid; j < w; j += nt) {
+        if (!(best > tol)) { sing = 1; break; }
+        if (piv != c) {
+            for (int j = lane; j < w; j += 64) {
                 const double t = W[c * w + j];
-                W[c * w + j] = W[p * w + j];
-                W[p * w + j] = t;
+                W[c * w + j] = W[piv * w + j];
+                W[piv * w + j] = t;
             }
         }
         __syncthreads();
         const double inv = 1.0 / W[c * w + c];
         __syncthreads();
-        for (int j = tid; j < w; j += nt) W[c * w + j] *= inv;
+        for (int j = lane; j < w; j += 64) W[c * w + j] *= inv;
         __syncthreads();
-        for (int idx = tid; idx < d * w; idx += nt) {
-            const int r = idx / w, j = idx - r * w;
-            if (r == c || j == c) continue;
-            W[idx] -= W[r * w + c] * W[c * w + j];
+        if (lane < d && lane != c) {
+            const double f = W[lane * w + c];
+            if (f != 0.0)
+                for (int j = 0; j < w; ++j) W[lane * w + j] = fma(-f, W[c * w + j], W[lane * w + j]);
         }
         __syncthreads();
-        for (int r = tid; r < d; r += nt)
-            if (r != c) W[r * w + c] = 0.0;
-        __syncthreads();
     }
-    const bool bad = s_sing != 0;
-    if (bad && tid == 0 && status) atomicOr(status, s_sing == 1 ? STATUS_SINGULAR : STATUS_NONFINITE);
-    for (int idx = tid; idx < d * d; idx += nt) {
+    const bool bad = sing != 0;
+    if (bad && lane == 0 && status) atomicOr(status, sing == 1 ? STATUS_SINGULAR : STATUS_NONFINITE);
+    for (int idx = lane; idx < d * d; idx += 64) {
         const int i = idx / d, j = idx - i * d;
         const double v = bad ? __longlong_as_double(0x7ff8000000000000LL) : W[i * w + d + j];
         if (out64) out64[idx] = v;
@@ -97,7 +78,7 @@ hipError_t gj_inverse(const double *A0, int d, int e0_minus, double *out64, floa
                       hipStream_t st) {
     const size_t lds = (size_t)d * 2 * d * sizeof(double);
     launch_begin("gj_kernel", (double)d * d * 8.0 * 2, 2.0 * d * d * d);
-    hipLaunchKernelGGL(gj_kernel, dim3(1), dim3(256), lds, st, A0, d, e0_minus, out64, out32, status);
+    hipLaunchKernelGGL(gj_kernel, dim3(1), dim3(64), lds, st, A0, d, e0_minus, out64, out32, status);
     launch_end();
     return hipGetLastError();
 }

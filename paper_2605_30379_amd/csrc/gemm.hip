@@ -189,9 +189,164 @@ static hipError_t launch_gemm(const FftPlan &plan, const GemmDesc &g, const cplx
     return hipGetLastError();
 }
 
+// Square products C = A B (d x d, no transposes) with the padded dimension DP
+// a compile-time constant: TM x TN register tiles, NF frequencies per
+// workgroup, the contraction staged through LDS in chunks of KC.
+template <int DP> struct SqCfg {
+    static constexpr int TM = DP <= 8 ? 1 : DP <= 16 ? 2 : DP <= 24 ? 3 : 4;
+    static constexpr int TN = DP <= 8 ? 2 : DP <= 16 ? 2 : 4;
+    static constexpr int TI = (DP + TM - 1) / TM, TJ = (DP + TN - 1) / TN;
+    static constexpr int TILES = TI * TJ;
+    static constexpr int NF = TILES >= 256 ? 1 : 256 / TILES;
+    static constexpr int THREADS = NF * TILES;
+    static constexpr int KC = DP <= 16 ? DP : 8;
+    static constexpr int AS = NF * DP * (KC + 1);          // complex elements of the A chunk
+    static constexpr int BS = NF * KC * (DP + 1);          // complex elements of the B chunk
+};
+
+template <typename T, int DP>
+__global__ void __launch_bounds__(SqCfg<DP>::THREADS)
+freq_gemm_sq_kernel(const cplx<T> *__restrict__ ZA, const cplx<T> *__restrict__ ZB, cplx<T> *__restrict__ ZC,
+                    FftPlan plan, int d) {
+    using Cfg = SqCfg<DP>;
+    constexpr int TM = Cfg::TM, TN = Cfg::TN, NF = Cfg::NF, KC = Cfg::KC, NT = Cfg::THREADS;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    cplx<T> *As = reinterpret_cast<cplx<T> *>(smem_raw);
+    cplx<T> *Bs = As + Cfg::AS;
+    __shared__ int64_t rows1[NF], rows2[NF];
+    const int64_t L = (int64_t)1 << plan.lgL;
+    const int64_t F = L / 2 + 1;
+    const int64_t k0 = (int64_t)blockIdx.x * NF;
+    const int tid = threadIdx.x;
+    const int nl = (d * d + 1) >> 1;
+    if (tid < NF) {
+        const int64_t k = k0 + tid;
+        rows1[tid] = k < F ? freq_row(plan, k) : 0;
+        rows2[tid] = k < F ? freq_row(plan, (L - k) & (L - 1)) : 0;
+    }
+    __syncthreads();
+    const int f = tid / Cfg::TILES, tile = tid - f * Cfg::TILES;
+    const int i0 = (tile / Cfg::TJ) * TM, j0 = (tile % Cfg::TJ) * TN;
+    const bool active = k0 + f < F;
+    cplx<T> acc[TM][TN];
+#pragma unroll
+    for (int a = 0; a < TM; ++a)
+#pragma unroll
+        for (int b = 0; b < TN; ++b) acc[a][b] = mk<T>(0, 0);
+
+    for (int kc = 0; kc < d; kc += KC) {
+        for (int idx = tid; idx < NF * DP * KC; idx += NT) {
+            const int ff = idx / (DP * KC), rem = idx - ff * (DP * KC);
+            const int i = rem / KC, t = rem - i * KC;
+            cplx<T> v = mk<T>(0, 0);
+            if (i < d && kc + t < d && k0 + ff < F) v = unpack<T>(ZA, nl, rows1[ff], rows2[ff], i * d + kc + t);
+            As[(ff * DP + i) * (KC + 1) + t] = v;
+        }
+        for (int idx = tid; idx < NF * KC * DP; idx += NT) {
+            const int ff = idx / (KC * DP), rem = idx - ff * (KC * DP);
+            const int t = rem / DP, j = rem - t * DP;
+            cplx<T> v = mk<T>(0, 0);
+            if (j < d && kc + t < d && k0 + ff < F) v = unpack<T>(ZB, nl, rows1[ff], rows2[ff], (kc + t) * d + j);
+            Bs[(ff * KC + t) * (DP + 1) + j] = v;
+        }
+        __syncthreads();
+        const cplx<T> *Af = As + f * DP * (KC + 1);
+        const cplx<T> *Bf = Bs + f * KC * (DP + 1);
+#pragma unroll
+        for (int t = 0; t < KC; ++t) {
+            cplx<T> av[TM], bv[TN];
+#pragma unroll
+            for (int a = 0; a < TM; ++a) av[a] = (i0 + a < DP) ? Af[(i0 + a) * (KC + 1) + t] : mk<T>(0, 0);
+#pragma unroll
+            for (int b = 0; b < TN; ++b) bv[b] = (j0 + b < DP) ? Bf[t * (DP + 1) + j0 + b] : mk<T>(0, 0);
+#pragma unroll
+            for (int a = 0; a < TM; ++a)
+#pragma unroll
+                for (int b = 0; b < TN; ++b) {
+                    acc[a][b].x = fma(av[a].x, bv[b].x, fma(-av[a].y, bv[b].y, acc[a][b].x));
+                    acc[a][b].y = fma(av[a].x, bv[b].y, fma(av[a].y, bv[b].x, acc[a][b].y));
+                }
+        }
+        __syncthreads();
+    }
+
+    if ((d & 1) == 0) {
+        // d even and TN even: each thread owns whole lane pairs of its rows.
+        if (active) {
+#pragma unroll
+            for (int a = 0; a < TM; ++a) {
+                const int i = i0 + a;
+                if (i >= d) continue;
+#pragma unroll
+                for (int b = 0; b < TN; b += 2) {
+                    const int j = j0 + b;
+                    if (j >= d) continue;
+                    pack_store<T>(ZC, nl, rows1[f], rows2[f], (i * d + j) >> 1, acc[a][b], acc[a][b + 1]);
+                }
+            }
+        }
+    } else {
+        cplx<T> *Cs = As;   // [NF][d*d + 1], fits in the A and B chunk area
+        const int ld = d * d + 1;
+        if (active) {
+#pragma unroll
+            for (int a = 0; a < TM; ++a)
+#pragma unroll
+                for (int b = 0; b < TN; ++b)
+                    if (i0 + a < d && j0 + b < d) Cs[f * ld + (i0 + a) * d + j0 + b] = acc[a][b];
+        }
+        __syncthreads();
+        for (int idx = tid; idx < NF * nl; idx += NT) {
+            const int ff = idx / nl, c = idx - ff * nl;
+            if (k0 + ff >= F) continue;
+            const int e = 2 * c;
+            const cplx<T> ce = Cs[ff * ld + e];
+            const cplx<T> co = (e + 1 < d * d) ? Cs[ff * ld + e + 1] : mk<T>(0, 0);
+            pack_store<T>(ZC, nl, rows1[ff], rows2[ff], c, ce, co);
+        }
+    }
+}
+
+template <typename T, int DP>
+static hipError_t launch_gemm_sq(const FftPlan &plan, int d, const cplx<T> *ZA, const cplx<T> *ZB, cplx<T> *ZC,
+                                 hipStream_t st) {
+    using Cfg = SqCfg<DP>;
+    size_t lds = (size_t)(Cfg::AS + Cfg::BS) * sizeof(cplx<T>);
+    const size_t cs = (size_t)Cfg::NF * (d * d + 1) * sizeof(cplx<T>);
+    if ((d & 1) && cs > lds) lds = cs;
+    const int64_t F = ((int64_t)1 << plan.lgL) / 2 + 1;
+    const int64_t blocks = (F + Cfg::NF - 1) / Cfg::NF;
+    char name[96];
+    snprintf(name, sizeof name, "freq_gemm_sq_kernel<%s, %d>", sizeof(T) == 8 ? "double" : "float", DP);
+    const double Lr = (double)((int64_t)1 << plan.lgL);
+    const int nl = (d * d + 1) / 2;
+    launch_begin(name, Lr * 3.0 * nl * sizeof(cplx<T>), (double)F * 8.0 * d * d * d);
+    hipLaunchKernelGGL((freq_gemm_sq_kernel<T, DP>), dim3((unsigned)blocks), dim3(Cfg::THREADS), lds, st, ZA, ZB, ZC,
+                       plan, d);
+    launch_end();
+    return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t gemm_sq(const FftPlan &plan, int d, const cplx<T> *ZA, const cplx<T> *ZB, cplx<T> *ZC,
+                          hipStream_t st) {
+    switch ((d + 7) / 8) {
+        case 1: return launch_gemm_sq<T, 8>(plan, d, ZA, ZB, ZC, st);
+        case 2: return launch_gemm_sq<T, 16>(plan, d, ZA, ZB, ZC, st);
+        case 3: return launch_gemm_sq<T, 24>(plan, d, ZA, ZB, ZC, st);
+        case 4: return launch_gemm_sq<T, 32>(plan, d, ZA, ZB, ZC, st);
+        case 5: return launch_gemm_sq<T, 40>(plan, d, ZA, ZB, ZC, st);
+        case 6: return launch_gemm_sq<T, 48>(plan, d, ZA, ZB, ZC, st);
+        case 7: return launch_gemm_sq<T, 56>(plan, d, ZA, ZB, ZC, st);
+        default: return launch_gemm_sq<T, 64>(plan, d, ZA, ZB, ZC, st);
+    }
+}
+
 template <typename T>
 hipError_t freq_gemm(const FftPlan &plan, const GemmDesc &g, const cplx<T> *ZA, const cplx<T> *ZB, cplx<T> *ZC,
                      hipStream_t st) {
+    if (g.ra == g.m && g.m == g.cb && !g.transA && !g.transB && g.ra <= 64)
+        return gemm_sq<T>(plan, g.ra, ZA, ZB, ZC, st);
     const int dmax = g.ra > g.cb ? g.ra : g.cb;
     if (dmax <= 8) return launch_gemm<T, 1, 1>(plan, g, ZA, ZB, ZC, st);
     if (dmax <= 24) return launch_gemm<T, 2, 2>(plan, g, ZA, ZB, ZC, st);

@@ -89,8 +89,16 @@ def weibull_pmf(shape, scale, n: int, n_rows: int | None = None, device="cpu"):
     scale = torch.as_tensor(scale, dtype=torch.float64, device=device)
     k = _steps(n_rows, device).reshape((-1,) + (1,) * shape.dim())
     km1 = torch.clamp(k - 1.0, min=0.0)
-    hk = (k / scale) ** shape                       # cumulative hazard at k
-    hkm1 = (km1 / scale) ** shape
+
+    def hazard(t):
+        # (t/scale)^shape with a safe base at t = 0, so the shape derivative
+        # there is 0 instead of 0 * log(0).
+        pos = t > 0
+        base = torch.where(pos, t, torch.ones_like(t)) / scale
+        return torch.where(pos, base ** shape, torch.zeros_like(base))
+
+    hk = hazard(k)                                  # cumulative hazard at k
+    hkm1 = hazard(km1)
     f = torch.exp(-hkm1) * (-torch.expm1(-(hk - hkm1)))
     f = torch.where(k >= 1, f, torch.zeros_like(f))
     if n <= 1:
@@ -263,3 +271,34 @@ def paper_uniform_poisson(s: int, n: int) -> Kernel:
             if i != j:
                 q[:, i, j] = p[i, j] * shifted_poisson_pmf(3.0 + ((i + 1 + j + 1) % 4), n)
     return Kernel(torch.from_numpy(q), p, {"family": "poisson_uniform"})
+
+
+# ---------------------------------------------------------------------------
+# Differentiable parameterisation (input construction for gradient studies).
+# ---------------------------------------------------------------------------
+
+def weibull_params(d: int, seed: int, device="cpu"):
+    """Draws of :func:`weibull_kernel` as tensors (shape, scale, logits), with
+    logits = log p off the diagonal (so the masked softmax reproduces p)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    p = dirichlet_rows(rng, d)
+    shape = rng.uniform(0.5, 2.0, size=(d, d))
+    scale = rng.uniform(2.0, 20.0, size=(d, d))
+    logits = np.where(np.eye(d) > 0, 0.0, np.log(np.where(p > 0, p, 1.0)))
+    f64 = dict(dtype=torch.float64, device=device)
+    return torch.tensor(shape, **f64), torch.tensor(scale, **f64), torch.tensor(logits, **f64)
+
+
+def masked_softmax_rows(logits: torch.Tensor) -> torch.Tensor:
+    """Row-wise softmax over the off-diagonal entries; zero diagonal."""
+    d = logits.shape[0]
+    mask = torch.eye(d, dtype=torch.bool, device=logits.device)
+    z = logits.masked_fill(mask, float("-inf"))
+    return torch.softmax(z, dim=1)
+
+
+def weibull_kernel_from_params(shape: torch.Tensor, scale: torch.Tensor, logits: torch.Tensor, n: int):
+    """q(k) = softmax_offdiag(logits) * Weibull pmf(k; shape, scale); differentiable."""
+    p = masked_softmax_rows(logits)
+    f = weibull_pmf(shape, scale, n, device=shape.device)
+    return p.unsqueeze(0) * f

@@ -1,0 +1,207 @@
+"""Full-size GPU checks of the named workloads, in the launch configuration
+bench.py times (one call of the C-ABI per inversion, default stream).
+
+At these sizes the quadratic oracle cannot produce every output, so each
+test combines:
+  * oracle values on a prefix (exact sub-problem by finite-horizon exactness,
+    Proposition 2.3): the full matrix on a short prefix and sampled columns
+    or rows on a longer one;
+  * closed forms at any horizon (the Markov case, geometric sojourns);
+  * identities that hold at any size (row sums of P equal one, residuals
+    e0 - A*psi computed with numpy's own FFT, independent of the GPU code).
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import smk_inputs as si
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def mr():
+    import paper_2605_30379_amd as m
+    assert torch.cuda.is_available()
+    m.lib()
+    return m
+
+
+def _np(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def _maxerr(a, b):
+    return float(np.max(np.abs(np.asarray(a) - np.asarray(b))))
+
+
+def test_c2_fp64_full_size(mr, orc):
+    """d = 16, n = 65536, Weibull (seed 1), FP64: max-abs <= 1e-12."""
+    d, n = 16, 65536
+    print("[c2] generating", flush=True)
+    k = si.weibull_kernel(d, n, si.CONFIG_SEEDS["c2"], device="cuda")
+    psi = mr.psi_inverse(k.q, "fp64", check=True)
+    P = mr.transition(psi, k.q)
+    qh = k.q[:2048].cpu().numpy()
+    ref = orc.psi(qh)
+    assert _maxerr(_np(psi[:2048]), ref) <= 1e-12
+    print("[c2] prefix column", flush=True)
+    npre = 8192
+    col = orc.psi(k.q[:npre].cpu().numpy(), cols=[5])
+    assert _maxerr(_np(psi[:npre, :, 5:6]), col) <= 1e-12
+    # Exact identity at every k: rows of P sum to one.
+    assert float((P.sum(dim=2) - 1).abs().max()) <= 1e-12
+    # Residuals over the whole horizon with numpy's FFT (Proposition 2.6 inputs).
+    print("[c2] residuals", flush=True)
+    rl, rr, ml, mrr = orc.residuals_fft(k.q.cpu().numpy(), _np(psi))
+    print(f"[c2] residual sums {rl:.3e} {rr:.3e} max {ml:.3e} {mrr:.3e}", flush=True)
+    assert ml <= 1e-13 and mrr <= 1e-13
+
+
+def test_c2_markov_closed_form_full_size(mr, orc):
+    """Geometric sojourns (seed 2), d = 16, n = 65536: psi(k) = M^(k-1)(M - diag a)
+    and P(k) = M^k at sampled k across the whole horizon."""
+    d, n = 16, 65536
+    k = si.geometric_kernel(d, n, si.CONFIG_SEEDS["c2_geom"], device="cuda")
+    psi = mr.psi_inverse(k.q, "fp64", check=True)
+    P = mr.transition(psi, k.q)
+    ks = np.unique(np.concatenate([np.arange(0, 40), np.linspace(40, n - 1, 60).astype(int)]))
+    kt = torch.as_tensor(ks, device="cuda")
+    assert _maxerr(_np(psi[kt]), orc.geometric_psi(k.params["M"], k.params["a"], ks)) <= 1e-12
+    assert _maxerr(_np(P[kt]), orc.geometric_P(k.params["M"], ks)) <= 1e-12
+
+
+def test_c3_mixed_full_size(mr, orc):
+    """d = 64, n = 262144, lognormal (seed 3), mixed form: max-abs <= 1e-10
+    against the oracle prefix, against the FP64 path over the whole horizon,
+    and for P and reliability (up set = first 32 states)."""
+    d, n = 64, 262144
+    print("[c3] generating", flush=True)
+    k = si.lognormal_kernel(d, n, si.CONFIG_SEEDS["c3"], device="cuda")
+    psim = mr.psi_inverse(k.q, "mixed", check=True)
+    print("[c3] oracle prefix", flush=True)
+    npre = 512
+    qh = k.q[:npre].cpu().numpy()
+    ref = orc.psi(qh)
+    assert _maxerr(_np(psim[:npre]), ref) <= 1e-10
+    psi64 = mr.psi_inverse(k.q, "fp64", check=True)
+    assert float((psim - psi64).abs().max()) <= 1e-10
+    Pm = mr.transition(psim, k.q)
+    assert float((Pm.sum(dim=2) - 1).abs().max()) <= 1e-10
+    P64 = mr.transition(psi64, k.q)
+    assert float((Pm - P64).abs().max()) <= 1e-10
+    del Pm, P64, psi64
+    up = [1] * 32 + [0] * 32
+    alpha = np.eye(d)[0]
+    R = mr.reliability(k.q, up, alpha, precision="mixed")
+    Rref = orc.reliability(qh, np.array(up), alpha)
+    assert _maxerr(_np(R[:npre]), Rref) <= 1e-10
+    R64 = mr.reliability(k.q, up, alpha, precision="fp64")
+    assert float((R - R64).abs().max()) <= 1e-10
+
+
+def test_c3_markov_closed_form_mixed(mr, orc):
+    """Mixed form on the Markov case at d = 64, n = 262144."""
+    d, n = 64, 262144
+    k = si.geometric_kernel(d, n, 33, device="cuda")
+    psim = mr.psi_inverse(k.q, "mixed", check=True)
+    ks = np.unique(np.linspace(0, n - 1, 40).astype(int))
+    kt = torch.as_tensor(ks, device="cuda")
+    assert _maxerr(_np(psim[kt]), orc.geometric_psi(k.params["M"], k.params["a"], ks)) <= 1e-10
+
+
+def _c5_loss(mr, q, up, alpha, target):
+    """sum_k A(k) + F_{target}(n-1) through the library's autograd Functions."""
+    d = q.shape[1]
+    psi = mr.PsiInverse.apply(q)
+    P = mr.Transition.apply(psi, q)
+    A = mr.Contract.apply(P, alpha, up)
+    C = [i for i in range(d) if i != target]
+    qCC = mr.GatherBlock.apply(q, C, C)
+    qCD = mr.GatherBlock.apply(q, C, [target])
+    g = mr.RenewalApply.apply(mr.PsiInverse.apply(qCC), qCD)
+    aC = torch.zeros(d - 1, dtype=torch.float64)
+    aC[0] = 1.0
+    F = mr.Contract.apply(g, aC, torch.ones(1, dtype=torch.float64), True)
+    return A.sum() + F[-1]
+
+
+def test_c5_gradient_chain_matches_oracle_forward_mode(mr, orc):
+    """The GPU gradient of the full loss with respect to q, contracted with a
+    random direction dq, against the oracle's forward-mode derivative of the
+    same chain (dpsi = dq*psi + q*dpsi, dP = dpsi*Hbar + psi*dHbar, ...)."""
+    d, n, target = 6, 200, 5
+    k = si.weibull_kernel(d, n, 55)
+    up = torch.tensor([1.0] * 3 + [0.0] * 3, dtype=torch.float64)
+    alpha = torch.zeros(d, dtype=torch.float64)
+    alpha[0] = 1.0
+    q = k.q.cuda().requires_grad_(True)
+    _c5_loss(mr, q, up, alpha, target).backward()
+    g = _np(q.grad)
+    rng = np.random.default_rng(5)
+    qn = k.q.numpy()
+    for _ in range(2):
+        dq = rng.standard_normal(qn.shape)
+        dq[0] = 0
+        psi = orc.psi(qn)
+        dpsi = orc.forward_mode(qn, psi, dq)
+        hb = orc.hbar(qn)
+        dhb = -np.cumsum(dq.sum(axis=2), axis=0)
+        dhb[0] = 0.0
+        H = np.zeros((n, d, d))
+        dH = np.zeros((n, d, d))
+        for t in range(n):
+            H[t] = np.diag(hb[t])
+            dH[t] = np.diag(dhb[t])
+        dP = orc.conv(dpsi, H) + orc.conv(psi, dH)
+        dA = np.einsum("i,kij,j->", alpha.numpy(), dP, up.numpy())
+        C = [i for i in range(d) if i != target]
+        qCC = np.ascontiguousarray(qn[:, C][:, :, C])
+        qCD = np.ascontiguousarray(qn[:, C][:, :, [target]])
+        dCC = np.ascontiguousarray(dq[:, C][:, :, C])
+        dCD = np.ascontiguousarray(dq[:, C][:, :, [target]])
+        psiC = orc.psi(qCC)
+        dpsiC = orc.forward_mode(qCC, psiC, dCC)
+        dg = orc.conv(dpsiC, qCD) + orc.conv(psiC, dCD)
+        dF = dg[:, 0, 0].sum()
+        ref = dA + dF
+        got = float(np.sum(g * dq))
+        assert abs(got - ref) <= 1e-9 * max(1.0, abs(ref))
+
+
+def test_c5_full_size_gradients_vs_central_differences(mr):
+    """d = 32, n = 65536, Weibull (seed 5).  Loss = sum_k A(k) (U = first 16
+    states) + first-entrance probability into state d-1 at n-1.  Gradients with
+    respect to every Weibull shape, scale and jump logit (3 d (d-1) = 2976 live
+    parameters) through the adjoint kernels, checked along random directions
+    against central differences with h = 1e-6 in FP64."""
+    d, n, target = 32, 65536, 31
+    shape, scale, logits = si.weibull_params(d, si.CONFIG_SEEDS["c5"], device="cuda")
+    up = torch.tensor([1.0] * 16 + [0.0] * 16, dtype=torch.float64)
+    alpha = torch.zeros(d, dtype=torch.float64)
+    alpha[0] = 1.0
+    params = [t.clone().requires_grad_(True) for t in (shape, scale, logits)]
+    loss = _c5_loss(mr, si.weibull_kernel_from_params(*params, n), up, alpha, target)
+    loss.backward()
+    grads = [p.grad.detach() for p in params]
+    off = ~torch.eye(d, dtype=torch.bool, device="cuda")
+    for g in grads:
+        assert torch.isfinite(g).all()
+        assert float(g[~off].abs().max()) == 0.0          # diagonal entries do not enter q
+    assert int(sum(int((g[off] != 0).sum()) for g in grads)) == 3 * d * (d - 1)
+    gen = torch.Generator(device="cpu").manual_seed(0)
+    h = 1e-6
+    for trial in range(3):
+        dirs = [torch.randn(d, d, generator=gen, dtype=torch.float64).cuda() * off for _ in range(3)]
+        with torch.no_grad():
+            lp = _c5_loss(mr, si.weibull_kernel_from_params(*[p + h * v for p, v in zip(params, dirs)], n),
+                          up, alpha, target)
+            lm = _c5_loss(mr, si.weibull_kernel_from_params(*[p - h * v for p, v in zip(params, dirs)], n),
+                          up, alpha, target)
+        fd = float((lp - lm) / (2 * h))
+        an = float(sum((g * v).sum() for g, v in zip(grads, dirs)))
+        print(f"[c5] trial {trial}: adjoint {an:.10e} fd {fd:.10e} rel {abs(an - fd) / abs(an):.2e}", flush=True)
+        assert abs(an - fd) <= 1e-5 * abs(an)
