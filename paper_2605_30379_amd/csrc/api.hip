@@ -6,6 +6,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <functional>
 #include <string>
 #include <vector>
 
@@ -50,6 +51,9 @@ struct mrinv_handle_s {
     double *scratch = nullptr;      // small per-handle scratch (index lists, vectors, 1-lane scans)
     void *timer = nullptr;          // launch timing records (mrinv_set_timing)
     bool timing = false;
+    void *pinned = nullptr;         // pinned staging buffer of batched descriptor tables
+    size_t pinned_bytes = 0;
+    hipEvent_t pinned_done = nullptr;   // recorded after the last transfer out of `pinned`
     Twiddles<double> t64() const { return {tw64, tw64 + TW_HI_SIZE}; }
     Twiddles<float> t32() const { return {tw64, tw64 + TW_HI_SIZE}; }
 };
@@ -87,6 +91,7 @@ extern "C" mrinv_status_t mrinv_create(mrinv_handle_t *handle, void *stream) {
     HIP_TRY(hipMemcpy(h->tw64, hi.data(), TW_HI_SIZE * sizeof(double2), hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(h->tw64 + TW_HI_SIZE, lo.data(), TW_LO_SIZE * sizeof(double2), hipMemcpyHostToDevice));
     HIP_TRY(hipMemset(h->status, 0, 256));
+    HIP_TRY(hipEventCreateWithFlags(&h->pinned_done, hipEventDisableTiming));
     HIP_TRY(hipDeviceSynchronize());
     *handle = h;
     g_last_error.clear();
@@ -101,6 +106,8 @@ extern "C" mrinv_status_t mrinv_destroy(mrinv_handle_t h) {
     if (h->status) (void)hipFree(h->status);
     if (h->scratch) (void)hipFree(h->scratch);
     if (h->timer) timer_destroy(h->timer);
+    if (h->pinned) (void)hipHostFree(h->pinned);
+    if (h->pinned_done) (void)hipEventDestroy(h->pinned_done);
     delete h;
     return MRINV_OK;
 }
@@ -265,8 +272,8 @@ extern "C" size_t mrinv_workspace_size(mrinv_op_t op, int d, int64_t n, int r, m
 // Transform helpers
 // ---------------------------------------------------------------------------
 template <typename T> static Twiddles<T> tw_of(mrinv_handle_t h);
-template <> Twiddles<double> tw_of<double>(mrinv_handle_t h) { return h->t64(); }
-template <> Twiddles<float> tw_of<float>(mrinv_handle_t h) { return h->t32(); }
+template <> Twiddles<double> tw_of<double>(mrinv_handle_t h) { return h ? h->t64() : Twiddles<double>{}; }
+template <> Twiddles<float> tw_of<float>(mrinv_handle_t h) { return h ? h->t32() : Twiddles<float>{}; }
 
 static SrcDesc src_real(const void *p, bool dbl, int64_t ld, int nreal, int64_t lo, int64_t hi, int64_t rev = -1,
                         int e0_d = 0) {
@@ -820,17 +827,372 @@ extern "C" mrinv_status_t mrinv_residual_norms(mrinv_handle_t h, const double *q
 }
 
 // ---------------------------------------------------------------------------
-// Batched inversion
+// Batched inversion.  All problems active at Newton step r share the length
+// L = 2^(r+1) (the truncated last step of a problem has the same L), so each
+// phase of a step is one launch over every active problem, grouped only by
+// lanes per workgroup (FFT passes) or by padded dimension class (products).
+// Descriptors of every launch are planned on the host, copied to the device
+// in one transfer, then the launches are enqueued.  Problems are split into
+// sub-batches so that the spectra of one phase fit under BATCH_SPEC_CAP.
 // ---------------------------------------------------------------------------
+// Handle fields for the planner, which also runs without a handle to size
+// the workspace.
+static hipStream_t stream_of(mrinv_handle_t h) { return h ? h->stream : nullptr; }
+static unsigned int *status_of(mrinv_handle_t h) { return h ? h->status : nullptr; }
+
+constexpr size_t BATCH_SPEC_CAP = (size_t)24 << 30;
+
+struct BatchPlan {
+    std::vector<unsigned char> table;        // host image of the device descriptor table
+    std::vector<std::function<hipError_t(char *)>> launches;   // each takes the device table base
+    size_t table_bytes = 0, x_off = 0, r_off = 0, spec_off = 0, spec_bytes = 0, total = 0;
+    template <typename D> size_t put(const std::vector<D> &v) {
+        const size_t off = align256(table.size());
+        table.resize(off + v.size() * sizeof(D));
+        memcpy(table.data() + off, v.data(), v.size() * sizeof(D));
+        return off;
+    }
+};
+
+template <typename T>
+static void plan_fft(BatchPlan &bp, mrinv_handle_t h, int mode, const FftPlan &p, int pass,
+                     const std::vector<PassProblem<T>> &probs) {
+    if (probs.empty()) return;
+    const bool dbl = sizeof(T) == 8;
+    // group by lanes per workgroup
+    for (int C : {2, 8, 16}) {
+        std::vector<PassProblem<T>> g;
+        for (auto &q : probs)
+            if (fft_lanes_per_block(dbl, q.nl) == C) g.push_back(q);
+        if (g.empty()) continue;
+        const int64_t total = fft_batch_layout<T>(p, pass, g.data(), (int)g.size(), C);
+        double bytes = 0;
+        for (auto &q : g) bytes += 2.0 * ((double)((int64_t)1 << p.lgL)) * q.nl * sizeof(cplx<T>);
+        const size_t off = bp.put(g);
+        const int cnt = (int)g.size();
+        const Twiddles<T> tw = tw_of<T>(h);
+        hipStream_t st = stream_of(h);
+        bp.launches.push_back([=](char *base) {
+            return fft_pass_batched<T>(mode, p, pass, C, (const PassProblem<T> *)(base + off), cnt, total, bytes, tw, st);
+        });
+    }
+}
+
+template <typename T>
+static void plan_gemm(BatchPlan &bp, mrinv_handle_t h, const FftPlan &p, const std::vector<GemmProblem<T>> &probs) {
+    for (int cls = 1; cls <= 8; ++cls) {
+        std::vector<GemmProblem<T>> g;
+        for (auto &q : probs)
+            if (gemm_sq_class(q.d) == cls) g.push_back(q);
+        if (g.empty()) continue;
+        const int64_t total = gemm_batch_layout<T>(p, g.data(), (int)g.size());
+        double bytes = 0, flops = 0;
+        const double Lr = (double)((int64_t)1 << p.lgL);
+        for (auto &q : g) {
+            bytes += Lr * 3.0 * nl_of((int64_t)q.d * q.d) * sizeof(cplx<T>);
+            flops += (Lr / 2 + 1) * 8.0 * q.d * q.d * q.d;
+        }
+        const size_t off = bp.put(g);
+        const int cnt = (int)g.size();
+        hipStream_t st = stream_of(h);
+        bp.launches.push_back([=](char *base) {
+            return freq_gemm_batched<T>(p, cls, (const GemmProblem<T> *)(base + off), cnt, total, bytes, flops, st);
+        });
+    }
+}
+
+// Forward transform of a real source per problem into its spectrum.
+template <typename T>
+static void plan_fwd(BatchPlan &bp, mrinv_handle_t h, const FftPlan &p, const std::vector<cplx<T> *> &Z,
+                     const std::vector<int> &nl, const std::vector<SrcDesc> &src) {
+    std::vector<PassProblem<T>> v(Z.size());
+    for (size_t i = 0; i < Z.size(); ++i) {
+        v[i] = PassProblem<T>{};
+        v[i].z = Z[i];
+        v[i].nl = nl[i];
+        v[i].src = src[i];
+        v[i].dst = dst_z();
+    }
+    plan_fft<T>(bp, h, 0, p, 0, v);
+    for (auto &x : v) x.src = src_z();
+    for (int j = 1; j < p.npass; ++j) plan_fft<T>(bp, h, 0, p, j, v);
+}
+
+template <typename T>
+static void plan_inv(BatchPlan &bp, mrinv_handle_t h, const FftPlan &p, const std::vector<cplx<T> *> &Z,
+                     const std::vector<int> &nl, const std::vector<DstDesc> &dst) {
+    std::vector<PassProblem<T>> v(Z.size());
+    for (size_t i = 0; i < Z.size(); ++i) {
+        v[i] = PassProblem<T>{};
+        v[i].z = Z[i];
+        v[i].nl = nl[i];
+        v[i].src = src_z();
+        v[i].dst = dst_z();
+    }
+    for (int j = p.npass - 1; j >= 1; --j) plan_fft<T>(bp, h, 1, p, j, v);
+    for (size_t i = 0; i < Z.size(); ++i) v[i].dst = dst[i];
+    plan_fft<T>(bp, h, 1, p, 0, v);
+}
+
+template <typename T>
+static void plan_remask(BatchPlan &bp, mrinv_handle_t h, const FftPlan &p, const std::vector<cplx<T> *> &Z,
+                        const std::vector<int> &nl, const std::vector<int64_t> &lo, const std::vector<int64_t> &hi,
+                        bool neg) {
+    std::vector<PassProblem<T>> v(Z.size());
+    for (size_t i = 0; i < Z.size(); ++i) {
+        v[i] = PassProblem<T>{};
+        v[i].z = Z[i];
+        v[i].nl = nl[i];
+        v[i].src = src_z();
+        v[i].dst = dst_z();
+    }
+    for (int j = p.npass - 1; j >= 1; --j) plan_fft<T>(bp, h, 1, p, j, v);
+    for (size_t i = 0; i < Z.size(); ++i) {
+        v[i].dst.lo = lo[i];
+        v[i].dst.hi = hi[i];
+        v[i].dst.op = neg ? OP_NEG : OP_STORE;
+        v[i].dst.scale = 1.0 / (double)((int64_t)1 << p.lgL);
+    }
+    plan_fft<T>(bp, h, 2, p, 0, v);
+    for (auto &x : v) x.dst = dst_z();
+    for (int j = 1; j < p.npass; ++j) plan_fft<T>(bp, h, 0, p, j, v);
+}
+
+struct BatchProblem {
+    const double *q;
+    double *psi;
+    int d;
+    int64_t n;
+    float *X, *R;   // mixed form
+};
+
+// Sub-batches of `idx` whose summed need stays under the cap (at least one each).
+static std::vector<std::vector<int>> split_by_cap(const std::vector<int> &idx, const std::vector<size_t> &need) {
+    std::vector<std::vector<int>> out;
+    std::vector<int> cur;
+    size_t acc = 0;
+    for (size_t k = 0; k < idx.size(); ++k) {
+        if (!cur.empty() && acc + need[k] > BATCH_SPEC_CAP) {
+            out.push_back(cur);
+            cur.clear();
+            acc = 0;
+        }
+        cur.push_back(idx[k]);
+        acc += need[k];
+    }
+    if (!cur.empty()) out.push_back(cur);
+    return out;
+}
+
+template <typename T>
+static void plan_newton(BatchPlan &bp, mrinv_handle_t h, std::vector<BatchProblem> &P, char *spec, size_t &spec_max) {
+    const bool dbl = sizeof(T) == 8;
+    const int64_t nmax = [&] { int64_t m = 0; for (auto &b : P) m = std::max(m, b.n); return m; }();
+    for (int64_t m = 1; m < nmax; m *= 2) {
+        const FftPlan p = make_plan(ceil_log2(2 * m));
+        const int64_t L = (int64_t)1 << p.lgL;
+        std::vector<int> act;
+        std::vector<size_t> need;
+        for (int i = 0; i < (int)P.size(); ++i)
+            if (P[i].n > m) {
+                act.push_back(i);
+                need.push_back(3 * spec_bytes(p.lgL, (int64_t)P[i].d * P[i].d, dbl));
+            }
+        for (auto &sub : split_by_cap(act, need)) {
+            std::vector<cplx<T> *> SA, SB, ST;
+            std::vector<int> nl;
+            std::vector<SrcDesc> sa, sb;
+            std::vector<DstDesc> du;
+            std::vector<int64_t> lo, hi;
+            std::vector<GemmProblem<T>> g1, g2;
+            size_t used = 0;
+            for (int i : sub) {
+                const BatchProblem &b = P[i];
+                const int64_t d2 = (int64_t)b.d * b.d;
+                const size_t sbz = spec_bytes(p.lgL, d2, dbl);
+                SA.push_back((cplx<T> *)(spec + used));
+                SB.push_back((cplx<T> *)(spec + used + sbz));
+                ST.push_back((cplx<T> *)(spec + used + 2 * sbz));
+                used += 3 * sbz;
+                nl.push_back(nl_of(d2));
+                const int64_t m2 = std::min(2 * m, b.n);
+                void *out = dbl ? (void *)b.psi : (void *)b.X;
+                sa.push_back(src_real(b.q, true, d2, (int)d2, 0, m2, -1, b.d));
+                sb.push_back(src_real(out, dbl, d2, (int)d2, 0, m));
+                du.push_back(dst_real(out, dbl, d2, (int)d2, m, m2, 1.0 / (double)L, OP_STORE, -1,
+                                      dbl ? status_of(h) : nullptr));
+                lo.push_back(m);
+                hi.push_back(m2);
+                GemmProblem<T> x{};
+                x.A = SA.back(); x.B = SB.back(); x.C = ST.back(); x.d = b.d;
+                g1.push_back(x);
+                GemmProblem<T> y{};
+                y.A = SB.back(); y.B = ST.back(); y.C = SA.back(); y.d = b.d;
+                g2.push_back(y);
+            }
+            spec_max = std::max(spec_max, used);
+            plan_fwd<T>(bp, h, p, SA, nl, sa);
+            plan_fwd<T>(bp, h, p, SB, nl, sb);
+            plan_gemm<T>(bp, h, p, g1);
+            plan_remask<T>(bp, h, p, ST, nl, lo, hi, true);
+            plan_gemm<T>(bp, h, p, g2);
+            plan_inv<T>(bp, h, p, SA, nl, du);
+        }
+    }
+}
+
+static void plan_sweeps(BatchPlan &bp, mrinv_handle_t h, std::vector<BatchProblem> &P, char *spec, size_t &spec_max) {
+    // Group by the residual length 2^ceil(log2(2n-1)).
+    std::vector<int> lgs;
+    for (auto &b : P) lgs.push_back(lg_full(b.n));
+    std::vector<int> uniq = lgs;
+    std::sort(uniq.begin(), uniq.end());
+    uniq.erase(std::unique(uniq.begin(), uniq.end()), uniq.end());
+    for (int lg : uniq) {
+        const FftPlan p = make_plan(lg);
+        const double invL = 1.0 / (double)((int64_t)1 << lg);
+        std::vector<int> grp;
+        std::vector<size_t> need;
+        for (int i = 0; i < (int)P.size(); ++i)
+            if (lgs[i] == lg) {
+                grp.push_back(i);
+                need.push_back(3 * spec_bytes(lg, (int64_t)P[i].d * P[i].d, true));
+            }
+        for (auto &sub : split_by_cap(grp, need)) {
+            for (int sweep = 0; sweep < MIXED_SWEEPS; ++sweep) {
+                const bool last = sweep == MIXED_SWEEPS - 1;
+                std::vector<cplx<double> *> A64, B64, T64;
+                std::vector<cplx<float> *> A32, B32, T32;
+                std::vector<int> nl;
+                std::vector<SrcDesc> sq, sx, sr;
+                std::vector<DstDesc> dr, dx;
+                std::vector<GemmProblem<double>> g64;
+                std::vector<GemmProblem<float>> g32;
+                size_t used = 0, used32 = 0;
+                for (int i : sub) {
+                    const BatchProblem &b = P[i];
+                    const int64_t d2 = (int64_t)b.d * b.d;
+                    const size_t s64 = spec_bytes(lg, d2, true), s32 = spec_bytes(lg, d2, false);
+                    A64.push_back((cplx<double> *)(spec + used));
+                    B64.push_back((cplx<double> *)(spec + used + s64));
+                    T64.push_back((cplx<double> *)(spec + used + 2 * s64));
+                    used += 3 * s64;
+                    A32.push_back((cplx<float> *)(spec + used32));
+                    B32.push_back((cplx<float> *)(spec + used32 + s32));
+                    T32.push_back((cplx<float> *)(spec + used32 + 2 * s32));
+                    used32 += 3 * s32;
+                    nl.push_back(nl_of(d2));
+                    sq.push_back(src_real(b.q, true, d2, (int)d2, 0, b.n, -1, b.d));
+                    sx.push_back(src_real(b.X, false, d2, (int)d2, 0, b.n));
+                    sr.push_back(src_real(b.R, false, d2, (int)d2, 0, b.n));
+                    DstDesc r = dst_real(b.R, false, d2, (int)d2, 0, b.n, invL, OP_E0MINUS);
+                    r.e0_d = b.d;
+                    dr.push_back(r);
+                    DstDesc x = last ? dst_real(b.psi, true, d2, (int)d2, 0, b.n, invL, OP_XPLUS, -1, status_of(h))
+                                     : dst_real(b.X, false, d2, (int)d2, 0, b.n, invL, OP_XPLUS);
+                    x.aux = b.X;
+                    dx.push_back(x);
+                    GemmProblem<double> u{};
+                    u.A = A64.back(); u.B = B64.back(); u.C = T64.back(); u.d = b.d;
+                    g64.push_back(u);
+                    GemmProblem<float> w{};
+                    w.A = A32.back(); w.B = B32.back(); w.C = T32.back(); w.d = b.d;
+                    g32.push_back(w);
+                }
+                spec_max = std::max(spec_max, used);
+                plan_fwd<double>(bp, h, p, A64, nl, sq);
+                plan_fwd<double>(bp, h, p, B64, nl, sx);
+                plan_gemm<double>(bp, h, p, g64);
+                plan_inv<double>(bp, h, p, T64, nl, dr);
+                plan_fwd<float>(bp, h, p, A32, nl, sx);
+                plan_fwd<float>(bp, h, p, B32, nl, sr);
+                plan_gemm<float>(bp, h, p, g32);
+                plan_inv<float>(bp, h, p, T32, nl, dx);
+            }
+        }
+    }
+}
+
+// Builds the whole schedule for a workspace at `ws` (nullptr: sizing only).
+static mrinv_status_t plan_batched(mrinv_handle_t h, int count, const double *const *q_ptrs, const int *d,
+                                   const int64_t *n, mrinv_precision_t prec, double *const *psi_ptrs, char *ws,
+                                   BatchPlan &bp) {
+    if (count < 1 || !d || !n) return fail(MRINV_E_ARG, "bad batch");
+    if (prec != MRINV_FP64 && prec != MRINV_MIXED_FP32) return fail(MRINV_E_ARG, "unknown precision");
+    std::vector<BatchProblem> P(count);
+    for (int b = 0; b < count; ++b) {
+        CHECK(check_dn(d[b], n[b]));
+        P[b].q = q_ptrs ? q_ptrs[b] : nullptr;
+        P[b].psi = psi_ptrs ? psi_ptrs[b] : nullptr;
+        P[b].d = d[b];
+        P[b].n = n[b];
+    }
+    // Pass 1 sizes the table; pass 2 fills it with final addresses.
+    const bool mixed = prec == MRINV_MIXED_FP32;
+    size_t xr = 0;
+    if (mixed)
+        for (auto &b : P) xr += align256((size_t)b.n * b.d * b.d * sizeof(float));
+    for (int round = 0; round < 2; ++round) {
+        const size_t table_guess = round == 0 ? 0 : bp.table_bytes;
+        BatchPlan cur;
+        char *base = ws ? ws : nullptr;
+        const size_t x_off = align256(table_guess), r_off = x_off + xr, spec_off = r_off + xr;
+        size_t xo = 0;
+        for (auto &b : P) {
+            if (mixed) {
+                b.X = (float *)((base ? base : (char *)0) + x_off + xo);
+                b.R = (float *)((base ? base : (char *)0) + r_off + xo);
+                xo += align256((size_t)b.n * b.d * b.d * sizeof(float));
+            }
+        }
+        char *spec = (base ? base : (char *)0) + spec_off;
+        size_t spec_max = 0;
+        // Seeds for every problem in one launch.
+        std::vector<GjProblem> gj(count);
+        int dmax = 0;
+        for (int b = 0; b < count; ++b) {
+            gj[b].A0 = P[b].q;
+            gj[b].d = P[b].d;
+            gj[b].e0_minus = 1;
+            gj[b].out64 = mixed ? nullptr : P[b].psi;
+            gj[b].out32 = mixed ? P[b].X : nullptr;
+            dmax = std::max(dmax, P[b].d);
+        }
+        const size_t goff = cur.put(gj);
+        {
+            unsigned int *status = status_of(h);
+            hipStream_t st = stream_of(h);
+            const int cnt = count;
+            cur.launches.push_back([=](char *tb) {
+                return gj_inverse_batched((const GjProblem *)(tb + goff), cnt, dmax, status, st);
+            });
+        }
+        if (mixed) {
+            plan_newton<float>(cur, h, P, spec, spec_max);
+            plan_sweeps(cur, h, P, spec, spec_max);
+        } else {
+            plan_newton<double>(cur, h, P, spec, spec_max);
+        }
+        cur.table_bytes = align256(cur.table.size());
+        if (round == 0) {
+            bp.table_bytes = cur.table_bytes;
+            continue;
+        }
+        cur.x_off = x_off;
+        cur.r_off = r_off;
+        cur.spec_off = spec_off;
+        cur.spec_bytes = spec_max;
+        cur.total = spec_off + spec_max;
+        bp = std::move(cur);
+    }
+    return MRINV_OK;
+}
+
 extern "C" size_t mrinv_batched_workspace_size(int count, const int *d, const int64_t *n, mrinv_precision_t prec) {
     if (count < 1 || !d || !n) return 0;
-    size_t mx = 0;
-    for (int b = 0; b < count; ++b) {
-        const size_t w = mrinv_workspace_size(MRINV_OP_PSI_INVERSE, d[b], n[b], 0, prec);
-        if (!w) return 0;
-        mx = std::max(mx, w);
-    }
-    return mx;
+    BatchPlan bp;
+    if (plan_batched(nullptr, count, nullptr, d, n, prec, nullptr, nullptr, bp) != MRINV_OK) return 0;
+    return bp.total;
 }
 
 extern "C" mrinv_status_t mrinv_psi_inverse_batched(mrinv_handle_t h, int count, const double *const *q_ptrs,
@@ -838,8 +1200,28 @@ extern "C" mrinv_status_t mrinv_psi_inverse_batched(mrinv_handle_t h, int count,
                                                     double *const *psi_ptrs, void *ws, size_t wsb) {
     TimerScope _ts(h);
     if (!h || count < 1 || !q_ptrs || !d || !n || !psi_ptrs) return fail(MRINV_E_ARG, "NULL handle or pointer");
-    for (int b = 0; b < count; ++b) {
-        CHECK(mrinv_psi_inverse(h, q_ptrs[b], d[b], n[b], precision, psi_ptrs[b], ws, wsb));
+    for (int b = 0; b < count; ++b)
+        if (!q_ptrs[b] || !psi_ptrs[b]) return fail(MRINV_E_ARG, "NULL problem pointer %d", b);
+    BatchPlan bp;
+    CHECK(plan_batched(h, count, q_ptrs, d, n, precision, psi_ptrs, (char *)ws, bp));
+    CHECK(check_ws(ws, wsb, bp.total));
+    // Stage the descriptor table through pinned host memory (reused across calls;
+    // the previous transfer is waited for before the buffer is rewritten).
+    if (h->pinned_bytes < bp.table.size()) {
+        if (h->pinned) {
+            (void)hipEventSynchronize(h->pinned_done);
+            (void)hipHostFree(h->pinned);
+        }
+        h->pinned = nullptr;
+        h->pinned_bytes = 0;
+        HIP_TRY(hipHostMalloc(&h->pinned, bp.table.size()));
+        h->pinned_bytes = bp.table.size();
+    } else if (h->pinned) {
+        HIP_TRY(hipEventSynchronize(h->pinned_done));
     }
+    memcpy(h->pinned, bp.table.data(), bp.table.size());
+    HIP_TRY(hipMemcpyAsync(ws, h->pinned, bp.table.size(), hipMemcpyHostToDevice, h->stream));
+    HIP_TRY(hipEventRecord(h->pinned_done, h->stream));
+    for (auto &launch : bp.launches) HIP_TRY(launch((char *)ws));
     return MRINV_OK;
 }

@@ -12,8 +12,8 @@ namespace mrinv {
 // at or below d * 2^-53 * max|A(0)| marks A(0) singular (Theorem 2.1: the
 // sequence is invertible iff A(0) is) and the output becomes NaN.
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(64) gj_kernel(const double *A0, int d, int e0_minus, double *out64, float *out32,
-                                                unsigned int *status) {
+__device__ __forceinline__ void gj_body(const double *A0, int d, int e0_minus, double *out64, float *out32,
+                                        unsigned int *status) {
     // One wavefront; lane r owns row r of W = [A(0) | I] (kept in LDS).
     extern __shared__ __align__(16) unsigned char smem_raw[];
     double *W = reinterpret_cast<double *>(smem_raw);   // [d][2d]
@@ -72,6 +72,24 @@ __global__ void __launch_bounds__(64) gj_kernel(const double *A0, int d, int e0_
         if (out64) out64[idx] = v;
         if (out32) out32[idx] = (float)v;
     }
+}
+
+__global__ void __launch_bounds__(64) gj_kernel(const double *A0, int d, int e0_minus, double *out64, float *out32,
+                                                unsigned int *status) {
+    gj_body(A0, d, e0_minus, out64, out32, status);
+}
+
+__global__ void __launch_bounds__(64) gj_batched_kernel(const GjProblem *probs, unsigned int *status) {
+    const GjProblem &p = probs[blockIdx.x];
+    gj_body(p.A0, p.d, p.e0_minus, p.out64, p.out32, status);
+}
+
+hipError_t gj_inverse_batched(const GjProblem *probs, int nprob, int dmax, unsigned int *status, hipStream_t st) {
+    const size_t lds = (size_t)dmax * 2 * dmax * sizeof(double);
+    launch_begin("gj_batched_kernel", (double)nprob * dmax * dmax * 16.0, 2.0 * nprob * dmax * dmax * dmax);
+    hipLaunchKernelGGL(gj_batched_kernel, dim3(nprob), dim3(64), lds, st, probs, status);
+    launch_end();
+    return hipGetLastError();
 }
 
 hipError_t gj_inverse(const double *A0, int d, int e0_minus, double *out64, float *out32, unsigned int *status,

@@ -163,23 +163,23 @@ __device__ __forceinline__ void store_real(const DstDesc &d, int64_t t, int lane
 // MODE 0: forward pass; MODE 1: inverse pass; MODE 2: inverse pass, then the
 // mask/scale/negate of `dst` (rows outside [lo, hi) become zero), then the
 // forward pass of the same geometry, in place.
+// The body of one pass for one column of one problem.
 template <typename T, int LGP, int C, int MODE>
-__global__ void __launch_bounds__(C << (LGP - min_stage_lg(LGP)))
-fft_pass_kernel(cplx<T> *z, PassGeom g, SrcDesc src, DstDesc dst, Twiddles<T> tw) {
+__device__ __forceinline__ void fft_pass_body(cplx<T> *z, const PassGeom &g, int nl, int nchunks, int64_t blk,
+                                              const SrcDesc &src, const DstDesc &dst, const Twiddles<T> &tw) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cplx<T> *lds = reinterpret_cast<cplx<T> *>(smem_raw);
     constexpr int LDS_STRIDE = C + 1;
     const int c = threadIdx.x % C;
     const int grp = threadIdx.x / C;
-    const int chunk = blockIdx.x % g.nchunks;
-    const int64_t col = blockIdx.x / g.nchunks;
+    const int chunk = (int)(blk % nchunks);
+    const int64_t col = blk / nchunks;
     const int64_t S = g.S;
     const int64_t b = col >> (g.lgB - LGP);          // S = 2^(lgB - LGP)
     const uint32_t m = (uint32_t)(col & (S - 1));
     const int64_t base = b * ((int64_t)1 << g.lgB) + m;
     const int lane = chunk * C + c;
-    const bool lane_ok = lane < g.nl;
-    const int nl = g.nl;
+    const bool lane_ok = lane < nl;
 
     // Forward twiddle on output r: W_B^{m r}; inverse on input r: W_B^{-m r}.
     auto fwd_store = [&](int idx, cplx<T> v) {
@@ -223,6 +223,27 @@ fft_pass_kernel(cplx<T> *z, PassGeom g, SrcDesc src, DstDesc dst, Twiddles<T> tw
         auto lds_load = [&](int idx) { return lds[idx * LDS_STRIDE + c]; };
         wg_fft<T, LGP, false>(lds, LDS_STRIDE, c, grp, lds_load, fwd_store, true, false, tw);
     }
+}
+
+template <typename T, int LGP, int C, int MODE>
+__global__ void __launch_bounds__(C << (LGP - min_stage_lg(LGP)))
+fft_pass_kernel(cplx<T> *z, PassGeom g, SrcDesc src, DstDesc dst, Twiddles<T> tw) {
+    fft_pass_body<T, LGP, C, MODE>(z, g, g.nl, g.nchunks, blockIdx.x, src, dst, tw);
+}
+
+// Batched: the workgroup's problem is found by binary search over wg_begin.
+template <typename T, int LGP, int C, int MODE>
+__global__ void __launch_bounds__(C << (LGP - min_stage_lg(LGP)))
+fft_pass_batched_kernel(const PassProblem<T> *probs, int nprob, PassGeom g, Twiddles<T> tw) {
+    int lo = 0, hi = nprob - 1;
+    const int64_t bid = blockIdx.x;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (probs[mid].wg_begin <= bid) lo = mid;
+        else hi = mid - 1;
+    }
+    const PassProblem<T> &pp = probs[lo];
+    fft_pass_body<T, LGP, C, MODE>(pp.z, g, pp.nl, pp.nchunks, bid - pp.wg_begin, pp.src, pp.dst, tw);
 }
 
 // ---------------------------------------------------------------------------
@@ -326,6 +347,92 @@ hipError_t fft_pass(int mode, const FftPlan &plan, int pass, int nl, cplx<T> *z,
         default: return launch_pass_m<T, 2>(lgP, C, z, g, src, dst, tw, st);
     }
 }
+
+template <typename T, int LGP, int C, int MODE>
+static hipError_t launch_batched_t(const PassProblem<T> *probs, int nprob, int64_t total, const PassGeom &g,
+                                   double bytes, const Twiddles<T> &tw, hipStream_t st) {
+    const int threads = C << (LGP - min_stage_lg(LGP));
+    const size_t lds = (num_stages(LGP) > 1 || MODE == 2) ? ((size_t)1 << LGP) * (C + 1) * sizeof(cplx<T>) : 0;
+    auto kern = fft_pass_batched_kernel<T, LGP, C, MODE>;
+    static bool attr_set = false;
+    if (!attr_set && lds > 64 * 1024) {
+        (void)hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        (void)hipGetLastError();
+        attr_set = true;
+    }
+    char name[96];
+    snprintf(name, sizeof name, "fft_pass_batched_kernel<%s, %d, %d, %d>", sizeof(T) == 8 ? "double" : "float", LGP,
+             C, MODE);
+    launch_begin(name, bytes, 0.0);
+    hipLaunchKernelGGL(kern, dim3((unsigned)total), dim3(threads), lds, st, probs, nprob, g, tw);
+    launch_end();
+    return hipGetLastError();
+}
+
+template <typename T, int C, int MODE>
+static hipError_t launch_batched_c(int lgP, const PassProblem<T> *probs, int nprob, int64_t total,
+                                   const PassGeom &g, double bytes, const Twiddles<T> &tw, hipStream_t st) {
+    switch (lgP) {
+        case 1: return launch_batched_t<T, 1, C, MODE>(probs, nprob, total, g, bytes, tw, st);
+        case 2: return launch_batched_t<T, 2, C, MODE>(probs, nprob, total, g, bytes, tw, st);
+        case 3: return launch_batched_t<T, 3, C, MODE>(probs, nprob, total, g, bytes, tw, st);
+        case 4: return launch_batched_t<T, 4, C, MODE>(probs, nprob, total, g, bytes, tw, st);
+        case 5: return launch_batched_t<T, 5, C, MODE>(probs, nprob, total, g, bytes, tw, st);
+        case 6: return launch_batched_t<T, 6, C, MODE>(probs, nprob, total, g, bytes, tw, st);
+        case 7: return launch_batched_t<T, 7, C, MODE>(probs, nprob, total, g, bytes, tw, st);
+        case 8: return launch_batched_t<T, 8, C, MODE>(probs, nprob, total, g, bytes, tw, st);
+        case 9: return launch_batched_t<T, 9, C, MODE>(probs, nprob, total, g, bytes, tw, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+static PassGeom pass_geom(const FftPlan &plan, int pass) {
+    PassGeom g{};
+    g.L = (int64_t)1 << plan.lgL;
+    int lgB = plan.lgL;
+    for (int j = 0; j < pass; ++j) lgB -= plan.lgP[j];
+    g.lgB = lgB;
+    g.S = (int64_t)1 << (lgB - plan.lgP[pass]);
+    return g;
+}
+
+template <typename T>
+int64_t fft_batch_layout(const FftPlan &plan, int pass, PassProblem<T> *probs, int nprob, int C) {
+    const int64_t cols = ((int64_t)1 << plan.lgL) >> plan.lgP[pass];
+    int64_t acc = 0;
+    for (int i = 0; i < nprob; ++i) {
+        probs[i].nchunks = (probs[i].nl + C - 1) / C;
+        probs[i].wg_begin = acc;
+        acc += cols * probs[i].nchunks;
+    }
+    return acc;
+}
+
+template <typename T>
+hipError_t fft_pass_batched(int mode, const FftPlan &plan, int pass, int C, const PassProblem<T> *probs, int nprob,
+                            int64_t total, double bytes, const Twiddles<T> &tw, hipStream_t st) {
+    const PassGeom g = pass_geom(plan, pass);
+    const int lgP = plan.lgP[pass];
+    switch (mode * 100 + C) {
+        case 2: return launch_batched_c<T, 2, 0>(lgP, probs, nprob, total, g, bytes, tw, st);
+        case 8: return launch_batched_c<T, 8, 0>(lgP, probs, nprob, total, g, bytes, tw, st);
+        case 16: return launch_batched_c<T, 16, 0>(lgP, probs, nprob, total, g, bytes, tw, st);
+        case 102: return launch_batched_c<T, 2, 1>(lgP, probs, nprob, total, g, bytes, tw, st);
+        case 108: return launch_batched_c<T, 8, 1>(lgP, probs, nprob, total, g, bytes, tw, st);
+        case 116: return launch_batched_c<T, 16, 1>(lgP, probs, nprob, total, g, bytes, tw, st);
+        case 202: return launch_batched_c<T, 2, 2>(lgP, probs, nprob, total, g, bytes, tw, st);
+        case 208: return launch_batched_c<T, 8, 2>(lgP, probs, nprob, total, g, bytes, tw, st);
+        case 216: return launch_batched_c<T, 16, 2>(lgP, probs, nprob, total, g, bytes, tw, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template int64_t fft_batch_layout<double>(const FftPlan &, int, PassProblem<double> *, int, int);
+template int64_t fft_batch_layout<float>(const FftPlan &, int, PassProblem<float> *, int, int);
+template hipError_t fft_pass_batched<double>(int, const FftPlan &, int, int, const PassProblem<double> *, int,
+                                             int64_t, double, const Twiddles<double> &, hipStream_t);
+template hipError_t fft_pass_batched<float>(int, const FftPlan &, int, int, const PassProblem<float> *, int,
+                                            int64_t, double, const Twiddles<float> &, hipStream_t);
 
 template hipError_t fft_pass<double>(int, const FftPlan &, int, int, cplx<double> *, const SrcDesc &,
                                      const DstDesc &, const Twiddles<double> &, hipStream_t);

@@ -205,9 +205,9 @@ template <int DP> struct SqCfg {
 };
 
 template <typename T, int DP>
-__global__ void __launch_bounds__(SqCfg<DP>::THREADS)
-freq_gemm_sq_kernel(const cplx<T> *__restrict__ ZA, const cplx<T> *__restrict__ ZB, cplx<T> *__restrict__ ZC,
-                    FftPlan plan, int d) {
+__device__ __forceinline__ void freq_gemm_sq_body(const cplx<T> *__restrict__ ZA, const cplx<T> *__restrict__ ZB,
+                                                  cplx<T> *__restrict__ ZC, const FftPlan &plan, int d,
+                                                  int64_t blk) {
     using Cfg = SqCfg<DP>;
     constexpr int TM = Cfg::TM, TN = Cfg::TN, NF = Cfg::NF, KC = Cfg::KC, NT = Cfg::THREADS;
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -216,7 +216,7 @@ freq_gemm_sq_kernel(const cplx<T> *__restrict__ ZA, const cplx<T> *__restrict__ 
     __shared__ int64_t rows1[NF], rows2[NF];
     const int64_t L = (int64_t)1 << plan.lgL;
     const int64_t F = L / 2 + 1;
-    const int64_t k0 = (int64_t)blockIdx.x * NF;
+    const int64_t k0 = blk * NF;
     const int tid = threadIdx.x;
     const int nl = (d * d + 1) >> 1;
     if (tid < NF) {
@@ -308,12 +308,99 @@ freq_gemm_sq_kernel(const cplx<T> *__restrict__ ZA, const cplx<T> *__restrict__ 
 }
 
 template <typename T, int DP>
+__global__ void __launch_bounds__(SqCfg<DP>::THREADS)
+freq_gemm_sq_kernel(const cplx<T> *__restrict__ ZA, const cplx<T> *__restrict__ ZB, cplx<T> *__restrict__ ZC,
+                    FftPlan plan, int d) {
+    freq_gemm_sq_body<T, DP>(ZA, ZB, ZC, plan, d, blockIdx.x);
+}
+
+template <typename T, int DP>
+__global__ void __launch_bounds__(SqCfg<DP>::THREADS)
+freq_gemm_sq_batched_kernel(const GemmProblem<T> *probs, int nprob, FftPlan plan) {
+    int lo = 0, hi = nprob - 1;
+    const int64_t bid = blockIdx.x;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (probs[mid].wg_begin <= bid) lo = mid;
+        else hi = mid - 1;
+    }
+    const GemmProblem<T> &pp = probs[lo];
+    freq_gemm_sq_body<T, DP>(pp.A, pp.B, pp.C, plan, pp.d, bid - pp.wg_begin);
+}
+
+template <typename T, int DP>
+static size_t sq_lds_bytes(int dmax_odd) {
+    using Cfg = SqCfg<DP>;
+    size_t lds = (size_t)(Cfg::AS + Cfg::BS) * sizeof(cplx<T>);
+    const size_t cs = (size_t)Cfg::NF * (dmax_odd * dmax_odd + 1) * sizeof(cplx<T>);
+    return cs > lds ? cs : lds;
+}
+
+template <typename T, int DP>
+static hipError_t launch_gemm_sq_batched(const FftPlan &plan, const GemmProblem<T> *probs, int nprob, int64_t total,
+                                         double bytes, double flops, hipStream_t st) {
+    using Cfg = SqCfg<DP>;
+    const size_t lds = sq_lds_bytes<T, DP>(DP - 1);
+    char name[96];
+    snprintf(name, sizeof name, "freq_gemm_sq_batched_kernel<%s, %d>", sizeof(T) == 8 ? "double" : "float", DP);
+    launch_begin(name, bytes, flops);
+    hipLaunchKernelGGL((freq_gemm_sq_batched_kernel<T, DP>), dim3((unsigned)total), dim3(Cfg::THREADS), lds, st,
+                       probs, nprob, plan);
+    launch_end();
+    return hipGetLastError();
+}
+
+int gemm_sq_class(int d) { return (d + 7) / 8; }
+
+template <typename T>
+int64_t gemm_batch_layout(const FftPlan &plan, GemmProblem<T> *probs, int nprob) {
+    const int64_t F = ((int64_t)1 << plan.lgL) / 2 + 1;
+    int64_t acc = 0;
+    for (int i = 0; i < nprob; ++i) {
+        int nf = 1;
+        switch (gemm_sq_class(probs[i].d)) {
+            case 1: nf = SqCfg<8>::NF; break;
+            case 2: nf = SqCfg<16>::NF; break;
+            case 3: nf = SqCfg<24>::NF; break;
+            case 4: nf = SqCfg<32>::NF; break;
+            case 5: nf = SqCfg<40>::NF; break;
+            case 6: nf = SqCfg<48>::NF; break;
+            case 7: nf = SqCfg<56>::NF; break;
+            default: nf = SqCfg<64>::NF; break;
+        }
+        probs[i].wg_begin = acc;
+        acc += (F + nf - 1) / nf;
+    }
+    return acc;
+}
+
+template <typename T>
+hipError_t freq_gemm_batched(const FftPlan &plan, int dclass, const GemmProblem<T> *probs, int nprob, int64_t total,
+                             double bytes, double flops, hipStream_t st) {
+    switch (dclass) {
+        case 1: return launch_gemm_sq_batched<T, 8>(plan, probs, nprob, total, bytes, flops, st);
+        case 2: return launch_gemm_sq_batched<T, 16>(plan, probs, nprob, total, bytes, flops, st);
+        case 3: return launch_gemm_sq_batched<T, 24>(plan, probs, nprob, total, bytes, flops, st);
+        case 4: return launch_gemm_sq_batched<T, 32>(plan, probs, nprob, total, bytes, flops, st);
+        case 5: return launch_gemm_sq_batched<T, 40>(plan, probs, nprob, total, bytes, flops, st);
+        case 6: return launch_gemm_sq_batched<T, 48>(plan, probs, nprob, total, bytes, flops, st);
+        case 7: return launch_gemm_sq_batched<T, 56>(plan, probs, nprob, total, bytes, flops, st);
+        default: return launch_gemm_sq_batched<T, 64>(plan, probs, nprob, total, bytes, flops, st);
+    }
+}
+
+template int64_t gemm_batch_layout<double>(const FftPlan &, GemmProblem<double> *, int);
+template int64_t gemm_batch_layout<float>(const FftPlan &, GemmProblem<float> *, int);
+template hipError_t freq_gemm_batched<double>(const FftPlan &, int, const GemmProblem<double> *, int, int64_t,
+                                              double, double, hipStream_t);
+template hipError_t freq_gemm_batched<float>(const FftPlan &, int, const GemmProblem<float> *, int, int64_t, double,
+                                             double, hipStream_t);
+
+template <typename T, int DP>
 static hipError_t launch_gemm_sq(const FftPlan &plan, int d, const cplx<T> *ZA, const cplx<T> *ZB, cplx<T> *ZC,
                                  hipStream_t st) {
     using Cfg = SqCfg<DP>;
-    size_t lds = (size_t)(Cfg::AS + Cfg::BS) * sizeof(cplx<T>);
-    const size_t cs = (size_t)Cfg::NF * (d * d + 1) * sizeof(cplx<T>);
-    if ((d & 1) && cs > lds) lds = cs;
+    const size_t lds = sq_lds_bytes<T, DP>((d & 1) ? d : 0);
     const int64_t F = ((int64_t)1 << plan.lgL) / 2 + 1;
     const int64_t blocks = (F + Cfg::NF - 1) / Cfg::NF;
     char name[96];

@@ -76,6 +76,36 @@ struct DstDesc {
     unsigned int *status;  // optional: set STATUS_NONFINITE on non-finite output
 };
 
+// One problem of a batched pass launch: its spectrum buffer, lane count and
+// (for the first / last pass) real source and destination.  Workgroups
+// [wg_begin, wg_begin + nchunks * L / P) of the launch belong to it.
+template <typename T> struct PassProblem {
+    cplx<T> *z;
+    int nl;
+    int nchunks;
+    int64_t wg_begin;
+    SrcDesc src;
+    DstDesc dst;
+};
+
+// One problem of a batched square product launch.
+template <typename T> struct GemmProblem {
+    const cplx<T> *A;
+    const cplx<T> *B;
+    cplx<T> *C;
+    int d;
+    int64_t wg_begin;
+};
+
+// One problem of a batched Gauss-Jordan launch (one workgroup each).
+struct GjProblem {
+    const double *A0;
+    double *out64;
+    float *out32;
+    int d;
+    int e0_minus;
+};
+
 inline SrcDesc src_z() { SrcDesc s{}; s.kind = SRC_Z; s.rev = -1; return s; }
 inline DstDesc dst_z() { DstDesc d{}; d.kind = DST_Z; d.rev = -1; d.scale = 1.0; return d; }
 
@@ -85,6 +115,14 @@ int fft_lanes_per_block(bool dbl, int nl);
 template <typename T>
 hipError_t fft_pass(int mode, const FftPlan &plan, int pass, int nl, cplx<T> *z, const SrcDesc &src,
                     const DstDesc &dst, const Twiddles<T> &tw, hipStream_t st);
+// The same pass over many problems in one launch.  probs is a device array of
+// nprob descriptors with wg_begin filled by fft_batch_layout; every problem
+// uses C lanes per workgroup.  Returns the total workgroup count via *total.
+template <typename T>
+int64_t fft_batch_layout(const FftPlan &plan, int pass, PassProblem<T> *host_probs, int nprob, int C);
+template <typename T>
+hipError_t fft_pass_batched(int mode, const FftPlan &plan, int pass, int C, const PassProblem<T> *dev_probs,
+                            int nprob, int64_t total_wg, double bytes, const Twiddles<T> &tw, hipStream_t st);
 
 // Frequency-domain products.  Spectra are packed (two real lanes per complex
 // lane) in the digit-reversed order of `plan`.
@@ -96,6 +134,14 @@ struct GemmDesc {
 template <typename T>
 hipError_t freq_gemm(const FftPlan &plan, const GemmDesc &g, const cplx<T> *ZA, const cplx<T> *ZB, cplx<T> *ZC,
                      hipStream_t st);
+// Square products of many problems with the same padded dimension class
+// (d rounded up to a multiple of 8) in one launch.
+int gemm_sq_class(int d);
+template <typename T>
+int64_t gemm_batch_layout(const FftPlan &plan, GemmProblem<T> *host_probs, int nprob);
+template <typename T>
+hipError_t freq_gemm_batched(const FftPlan &plan, int dclass, const GemmProblem<T> *dev_probs, int nprob,
+                             int64_t total_wg, double bytes, double flops, hipStream_t st);
 // C = A * diag(h): A ra x cb, h has cb lanes.
 template <typename T>
 hipError_t freq_diag(const FftPlan &plan, int ra, int cb, const cplx<T> *ZA, const cplx<T> *ZH, cplx<T> *ZC,
@@ -109,6 +155,9 @@ hipError_t freq_coldot(const FftPlan &plan, int ra, int cb, const cplx<T> *ZA, c
 // of out (float64 and/or float32 copies, either may be null).
 hipError_t gj_inverse(const double *A0, int d, int e0_minus, double *out64, float *out32, unsigned int *status,
                       hipStream_t st);
+
+hipError_t gj_inverse_batched(const GjProblem *dev_probs, int nprob, int dmax, unsigned int *status,
+                              hipStream_t st);
 
 hipError_t survival(const double *q, int d, int64_t n, double *hb, hipStream_t st);
 hipError_t contract(const double *X, int64_t n, int rows, int cols, const double *u, const double *v,

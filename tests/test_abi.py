@@ -70,3 +70,19 @@ def test_product_does_not_import_the_oracle():
             if f.endswith((".py", ".hip", ".h", ".cpp")):
                 text = open(os.path.join(dirpath, f), errors="replace").read()
                 assert "import oracle" not in text and "from oracle" not in text and "liborc" not in text, f
+
+
+def test_batched_workspace_query_without_a_handle(L):
+    """The batched planner also sizes the workspace without a handle or GPU."""
+    import ctypes
+    import smk_inputs as si
+    w = si.batch_workload()
+    d = (ctypes.c_int * 512)(*[x["d"] for x in w])
+    n = (ctypes.c_int64 * 512)(*[x["n"] for x in w])
+    L.mrinv_batched_workspace_size.restype = ctypes.c_size_t
+    fp64 = L.mrinv_batched_workspace_size(512, d, n, 0)
+    mixed = L.mrinv_batched_workspace_size(512, d, n, 1)
+    assert 0 < fp64 < mixed < (96 << 30)
+    bad = (ctypes.c_int * 1)(65)
+    one = (ctypes.c_int64 * 1)(10)
+    assert L.mrinv_batched_workspace_size(1, bad, one, 0) == 0

@@ -297,3 +297,22 @@ def test_deterministic_reruns(mr):
     b = mr.psi_inverse(q)
     torch.cuda.synchronize()
     assert torch.equal(a, b)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_batched_matches_single_calls_and_oracle(mr, orc, precision):
+    """Uneven batch (odd and even d, ragged n, n = 1): each problem equals the
+    single-problem call (same kernels, same plans) and the oracle."""
+    specs = [(1, 5), (2, 1), (3, 37), (5, 300), (8, 1000), (16, 513), (17, 64), (31, 200), (33, 129), (48, 70),
+             (4, 2048), (6, 3000)]
+    qs = [si.family_kernel("weibull" if i % 2 else "lognormal", d, n, 300 + i).q.cuda()
+          for i, (d, n) in enumerate(specs)]
+    outs = mr.psi_inverse_batched(qs, precision)
+    mr.sync_status()
+    tol = FP64_TOL if precision == "fp64" else MIXED_TOL
+    for (d, n), q, o in zip(specs, qs, outs):
+        single = mr.psi_inverse(q, precision)
+        torch.cuda.synchronize()
+        assert torch.equal(o, single), (d, n)
+        ref = orc.psi(q[: min(n, 600)].cpu().numpy())
+        assert _maxerr(_np(o[: min(n, 600)]), ref) <= tol, (d, n)

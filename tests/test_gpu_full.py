@@ -205,3 +205,31 @@ def test_c5_full_size_gradients_vs_central_differences(mr):
         an = float(sum((g * v).sum() for g, v in zip(grads, dirs)))
         print(f"[c5] trial {trial}: adjoint {an:.10e} fd {fd:.10e} rel {abs(an - fd) / abs(an):.2e}", flush=True)
         assert abs(an - fd) <= 1e-5 * abs(an)
+
+
+def test_c4_batched_uneven_workload(mr, orc):
+    """512 problems, d uniform in 3..48, n log-uniform in [1024, 32768],
+    Weibull or lognormal by coin flip (master seed 4), mixed form in one
+    batched call.  32 sampled problems against the oracle on a prefix, 8 of
+    them bitwise against the single-problem call, and for all 512 the
+    invariants psi >= 0 and substochastic rows (k >= 1)."""
+    work = si.batch_workload(si.CONFIG_SEEDS["c4"], 512)
+    print("[c4] generating", flush=True)
+    qs = [si.family_kernel(w["family"], w["d"], w["n"], w["seed"], device="cuda").q for w in work]
+    print("[c4] batched inversion", flush=True)
+    outs = mr.psi_inverse_batched(qs, "mixed")
+    mr.sync_status()
+    rng = np.random.default_rng(4)
+    sample = rng.choice(len(work), 32, replace=False)
+    for j, b in enumerate(sample):
+        q, o = qs[b], outs[b]
+        npre = 256 if work[b]["d"] > 32 else 512
+        ref = orc.psi(q[:npre].cpu().numpy())
+        assert _maxerr(_np(o[:npre]), ref) <= 1e-10, work[b]
+        if j < 8:
+            single = mr.psi_inverse(q, "mixed")
+            torch.cuda.synchronize()
+            assert torch.equal(single, o), work[b]
+    for w, o in zip(work, outs):
+        assert float(o.min()) >= -1e-12, w
+        assert float(o[1:].sum(dim=2).max()) <= 1 + 1e-10, w
