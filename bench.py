@@ -189,6 +189,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true", help="skip the accuracy checks against the oracle")
     ap.add_argument("--forms", default="fp64,mixed", help="comma-separated forms to time (value form first)")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run one 1 GiB device-to-device copy first (reference for HBM counter runs)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -209,6 +211,13 @@ def main():
     print(f"[bench] config {args.config}: d={d} n={n} {cfg['family']}", file=sys.stderr, flush=True)
     q = si.family_kernel(cfg["family"], d, n, cfg["seed"], device=dev).q
     torch.cuda.synchronize()
+    if args.calibrate_copy:
+        # A plain copy of known size: 1 GiB read + 1 GiB written.
+        src = torch.ones(1 << 27, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     forms = [f for f in args.forms.split(",") if f]
     if cfg["form"] not in forms:

@@ -226,6 +226,34 @@ size_t mrinv_batched_workspace_size(int count, const int *d, const int64_t *n,
 mrinv_status_t mrinv_residual_norms(mrinv_handle_t h, const double *q, const double *X, int d,
                                     int64_t n, double *out, void *ws, size_t ws_bytes);
 
+/* Launch-shape and schedule choices of a handle.  Defaults come from
+ * mrinv_create; mrinv_autotune measures alternatives on a given problem and
+ * keeps the fastest.  None of them changes what is computed. */
+typedef struct {
+    int lgp_max;        /* largest FFT pass radix exponent, 5..9 (default 9: passes of <= 512 rows) */
+    int lanes_fp64;     /* complex lanes per FFT workgroup in float64: 8 or 16 (default 16) */
+    int lanes_fp32;     /* complex lanes per FFT workgroup in float32: 8 or 16 (default 16) */
+    int seed_m0;        /* coefficients formed by the coefficient recursion (Section 2.2) before
+                           Newton starts; rounded down to a power of two, 1..256 (default 16) */
+    int pair_forward;   /* nonzero: forward transforms of both Newton operands in one launch (default 1) */
+    int twiddle_tables; /* 0: every twiddle is a product of two table entries formed on the fly;
+                           1: in-workgroup twiddles from a 512-root table; 2: also per-pass outer
+                           twiddle tables built in the workspace (default 1).  Values are identical. */
+    int block_order;    /* FFT workgroup order: 0 = the lane chunks of one column together,
+                           1 = columns first, spreading concurrent accesses over more memory (default 1) */
+} mrinv_tuning_t;
+
+mrinv_status_t mrinv_get_tuning(mrinv_handle_t h, mrinv_tuning_t *out);
+mrinv_status_t mrinv_set_tuning(mrinv_handle_t h, const mrinv_tuning_t *t);
+
+/* Time mrinv_psi_inverse on q (device [n][d][d]) under a set of candidate
+ * tunings (pass radix cap, lanes per workgroup, recursion seed length), keep
+ * the fastest in the handle and report it in *chosen (may be NULL).  psi
+ * receives the result; ws as for mrinv_psi_inverse.  Synchronises. */
+mrinv_status_t mrinv_autotune(mrinv_handle_t h, const double *q, int d, int64_t n,
+                              mrinv_precision_t precision, double *psi, void *ws, size_t ws_bytes,
+                              mrinv_tuning_t *chosen);
+
 /* Per-kernel timing, a profiling aid that is off by default.  While enabled,
  * every kernel launch of the library is bracketed by HIP events on the
  * handle's stream and tagged with the algorithmic bytes (one read of each

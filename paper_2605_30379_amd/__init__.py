@@ -31,7 +31,7 @@ __all__ = [
     "gather_block", "psi_inverse_backward", "markov_renewal_apply_backward", "transition_backward",
     "contract_backward", "scatter_block_add", "psi_inverse_batched", "residual_norms", "sync_status",
     "PsiInverse", "RenewalApply", "Transition", "Contract", "GatherBlock", "workspace_size",
-    "FP64", "MIXED_FP32", "OPS",
+    "FP64", "MIXED_FP32", "OPS", "Tuning", "get_tuning", "set_tuning", "autotune",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -45,6 +45,16 @@ OPS = {"psi_inverse": 0, "apply": 1, "transition": 2, "psi_backward": 3, "apply_
 
 _STATUS = {0: "ok", 1: "invalid argument", 2: "A(0) singular", 3: "non-finite value",
            4: "workspace too small", 5: "unsupported size", 6: "HIP runtime error"}
+
+
+class Tuning(ctypes.Structure):
+    """Launch-shape and schedule choices of a handle (mrinv_tuning_t)."""
+    _fields_ = [("lgp_max", ctypes.c_int), ("lanes_fp64", ctypes.c_int), ("lanes_fp32", ctypes.c_int),
+                ("seed_m0", ctypes.c_int), ("pair_forward", ctypes.c_int), ("twiddle_tables", ctypes.c_int),
+                ("block_order", ctypes.c_int)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
 
 
 class MrinvError(RuntimeError):
@@ -99,6 +109,9 @@ def lib():
                                                 ctypes.POINTER(vp), vp, sz]),
             "mrinv_batched_workspace_size": (sz, [i32, ip, ctypes.POINTER(i64), i32]),
             "mrinv_residual_norms": (i32, [vp, vp, vp, i32, i64, dp, vp, sz]),
+            "mrinv_get_tuning": (i32, [vp, ctypes.POINTER(Tuning)]),
+            "mrinv_set_tuning": (i32, [vp, ctypes.POINTER(Tuning)]),
+            "mrinv_autotune": (i32, [vp, vp, i32, i64, i32, vp, vp, sz, ctypes.POINTER(Tuning)]),
         }
         for name, (res, args) in sigs.items():
             fn = getattr(L, name)
@@ -153,6 +166,37 @@ def _ws(nbytes: int, device) -> torch.Tensor:
 
 def workspace_size(op: str, d: int, n: int, r: int = 0, precision="fp64") -> int:
     return int(lib().mrinv_workspace_size(OPS[op], d, n, r, _PREC[precision]))
+
+
+def get_tuning(device=None) -> dict:
+    dev = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+    t = Tuning()
+    _check(lib().mrinv_get_tuning(_handle(dev), ctypes.byref(t)))
+    return t.as_dict()
+
+
+def set_tuning(device=None, **kw):
+    """Change tuning fields (lgp_max, lanes_fp64, lanes_fp32, seed_m0, pair_forward)."""
+    dev = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+    t = Tuning()
+    h = _handle(dev)
+    _check(lib().mrinv_get_tuning(h, ctypes.byref(t)))
+    for k, v in kw.items():
+        setattr(t, k, int(v))
+    _check(lib().mrinv_set_tuning(h, ctypes.byref(t)))
+
+
+def autotune(q: torch.Tensor, precision="fp64") -> dict:
+    """Measure candidate tunings on q, keep the fastest in the device's handle."""
+    q = _seq(q, "q")
+    n, d, _ = q.shape
+    prec = _PREC[precision]
+    out = torch.empty_like(q)
+    ws = _ws(lib().mrinv_workspace_size(0, d, n, 0, prec), q.device)
+    t = Tuning()
+    _check(lib().mrinv_autotune(_handle(q.device), _ptr(q), d, n, prec, _ptr(out), _ptr(ws), ws.numel(),
+                                ctypes.byref(t)))
+    return t.as_dict()
 
 
 def sync_status(device=None):

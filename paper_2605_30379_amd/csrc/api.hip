@@ -51,11 +51,12 @@ struct mrinv_handle_s {
     double *scratch = nullptr;      // small per-handle scratch (index lists, vectors, 1-lane scans)
     void *timer = nullptr;          // launch timing records (mrinv_set_timing)
     bool timing = false;
+    mrinv_tuning_t tune{9, 16, 16, 16, 1, 1, 0};
     void *pinned = nullptr;         // pinned staging buffer of batched descriptor tables
     size_t pinned_bytes = 0;
     hipEvent_t pinned_done = nullptr;   // recorded after the last transfer out of `pinned`
-    Twiddles<double> t64() const { return {tw64, tw64 + TW_HI_SIZE}; }
-    Twiddles<float> t32() const { return {tw64, tw64 + TW_HI_SIZE}; }
+    Twiddles<double> t64() const { return {tw64, tw64 + TW_HI_SIZE, tw64 + TW_HI_SIZE + TW_LO_SIZE, nullptr}; }
+    Twiddles<float> t32() const { return {tw64, tw64 + TW_HI_SIZE, tw64 + TW_HI_SIZE + TW_LO_SIZE, nullptr}; }
 };
 
 static void host_twiddles(std::vector<double2> &hi, std::vector<double2> &lo) {
@@ -81,7 +82,10 @@ extern "C" mrinv_status_t mrinv_create(mrinv_handle_t *handle, void *stream) {
     HIP_TRY(hipGetDevice(&h->device));
     std::vector<double2> hi, lo;
     host_twiddles(hi, lo);
-    const size_t n64 = (TW_HI_SIZE + TW_LO_SIZE) * sizeof(double2);
+    const size_t n64 = (TW_HI_SIZE + TW_LO_SIZE + 512) * sizeof(double2);
+    // 512th roots W_512^j = W_{2^22}^{j 2^13} = hi[4j] (the lo factor is 1).
+    std::vector<double2> root(512);
+    for (int j = 0; j < 512; ++j) root[j] = hi[4 * j];
     if (hipMalloc((void **)&h->tw64, n64) != hipSuccess ||
         hipMalloc((void **)&h->status, 256) != hipSuccess ||
         hipMalloc((void **)&h->scratch, SCRATCH_BYTES) != hipSuccess) {
@@ -90,6 +94,7 @@ extern "C" mrinv_status_t mrinv_create(mrinv_handle_t *handle, void *stream) {
     }
     HIP_TRY(hipMemcpy(h->tw64, hi.data(), TW_HI_SIZE * sizeof(double2), hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(h->tw64 + TW_HI_SIZE, lo.data(), TW_LO_SIZE * sizeof(double2), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(h->tw64 + TW_HI_SIZE + TW_LO_SIZE, root.data(), 512 * sizeof(double2), hipMemcpyHostToDevice));
     HIP_TRY(hipMemset(h->status, 0, 256));
     HIP_TRY(hipEventCreateWithFlags(&h->pinned_done, hipEventDisableTiming));
     HIP_TRY(hipDeviceSynchronize());
@@ -181,10 +186,10 @@ static int ceil_log2(int64_t x) {
 // Transform length of a product truncated at n whose operands have n terms.
 static int lg_full(int64_t n) { return std::max(1, ceil_log2(2 * n - 1)); }
 
-static FftPlan make_plan(int lgL) {
+static FftPlan make_plan(int lgL, int lgp_max = LGP_MAX) {
     FftPlan p{};
     p.lgL = lgL;
-    p.npass = (lgL + LGP_MAX - 1) / LGP_MAX;
+    p.npass = (lgL + lgp_max - 1) / lgp_max;
     if (p.npass < 1) p.npass = 1;
     int rem = lgL;
     for (int j = 0; j < p.npass; ++j) {
@@ -213,13 +218,22 @@ struct Carve {
     }
 };
 
+// Outer-twiddle tables of all Newton steps up to 2^lgN plus, for the mixed
+// form, the sweep length 2^lg2 in both precisions (bounds valid for every
+// pass split: tables of one plan hold at most 1.1 L entries).
+static size_t ws_twiddles(int lgN, int lg2, mrinv_precision_t prec) {
+    const size_t L = (size_t)1 << lgN;
+    if (prec == MRINV_FP64) return align256(3 * L * 16) + 4096;
+    return align256(3 * L * 8) + align256(2 * ((size_t)1 << lg2) * 16) + align256(2 * ((size_t)1 << lg2) * 8) + 4096;
+}
+
 static size_t ws_psi(int d, int64_t n, mrinv_precision_t prec) {
     const int64_t d2 = (int64_t)d * d;
     const int lgN = std::max(1, ceil_log2(n));
-    if (prec == MRINV_FP64) return 3 * spec_bytes(lgN, d2, true);
     const int lg2 = lg_full(n);
+    if (prec == MRINV_FP64) return 3 * spec_bytes(lgN, d2, true) + ws_twiddles(lgN, lg2, prec);
     size_t spec = std::max(3 * spec_bytes(lgN, d2, false), 3 * spec_bytes(lg2, d2, true));
-    return spec + 2 * align256((size_t)n * d2 * sizeof(float));
+    return spec + 2 * align256((size_t)n * d2 * sizeof(float)) + ws_twiddles(lgN, lg2, prec);
 }
 
 static size_t ws_apply(int d, int64_t n, int r) {
@@ -272,8 +286,18 @@ extern "C" size_t mrinv_workspace_size(mrinv_op_t op, int d, int64_t n, int r, m
 // Transform helpers
 // ---------------------------------------------------------------------------
 template <typename T> static Twiddles<T> tw_of(mrinv_handle_t h);
-template <> Twiddles<double> tw_of<double>(mrinv_handle_t h) { return h ? h->t64() : Twiddles<double>{}; }
-template <> Twiddles<float> tw_of<float>(mrinv_handle_t h) { return h ? h->t32() : Twiddles<float>{}; }
+template <> Twiddles<double> tw_of<double>(mrinv_handle_t h) {
+    if (!h) return Twiddles<double>{};
+    Twiddles<double> t = h->t64();
+    if (h->tune.twiddle_tables == 0) t.root = nullptr;
+    return t;
+}
+template <> Twiddles<float> tw_of<float>(mrinv_handle_t h) {
+    if (!h) return Twiddles<float>{};
+    Twiddles<float> t = h->t32();
+    if (h->tune.twiddle_tables == 0) t.root = nullptr;
+    return t;
+}
 
 static SrcDesc src_real(const void *p, bool dbl, int64_t ld, int nreal, int64_t lo, int64_t hi, int64_t rev = -1,
                         int e0_d = 0) {
@@ -305,12 +329,41 @@ static DstDesc dst_real(void *p, bool dbl, int64_t ld, int nreal, int64_t lo, in
     return d;
 }
 
+static int order_of(mrinv_handle_t h) { return h ? h->tune.block_order : 0; }
+template <typename T> static int lanes_of(mrinv_handle_t h) {
+    return h ? (sizeof(T) == 8 ? h->tune.lanes_fp64 : h->tune.lanes_fp32) : 0;
+}
+static FftPlan hplan(mrinv_handle_t h, int lgL) { return make_plan(lgL, h ? h->tune.lgp_max : LGP_MAX); }
+
 // Forward transform of a real source into Z (all passes).
 template <typename T>
 static hipError_t fwd(mrinv_handle_t h, const FftPlan &p, int nl, cplx<T> *Z, const SrcDesc &src) {
     const Twiddles<T> tw = tw_of<T>(h);
-    hipError_t e = fft_pass<T>(0, p, 0, nl, Z, src, dst_z(), tw, h->stream);
-    for (int j = 1; j < p.npass && e == hipSuccess; ++j) e = fft_pass<T>(0, p, j, nl, Z, src_z(), dst_z(), tw, h->stream);
+    const int ln = lanes_of<T>(h);
+    hipError_t e = fft_pass<T>(0, p, 0, nl, Z, src, dst_z(), tw, h->stream, ln, order_of(h));
+    for (int j = 1; j < p.npass && e == hipSuccess; ++j)
+        e = fft_pass<T>(0, p, j, nl, Z, src_z(), dst_z(), tw, h->stream, ln, order_of(h));
+    return e;
+}
+
+// Forward transforms of two real sources (same plan) into ZA and ZB; with
+// pair_forward each pass of both is one launch.
+template <typename T>
+static hipError_t fwd2(mrinv_handle_t h, const FftPlan &p, int nl, cplx<T> *ZA, const SrcDesc &sa, cplx<T> *ZB,
+                       const SrcDesc &sb) {
+    if (!h->tune.pair_forward) {
+        hipError_t e = fwd<T>(h, p, nl, ZA, sa);
+        return e == hipSuccess ? fwd<T>(h, p, nl, ZB, sb) : e;
+    }
+    const Twiddles<T> tw = tw_of<T>(h);
+    PassProblem<T> a{}, b{};
+    a.z = ZA; a.nl = nl; a.src = sa; a.dst = dst_z();
+    b.z = ZB; b.nl = nl; b.src = sb; b.dst = dst_z();
+    hipError_t e = fft_pass_pair<T>(p, 0, a, b, tw, h->stream, lanes_of<T>(h), order_of(h));
+    a.src = src_z();
+    b.src = src_z();
+    for (int j = 1; j < p.npass && e == hipSuccess; ++j)
+        e = fft_pass_pair<T>(p, j, a, b, tw, h->stream, lanes_of<T>(h), order_of(h));
     return e;
 }
 
@@ -318,9 +371,11 @@ static hipError_t fwd(mrinv_handle_t h, const FftPlan &p, int nl, cplx<T> *Z, co
 template <typename T>
 static hipError_t inv(mrinv_handle_t h, const FftPlan &p, int nl, cplx<T> *Z, const DstDesc &dst) {
     const Twiddles<T> tw = tw_of<T>(h);
+    const int ln = lanes_of<T>(h);
     hipError_t e = hipSuccess;
-    for (int j = p.npass - 1; j >= 1 && e == hipSuccess; --j) e = fft_pass<T>(1, p, j, nl, Z, src_z(), dst_z(), tw, h->stream);
-    if (e == hipSuccess) e = fft_pass<T>(1, p, 0, nl, Z, src_z(), dst, tw, h->stream);
+    for (int j = p.npass - 1; j >= 1 && e == hipSuccess; --j)
+        e = fft_pass<T>(1, p, j, nl, Z, src_z(), dst_z(), tw, h->stream, ln, order_of(h));
+    if (e == hipSuccess) e = fft_pass<T>(1, p, 0, nl, Z, src_z(), dst, tw, h->stream, ln, order_of(h));
     return e;
 }
 
@@ -329,15 +384,18 @@ static hipError_t inv(mrinv_handle_t h, const FftPlan &p, int nl, cplx<T> *Z, co
 template <typename T>
 static hipError_t remask(mrinv_handle_t h, const FftPlan &p, int nl, cplx<T> *Z, int64_t lo, int64_t hi, bool neg) {
     const Twiddles<T> tw = tw_of<T>(h);
+    const int ln = lanes_of<T>(h);
     hipError_t e = hipSuccess;
-    for (int j = p.npass - 1; j >= 1 && e == hipSuccess; --j) e = fft_pass<T>(1, p, j, nl, Z, src_z(), dst_z(), tw, h->stream);
+    for (int j = p.npass - 1; j >= 1 && e == hipSuccess; --j)
+        e = fft_pass<T>(1, p, j, nl, Z, src_z(), dst_z(), tw, h->stream, ln, order_of(h));
     DstDesc m = dst_z();
     m.lo = lo;
     m.hi = hi;
     m.op = neg ? OP_NEG : OP_STORE;
     m.scale = 1.0 / (double)((int64_t)1 << p.lgL);
-    if (e == hipSuccess) e = fft_pass<T>(2, p, 0, nl, Z, src_z(), m, tw, h->stream);
-    for (int j = 1; j < p.npass && e == hipSuccess; ++j) e = fft_pass<T>(0, p, j, nl, Z, src_z(), dst_z(), tw, h->stream);
+    if (e == hipSuccess) e = fft_pass<T>(2, p, 0, nl, Z, src_z(), m, tw, h->stream, ln, order_of(h));
+    for (int j = 1; j < p.npass && e == hipSuccess; ++j)
+        e = fft_pass<T>(0, p, j, nl, Z, src_z(), dst_z(), tw, h->stream, ln, order_of(h));
     return e;
 }
 
@@ -354,6 +412,35 @@ static GemmDesc gdesc(int ra, int m, int cb, int ta = 0, int tb = 0) {
     return g;
 }
 
+// Length of the recursion seed: the largest power of two <= min(seed_m0, n).
+static int64_t seed_len(mrinv_handle_t h, int64_t n) {
+    const int64_t cap = std::min<int64_t>(h ? h->tune.seed_m0 : 16, n);
+    int64_t m0 = 1;
+    while (2 * m0 <= cap) m0 *= 2;
+    return m0;
+}
+
+// Register the outer-twiddle tables of plan p (every pass but the last,
+// whose column offset is always 0) in g, carving them from region.
+static void add_tables(TwGen &g, FftPlan &p, bool dbl, char *&region, char *end) {
+    int lgB = p.lgL;
+    for (int j = 0; j < p.npass; ++j) {
+        const size_t bytes = align256(((size_t)1 << lgB) * (dbl ? 16 : 8));
+        if (j < p.npass - 1 && g.count < MAX_TW_TABLES && region + bytes <= end) {
+            g.begin[g.count] = g.total;
+            g.dst[g.count] = region;
+            g.lgB[g.count] = lgB;
+            g.lgP[g.count] = p.lgP[j];
+            g.dbl[g.count] = dbl ? 1 : 0;
+            g.total += (int64_t)1 << lgB;
+            g.count++;
+            p.outer[j] = region;
+            region += bytes;
+        }
+        lgB -= p.lgP[j];
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Newton inversion (eq. (newton)) in precision T.  src is A (e0 == 0) or q
 // (e0 == 1, A = e0 - q); the result's coefficients are written to out
@@ -365,18 +452,31 @@ static GemmDesc gdesc(int ra, int m, int cb, int ta = 0, int tb = 0) {
 // ---------------------------------------------------------------------------
 template <typename T>
 static mrinv_status_t newton(mrinv_handle_t h, const double *src, int e0, int d, int64_t n, void *out,
-                             cplx<T> *SA, cplx<T> *SB, cplx<T> *ST) {
+                             cplx<T> *SA, cplx<T> *SB, cplx<T> *ST, char *twr, char *twr_end) {
     const bool dbl = sizeof(T) == 8;
     const int d2 = d * d;
     const int nl = nl_of(d2);
     HIP_TRY(gj_inverse(src, d, e0, dbl ? (double *)out : nullptr, dbl ? nullptr : (float *)out, h->status, h->stream));
+    // The first m0 coefficients by the coefficient recursion (one launch),
+    // then Newton doubling from m0.
+    const int64_t m0 = seed_len(h, n);
+    if (m0 > 1) HIP_TRY(seed_recursion<T>(src, e0, d, (int)m0, (T *)out, h->stream));
     const GemmDesc g = gdesc(d, d, d);
-    for (int64_t m = 1; m < n;) {
+    // Plans of every step and their outer-twiddle tables (one launch).
+    std::vector<FftPlan> plans;
+    TwGen tg{};
+    for (int64_t m = m0; m < n; m = std::min(2 * m, n)) {
+        plans.push_back(hplan(h, ceil_log2(std::min(2 * m, n))));
+        if (twr && h->tune.twiddle_tables >= 2) add_tables(tg, plans.back(), dbl, twr, twr_end);
+    }
+    HIP_TRY(gen_outer_twiddles(tg, h->tw64, h->tw64 + TW_HI_SIZE, h->stream));
+    size_t step = 0;
+    for (int64_t m = m0; m < n;) {
         const int64_t m2 = std::min(2 * m, n);
-        const FftPlan p = make_plan(ceil_log2(m2));
+        const FftPlan p = plans[step++];
         const double invL = 1.0 / (double)((int64_t)1 << p.lgL);
-        HIP_TRY(fwd<T>(h, p, nl, SA, src_real(src, true, d2, d2, 0, m2, -1, e0 ? d : 0)));
-        HIP_TRY(fwd<T>(h, p, nl, SB, src_real(out, dbl, d2, d2, 0, m)));
+        HIP_TRY(fwd2<T>(h, p, nl, SA, src_real(src, true, d2, d2, 0, m2, -1, e0 ? d : 0), SB,
+                        src_real(out, dbl, d2, d2, 0, m)));
         HIP_TRY(freq_gemm<T>(p, g, SA, SB, ST, h->stream));
         HIP_TRY(remask<T>(h, p, nl, ST, m, m2, true));
         HIP_TRY(freq_gemm<T>(p, g, SB, ST, SA, h->stream));
@@ -423,12 +523,15 @@ static mrinv_status_t inverse_impl(mrinv_handle_t h, const double *src, int e0, 
     const int nl = nl_of(d2);
     const int lgN = std::max(1, ceil_log2(n));
     Carve cv(ws);
+    const size_t twb = ws_twiddles(lgN, lg_full(n), prec);
+    char *twr = cv.take<char>(twb);
+    char *twr_end = twr + twb;
     if (prec == MRINV_FP64) {
         const size_t sb = spec_bytes(lgN, d2, true);
         auto *SA = cv.take<cplx<double>>(sb);
         auto *SB = cv.take<cplx<double>>(sb);
         auto *ST = cv.take<cplx<double>>(sb);
-        return newton<double>(h, src, e0, d, n, out, SA, SB, ST);
+        return newton<double>(h, src, e0, d, n, out, SA, SB, ST, twr, twr_end);
     }
     // Mixed: float32 Newton into X, then one sweep with a float64 residual.
     float *X = cv.take<float>((size_t)n * d2 * sizeof(float));
@@ -439,9 +542,21 @@ static mrinv_status_t inverse_impl(mrinv_handle_t h, const double *src, int e0, 
         auto *SA = (cplx<float> *)spec;
         auto *SB = (cplx<float> *)(spec + sb);
         auto *ST = (cplx<float> *)(spec + 2 * sb);
-        CHECK(newton<float>(h, src, e0, d, n, X, SA, SB, ST));
+        CHECK(newton<float>(h, src, e0, d, n, X, SA, SB, ST, twr, twr_end));
     }
-    const FftPlan p2 = make_plan(lg_full(n));
+    // The sweep plan in both precisions, each with its own outer tables
+    // (carved after the Newton tables, which newton() left in the region).
+    FftPlan p2 = hplan(h, lg_full(n));
+    FftPlan p2f = p2;
+    {
+        char *r2 = twr + align256(3 * ((size_t)1 << lgN) * 8);
+        TwGen tg{};
+        if (h->tune.twiddle_tables >= 2) {
+            add_tables(tg, p2, true, r2, twr_end);
+            add_tables(tg, p2f, false, r2, twr_end);
+        }
+        HIP_TRY(gen_outer_twiddles(tg, h->tw64, h->tw64 + TW_HI_SIZE, h->stream));
+    }
     const double invL = 1.0 / (double)((int64_t)1 << p2.lgL);
     const GemmDesc g = gdesc(d, d, d);
     for (int sweep = 0; sweep < MIXED_SWEEPS; ++sweep) {
@@ -452,8 +567,8 @@ static mrinv_status_t inverse_impl(mrinv_handle_t h, const double *src, int e0, 
             auto *SA = (cplx<double> *)spec;
             auto *SB = (cplx<double> *)(spec + sb);
             auto *ST = (cplx<double> *)(spec + 2 * sb);
-            HIP_TRY(fwd<double>(h, p2, nl, SA, src_real(src, true, d2, d2, 0, n, -1, e0 ? d : 0)));
-            HIP_TRY(fwd<double>(h, p2, nl, SB, src_real(X, false, d2, d2, 0, n)));
+            HIP_TRY(fwd2<double>(h, p2, nl, SA, src_real(src, true, d2, d2, 0, n, -1, e0 ? d : 0), SB,
+                                 src_real(X, false, d2, d2, 0, n)));
             HIP_TRY(freq_gemm<double>(p2, g, SA, SB, ST, h->stream));
             DstDesc dr = dst_real(R, false, d2, d2, 0, n, invL, OP_E0MINUS);
             dr.e0_d = d;
@@ -466,13 +581,12 @@ static mrinv_status_t inverse_impl(mrinv_handle_t h, const double *src, int e0, 
             auto *SA = (cplx<float> *)spec;
             auto *SB = (cplx<float> *)(spec + sb);
             auto *ST = (cplx<float> *)(spec + 2 * sb);
-            HIP_TRY(fwd<float>(h, p2, nl, SA, src_real(X, false, d2, d2, 0, n)));
-            HIP_TRY(fwd<float>(h, p2, nl, SB, src_real(R, false, d2, d2, 0, n)));
-            HIP_TRY(freq_gemm<float>(p2, g, SA, SB, ST, h->stream));
+            HIP_TRY(fwd2<float>(h, p2f, nl, SA, src_real(X, false, d2, d2, 0, n), SB, src_real(R, false, d2, d2, 0, n)));
+            HIP_TRY(freq_gemm<float>(p2f, g, SA, SB, ST, h->stream));
             DstDesc dx = last ? dst_real(out, true, d2, d2, 0, n, invL, OP_XPLUS, -1, h->status)
                               : dst_real(X, false, d2, d2, 0, n, invL, OP_XPLUS);
             dx.aux = X;
-            HIP_TRY(inv<float>(h, p2, nl, ST, dx));
+            HIP_TRY(inv<float>(h, p2f, nl, ST, dx));
         }
     }
     return MRINV_OK;
@@ -492,6 +606,90 @@ extern "C" mrinv_status_t mrinv_series_inverse(mrinv_handle_t h, const double *A
 }
 
 // ---------------------------------------------------------------------------
+// Tuning and autotuning
+// ---------------------------------------------------------------------------
+static mrinv_status_t check_tuning(const mrinv_tuning_t &t) {
+    if (t.lgp_max < 5 || t.lgp_max > LGP_MAX) return fail(MRINV_E_ARG, "lgp_max %d not in 5..%d", t.lgp_max, LGP_MAX);
+    if (t.lanes_fp64 != 8 && t.lanes_fp64 != 16 && t.lanes_fp64 != 32)
+        return fail(MRINV_E_ARG, "lanes_fp64 must be 8, 16 or 32");
+    if (t.lanes_fp32 != 8 && t.lanes_fp32 != 16 && t.lanes_fp32 != 32)
+        return fail(MRINV_E_ARG, "lanes_fp32 must be 8, 16 or 32");
+    if (t.seed_m0 < 1 || t.seed_m0 > 256) return fail(MRINV_E_ARG, "seed_m0 %d not in 1..256", t.seed_m0);
+    if (t.twiddle_tables < 0 || t.twiddle_tables > 2) return fail(MRINV_E_ARG, "twiddle_tables must be 0, 1 or 2");
+    if (t.block_order < 0 || t.block_order > 1) return fail(MRINV_E_ARG, "block_order must be 0 or 1");
+    return MRINV_OK;
+}
+
+extern "C" mrinv_status_t mrinv_get_tuning(mrinv_handle_t h, mrinv_tuning_t *out) {
+    if (!h || !out) return fail(MRINV_E_ARG, "NULL handle or pointer");
+    *out = h->tune;
+    return MRINV_OK;
+}
+
+extern "C" mrinv_status_t mrinv_set_tuning(mrinv_handle_t h, const mrinv_tuning_t *t) {
+    if (!h || !t) return fail(MRINV_E_ARG, "NULL handle or pointer");
+    CHECK(check_tuning(*t));
+    h->tune = *t;
+    return MRINV_OK;
+}
+
+// Milliseconds per inversion under the handle's current tuning.
+static mrinv_status_t time_inverse(mrinv_handle_t h, const double *q, int d, int64_t n, mrinv_precision_t prec,
+                                   double *psi, void *ws, size_t wsb, int reps, float *ms) {
+    hipEvent_t a, b;
+    HIP_TRY(hipEventCreate(&a));
+    HIP_TRY(hipEventCreate(&b));
+    mrinv_status_t st = inverse_impl(h, q, 1, d, n, prec, psi, ws, wsb);
+    if (st == MRINV_OK) (void)hipEventRecord(a, h->stream);
+    for (int r = 0; r < reps && st == MRINV_OK; ++r) st = inverse_impl(h, q, 1, d, n, prec, psi, ws, wsb);
+    if (st == MRINV_OK) {
+        (void)hipEventRecord(b, h->stream);
+        (void)hipEventSynchronize(b);
+        float t = 0.f;
+        (void)hipEventElapsedTime(&t, a, b);
+        *ms = t / reps;
+    }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    return st;
+}
+
+extern "C" mrinv_status_t mrinv_autotune(mrinv_handle_t h, const double *q, int d, int64_t n,
+                                         mrinv_precision_t precision, double *psi, void *ws, size_t wsb,
+                                         mrinv_tuning_t *chosen) {
+    if (!h || !q || !psi) return fail(MRINV_E_ARG, "NULL handle or pointer");
+    CHECK(check_dn(d, n));
+    CHECK(check_ws(ws, wsb, ws_psi(d, n, precision)));
+    // Coordinate search from the current tuning: one knob at a time.
+    mrinv_tuning_t best = h->tune;
+    float best_ms = 0.f;
+    h->tune = best;
+    CHECK(time_inverse(h, q, d, n, precision, psi, ws, wsb, 3, &best_ms));
+    auto trial = [&](mrinv_tuning_t t) -> mrinv_status_t {
+        if (check_tuning(t) != MRINV_OK) return MRINV_OK;
+        h->tune = t;
+        float ms = 0.f;
+        mrinv_status_t st = time_inverse(h, q, d, n, precision, psi, ws, wsb, 3, &ms);
+        if (st != MRINV_OK) return st;
+        if (ms < best_ms) { best_ms = ms; best = t; }
+        return MRINV_OK;
+    };
+    for (int v : {7, 8, 9}) { mrinv_tuning_t t = best; t.lgp_max = v; CHECK(trial(t)); }
+    for (int v : {8, 16}) { mrinv_tuning_t t = best; t.lanes_fp64 = v; CHECK(trial(t)); }
+    if (precision != MRINV_FP64)
+        for (int v : {8, 16}) { mrinv_tuning_t t = best; t.lanes_fp32 = v; CHECK(trial(t)); }
+    for (int v : {1, 16, 32, 64, 128}) { mrinv_tuning_t t = best; t.seed_m0 = v; CHECK(trial(t)); }
+    for (int v : {0, 1}) { mrinv_tuning_t t = best; t.pair_forward = v; CHECK(trial(t)); }
+    for (int v : {0, 1, 2}) { mrinv_tuning_t t = best; t.twiddle_tables = v; CHECK(trial(t)); }
+    for (int v : {0, 1}) { mrinv_tuning_t t = best; t.block_order = v; CHECK(trial(t)); }
+    h->tune = best;
+    CHECK(inverse_impl(h, q, 1, d, n, precision, psi, ws, wsb));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    if (chosen) *chosen = best;
+    return MRINV_OK;
+}
+
+// ---------------------------------------------------------------------------
 // Products with psi
 // ---------------------------------------------------------------------------
 extern "C" mrinv_status_t mrinv_markov_renewal_apply(mrinv_handle_t h, const double *psi, int d, int64_t n,
@@ -501,7 +699,7 @@ extern "C" mrinv_status_t mrinv_markov_renewal_apply(mrinv_handle_t h, const dou
     CHECK(check_dn(d, n));
     if (r < 1 || r > MRINV_MAX_D) return fail(r < 1 ? MRINV_E_ARG : MRINV_E_UNSUPPORTED, "bad r=%d", r);
     CHECK(check_ws(ws, wsb, ws_apply(d, n, r)));
-    const FftPlan p = make_plan(lg_full(n));
+    const FftPlan p = hplan(h, lg_full(n));
     const int64_t d2 = (int64_t)d * d, dr = (int64_t)d * r;
     Carve cv(ws);
     auto *SP = cv.take<cplx<double>>(spec_bytes(p.lgL, d2, true));
@@ -529,7 +727,7 @@ extern "C" mrinv_status_t mrinv_transition(mrinv_handle_t h, const double *psi, 
     if (!h || !psi || !q || !P) return fail(MRINV_E_ARG, "NULL handle or pointer");
     CHECK(check_dn(d, n));
     CHECK(check_ws(ws, wsb, ws_transition(d, n)));
-    const FftPlan p = make_plan(lg_full(n));
+    const FftPlan p = hplan(h, lg_full(n));
     const int64_t d2 = (int64_t)d * d;
     Carve cv(ws);
     double *hb = cv.take<double>((size_t)n * d * sizeof(double));
@@ -700,7 +898,7 @@ extern "C" mrinv_status_t mrinv_psi_inverse_backward(mrinv_handle_t h, const dou
     if (!h || !psi || !psi_bar || !q_bar) return fail(MRINV_E_ARG, "NULL handle or pointer");
     CHECK(check_dn(d, n));
     CHECK(check_ws(ws, wsb, ws_psi_backward(d, n)));
-    const FftPlan p = make_plan(lg_full(n));
+    const FftPlan p = hplan(h, lg_full(n));
     const int64_t d2 = (int64_t)d * d;
     const int nl = nl_of(d2);
     Carve cv(ws);
@@ -729,7 +927,7 @@ extern "C" mrinv_status_t mrinv_markov_renewal_apply_backward(mrinv_handle_t h, 
     CHECK(check_dn(d, n));
     if (r < 1 || r > MRINV_MAX_D) return fail(r < 1 ? MRINV_E_ARG : MRINV_E_UNSUPPORTED, "bad r=%d", r);
     CHECK(check_ws(ws, wsb, ws_apply_backward(d, n, r)));
-    const FftPlan p = make_plan(lg_full(n));
+    const FftPlan p = hplan(h, lg_full(n));
     const int64_t d2 = (int64_t)d * d, dr = (int64_t)d * r;
     Carve cv(ws);
     auto *SP = cv.take<cplx<double>>(spec_bytes(p.lgL, d2, true));
@@ -760,7 +958,7 @@ extern "C" mrinv_status_t mrinv_transition_backward(mrinv_handle_t h, const doub
     if (!h || !psi || !q || !P_bar) return fail(MRINV_E_ARG, "NULL handle or pointer");
     CHECK(check_dn(d, n));
     CHECK(check_ws(ws, wsb, ws_transition_backward(d, n)));
-    const FftPlan p = make_plan(lg_full(n));
+    const FftPlan p = hplan(h, lg_full(n));
     const int64_t d2 = (int64_t)d * d;
     Carve cv(ws);
     double *hb = cv.take<double>((size_t)n * d * 8);
@@ -794,7 +992,7 @@ extern "C" mrinv_status_t mrinv_residual_norms(mrinv_handle_t h, const double *q
     TimerScope _ts(h);
     if (!h || !q || !X || !out) return fail(MRINV_E_ARG, "NULL handle or pointer");
     CHECK(check_dn(d, n));
-    const FftPlan p = make_plan(lg_full(n));
+    const FftPlan p = hplan(h, lg_full(n));
     const int64_t d2 = (int64_t)d * d;
     const int nl = nl_of(d2);
     const size_t need = 3 * spec_bytes(p.lgL, d2, true) + 2 * align256((size_t)n * d2 * 8);
@@ -988,13 +1186,41 @@ template <typename T>
 static void plan_newton(BatchPlan &bp, mrinv_handle_t h, std::vector<BatchProblem> &P, char *spec, size_t &spec_max) {
     const bool dbl = sizeof(T) == 8;
     const int64_t nmax = [&] { int64_t m = 0; for (auto &b : P) m = std::max(m, b.n); return m; }();
+    // Seeds: the first m0 coefficients of each problem by the recursion.
+    {
+        std::vector<SeedProblem> sp;
+        int cols = 0, dmax = 0, m0max = 0;
+        for (auto &b : P) {
+            const int64_t m0 = seed_len(h, b.n);
+            if (m0 <= 1) continue;
+            SeedProblem x{};
+            x.A = b.q;
+            x.out = dbl ? (void *)b.psi : (void *)b.X;
+            x.d = b.d;
+            x.m0 = (int)m0;
+            x.e0 = 1;
+            x.col_begin = cols;
+            cols += b.d;
+            dmax = std::max(dmax, b.d);
+            m0max = std::max(m0max, (int)m0);
+            sp.push_back(x);
+        }
+        if (!sp.empty()) {
+            const size_t off = bp.put(sp);
+            const int cnt = (int)sp.size();
+            hipStream_t st = stream_of(h);
+            bp.launches.push_back([=](char *base) {
+                return seed_recursion_batched<T>((const SeedProblem *)(base + off), cnt, cols, dmax, m0max, st);
+            });
+        }
+    }
     for (int64_t m = 1; m < nmax; m *= 2) {
-        const FftPlan p = make_plan(ceil_log2(2 * m));
+        const FftPlan p = hplan(h, ceil_log2(2 * m));
         const int64_t L = (int64_t)1 << p.lgL;
         std::vector<int> act;
         std::vector<size_t> need;
         for (int i = 0; i < (int)P.size(); ++i)
-            if (P[i].n > m) {
+            if (P[i].n > m && m >= seed_len(h, P[i].n)) {
                 act.push_back(i);
                 need.push_back(3 * spec_bytes(p.lgL, (int64_t)P[i].d * P[i].d, dbl));
             }
@@ -1049,7 +1275,7 @@ static void plan_sweeps(BatchPlan &bp, mrinv_handle_t h, std::vector<BatchProble
     std::sort(uniq.begin(), uniq.end());
     uniq.erase(std::unique(uniq.begin(), uniq.end()), uniq.end());
     for (int lg : uniq) {
-        const FftPlan p = make_plan(lg);
+        const FftPlan p = hplan(h, lg);
         const double invL = 1.0 / (double)((int64_t)1 << lg);
         std::vector<int> grp;
         std::vector<size_t> need;

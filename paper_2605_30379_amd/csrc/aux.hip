@@ -102,6 +102,109 @@ hipError_t gj_inverse(const double *A0, int d, int e0_minus, double *out64, floa
 }
 
 // ---------------------------------------------------------------------------
+// First coefficients by the coefficient recursion (Section 2.2): from the
+// order-k coefficient of A*X = e0,
+//     X(k) = -A(0)^-1 sum_{l=1..k} A(l) X(k-l),   k = 1..m0-1,
+// with X(0) = A(0)^-1 already in out row 0.  Column c of X depends only on
+// column c of earlier coefficients, so workgroup c computes column c; its
+// threads split (row, range of l) and the partial sums are reduced in LDS.
+// The sums are formed in float64 whatever the output type.
+// ---------------------------------------------------------------------------
+constexpr int SEED_THREADS = 256;
+
+template <typename T>
+__device__ __forceinline__ void seed_recursion_body(const double *A, int e0, int d, int m0, T *out, int c) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    double *xcol = reinterpret_cast<double *>(smem_raw);   // [m0][d] history of column c
+    double *a0 = xcol + (size_t)m0 * d;                      // [d][d] A(0)^-1
+    double *part = a0 + (size_t)d * d;                       // [chunks][d]
+    double *Ssum = part + (size_t)SEED_THREADS;              // [d]
+    const int tid = threadIdx.x;
+    const int chunks = SEED_THREADS / d;                     // d <= 64 -> at least 4
+    const int r = tid % d, ch = tid / d;
+    const size_t dd = (size_t)d * d;
+    for (int e = tid; e < d * d; e += SEED_THREADS) a0[e] = (double)out[e];
+    for (int i = tid; i < d; i += SEED_THREADS) xcol[i] = (double)out[(size_t)i * d + c];
+    __syncthreads();
+    for (int k = 1; k < m0; ++k) {
+        double s = 0.0;
+        if (ch < chunks) {
+            // l in [1, k], split into `chunks` interleaved ranges
+            for (int l = 1 + ch; l <= k; l += chunks) {
+                const double *Al = A + (size_t)l * dd + (size_t)r * d;
+                const double *xk = xcol + (size_t)(k - l) * d;
+                double acc = 0.0;
+                for (int t = 0; t < d; ++t) acc = fma(e0 ? -Al[t] : Al[t], xk[t], acc);
+                s += acc;
+            }
+            part[ch * d + r] = s;
+        }
+        __syncthreads();
+        if (tid < d) {
+            double tot = 0.0;
+            for (int q = 0; q < chunks; ++q) tot += part[q * d + tid];
+            Ssum[tid] = tot;
+        }
+        __syncthreads();
+        if (tid < d) {
+            double v = 0.0;
+            for (int u = 0; u < d; ++u) v = fma(a0[tid * d + u], Ssum[u], v);
+            v = -v;
+            xcol[(size_t)k * d + tid] = v;
+            out[(size_t)k * dd + (size_t)tid * d + c] = (T)v;
+        }
+        __syncthreads();
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(SEED_THREADS)
+seed_recursion_kernel(const double *A, int e0, int d, int m0, T *out) {
+    seed_recursion_body<T>(A, e0, d, m0, out, blockIdx.x);
+}
+
+// Batched: one workgroup per (problem, column); the problem is found by
+// binary search over col_begin.
+template <typename T>
+__global__ void __launch_bounds__(SEED_THREADS) seed_recursion_batched_kernel(const SeedProblem *probs, int nprob) {
+    int lo = 0, hi = nprob - 1;
+    const int bid = blockIdx.x;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (probs[mid].col_begin <= bid) lo = mid;
+        else hi = mid - 1;
+    }
+    const SeedProblem &p = probs[lo];
+    seed_recursion_body<T>(p.A, p.e0, p.d, p.m0, (T *)p.out, bid - p.col_begin);
+}
+
+template <typename T>
+hipError_t seed_recursion_batched(const SeedProblem *probs, int nprob, int total_cols, int dmax, int m0max,
+                                  hipStream_t st) {
+    const size_t lds = ((size_t)m0max * dmax + (size_t)dmax * dmax + SEED_THREADS + dmax) * sizeof(double);
+    launch_begin(sizeof(T) == 8 ? "seed_recursion_batched_kernel<double>" : "seed_recursion_batched_kernel<float>",
+                 0.0, 0.0);
+    hipLaunchKernelGGL(seed_recursion_batched_kernel<T>, dim3(total_cols), dim3(SEED_THREADS), lds, st, probs, nprob);
+    launch_end();
+    return hipGetLastError();
+}
+template hipError_t seed_recursion_batched<double>(const SeedProblem *, int, int, int, int, hipStream_t);
+template hipError_t seed_recursion_batched<float>(const SeedProblem *, int, int, int, int, hipStream_t);
+
+template <typename T>
+hipError_t seed_recursion(const double *A, int e0, int d, int m0, T *out, hipStream_t st) {
+    const size_t lds = ((size_t)m0 * d + (size_t)d * d + SEED_THREADS + d) * sizeof(double);
+    launch_begin(sizeof(T) == 8 ? "seed_recursion_kernel<double>" : "seed_recursion_kernel<float>",
+                 (double)m0 * d * d * 8.0 * 2, (double)m0 * m0 * d * d * d);
+    hipLaunchKernelGGL(seed_recursion_kernel<T>, dim3(d), dim3(SEED_THREADS), lds, st, A, e0, d, m0, out);
+    launch_end();
+    return hipGetLastError();
+}
+
+template hipError_t seed_recursion<double>(const double *, int, int, int, double *, hipStream_t);
+template hipError_t seed_recursion<float>(const double *, int, int, int, float *, hipStream_t);
+
+// ---------------------------------------------------------------------------
 // Inclusive scan over time of w lanes, Y[k][i] <- a + b * sum_{l<=k} Y[l][i]
 // (reverse != 0: sum over l >= k).  One workgroup per lane; each thread scans
 // a contiguous segment, segment totals are scanned in LDS.

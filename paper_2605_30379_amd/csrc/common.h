@@ -51,6 +51,8 @@ constexpr int TW_HI_SIZE = 1 << (TW_LG - TW_LO_BITS);
 template <typename T> struct Twiddles {
     const double2 *hi;
     const double2 *lo;
+    const double2 *root;   // W_512^j, j < 512 (the 512th roots, equal to hi[4j]); may be null
+    const void *outer;     // outer twiddles of the current pass, [m][kr] in precision T; may be null
 };
 
 // exp(-2 pi i * num / den) with den a power of two dividing TW_LMAX, num in [0, den).
@@ -58,6 +60,14 @@ template <typename T, bool INV>
 __device__ __forceinline__ cplx<T> twiddle(const Twiddles<T> &tw, uint32_t num, int lg_den) {
     uint32_t a = num << (TW_LG - lg_den);
     const double2 w = cmul<double>(tw.hi[a >> TW_LO_BITS], tw.lo[a & (TW_LO_SIZE - 1)]);
+    return mk<T>((T)w.x, INV ? -(T)w.y : (T)w.y);
+}
+
+// exp(-+2 pi i j / 2^lg) for lg <= 9 from the root table.
+template <typename T, bool INV>
+__device__ __forceinline__ cplx<T> root_twiddle(const Twiddles<T> &tw, uint32_t j, int lg) {
+    if (!tw.root) return twiddle<T, INV>(tw, j, lg);
+    const double2 w = tw.root[j << (9 - lg)];
     return mk<T>((T)w.x, INV ? -(T)w.y : (T)w.y);
 }
 

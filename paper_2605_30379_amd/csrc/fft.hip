@@ -56,7 +56,7 @@ __device__ __forceinline__ void fft_stage(int LGP, int lgNs, int grp, const Load
         for (int r = 0; r < R; ++r) v[r] = load(j + (r << (LGP - LGR)));
         if (lgNs > 0) {
 #pragma unroll
-            for (int r = 1; r < R; ++r) v[r] = cmul<T>(v[r], twiddle<T, INV>(tw, (uint32_t)(k0 * r), lgNs + LGR));
+            for (int r = 1; r < R; ++r) v[r] = cmul<T>(v[r], root_twiddle<T, INV>(tw, (uint32_t)(k0 * r), lgNs + LGR));
         }
         Dft<T, R, INV>::run(v);
     }
@@ -172,8 +172,16 @@ __device__ __forceinline__ void fft_pass_body(cplx<T> *z, const PassGeom &g, int
     constexpr int LDS_STRIDE = C + 1;
     const int c = threadIdx.x % C;
     const int grp = threadIdx.x / C;
-    const int chunk = (int)(blk % nchunks);
-    const int64_t col = blk / nchunks;
+    int chunk;
+    int64_t col;
+    if (g.col_fastest) {
+        const int64_t ncols = g.L >> LGP;
+        col = blk % ncols;
+        chunk = (int)(blk / ncols);
+    } else {
+        chunk = (int)(blk % nchunks);
+        col = blk / nchunks;
+    }
     const int64_t S = g.S;
     const int64_t b = col >> (g.lgB - LGP);          // S = 2^(lgB - LGP)
     const uint32_t m = (uint32_t)(col & (S - 1));
@@ -181,16 +189,25 @@ __device__ __forceinline__ void fft_pass_body(cplx<T> *z, const PassGeom &g, int
     const int lane = chunk * C + c;
     const bool lane_ok = lane < nl;
 
-    // Forward twiddle on output r: W_B^{m r}; inverse on input r: W_B^{-m r}.
+    // Forward twiddle on output r: W_B^{m r}; inverse on input r: W_B^{-m r},
+    // from the pass's table when there is one.
+    const cplx<T> *otw = reinterpret_cast<const cplx<T> *>(tw.outer) + ((size_t)m << LGP);
+    auto outer = [&](int idx, bool inv) {
+        if (tw.outer) {
+            const cplx<T> w = otw[idx];
+            return inv ? cconj<T>(w) : w;
+        }
+        return inv ? twiddle<T, true>(tw, m * (uint32_t)idx, g.lgB) : twiddle<T, false>(tw, m * (uint32_t)idx, g.lgB);
+    };
     auto fwd_store = [&](int idx, cplx<T> v) {
         if (!lane_ok) return;
-        if (m) v = cmul<T>(v, twiddle<T, false>(tw, m * (uint32_t)idx, g.lgB));
+        if (m) v = cmul<T>(v, outer(idx, false));
         z[(base + idx * S) * nl + lane] = v;
     };
     auto inv_load = [&](int idx) {
         if (!lane_ok) return mk<T>(0, 0);
         cplx<T> v = z[(base + idx * S) * nl + lane];
-        if (m) v = cmul<T>(v, twiddle<T, true>(tw, m * (uint32_t)idx, g.lgB));
+        if (m) v = cmul<T>(v, outer(idx, true));
         return v;
     };
 
@@ -229,6 +246,16 @@ template <typename T, int LGP, int C, int MODE>
 __global__ void __launch_bounds__(C << (LGP - min_stage_lg(LGP)))
 fft_pass_kernel(cplx<T> *z, PassGeom g, SrcDesc src, DstDesc dst, Twiddles<T> tw) {
     fft_pass_body<T, LGP, C, MODE>(z, g, g.nl, g.nchunks, blockIdx.x, src, dst, tw);
+}
+
+// Two problems of the same geometry by value (the forward transforms of both
+// operands of a product in one launch).
+template <typename T, int LGP, int C, int MODE>
+__global__ void __launch_bounds__(C << (LGP - min_stage_lg(LGP)))
+fft_pass_pair_kernel(PassProblem<T> a, PassProblem<T> b, PassGeom g, Twiddles<T> tw) {
+    const int64_t bid = blockIdx.x;
+    if (bid < b.wg_begin) fft_pass_body<T, LGP, C, MODE>(a.z, g, a.nl, a.nchunks, bid, a.src, a.dst, tw);
+    else fft_pass_body<T, LGP, C, MODE>(b.z, g, b.nl, b.nchunks, bid - b.wg_begin, b.src, b.dst, tw);
 }
 
 // Batched: the workgroup's problem is found by binary search over wg_begin.
@@ -311,6 +338,23 @@ static hipError_t launch_pass_c(int lgP, cplx<T> *z, const PassGeom &g, const Sr
     }
 }
 
+// 32 lanes per workgroup only up to 256-row passes (LDS).
+template <typename T, int MODE>
+static hipError_t launch_pass_c32(int lgP, cplx<T> *z, const PassGeom &g, const SrcDesc &src, const DstDesc &dst,
+                                  const Twiddles<T> &tw, hipStream_t st) {
+    switch (lgP) {
+        case 1: return launch_pass_t<T, 1, 32, MODE>(z, g, src, dst, tw, st);
+        case 2: return launch_pass_t<T, 2, 32, MODE>(z, g, src, dst, tw, st);
+        case 3: return launch_pass_t<T, 3, 32, MODE>(z, g, src, dst, tw, st);
+        case 4: return launch_pass_t<T, 4, 32, MODE>(z, g, src, dst, tw, st);
+        case 5: return launch_pass_t<T, 5, 32, MODE>(z, g, src, dst, tw, st);
+        case 6: return launch_pass_t<T, 6, 32, MODE>(z, g, src, dst, tw, st);
+        case 7: return launch_pass_t<T, 7, 32, MODE>(z, g, src, dst, tw, st);
+        case 8: return launch_pass_t<T, 8, 32, MODE>(z, g, src, dst, tw, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
 template <typename T, int MODE>
 static hipError_t launch_pass_m(int lgP, int C, cplx<T> *z, const PassGeom &g, const SrcDesc &src,
                                 const DstDesc &dst, const Twiddles<T> &tw, hipStream_t st) {
@@ -318,6 +362,7 @@ static hipError_t launch_pass_m(int lgP, int C, cplx<T> *z, const PassGeom &g, c
         case 2: return launch_pass_c<T, 2, MODE>(lgP, z, g, src, dst, tw, st);
         case 8: return launch_pass_c<T, 8, MODE>(lgP, z, g, src, dst, tw, st);
         case 16: return launch_pass_c<T, 16, MODE>(lgP, z, g, src, dst, tw, st);
+        case 32: return launch_pass_c32<T, MODE>(lgP, z, g, src, dst, tw, st);
         default: return hipErrorInvalidValue;
     }
 }
@@ -330,21 +375,25 @@ int fft_lanes_per_block(bool dbl, int nl) {
 
 template <typename T>
 hipError_t fft_pass(int mode, const FftPlan &plan, int pass, int nl, cplx<T> *z, const SrcDesc &src,
-                    const DstDesc &dst, const Twiddles<T> &tw, hipStream_t st) {
-    PassGeom g;
+                    const DstDesc &dst, const Twiddles<T> &tw, hipStream_t st, int lanes, int order) {
+    PassGeom g{};
+    g.col_fastest = order;
     g.L = (int64_t)1 << plan.lgL;
     int lgB = plan.lgL;
     for (int j = 0; j < pass; ++j) lgB -= plan.lgP[j];
     g.lgB = lgB;
     g.S = (int64_t)1 << (lgB - plan.lgP[pass]);
     g.nl = nl;
-    const int C = fft_lanes_per_block(sizeof(T) == 8, nl);
-    g.nchunks = (nl + C - 1) / C;
     const int lgP = plan.lgP[pass];
+    int C = nl <= 2 ? 2 : (lanes ? lanes : fft_lanes_per_block(sizeof(T) == 8, nl));
+    if (C == 32 && (lgP > 8 || nl <= 16)) C = 16;
+    g.nchunks = (nl + C - 1) / C;
+    Twiddles<T> t = tw;
+    t.outer = plan.outer[pass];
     switch (mode) {
-        case 0: return launch_pass_m<T, 0>(lgP, C, z, g, src, dst, tw, st);
-        case 1: return launch_pass_m<T, 1>(lgP, C, z, g, src, dst, tw, st);
-        default: return launch_pass_m<T, 2>(lgP, C, z, g, src, dst, tw, st);
+        case 0: return launch_pass_m<T, 0>(lgP, C, z, g, src, dst, t, st);
+        case 1: return launch_pass_m<T, 1>(lgP, C, z, g, src, dst, t, st);
+        default: return launch_pass_m<T, 2>(lgP, C, z, g, src, dst, t, st);
     }
 }
 
@@ -367,6 +416,45 @@ static hipError_t launch_batched_t(const PassProblem<T> *probs, int nprob, int64
     hipLaunchKernelGGL(kern, dim3((unsigned)total), dim3(threads), lds, st, probs, nprob, g, tw);
     launch_end();
     return hipGetLastError();
+}
+
+template <typename T, int LGP, int C, int MODE>
+static hipError_t launch_pair_t(const PassProblem<T> &a, const PassProblem<T> &b, int64_t total, const PassGeom &g,
+                                double bytes, const Twiddles<T> &tw, hipStream_t st) {
+    const int threads = C << (LGP - min_stage_lg(LGP));
+    const size_t lds = (num_stages(LGP) > 1 || MODE == 2) ? ((size_t)1 << LGP) * (C + 1) * sizeof(cplx<T>) : 0;
+    auto kern = fft_pass_pair_kernel<T, LGP, C, MODE>;
+    static bool attr_set = false;
+    if (!attr_set && lds > 64 * 1024) {
+        (void)hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        (void)hipGetLastError();
+        attr_set = true;
+    }
+    char name[96];
+    snprintf(name, sizeof name, "fft_pass_pair_kernel<%s, %d, %d, %d>", sizeof(T) == 8 ? "double" : "float", LGP, C,
+             MODE);
+    launch_begin(name, bytes, 0.0);
+    hipLaunchKernelGGL(kern, dim3((unsigned)total), dim3(threads), lds, st, a, b, g, tw);
+    launch_end();
+    return hipGetLastError();
+}
+
+template <typename T, int C>
+static hipError_t launch_pair_c(int lgP, const PassProblem<T> &a, const PassProblem<T> &b, int64_t total,
+                                const PassGeom &g, double bytes, const Twiddles<T> &tw, hipStream_t st) {
+    if (C == 32 && lgP > 8) return hipErrorInvalidValue;
+    switch (lgP) {
+        case 1: return launch_pair_t<T, 1, C, 0>(a, b, total, g, bytes, tw, st);
+        case 2: return launch_pair_t<T, 2, C, 0>(a, b, total, g, bytes, tw, st);
+        case 3: return launch_pair_t<T, 3, C, 0>(a, b, total, g, bytes, tw, st);
+        case 4: return launch_pair_t<T, 4, C, 0>(a, b, total, g, bytes, tw, st);
+        case 5: return launch_pair_t<T, 5, C, 0>(a, b, total, g, bytes, tw, st);
+        case 6: return launch_pair_t<T, 6, C, 0>(a, b, total, g, bytes, tw, st);
+        case 7: return launch_pair_t<T, 7, C, 0>(a, b, total, g, bytes, tw, st);
+        case 8: return launch_pair_t<T, 8, C, 0>(a, b, total, g, bytes, tw, st);
+        case 9: return launch_pair_t<T, 9, (C > 16 ? 16 : C), 0>(a, b, total, g, bytes, tw, st);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 template <typename T, int C, int MODE>
@@ -410,9 +498,11 @@ int64_t fft_batch_layout(const FftPlan &plan, int pass, PassProblem<T> *probs, i
 
 template <typename T>
 hipError_t fft_pass_batched(int mode, const FftPlan &plan, int pass, int C, const PassProblem<T> *probs, int nprob,
-                            int64_t total, double bytes, const Twiddles<T> &tw, hipStream_t st) {
+                            int64_t total, double bytes, const Twiddles<T> &tw_in, hipStream_t st) {
     const PassGeom g = pass_geom(plan, pass);
     const int lgP = plan.lgP[pass];
+    Twiddles<T> tw = tw_in;
+    tw.outer = plan.outer[pass];
     switch (mode * 100 + C) {
         case 2: return launch_batched_c<T, 2, 0>(lgP, probs, nprob, total, g, bytes, tw, st);
         case 8: return launch_batched_c<T, 8, 0>(lgP, probs, nprob, total, g, bytes, tw, st);
@@ -434,9 +524,66 @@ template hipError_t fft_pass_batched<double>(int, const FftPlan &, int, int, con
 template hipError_t fft_pass_batched<float>(int, const FftPlan &, int, int, const PassProblem<float> *, int,
                                             int64_t, double, const Twiddles<float> &, hipStream_t);
 
+// Outer-twiddle tables (see TwGen); values are the same two-level products
+// the passes would otherwise form on the fly.
+__global__ void gen_outer_twiddles_kernel(TwGen g, const double2 *hi, const double2 *lo) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= g.total) return;
+    int t = 0;
+    while (t + 1 < g.count && g.begin[t + 1] <= i) ++t;
+    const int64_t e = i - g.begin[t];
+    const uint32_t m = (uint32_t)(e >> g.lgP[t]), kr = (uint32_t)(e & ((1 << g.lgP[t]) - 1));
+    Twiddles<double> tw{hi, lo, nullptr, nullptr};
+    const double2 w = twiddle<double, false>(tw, m * kr, g.lgB[t]);
+    if (g.dbl[t]) ((double2 *)g.dst[t])[e] = w;
+    else ((float2 *)g.dst[t])[e] = make_float2((float)w.x, (float)w.y);
+}
+
+hipError_t gen_outer_twiddles(const TwGen &g, const double2 *hi, const double2 *lo, hipStream_t st) {
+    if (g.count == 0 || g.total == 0) return hipSuccess;
+    launch_begin("gen_outer_twiddles_kernel", 0.0, 0.0);
+    hipLaunchKernelGGL(gen_outer_twiddles_kernel, dim3((unsigned)((g.total + 255) / 256)), dim3(256), 0, st, g, hi, lo);
+    launch_end();
+    return hipGetLastError();
+}
+
 template hipError_t fft_pass<double>(int, const FftPlan &, int, int, cplx<double> *, const SrcDesc &,
-                                     const DstDesc &, const Twiddles<double> &, hipStream_t);
+                                     const DstDesc &, const Twiddles<double> &, hipStream_t, int, int);
 template hipError_t fft_pass<float>(int, const FftPlan &, int, int, cplx<float> *, const SrcDesc &,
-                                    const DstDesc &, const Twiddles<float> &, hipStream_t);
+                                    const DstDesc &, const Twiddles<float> &, hipStream_t, int, int);
+
+template <typename T>
+hipError_t fft_pass_pair(const FftPlan &plan, int pass, PassProblem<T> a, PassProblem<T> b, const Twiddles<T> &tw,
+                         hipStream_t st, int lanes, int order) {
+    PassGeom g = pass_geom(plan, pass);
+    g.col_fastest = order;
+    const int nlmin = a.nl < b.nl ? a.nl : b.nl;
+    int C = nlmin <= 2 ? 2 : (lanes ? lanes : fft_lanes_per_block(sizeof(T) == 8, a.nl > b.nl ? a.nl : b.nl));
+    if (C == 32 && (plan.lgP[pass] > 8 || nlmin <= 16)) C = 16;
+    const int64_t cols = g.L >> plan.lgP[pass];
+    a.nchunks = (a.nl + C - 1) / C;
+    b.nchunks = (b.nl + C - 1) / C;
+    a.wg_begin = 0;
+    b.wg_begin = cols * a.nchunks;
+    const int64_t total = b.wg_begin + cols * b.nchunks;
+    PassGeom ga = g, gb = g;
+    ga.nl = a.nl; ga.nchunks = a.nchunks;
+    gb.nl = b.nl; gb.nchunks = b.nchunks;
+    const double bytes = pass_bytes<T>(0, ga, a.src, a.dst) + pass_bytes<T>(0, gb, b.src, b.dst);
+    const int lgP = plan.lgP[pass];
+    Twiddles<T> t = tw;
+    t.outer = plan.outer[pass];
+    switch (C) {
+        case 2: return launch_pair_c<T, 2>(lgP, a, b, total, g, bytes, t, st);
+        case 8: return launch_pair_c<T, 8>(lgP, a, b, total, g, bytes, t, st);
+        case 16: return launch_pair_c<T, 16>(lgP, a, b, total, g, bytes, t, st);
+        case 32: return launch_pair_c<T, 32>(lgP, a, b, total, g, bytes, t, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+template hipError_t fft_pass_pair<double>(const FftPlan &, int, PassProblem<double>, PassProblem<double>,
+                                          const Twiddles<double> &, hipStream_t, int, int);
+template hipError_t fft_pass_pair<float>(const FftPlan &, int, PassProblem<float>, PassProblem<float>,
+                                         const Twiddles<float> &, hipStream_t, int, int);
 
 }  // namespace mrinv

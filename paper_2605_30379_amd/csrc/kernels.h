@@ -29,8 +29,22 @@ constexpr int LGP_MAX = 9;   // largest radix of one FFT pass (512 rows in LDS)
 struct FftPlan {
     int lgL;
     int npass;
-    int lgP[MAX_PASSES];   // pass radices, first pass = outermost (largest stride)
+    int lgP[MAX_PASSES];          // pass radices, first pass = outermost (largest stride)
+    const void *outer[MAX_PASSES];  // optional precomputed outer twiddles of each pass
 };
+
+// Outer-twiddle tables to generate in one launch: table t holds
+// W_B^(m kr) at [m * P + kr] for B = 2^lgB, P = 2^lgP (B entries), stored as
+// float64 or float32 pairs.
+constexpr int MAX_TW_TABLES = 32;
+struct TwGen {
+    int count;
+    int64_t total;                 // entries over all tables
+    int64_t begin[MAX_TW_TABLES];  // first entry index of each table
+    void *dst[MAX_TW_TABLES];
+    int lgB[MAX_TW_TABLES], lgP[MAX_TW_TABLES], dbl[MAX_TW_TABLES];
+};
+hipError_t gen_outer_twiddles(const TwGen &g, const double2 *hi, const double2 *lo, hipStream_t st);
 
 // Geometry of one pass (device side).
 struct PassGeom {
@@ -39,6 +53,7 @@ struct PassGeom {
     int lgB;          // block size 2^lgB
     int nl;           // complex lanes per row
     int nchunks;      // lane chunks per column
+    int col_fastest;  // workgroup order: 0 = all lane chunks of a column together, 1 = columns first
 };
 
 enum SrcKind { SRC_Z = 0, SRC_REAL64 = 1, SRC_REAL32 = 2 };
@@ -112,9 +127,15 @@ inline DstDesc dst_z() { DstDesc d{}; d.kind = DST_Z; d.rev = -1; d.scale = 1.0;
 int fft_lanes_per_block(bool dbl, int nl);
 
 // mode 0 forward, 1 inverse, 2 inverse + mask + forward (same pass).
+// lanes: complex lanes per workgroup (8 or 16), 0 for the default;
+// order: workgroup order (see PassGeom::col_fastest).
 template <typename T>
 hipError_t fft_pass(int mode, const FftPlan &plan, int pass, int nl, cplx<T> *z, const SrcDesc &src,
-                    const DstDesc &dst, const Twiddles<T> &tw, hipStream_t st);
+                    const DstDesc &dst, const Twiddles<T> &tw, hipStream_t st, int lanes = 0, int order = 0);
+// Forward pass of two problems of the same plan in one launch (z, nl, src set).
+template <typename T>
+hipError_t fft_pass_pair(const FftPlan &plan, int pass, PassProblem<T> a, PassProblem<T> b, const Twiddles<T> &tw,
+                         hipStream_t st, int lanes = 0, int order = 0);
 // The same pass over many problems in one launch.  probs is a device array of
 // nprob descriptors with wg_begin filled by fft_batch_layout; every problem
 // uses C lanes per workgroup.  Returns the total workgroup count via *total.
@@ -155,6 +176,22 @@ hipError_t freq_coldot(const FftPlan &plan, int ra, int cb, const cplx<T> *ZA, c
 // of out (float64 and/or float32 copies, either may be null).
 hipError_t gj_inverse(const double *A0, int d, int e0_minus, double *out64, float *out32, unsigned int *status,
                       hipStream_t st);
+
+// One problem of a batched recursion seed launch (d workgroups each).
+struct SeedProblem {
+    const double *A;
+    void *out;          // float64 or float32 per the launch
+    int d, m0, e0;
+    int col_begin;
+};
+template <typename T>
+hipError_t seed_recursion_batched(const SeedProblem *probs, int nprob, int total_cols, int dmax, int m0max,
+                                  hipStream_t st);
+
+// X(1..m0-1) by the coefficient recursion, X(0) already in out row 0;
+// e0 != 0 means the source is q and A = e0 - q.
+template <typename T>
+hipError_t seed_recursion(const double *A, int e0, int d, int m0, T *out, hipStream_t st);
 
 hipError_t gj_inverse_batched(const GjProblem *dev_probs, int nprob, int dmax, unsigned int *status,
                               hipStream_t st);
