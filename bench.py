@@ -29,6 +29,8 @@ CONFIGS = {
     "c1": dict(d=4, n=256, family="weibull", seed=0, form="fp64"),
     "c2": dict(d=16, n=65536, family="weibull", seed=1, form="fp64"),
     "c3": dict(d=64, n=262144, family="lognormal", seed=3, form="mixed"),
+    "c4": dict(d=0, n=0, family="mixed", seed=4, form="mixed"),
+    "c5": dict(d=32, n=65536, family="weibull", seed=5, form="fp64"),
 }
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
@@ -179,6 +181,72 @@ def cpu_baseline(cfg, budget_s: float):
             "sample_seconds": round(t, 3), "extrapolated_full_seconds": round(t_full, 2)}
 
 
+def run_batched(args, mr, torch, si, dev):
+    """512 uneven problems (d in 3..48, n log-uniform in [1024, 32768]) in one
+    batched call per step, mixed form; also the same problems one call each."""
+    work = si.batch_workload(CONFIGS["c4"]["seed"], 512)
+    qs = [si.family_kernel(w["family"], w["d"], w["n"], w["seed"], device=dev).q for w in work]
+    torch.cuda.synchronize()
+    fl = sum(f_nom(w["d"], w["n"]) for w in work)
+    res = {}
+    for form in [f for f in args.forms.split(",") if f]:
+        ms = time_steps(lambda: mr.psi_inverse_batched(qs, form), args.steps, args.warmup, torch)
+        mr.sync_status(dev)
+        ms_single = time_steps(lambda: [mr.psi_inverse(q, form) for q in qs], max(1, args.steps // 4), 1, torch)
+        res[form] = {"ms": ms, "tflops": fl / (ms * 1e-3) / 1e12, "ms_one_call_each": ms_single}
+        print(f"[bench] c4 {form}: batched {ms:.3f} ms, one call each {ms_single:.3f} ms", file=sys.stderr, flush=True)
+    v = res.get("mixed", next(iter(res.values())))
+    line = {
+        "metric": "psi inversion sec & effective TFLOP/s, mixed vs FP64 on 1 GPU @ max err<=1e-10",
+        "value": round(v["tflops"], 4), "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(v["ms"], 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
+        "config": {"workload": "c4: 512 uneven problems, d in 3..48, n log-uniform in [1024, 32768], "
+                               "Weibull or lognormal, one batched call", "problems": 512},
+        "forms": {f: {k: round(x, 4) for k, x in r.items()} for f, r in res.items()},
+        "nominal_flops": fl, "source_hash": source_hash(),
+    }
+    print(json.dumps(line), flush=True)
+
+
+def run_gradient(args, mr, torch, si, dev):
+    """Loss = sum_k A(k) + F_{d-1}(n-1) and its gradient with respect to all
+    Weibull shapes, scales and logits (d = 32, n = 65536), one step = forward
+    plus backward through the adjoint kernels."""
+    d, n = 32, 65536
+    shape, scale, logits = si.weibull_params(d, CONFIGS["c5"]["seed"], device=dev)
+    up = torch.tensor([1.0] * 16 + [0.0] * 16, dtype=torch.float64)
+    alpha = torch.zeros(d, dtype=torch.float64)
+    alpha[0] = 1.0
+    C = list(range(d - 1))
+    aC = torch.zeros(d - 1, dtype=torch.float64)
+    aC[0] = 1.0
+
+    def step():
+        ps = [t.clone().requires_grad_(True) for t in (shape, scale, logits)]
+        q = si.weibull_kernel_from_params(*ps, n)
+        psi = mr.PsiInverse.apply(q)
+        P = mr.Transition.apply(psi, q)
+        A = mr.Contract.apply(P, alpha, up)
+        g = mr.RenewalApply.apply(mr.PsiInverse.apply(mr.GatherBlock.apply(q, C, C)), mr.GatherBlock.apply(q, C, [d - 1]))
+        F = mr.Contract.apply(g, aC, torch.ones(1, dtype=torch.float64), True)
+        (A.sum() + F[-1]).backward()
+        return ps
+
+    ms = time_steps(step, args.steps, args.warmup, torch)
+    fwd_ms = time_steps(lambda: mr.psi_inverse(si.weibull_kernel(d, n, 5, device=dev).q), args.steps, 1, torch)
+    line = {
+        "metric": "psi inversion sec & effective TFLOP/s, mixed vs FP64 on 1 GPU @ max err<=1e-10",
+        "value": round(2 * f_nom(d, n) / (ms * 1e-3) / 1e12, 4), "unit": "TFLOP/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "c5: gradient of sum_k A(k) + F_{d-1}(n-1), d=32, n=65536, Weibull, "
+                               "2976 live parameters, forward + backward", "d": d, "n": n},
+        "psi_inverse_ms": round(fwd_ms, 4), "source_hash": source_hash(),
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -208,6 +276,10 @@ def main():
     d, n = cfg["d"], cfg["n"]
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
+    if args.config == "c4":
+        return run_batched(args, mr, torch, si, dev)
+    if args.config == "c5":
+        return run_gradient(args, mr, torch, si, dev)
     print(f"[bench] config {args.config}: d={d} n={n} {cfg['family']}", file=sys.stderr, flush=True)
     q = si.family_kernel(cfg["family"], d, n, cfg["seed"], device=dev).q
     torch.cuda.synchronize()

@@ -240,7 +240,9 @@ typedef struct {
                            1: in-workgroup twiddles from a 512-root table; 2: also per-pass outer
                            twiddle tables built in the workspace (default 1).  Values are identical. */
     int block_order;    /* FFT workgroup order: 0 = the lane chunks of one column together,
-                           1 = columns first, spreading concurrent accesses over more memory (default 1) */
+                           1 = columns first (default 0) */
+    int use_graph;      /* nonzero: mrinv_psi_inverse records its launches once into a HIP graph per
+                           (pointers, sizes, tuning) and replays it on later identical calls (default 0) */
 } mrinv_tuning_t;
 
 mrinv_status_t mrinv_get_tuning(mrinv_handle_t h, mrinv_tuning_t *out);

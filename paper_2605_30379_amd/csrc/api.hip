@@ -51,7 +51,19 @@ struct mrinv_handle_s {
     double *scratch = nullptr;      // small per-handle scratch (index lists, vectors, 1-lane scans)
     void *timer = nullptr;          // launch timing records (mrinv_set_timing)
     bool timing = false;
-    mrinv_tuning_t tune{9, 16, 16, 16, 1, 1, 0};
+    mrinv_tuning_t tune{9, 16, 16, 16, 1, 1, 0, 0};
+    // Graph of the last captured psi inversion and the call it belongs to.
+    struct {
+        bool valid = false;
+        const void *src = nullptr, *out = nullptr, *ws = nullptr;
+        size_t wsb = 0;
+        int d = 0, e0 = 0, prec = 0;
+        int64_t n = 0;
+        mrinv_tuning_t tune{};
+        hipGraph_t graph = nullptr;
+        hipGraphExec_t exec = nullptr;
+    } gc;
+    hipStream_t cap_stream = nullptr;
     void *pinned = nullptr;         // pinned staging buffer of batched descriptor tables
     size_t pinned_bytes = 0;
     hipEvent_t pinned_done = nullptr;   // recorded after the last transfer out of `pinned`
@@ -97,6 +109,7 @@ extern "C" mrinv_status_t mrinv_create(mrinv_handle_t *handle, void *stream) {
     HIP_TRY(hipMemcpy(h->tw64 + TW_HI_SIZE + TW_LO_SIZE, root.data(), 512 * sizeof(double2), hipMemcpyHostToDevice));
     HIP_TRY(hipMemset(h->status, 0, 256));
     HIP_TRY(hipEventCreateWithFlags(&h->pinned_done, hipEventDisableTiming));
+    HIP_TRY(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
     HIP_TRY(hipDeviceSynchronize());
     *handle = h;
     g_last_error.clear();
@@ -111,6 +124,9 @@ extern "C" mrinv_status_t mrinv_destroy(mrinv_handle_t h) {
     if (h->status) (void)hipFree(h->status);
     if (h->scratch) (void)hipFree(h->scratch);
     if (h->timer) timer_destroy(h->timer);
+    if (h->gc.exec) (void)hipGraphExecDestroy(h->gc.exec);
+    if (h->gc.graph) (void)hipGraphDestroy(h->gc.graph);
+    if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
     if (h->pinned) (void)hipHostFree(h->pinned);
     if (h->pinned_done) (void)hipEventDestroy(h->pinned_done);
     delete h;
@@ -592,9 +608,59 @@ static mrinv_status_t inverse_impl(mrinv_handle_t h, const double *src, int e0, 
     return MRINV_OK;
 }
 
+// inverse_impl, recorded into a HIP graph on the handle's capture stream the
+// first time a (pointers, sizes, tuning) key is seen and replayed on the
+// caller's stream afterwards.  Argument errors are reported before recording.
+static mrinv_status_t inverse_graphed(mrinv_handle_t h, const double *src, int e0, int d, int64_t n,
+                                      mrinv_precision_t prec, double *out, void *ws, size_t wsb) {
+    auto &gc = h->gc;
+    const bool hit = gc.valid && gc.src == src && gc.out == out && gc.ws == ws && gc.wsb == wsb && gc.d == d &&
+                     gc.n == n && gc.e0 == e0 && gc.prec == (int)prec &&
+                     memcmp(&gc.tune, &h->tune, sizeof(mrinv_tuning_t)) == 0;
+    if (!hit) {
+        if (!src || !out) return fail(MRINV_E_ARG, "NULL handle or pointer");
+        CHECK(check_dn(d, n));
+        CHECK(check_ws(ws, wsb, ws_psi(d, n, prec)));
+        if (gc.exec) (void)hipGraphExecDestroy(gc.exec);
+        if (gc.graph) (void)hipGraphDestroy(gc.graph);
+        gc.exec = nullptr;
+        gc.graph = nullptr;
+        gc.valid = false;
+        hipStream_t caller = h->stream;
+        h->stream = h->cap_stream;
+        HIP_TRY(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
+        mrinv_status_t st = inverse_impl(h, src, e0, d, n, prec, out, ws, wsb);
+        hipGraph_t g = nullptr;
+        hipError_t ec = hipStreamEndCapture(h->cap_stream, &g);
+        h->stream = caller;
+        if (st != MRINV_OK) {
+            if (g) (void)hipGraphDestroy(g);
+            return st;
+        }
+        HIP_TRY(ec);
+        hipGraphExec_t ex = nullptr;
+        HIP_TRY(hipGraphInstantiate(&ex, g, nullptr, nullptr, 0));
+        gc.graph = g;
+        gc.exec = ex;
+        gc.src = src;
+        gc.out = out;
+        gc.ws = ws;
+        gc.wsb = wsb;
+        gc.d = d;
+        gc.n = n;
+        gc.e0 = e0;
+        gc.prec = (int)prec;
+        gc.tune = h->tune;
+        gc.valid = true;
+    }
+    HIP_TRY(hipGraphLaunch(gc.exec, h->stream));
+    return MRINV_OK;
+}
+
 extern "C" mrinv_status_t mrinv_psi_inverse(mrinv_handle_t h, const double *q, int d, int64_t n,
                                             mrinv_precision_t precision, double *psi, void *ws, size_t ws_bytes) {
     TimerScope _ts(h);
+    if (h && h->tune.use_graph && !h->timing) return inverse_graphed(h, q, 1, d, n, precision, psi, ws, ws_bytes);
     return inverse_impl(h, q, 1, d, n, precision, psi, ws, ws_bytes);
 }
 
@@ -602,6 +668,7 @@ extern "C" mrinv_status_t mrinv_series_inverse(mrinv_handle_t h, const double *A
                                                mrinv_precision_t precision, double *Ainv, void *ws,
                                                size_t ws_bytes) {
     TimerScope _ts(h);
+    if (h && h->tune.use_graph && !h->timing) return inverse_graphed(h, A, 0, d, n, precision, Ainv, ws, ws_bytes);
     return inverse_impl(h, A, 0, d, n, precision, Ainv, ws, ws_bytes);
 }
 
@@ -617,6 +684,7 @@ static mrinv_status_t check_tuning(const mrinv_tuning_t &t) {
     if (t.seed_m0 < 1 || t.seed_m0 > 256) return fail(MRINV_E_ARG, "seed_m0 %d not in 1..256", t.seed_m0);
     if (t.twiddle_tables < 0 || t.twiddle_tables > 2) return fail(MRINV_E_ARG, "twiddle_tables must be 0, 1 or 2");
     if (t.block_order < 0 || t.block_order > 1) return fail(MRINV_E_ARG, "block_order must be 0 or 1");
+    if (t.use_graph < 0 || t.use_graph > 1) return fail(MRINV_E_ARG, "use_graph must be 0 or 1");
     return MRINV_OK;
 }
 
@@ -639,9 +707,9 @@ static mrinv_status_t time_inverse(mrinv_handle_t h, const double *q, int d, int
     hipEvent_t a, b;
     HIP_TRY(hipEventCreate(&a));
     HIP_TRY(hipEventCreate(&b));
-    mrinv_status_t st = inverse_impl(h, q, 1, d, n, prec, psi, ws, wsb);
+    mrinv_status_t st = mrinv_psi_inverse(h, q, d, n, prec, psi, ws, wsb);
     if (st == MRINV_OK) (void)hipEventRecord(a, h->stream);
-    for (int r = 0; r < reps && st == MRINV_OK; ++r) st = inverse_impl(h, q, 1, d, n, prec, psi, ws, wsb);
+    for (int r = 0; r < reps && st == MRINV_OK; ++r) st = mrinv_psi_inverse(h, q, d, n, prec, psi, ws, wsb);
     if (st == MRINV_OK) {
         (void)hipEventRecord(b, h->stream);
         (void)hipEventSynchronize(b);
@@ -682,8 +750,9 @@ extern "C" mrinv_status_t mrinv_autotune(mrinv_handle_t h, const double *q, int 
     for (int v : {0, 1}) { mrinv_tuning_t t = best; t.pair_forward = v; CHECK(trial(t)); }
     for (int v : {0, 1, 2}) { mrinv_tuning_t t = best; t.twiddle_tables = v; CHECK(trial(t)); }
     for (int v : {0, 1}) { mrinv_tuning_t t = best; t.block_order = v; CHECK(trial(t)); }
+    for (int v : {0, 1}) { mrinv_tuning_t t = best; t.use_graph = v; CHECK(trial(t)); }
     h->tune = best;
-    CHECK(inverse_impl(h, q, 1, d, n, precision, psi, ws, wsb));
+    CHECK(mrinv_psi_inverse(h, q, d, n, precision, psi, ws, wsb));
     HIP_TRY(hipStreamSynchronize(h->stream));
     if (chosen) *chosen = best;
     return MRINV_OK;

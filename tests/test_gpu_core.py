@@ -316,3 +316,48 @@ def test_batched_matches_single_calls_and_oracle(mr, orc, precision):
         assert torch.equal(o, single), (d, n)
         ref = orc.psi(q[: min(n, 600)].cpu().numpy())
         assert _maxerr(_np(o[: min(n, 600)]), ref) <= tol, (d, n)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_graph_replays_match_eager(mr, precision):
+    """With graph recording on, repeated calls with the same pointers replay
+    one HIP graph.  Every replay, with eager work and new input values in
+    between, must equal the eager (unrecorded) result bitwise."""
+    import ctypes
+    d, n = 6, 3000
+    prec = mr._PREC[precision]
+    q = si.weibull_kernel(d, n, 61).q.cuda()
+    q2 = si.lognormal_kernel(d, n, 62).q.cuda()
+    out = torch.empty_like(q)
+    ws = torch.empty(mr.workspace_size("psi_inverse", d, n, 0, precision), dtype=torch.uint8, device="cuda")
+    dev = q.device
+    L = mr.lib()
+
+    def call():
+        mr._check(L.mrinv_psi_inverse(mr._handle(dev), ctypes.c_void_p(q.data_ptr()), d, n, prec,
+                                      ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(ws.data_ptr()), ws.numel()))
+
+    base = mr.get_tuning()
+    try:
+        mr.set_tuning(use_graph=0)
+        call()
+        ref1 = out.clone()
+        saved = q.clone()
+        q.copy_(q2)
+        call()
+        ref2 = out.clone()
+        q.copy_(saved)
+        mr.set_tuning(use_graph=1)
+        for rep in range(4):
+            out.fill_(float("nan"))          # eager work between replays
+            torch.cuda.synchronize()
+            call()
+            torch.cuda.synchronize()
+            assert torch.equal(out, ref1), rep
+        q.copy_(q2)                          # same pointers, new values
+        call()
+        torch.cuda.synchronize()
+        assert torch.equal(out, ref2)
+        mr.sync_status()
+    finally:
+        mr.set_tuning(**base)
