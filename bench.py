@@ -141,10 +141,13 @@ def roofline_of(stats, traffic_file=None):
         if tr.get("kernel") == top["name"] and tr.get("source_hash") == source_hash():
             roof["traffic"] = tr.get("bytes_per_launch")
     breakdown = []
-    for s in stats[:8]:
+    for s in stats[:12]:
         a = s["total_ms"] / s["launches"] / 1e3
-        breakdown.append({"kernel": s["name"], "launches": s["launches"], "total_ms": round(s["total_ms"], 4),
-                          "avg_us": round(a * 1e6, 2), "GBps": round(s["bytes"] / s["launches"] / a / 1e9, 1)})
+        row = {"kernel": s["name"], "launches": s["launches"], "total_ms": round(s["total_ms"], 4),
+               "avg_us": round(a * 1e6, 2), "GBps": round(s["bytes"] / s["launches"] / a / 1e9, 1)}
+        if s["flops"] > 0:
+            row["TFLOPs"] = round(s["flops"] / s["launches"] / a / 1e12, 2)
+        breakdown.append(row)
     return roof, breakdown
 
 

@@ -243,6 +243,9 @@ typedef struct {
                            1 = columns first (default 0) */
     int use_graph;      /* nonzero: mrinv_psi_inverse records its launches once into a HIP graph per
                            (pointers, sizes, tuning) and replays it on later identical calls (default 0) */
+    int mfma;           /* square frequency-domain products for d > 8 on the matrix cores (16x16x4 MFMA in
+                           the working precision): 0 never (vector kernels), 1 when padding d to a multiple
+                           of 16 adds fewer than 8 (default), 2 always.  Results agree to rounding. */
 } mrinv_tuning_t;
 
 mrinv_status_t mrinv_get_tuning(mrinv_handle_t h, mrinv_tuning_t *out);

@@ -51,7 +51,7 @@ class Tuning(ctypes.Structure):
     """Launch-shape and schedule choices of a handle (mrinv_tuning_t)."""
     _fields_ = [("lgp_max", ctypes.c_int), ("lanes_fp64", ctypes.c_int), ("lanes_fp32", ctypes.c_int),
                 ("seed_m0", ctypes.c_int), ("pair_forward", ctypes.c_int), ("twiddle_tables", ctypes.c_int),
-                ("block_order", ctypes.c_int), ("use_graph", ctypes.c_int)]
+                ("block_order", ctypes.c_int), ("use_graph", ctypes.c_int), ("mfma", ctypes.c_int)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}

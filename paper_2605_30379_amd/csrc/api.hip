@@ -51,7 +51,7 @@ struct mrinv_handle_s {
     double *scratch = nullptr;      // small per-handle scratch (index lists, vectors, 1-lane scans)
     void *timer = nullptr;          // launch timing records (mrinv_set_timing)
     bool timing = false;
-    mrinv_tuning_t tune{9, 16, 16, 16, 1, 1, 0, 0};
+    mrinv_tuning_t tune{9, 16, 16, 16, 1, 1, 0, 0, 1};
     // Graph of the last captured psi inversion and the call it belongs to.
     struct {
         bool valid = false;
@@ -415,8 +415,9 @@ static hipError_t remask(mrinv_handle_t h, const FftPlan &p, int nl, cplx<T> *Z,
     return e;
 }
 
-static GemmDesc gdesc(int ra, int m, int cb, int ta = 0, int tb = 0) {
+static GemmDesc gdesc(mrinv_handle_t h, int ra, int m, int cb, int ta = 0, int tb = 0) {
     GemmDesc g{};
+    g.mfma = h ? h->tune.mfma : 1;
     g.ra = ra;
     g.m = m;
     g.cb = cb;
@@ -477,7 +478,7 @@ static mrinv_status_t newton(mrinv_handle_t h, const double *src, int e0, int d,
     // then Newton doubling from m0.
     const int64_t m0 = seed_len(h, n);
     if (m0 > 1) HIP_TRY(seed_recursion<T>(src, e0, d, (int)m0, (T *)out, h->stream));
-    const GemmDesc g = gdesc(d, d, d);
+    const GemmDesc g = gdesc(h, d, d, d);
     // Plans of every step and their outer-twiddle tables (one launch).
     std::vector<FftPlan> plans;
     TwGen tg{};
@@ -574,7 +575,7 @@ static mrinv_status_t inverse_impl(mrinv_handle_t h, const double *src, int e0, 
         HIP_TRY(gen_outer_twiddles(tg, h->tw64, h->tw64 + TW_HI_SIZE, h->stream));
     }
     const double invL = 1.0 / (double)((int64_t)1 << p2.lgL);
-    const GemmDesc g = gdesc(d, d, d);
+    const GemmDesc g = gdesc(h, d, d, d);
     for (int sweep = 0; sweep < MIXED_SWEEPS; ++sweep) {
         const bool last = sweep == MIXED_SWEEPS - 1;
         {
@@ -685,6 +686,7 @@ static mrinv_status_t check_tuning(const mrinv_tuning_t &t) {
     if (t.twiddle_tables < 0 || t.twiddle_tables > 2) return fail(MRINV_E_ARG, "twiddle_tables must be 0, 1 or 2");
     if (t.block_order < 0 || t.block_order > 1) return fail(MRINV_E_ARG, "block_order must be 0 or 1");
     if (t.use_graph < 0 || t.use_graph > 1) return fail(MRINV_E_ARG, "use_graph must be 0 or 1");
+    if (t.mfma < 0 || t.mfma > 2) return fail(MRINV_E_ARG, "mfma must be 0, 1 or 2");
     return MRINV_OK;
 }
 
@@ -751,6 +753,7 @@ extern "C" mrinv_status_t mrinv_autotune(mrinv_handle_t h, const double *q, int 
     for (int v : {0, 1, 2}) { mrinv_tuning_t t = best; t.twiddle_tables = v; CHECK(trial(t)); }
     for (int v : {0, 1}) { mrinv_tuning_t t = best; t.block_order = v; CHECK(trial(t)); }
     for (int v : {0, 1}) { mrinv_tuning_t t = best; t.use_graph = v; CHECK(trial(t)); }
+    for (int v : {0, 1, 2}) { mrinv_tuning_t t = best; t.mfma = v; CHECK(trial(t)); }
     h->tune = best;
     CHECK(mrinv_psi_inverse(h, q, d, n, precision, psi, ws, wsb));
     HIP_TRY(hipStreamSynchronize(h->stream));
@@ -776,7 +779,7 @@ extern "C" mrinv_status_t mrinv_markov_renewal_apply(mrinv_handle_t h, const dou
     auto *SM = cv.take<cplx<double>>(spec_bytes(p.lgL, dr, true));
     HIP_TRY(fwd<double>(h, p, nl_of(d2), SP, src_real(psi, true, d2, (int)d2, 0, n)));
     HIP_TRY(fwd<double>(h, p, nl_of(dr), SL, src_real(L, true, dr, (int)dr, 0, n)));
-    HIP_TRY(freq_gemm<double>(p, gdesc(d, d, r), SP, SL, SM, h->stream));
+    HIP_TRY(freq_gemm<double>(p, gdesc(h, d, d, r), SP, SL, SM, h->stream));
     const double invL = 1.0 / (double)((int64_t)1 << p.lgL);
     HIP_TRY(inv<double>(h, p, nl_of(dr), SM, dst_real(M, true, dr, (int)dr, 0, n, invL, OP_STORE, -1, h->status)));
     return MRINV_OK;
@@ -979,10 +982,10 @@ extern "C" mrinv_status_t mrinv_psi_inverse_backward(mrinv_handle_t h, const dou
     HIP_TRY(fwd<double>(h, p, nl, S1, src_real(psi, true, d2, (int)d2, 0, n)));
     HIP_TRY(fwd<double>(h, p, nl, S2, src_real(psi_bar, true, d2, (int)d2, 0, n, n - 1)));
     // V^r = Rev(psi_bar) * psi^T, kept on [0, n)
-    HIP_TRY(freq_gemm<double>(p, gdesc(d, d, d, 0, 1), S2, S1, S3, h->stream));
+    HIP_TRY(freq_gemm<double>(p, gdesc(h, d, d, d, 0, 1), S2, S1, S3, h->stream));
     HIP_TRY(remask<double>(h, p, nl, S3, 0, n, false));
     // q_bar^r = psi^T * V^r
-    HIP_TRY(freq_gemm<double>(p, gdesc(d, d, d, 1, 0), S1, S3, S2, h->stream));
+    HIP_TRY(freq_gemm<double>(p, gdesc(h, d, d, d, 1, 0), S1, S3, S2, h->stream));
     HIP_TRY(inv<double>(h, p, nl, S2, dst_real(q_bar, true, d2, (int)d2, 0, n, invL, OP_STORE, n - 1, h->status)));
     return MRINV_OK;
 }
@@ -1007,14 +1010,14 @@ extern "C" mrinv_status_t mrinv_markov_renewal_apply_backward(mrinv_handle_t h, 
     if (psi_bar_accum) {
         // psi_bar^r += Rev(M_bar) * L^T   (d x r times r x d)
         HIP_TRY(fwd<double>(h, p, nl_of(dr), SL, src_real(L, true, dr, (int)dr, 0, n)));
-        HIP_TRY(freq_gemm<double>(p, gdesc(d, r, d, 0, 1), SM, SL, SP, h->stream));
+        HIP_TRY(freq_gemm<double>(p, gdesc(h, d, r, d, 0, 1), SM, SL, SP, h->stream));
         HIP_TRY(inv<double>(h, p, nl_of(d2), SP,
                             dst_real(psi_bar_accum, true, d2, (int)d2, 0, n, invL, OP_ADD, n - 1, h->status)));
     }
     if (L_bar) {
         // L_bar^r = psi^T * Rev(M_bar)
         HIP_TRY(fwd<double>(h, p, nl_of(d2), SP, src_real(psi, true, d2, (int)d2, 0, n)));
-        HIP_TRY(freq_gemm<double>(p, gdesc(d, d, r, 1, 0), SP, SM, SL, h->stream));
+        HIP_TRY(freq_gemm<double>(p, gdesc(h, d, d, r, 1, 0), SP, SM, SL, h->stream));
         HIP_TRY(inv<double>(h, p, nl_of(dr), SL, dst_real(L_bar, true, dr, (int)dr, 0, n, invL, OP_STORE, n - 1, h->status)));
     }
     return MRINV_OK;
@@ -1074,7 +1077,7 @@ extern "C" mrinv_status_t mrinv_residual_norms(mrinv_handle_t h, const double *q
     double *RL = cv.take<double>((size_t)n * d2 * 8);
     double *RR = cv.take<double>((size_t)n * d2 * 8);
     const double invL = 1.0 / (double)((int64_t)1 << p.lgL);
-    const GemmDesc g = gdesc(d, d, d);
+    const GemmDesc g = gdesc(h, d, d, d);
     HIP_TRY(fwd<double>(h, p, nl, SA, src_real(q, true, d2, (int)d2, 0, n, -1, d)));
     HIP_TRY(fwd<double>(h, p, nl, SX, src_real(X, true, d2, (int)d2, 0, n)));
     DstDesc dl = dst_real(RL, true, d2, (int)d2, 0, n, invL, OP_E0MINUS);
@@ -1147,12 +1150,12 @@ static void plan_fft(BatchPlan &bp, mrinv_handle_t h, int mode, const FftPlan &p
 
 template <typename T>
 static void plan_gemm(BatchPlan &bp, mrinv_handle_t h, const FftPlan &p, const std::vector<GemmProblem<T>> &probs) {
-    for (int cls = 1; cls <= 8; ++cls) {
+    for (int cls = 1; cls <= 12; ++cls) {
         std::vector<GemmProblem<T>> g;
         for (auto &q : probs)
-            if (gemm_sq_class(q.d) == cls) g.push_back(q);
+            if (gemm_sq_class(q.d, h ? h->tune.mfma : 1) == cls) g.push_back(q);
         if (g.empty()) continue;
-        const int64_t total = gemm_batch_layout<T>(p, g.data(), (int)g.size());
+        const int64_t total = gemm_batch_layout<T>(p, g.data(), (int)g.size(), h ? h->tune.mfma : 1);
         double bytes = 0, flops = 0;
         const double Lr = (double)((int64_t)1 << p.lgL);
         for (auto &q : g) {

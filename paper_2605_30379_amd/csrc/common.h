@@ -63,14 +63,6 @@ __device__ __forceinline__ cplx<T> twiddle(const Twiddles<T> &tw, uint32_t num, 
     return mk<T>((T)w.x, INV ? -(T)w.y : (T)w.y);
 }
 
-// exp(-+2 pi i j / 2^lg) for lg <= 9 from the root table.
-template <typename T, bool INV>
-__device__ __forceinline__ cplx<T> root_twiddle(const Twiddles<T> &tw, uint32_t j, int lg) {
-    if (!tw.root) return twiddle<T, INV>(tw, j, lg);
-    const double2 w = tw.root[j << (9 - lg)];
-    return mk<T>((T)w.x, INV ? -(T)w.y : (T)w.y);
-}
-
 // ---------------------------------------------------------------------------
 // In-register DFT of size R in natural order (R = 1, 2, 4, 8, 16), forward
 // (exp(-2 pi i/R)) or inverse (exp(+2 pi i/R)), unnormalised.  Radix-2
@@ -126,7 +118,8 @@ template <typename T, int R, bool INV> struct Dft {
             const int idx = k * (16 / R);
             const T c = (T)root16_cos(idx), s = (T)root16_sin(idx);
             cplx<T> w = mk<T>(c, INV ? s : -s);
-            cplx<T> t = (k == 0) ? o[k] : cmul<T>(w, o[k]);
+            // k / R = 1/4: w = -i (forward) or +i (inverse), a swap and a sign
+            cplx<T> t = (k == 0) ? o[k] : (4 * k == R) ? mul_mi<T, INV>(o[k]) : cmul<T>(w, o[k]);
             v[k] = cadd<T>(e[k], t);
             v[k + H] = csub<T>(e[k], t);
         }

@@ -24,27 +24,27 @@
 // the data between stages.
 #include <stdio.h>
 
+#include <type_traits>
+
 #include "common.h"
 #include "kernels.h"
 
 namespace mrinv {
 
-template <typename T>
-struct PassCtx {
-    cplx<T> *z;
-    int64_t base;   // row of r = 0 in this column
-    int64_t S;      // row stride inside the column
-    uint32_t m;     // column offset inside its block (twiddle index)
-    int lgB;
-    int lane;       // complex lane
-    bool lane_ok;
-    int nl;
-};
+// Number of elements of a register array (the stage radix) in the generic
+// load/store callbacks.
+#define MR_RADIX(v) ((int)std::extent<std::remove_reference_t<decltype(v)>>::value)
 
-// One Stockham stage of radix 2^LGR inside a 2^LGP-point transform.
-template <typename T, int LGR, bool INV, typename Load, typename Store>
-__device__ __forceinline__ void fft_stage(int LGP, int lgNs, int grp, const Load &load, const Store &store,
-                                          const Twiddles<T> &tw, bool sync_between) {
+// One Stockham stage of radix R = 2^LGR inside a 2^LGP-point transform.
+// Group j = grp reads its elements j + r 2^(LGP-LGR) (r < R) through
+// load_all(j, LGP - LGR, v), multiplies element r by the stage twiddle
+// W_{2^(lgNs+LGR)}^{k r} (k = j mod 2^lgNs, from the workgroup's table
+// roots[i] = W_P^i), runs the R-point DFT and writes elements b + r 2^lgNs
+// through store_all(b, lgNs, v).  The callbacks issue all R memory accesses
+// before any result is used.
+template <typename T, int LGR, bool INV, typename LoadAll, typename StoreAll>
+__device__ __forceinline__ void fft_stage(int LGP, int lgNs, int grp, const LoadAll &load_all,
+                                          const StoreAll &store_all, const cplx<T> *roots, bool sync_between) {
     constexpr int R = 1 << LGR;
     const int nbf = 1 << (LGP - LGR);
     const bool active = grp < nbf;
@@ -52,112 +52,59 @@ __device__ __forceinline__ void fft_stage(int LGP, int lgNs, int grp, const Load
     const int j = grp;
     const int k0 = j & ((1 << lgNs) - 1);
     if (active) {
-#pragma unroll
-        for (int r = 0; r < R; ++r) v[r] = load(j + (r << (LGP - LGR)));
+        load_all(j, LGP - LGR, v);
         if (lgNs > 0) {
+            const int sh = LGP - lgNs - LGR;
 #pragma unroll
-            for (int r = 1; r < R; ++r) v[r] = cmul<T>(v[r], root_twiddle<T, INV>(tw, (uint32_t)(k0 * r), lgNs + LGR));
+            for (int r = 1; r < R; ++r) {
+                const cplx<T> w = roots[(k0 * r) << sh];
+                v[r] = INV ? cmulc<T>(v[r], w) : cmul<T>(v[r], w);
+            }
         }
         Dft<T, R, INV>::run(v);
     }
     if (sync_between) __syncthreads();
-    if (active) {
-        const int base = ((j >> lgNs) << (lgNs + LGR)) + k0;
-#pragma unroll
-        for (int r = 0; r < R; ++r) store(base + (r << lgNs), v[r]);
-    }
+    if (active) store_all(((j >> lgNs) << (lgNs + LGR)) + k0, lgNs, v);
 }
 
-// Full 2^LGP-point DFT of one column of C lanes.  gload(idx) / gstore(idx, v)
-// access natural-order element idx; src_lds / dst_lds say whether they are
-// the LDS buffer itself (then stages that read and write it synchronise).
+// Full 2^LGP-point DFT of one column of C lanes.  gload_all / gstore_all
+// access natural-order elements (see fft_stage); src_lds / dst_lds say whether
+// they are the LDS tile itself (then stages that read and write it
+// synchronise).
 template <typename T, int LGP, bool INV, typename GL, typename GS>
-__device__ __forceinline__ void wg_fft(cplx<T> *lds, int lds_stride, int c, int grp, const GL &gload,
-                                       const GS &gstore, bool src_lds, bool dst_lds, const Twiddles<T> &tw) {
+__device__ __forceinline__ void wg_fft(cplx<T> *lds, int lds_stride, int c, int grp, const GL &gload_all,
+                                       const GS &gstore_all, bool src_lds, bool dst_lds, const cplx<T> *roots) {
     constexpr int NS = num_stages(LGP);
     constexpr int R0 = stage_lg(LGP, 0), R1 = stage_lg(LGP, 1), R2 = stage_lg(LGP, 2);
-    auto lload = [&](int idx) { return lds[idx * lds_stride + c]; };
-    auto lstore = [&](int idx, cplx<T> v) { lds[idx * lds_stride + c] = v; };
+    auto lload_all = [&](int j, int lgs, auto &v) {
+#pragma unroll
+        for (int r = 0; r < MR_RADIX(v); ++r) v[r] = lds[(j + (r << lgs)) * lds_stride + c];
+    };
+    auto lstore_all = [&](int b, int lgs, auto &v) {
+#pragma unroll
+        for (int r = 0; r < MR_RADIX(v); ++r) lds[(b + (r << lgs)) * lds_stride + c] = v[r];
+    };
     if constexpr (NS == 1) {
-        fft_stage<T, R0, INV>(LGP, 0, grp, gload, gstore, tw, src_lds && dst_lds);
+        fft_stage<T, R0, INV>(LGP, 0, grp, gload_all, gstore_all, roots, src_lds && dst_lds);
     } else if constexpr (NS == 2) {
-        fft_stage<T, R0, INV>(LGP, 0, grp, gload, lstore, tw, src_lds);
+        fft_stage<T, R0, INV>(LGP, 0, grp, gload_all, lstore_all, roots, src_lds);
         __syncthreads();
-        fft_stage<T, R1, INV>(LGP, R0, grp, lload, gstore, tw, dst_lds);
+        fft_stage<T, R1, INV>(LGP, R0, grp, lload_all, gstore_all, roots, dst_lds);
     } else {
-        fft_stage<T, R0, INV>(LGP, 0, grp, gload, lstore, tw, src_lds);
+        fft_stage<T, R0, INV>(LGP, 0, grp, gload_all, lstore_all, roots, src_lds);
         __syncthreads();
-        fft_stage<T, R1, INV>(LGP, R0, grp, lload, lstore, tw, true);
+        fft_stage<T, R1, INV>(LGP, R0, grp, lload_all, lstore_all, roots, true);
         __syncthreads();
-        fft_stage<T, R2, INV>(LGP, R0 + R1, grp, lload, gstore, tw, dst_lds);
+        fft_stage<T, R2, INV>(LGP, R0 + R1, grp, lload_all, gstore_all, roots, dst_lds);
     }
 }
 
-template <typename T>
 __device__ __forceinline__ bool is_diag_lane(int e, int e0_d) {
     return e < e0_d * e0_d && (e % (e0_d + 1)) == 0;
 }
 
-// Read complex lane `lane` of real row t of the source (zero outside [lo, hi)).
-template <typename T>
-__device__ __forceinline__ cplx<T> load_real(const SrcDesc &s, int64_t t, int lane) {
-    if (t < s.lo || t >= s.hi) return mk<T>(0, 0);
-    const int64_t row = s.rev >= 0 ? s.rev - t : t;
-    const int e = 2 * lane;
-    T a = 0, b = 0;
-    if (s.kind == SRC_REAL64) {
-        const double *p = (const double *)s.p + row * s.ld;
-        a = (T)p[e];
-        if (e + 1 < s.nreal) b = (T)p[e + 1];
-    } else {
-        const float *p = (const float *)s.p + row * s.ld;
-        a = (T)p[e];
-        if (e + 1 < s.nreal) b = (T)p[e + 1];
-    }
-    if (s.e0_d > 0) {
-        a = (t == 0 && is_diag_lane<T>(e, s.e0_d) ? (T)1 : (T)0) - a;
-        b = (e + 1 < s.nreal) ? ((t == 0 && is_diag_lane<T>(e + 1, s.e0_d) ? (T)1 : (T)0) - b) : (T)0;
-    }
-    return mk<T>(a, b);
-}
-
 __device__ __forceinline__ void flag_nonfinite(unsigned int *status, double a, double b) {
     if (status && (!isfinite(a) || !isfinite(b))) atomicOr(status, STATUS_NONFINITE);
-}
-
-// Write complex lane `lane` (two real entries) of real row t of the destination.
-template <typename T>
-__device__ __forceinline__ void store_real(const DstDesc &d, int64_t t, int lane, cplx<T> v) {
-    if (t < d.lo || t >= d.hi) return;
-    const int64_t row = d.rev >= 0 ? d.rev - t : t;
-    const int e = 2 * lane;
-    const bool two = e + 1 < d.nreal;
-    double a = (double)v.x * d.scale, b = (double)v.y * d.scale;
-    switch (d.op) {
-        case OP_NEG: a = -a; b = -b; break;
-        case OP_E0MINUS:
-            a = (t == 0 && is_diag_lane<T>(e, d.e0_d) ? 1.0 : 0.0) - a;
-            b = (t == 0 && is_diag_lane<T>(e + 1, d.e0_d) ? 1.0 : 0.0) - b;
-            break;
-        default: break;
-    }
-    if (d.op == OP_XPLUS) {
-        const float *x = (const float *)d.aux + row * d.ld;
-        a += (double)x[e];
-        if (two) b += (double)x[e + 1];
-    }
-    if (d.kind == DST_REAL64) {
-        double *p = (double *)d.p + row * d.ld;
-        if (d.op == OP_ADD) { a += p[e]; if (two) b += p[e + 1]; }
-        p[e] = a;
-        if (two) p[e + 1] = b;
-    } else {
-        float *p = (float *)d.p + row * d.ld;
-        if (d.op == OP_ADD) { a += p[e]; if (two) b += p[e + 1]; }
-        p[e] = (float)a;
-        if (two) p[e + 1] = (float)b;
-    }
-    flag_nonfinite(d.status, a, two ? b : 0.0);
 }
 
 // MODE 0: forward pass; MODE 1: inverse pass; MODE 2: inverse pass, then the
@@ -167,9 +114,12 @@ __device__ __forceinline__ void store_real(const DstDesc &d, int64_t t, int lane
 template <typename T, int LGP, int C, int MODE>
 __device__ __forceinline__ void fft_pass_body(cplx<T> *z, const PassGeom &g, int nl, int nchunks, int64_t blk,
                                               const SrcDesc &src, const DstDesc &dst, const Twiddles<T> &tw) {
+    constexpr int P = 1 << LGP;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cplx<T> *lds = reinterpret_cast<cplx<T> *>(smem_raw);
     constexpr int LDS_STRIDE = C + 1;
+    cplx<T> *tws = lds + P * LDS_STRIDE;   // outer twiddles of this column
+    cplx<T> *roots = tws + P;              // roots[i] = W_P^i
     const int c = threadIdx.x % C;
     const int grp = threadIdx.x / C;
     int chunk;
@@ -188,57 +138,202 @@ __device__ __forceinline__ void fft_pass_body(cplx<T> *z, const PassGeom &g, int
     const int64_t base = b * ((int64_t)1 << g.lgB) + m;
     const int lane = chunk * C + c;
     const bool lane_ok = lane < nl;
+    // Lanes past nl read a valid lane and never store.
+    const int lane_c = lane_ok ? lane : nl - 1;
+    const int64_t rs = S * nl;                        // elements from row idx to row idx + 1
+    cplx<T> *zc = z + base * nl + lane_c;
 
-    // Forward twiddle on output r: W_B^{m r}; inverse on input r: W_B^{-m r},
-    // from the pass's table when there is one.
-    const cplx<T> *otw = reinterpret_cast<const cplx<T> *>(tw.outer) + ((size_t)m << LGP);
-    auto outer = [&](int idx, bool inv) {
-        if (tw.outer) {
-            const cplx<T> w = otw[idx];
-            return inv ? cconj<T>(w) : w;
+    // Forward twiddle on output r: W_B^{m r}; inverse on input r: W_B^{-m r}.
+    // They depend on the column only, so the workgroup forms its P outer
+    // twiddles (from the pass's table when there is one) and the P roots of
+    // its in-workgroup stages once; every lane reads them from LDS.
+    {
+        const cplx<T> *otw = reinterpret_cast<const cplx<T> *>(tw.outer) + ((size_t)m << LGP);
+        for (int i = threadIdx.x; i < P; i += blockDim.x) {
+            if (m) tws[i] = tw.outer ? otw[i] : twiddle<T, false>(tw, m * (uint32_t)i, g.lgB);
+            if (tw.root) {
+                const double2 w = tw.root[i << (9 - LGP)];
+                roots[i] = mk<T>((T)w.x, (T)w.y);
+            } else {
+                roots[i] = twiddle<T, false>(tw, (uint32_t)i, LGP);
+            }
         }
-        return inv ? twiddle<T, true>(tw, m * (uint32_t)idx, g.lgB) : twiddle<T, false>(tw, m * (uint32_t)idx, g.lgB);
+    }
+    __syncthreads();
+
+    auto z_load_all = [&](int j, int lgs, auto &v) {
+        const cplx<T> *q = zc + (int64_t)j * rs;
+        const int64_t step = rs << lgs;
+#pragma unroll
+        for (int r = 0; r < MR_RADIX(v); ++r) {
+            v[r] = *q;
+            q += step;
+        }
     };
-    auto fwd_store = [&](int idx, cplx<T> v) {
+    auto z_store_all = [&](int b0, int lgs, auto &v) {
         if (!lane_ok) return;
-        if (m) v = cmul<T>(v, outer(idx, false));
-        z[(base + idx * S) * nl + lane] = v;
+        cplx<T> *q = zc + (int64_t)b0 * rs;
+        const int64_t step = rs << lgs;
+#pragma unroll
+        for (int r = 0; r < MR_RADIX(v); ++r) {
+            *q = v[r];
+            q += step;
+        }
     };
-    auto inv_load = [&](int idx) {
-        if (!lane_ok) return mk<T>(0, 0);
-        cplx<T> v = z[(base + idx * S) * nl + lane];
-        if (m) v = cmul<T>(v, outer(idx, true));
-        return v;
+    auto fwd_store_all = [&](int b0, int lgs, auto &v) {
+        if (m) {
+#pragma unroll
+            for (int r = 0; r < MR_RADIX(v); ++r) v[r] = cmul<T>(v[r], tws[b0 + (r << lgs)]);
+        }
+        z_store_all(b0, lgs, v);
+    };
+    auto inv_load_all = [&](int j, int lgs, auto &v) {
+        z_load_all(j, lgs, v);
+        if (m) {
+#pragma unroll
+            for (int r = 0; r < MR_RADIX(v); ++r) v[r] = cmulc<T>(v[r], tws[j + (r << lgs)]);
+        }
     };
 
     if constexpr (MODE == 0) {
-        auto gload = [&](int idx) {
-            if (!lane_ok) return mk<T>(0, 0);
-            const int64_t row = base + idx * S;
-            if (src.kind == SRC_Z) return z[row * nl + lane];
-            return load_real<T>(src, row, lane);
+        // Real source: complex lane = entries (2 lane, 2 lane + 1) of row t
+        // (or rev - t), zero outside [lo, hi); e0 - source when e0_d > 0.
+        auto real_load_all = [&](int j, int lgs, auto &v) {
+            constexpr int R = MR_RADIX(v);
+            const int64_t t0 = base + (int64_t)j * S, dt = S << lgs;
+            const int e = 2 * lane_c;
+            const bool two = e + 1 < src.nreal;
+            const int64_t rstep = (src.rev >= 0 ? -dt : dt) * src.ld;
+            const int64_t row0 = src.rev >= 0 ? src.rev - t0 : t0;
+            if (src.kind == SRC_REAL64) {
+                const double *q = (const double *)src.p + row0 * src.ld + e;
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const int64_t t = t0 + r * dt;
+                    T a = 0, bb = 0;
+                    if (t >= src.lo && t < src.hi) {
+                        a = (T)q[0];
+                        if (two) bb = (T)q[1];
+                    }
+                    v[r] = mk<T>(a, bb);
+                    q += rstep;
+                }
+            } else {
+                const float *q = (const float *)src.p + row0 * src.ld + e;
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const int64_t t = t0 + r * dt;
+                    T a = 0, bb = 0;
+                    if (t >= src.lo && t < src.hi) {
+                        a = (T)q[0];
+                        if (two) bb = (T)q[1];
+                    }
+                    v[r] = mk<T>(a, bb);
+                    q += rstep;
+                }
+            }
+            if (src.e0_d > 0) {
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const int64_t t = t0 + r * dt;
+                    if (t < src.lo || t >= src.hi) continue;
+                    T a = -v[r].x, bb = two ? -v[r].y : (T)0;
+                    if (t == 0) {
+                        if (is_diag_lane(e, src.e0_d)) a += (T)1;
+                        if (two && is_diag_lane(e + 1, src.e0_d)) bb += (T)1;
+                    }
+                    v[r] = mk<T>(a, bb);
+                }
+            }
         };
-        wg_fft<T, LGP, false>(lds, LDS_STRIDE, c, grp, gload, fwd_store, false, false, tw);
+        auto gload_all = [&](int j, int lgs, auto &v) {
+            if (src.kind == SRC_Z) z_load_all(j, lgs, v);
+            else real_load_all(j, lgs, v);
+        };
+        wg_fft<T, LGP, false>(lds, LDS_STRIDE, c, grp, gload_all, fwd_store_all, false, false, roots);
     } else if constexpr (MODE == 1) {
-        auto gstore = [&](int idx, cplx<T> v) {
+        // Real destination: value = op(scale * v) (+ the old value or the
+        // float32 aux entry), rows t in [lo, hi) of row t (or rev - t).
+        auto real_store_all = [&](int b0, int lgs, auto &v) {
+            constexpr int R = MR_RADIX(v);
             if (!lane_ok) return;
-            const int64_t row = base + idx * S;
-            if (dst.kind == DST_Z) z[row * nl + lane] = v;
-            else store_real<T>(dst, row, lane, v);
+            const int64_t t0 = base + (int64_t)b0 * S, dt = S << lgs;
+            const int e = 2 * lane;
+            const bool two = e + 1 < dst.nreal;
+            const bool dbl = dst.kind == DST_REAL64;
+            double ax[R], bx[R];
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                ax[r] = 0.0;
+                bx[r] = 0.0;
+            }
+            if (dst.op == OP_ADD || dst.op == OP_XPLUS) {
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const int64_t t = t0 + r * dt;
+                    if (t < dst.lo || t >= dst.hi) continue;
+                    const int64_t row = dst.rev >= 0 ? dst.rev - t : t;
+                    if (dst.op == OP_XPLUS || !dbl) {
+                        const float *x = (const float *)(dst.op == OP_XPLUS ? dst.aux : dst.p) + row * dst.ld + e;
+                        ax[r] = (double)x[0];
+                        if (two) bx[r] = (double)x[1];
+                    } else {
+                        const double *x = (const double *)dst.p + row * dst.ld + e;
+                        ax[r] = x[0];
+                        if (two) bx[r] = x[1];
+                    }
+                }
+            }
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const int64_t t = t0 + r * dt;
+                if (t < dst.lo || t >= dst.hi) continue;
+                const int64_t row = dst.rev >= 0 ? dst.rev - t : t;
+                double a = (double)v[r].x * dst.scale, bb = (double)v[r].y * dst.scale;
+                if (dst.op == OP_NEG) {
+                    a = -a;
+                    bb = -bb;
+                } else if (dst.op == OP_E0MINUS) {
+                    a = (t == 0 && is_diag_lane(e, dst.e0_d) ? 1.0 : 0.0) - a;
+                    bb = (t == 0 && is_diag_lane(e + 1, dst.e0_d) ? 1.0 : 0.0) - bb;
+                }
+                a += ax[r];
+                bb += bx[r];
+                if (dbl) {
+                    double *p = (double *)dst.p + row * dst.ld + e;
+                    p[0] = a;
+                    if (two) p[1] = bb;
+                } else {
+                    float *p = (float *)dst.p + row * dst.ld + e;
+                    p[0] = (float)a;
+                    if (two) p[1] = (float)bb;
+                }
+                flag_nonfinite(dst.status, a, two ? bb : 0.0);
+            }
         };
-        wg_fft<T, LGP, true>(lds, LDS_STRIDE, c, grp, inv_load, gstore, false, false, tw);
+        auto gstore_all = [&](int b0, int lgs, auto &v) {
+            if (dst.kind == DST_Z) z_store_all(b0, lgs, v);
+            else real_store_all(b0, lgs, v);
+        };
+        wg_fft<T, LGP, true>(lds, LDS_STRIDE, c, grp, inv_load_all, gstore_all, false, false, roots);
     } else {
-        const T sc = (T)dst.scale;
-        auto mask_store = [&](int idx, cplx<T> v) {
-            const int64_t t = base + idx * S;
-            const bool keep = t >= dst.lo && t < dst.hi;
-            const T s = dst.op == OP_NEG ? -sc : sc;
-            lds[idx * LDS_STRIDE + c] = keep ? cscale<T>(v, s) : mk<T>(0, 0);
+        const T sc = dst.op == OP_NEG ? -(T)dst.scale : (T)dst.scale;
+        auto mask_store_all = [&](int b0, int lgs, auto &v) {
+#pragma unroll
+            for (int r = 0; r < MR_RADIX(v); ++r) {
+                const int idx = b0 + (r << lgs);
+                const int64_t t = base + idx * S;
+                const bool keep = t >= dst.lo && t < dst.hi;
+                lds[idx * LDS_STRIDE + c] = keep ? cscale<T>(v[r], sc) : mk<T>(0, 0);
+            }
         };
-        wg_fft<T, LGP, true>(lds, LDS_STRIDE, c, grp, inv_load, mask_store, false, true, tw);
+        wg_fft<T, LGP, true>(lds, LDS_STRIDE, c, grp, inv_load_all, mask_store_all, false, true, roots);
         __syncthreads();
-        auto lds_load = [&](int idx) { return lds[idx * LDS_STRIDE + c]; };
-        wg_fft<T, LGP, false>(lds, LDS_STRIDE, c, grp, lds_load, fwd_store, true, false, tw);
+        auto lds_load_all = [&](int j, int lgs, auto &v) {
+#pragma unroll
+            for (int r = 0; r < MR_RADIX(v); ++r) v[r] = lds[(j + (r << lgs)) * LDS_STRIDE + c];
+        };
+        wg_fft<T, LGP, false>(lds, LDS_STRIDE, c, grp, lds_load_all, fwd_store_all, true, false, roots);
     }
 }
 
@@ -299,11 +394,18 @@ static double pass_bytes(int mode, const PassGeom &g, const SrcDesc &src, const 
     return rd + wr;
 }
 
+// LDS of one pass workgroup: the P x C data tile (stride C + 1), the P outer
+// twiddles of its column and the P roots of its in-workgroup stages.
+template <typename T, int LGP, int C>
+static constexpr size_t pass_lds_bytes() {
+    return ((size_t)1 << LGP) * (C + 3) * sizeof(cplx<T>);
+}
+
 template <typename T, int LGP, int C, int MODE>
 static hipError_t launch_pass_t(cplx<T> *z, const PassGeom &g, const SrcDesc &src, const DstDesc &dst,
                                 const Twiddles<T> &tw, hipStream_t st) {
     const int threads = C << (LGP - min_stage_lg(LGP));
-    const size_t lds = (num_stages(LGP) > 1 || MODE == 2) ? ((size_t)1 << LGP) * (C + 1) * sizeof(cplx<T>) : 0;
+    const size_t lds = pass_lds_bytes<T, LGP, C>();
     auto kern = fft_pass_kernel<T, LGP, C, MODE>;
     static bool attr_set = false;
     if (!attr_set && lds > 64 * 1024) {
@@ -401,7 +503,7 @@ template <typename T, int LGP, int C, int MODE>
 static hipError_t launch_batched_t(const PassProblem<T> *probs, int nprob, int64_t total, const PassGeom &g,
                                    double bytes, const Twiddles<T> &tw, hipStream_t st) {
     const int threads = C << (LGP - min_stage_lg(LGP));
-    const size_t lds = (num_stages(LGP) > 1 || MODE == 2) ? ((size_t)1 << LGP) * (C + 1) * sizeof(cplx<T>) : 0;
+    const size_t lds = pass_lds_bytes<T, LGP, C>();
     auto kern = fft_pass_batched_kernel<T, LGP, C, MODE>;
     static bool attr_set = false;
     if (!attr_set && lds > 64 * 1024) {
@@ -422,7 +524,7 @@ template <typename T, int LGP, int C, int MODE>
 static hipError_t launch_pair_t(const PassProblem<T> &a, const PassProblem<T> &b, int64_t total, const PassGeom &g,
                                 double bytes, const Twiddles<T> &tw, hipStream_t st) {
     const int threads = C << (LGP - min_stage_lg(LGP));
-    const size_t lds = (num_stages(LGP) > 1 || MODE == 2) ? ((size_t)1 << LGP) * (C + 1) * sizeof(cplx<T>) : 0;
+    const size_t lds = pass_lds_bytes<T, LGP, C>();
     auto kern = fft_pass_pair_kernel<T, LGP, C, MODE>;
     static bool attr_set = false;
     if (!attr_set && lds > 64 * 1024) {

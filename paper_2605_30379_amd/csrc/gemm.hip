@@ -328,6 +328,265 @@ freq_gemm_sq_batched_kernel(const GemmProblem<T> *probs, int nprob, FftPlan plan
     freq_gemm_sq_body<T, DP>(pp.A, pp.B, pp.C, plan, pp.d, bid - pp.wg_begin);
 }
 
+// ---------------------------------------------------------------------------
+// Matrix-core form of the square products (d > 8).  The complex product
+// C = A B is four real products on the 16x16x4 MFMA tiles,
+//     Re C = Re A Re B - Im A Im B,   Im C = Re A Im B + Im A Re B,
+// accumulated in the working precision (FP64 MFMA for the FP64 path, FP32
+// MFMA for the FP32 path).  The matrix is padded to DP = 16 * ceil(d / 16);
+// wave w of a frequency owns the 16-row strip I = w of C (DP/16 output tiles),
+// the contraction is staged through LDS in chunks of 16.
+//
+// Operand and accumulator layouts of the 16x16x4 instructions (lane l):
+//     A[i][k] at lane i + 16 k,  B[k][j] at lane j + 16 k,
+//     FP64: accumulator r holds C[l/16 + 4r][l % 16],
+//     FP32: accumulator r holds C[4 (l/16) + r][l % 16].
+// ---------------------------------------------------------------------------
+typedef double mf_d4 __attribute__((ext_vector_type(4)));
+typedef float mf_f4 __attribute__((ext_vector_type(4)));
+
+template <typename T> struct MfmaOp;
+template <> struct MfmaOp<double> {
+    using V = mf_d4;
+    __device__ static __forceinline__ V mac(double a, double b, V c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    __device__ static __forceinline__ int row(int l, int r) { return (l >> 4) + 4 * r; }
+};
+template <> struct MfmaOp<float> {
+    using V = mf_f4;
+    __device__ static __forceinline__ V mac(float a, float b, V c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    __device__ static __forceinline__ int row(int l, int r) { return 4 * (l >> 4) + r; }
+};
+
+template <int DP> struct MfCfg {
+    static constexpr int WPF = DP / 16;                  // waves per frequency
+    static constexpr int NF = WPF >= 3 ? 1 : 4 / WPF;    // frequencies per workgroup
+    static constexpr int THREADS = 64 * WPF * NF;
+    static constexpr int KC = 16;                        // contraction chunk
+    static constexpr int LDA = KC + 1;                   // As[f][i][t], i < DP, t < KC
+    static constexpr int LDB = DP + 1;                   // Bs[f][t][j]
+    static constexpr int AS = DP * LDA;
+    static constexpr int BS = KC * LDB;
+};
+
+// LDS bytes of one workgroup; odd d stages C (d*d complex per frequency).
+template <typename T, int DP>
+static size_t mf_lds_bytes(int dmax_odd) {
+    using Cfg = MfCfg<DP>;
+    const size_t ab = (size_t)Cfg::NF * (Cfg::AS + Cfg::BS) * sizeof(cplx<T>);
+    const size_t cs = (size_t)Cfg::NF * ((size_t)dmax_odd * dmax_odd + 1) * sizeof(cplx<T>);
+    return cs > ab ? cs : ab;
+}
+
+template <typename T, int DP>
+__device__ __forceinline__ void freq_gemm_mfma_body(const cplx<T> *__restrict__ ZA, const cplx<T> *__restrict__ ZB,
+                                                    cplx<T> *__restrict__ ZC, const FftPlan &plan, int d,
+                                                    int64_t blk) {
+    using Cfg = MfCfg<DP>;
+    using Op = MfmaOp<T>;
+    using V = typename Op::V;
+    constexpr int WPF = Cfg::WPF, NF = Cfg::NF, KC = Cfg::KC, NT = Cfg::THREADS;
+    constexpr int LDA = Cfg::LDA, LDB = Cfg::LDB;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    cplx<T> *As = reinterpret_cast<cplx<T> *>(smem_raw);
+    cplx<T> *Bs = As + NF * Cfg::AS;
+    __shared__ int64_t rows1[NF], rows2[NF];
+    const int64_t L = (int64_t)1 << plan.lgL;
+    const int64_t F = L / 2 + 1;
+    const int64_t k0 = blk * NF;
+    const int tid = threadIdx.x;
+    const int nl = (d * d + 1) >> 1;
+    if (tid < NF) {
+        const int64_t k = k0 + tid;
+        rows1[tid] = k < F ? freq_row(plan, k) : 0;
+        rows2[tid] = k < F ? freq_row(plan, (L - k) & (L - 1)) : 0;
+    }
+    __syncthreads();
+    const int l = tid & 63, w = tid >> 6;
+    const int f = w / WPF, I = w - f * WPF;
+    const bool even = (d & 1) == 0;
+    V accR[WPF], accI[WPF];
+#pragma unroll
+    for (int J = 0; J < WPF; ++J)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) accR[J][r] = accI[J][r] = (T)0;
+
+    for (int kc = 0; kc < d; kc += KC) {
+        if (even) {
+            // Pairs of entries (e, e+1) share one packed lane: one load pair each.
+            constexpr int PA = DP * (KC / 2), PB = KC * (DP / 2);
+            for (int idx = tid; idx < NF * PA; idx += NT) {
+                const int ff = idx / PA, p = idx - ff * PA;
+                const int i = p / (KC / 2), t = 2 * (p - i * (KC / 2));
+                cplx<T> ev = mk<T>(0, 0), od = mk<T>(0, 0);
+                if (i < d && kc + t < d && k0 + ff < F) {
+                    const int c = (i * d + kc + t) >> 1;
+                    const cplx<T> z1 = ZA[rows1[ff] * nl + c], z2 = ZA[rows2[ff] * nl + c];
+                    ev = mk<T>((z1.x + z2.x) * (T)0.5, (z1.y - z2.y) * (T)0.5);
+                    od = mk<T>((z1.y + z2.y) * (T)0.5, (z2.x - z1.x) * (T)0.5);
+                }
+                cplx<T> *dst = As + ff * Cfg::AS + i * LDA + t;
+                dst[0] = ev;
+                dst[1] = od;
+            }
+            for (int idx = tid; idx < NF * PB; idx += NT) {
+                const int ff = idx / PB, p = idx - ff * PB;
+                const int t = p / (DP / 2), j = 2 * (p - t * (DP / 2));
+                cplx<T> ev = mk<T>(0, 0), od = mk<T>(0, 0);
+                if (j < d && kc + t < d && k0 + ff < F) {
+                    const int c = ((kc + t) * d + j) >> 1;
+                    const cplx<T> z1 = ZB[rows1[ff] * nl + c], z2 = ZB[rows2[ff] * nl + c];
+                    ev = mk<T>((z1.x + z2.x) * (T)0.5, (z1.y - z2.y) * (T)0.5);
+                    od = mk<T>((z1.y + z2.y) * (T)0.5, (z2.x - z1.x) * (T)0.5);
+                }
+                cplx<T> *dst = Bs + ff * Cfg::BS + t * LDB + j;
+                dst[0] = ev;
+                dst[1] = od;
+            }
+        } else {
+            for (int idx = tid; idx < NF * DP * KC; idx += NT) {
+                const int ff = idx / (DP * KC), p = idx - ff * (DP * KC);
+                const int i = p / KC, t = p - i * KC;
+                cplx<T> v = mk<T>(0, 0);
+                if (i < d && kc + t < d && k0 + ff < F) v = unpack<T>(ZA, nl, rows1[ff], rows2[ff], i * d + kc + t);
+                As[ff * Cfg::AS + i * LDA + t] = v;
+            }
+            for (int idx = tid; idx < NF * KC * DP; idx += NT) {
+                const int ff = idx / (KC * DP), p = idx - ff * (KC * DP);
+                const int t = p / DP, j = p - t * DP;
+                cplx<T> v = mk<T>(0, 0);
+                if (j < d && kc + t < d && k0 + ff < F) v = unpack<T>(ZB, nl, rows1[ff], rows2[ff], (kc + t) * d + j);
+                Bs[ff * Cfg::BS + t * LDB + j] = v;
+            }
+        }
+        __syncthreads();
+        const cplx<T> *Af = As + f * Cfg::AS + (I * 16 + (l & 15)) * LDA;
+        const cplx<T> *Bf = Bs + f * Cfg::BS + (l & 15);
+#pragma unroll
+        for (int ks = 0; ks < KC / 4; ++ks) {
+            const int t = 4 * ks + (l >> 4);
+            const cplx<T> a = Af[t];
+#pragma unroll
+            for (int J = 0; J < WPF; ++J) {
+                const cplx<T> b = Bf[t * LDB + J * 16];
+                accR[J] = Op::mac(a.x, b.x, accR[J]);
+                accR[J] = Op::mac(-a.y, b.y, accR[J]);
+                accI[J] = Op::mac(a.x, b.y, accI[J]);
+                accI[J] = Op::mac(a.y, b.x, accI[J]);
+            }
+        }
+        __syncthreads();
+    }
+
+    const bool fok = k0 + f < F;
+    if (even) {
+        // Entries (i, j) and (i, j^1) sit in lanes l and l^1 of the same
+        // accumulator element: the even lane writes row k, the odd lane row L-k.
+        const int64_t r1 = rows1[f], r2 = rows2[f];
+        const bool odd_lane = (l & 1) != 0;
+#pragma unroll
+        for (int J = 0; J < WPF; ++J) {
+            const int j = J * 16 + (l & 15);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int i = I * 16 + Op::row(l, r);
+                const T vr = accR[J][r], vi = accI[J][r];
+                const T pr = __shfl_xor(vr, 1), pi = __shfl_xor(vi, 1);
+                if (fok && i < d && j < d) {
+                    const int c = (i * d + (j & ~1)) >> 1;
+                    if (!odd_lane) ZC[r1 * nl + c] = mk<T>(vr - pi, vi + pr);
+                    else if (r2 != r1) ZC[r2 * nl + c] = mk<T>(pr + vi, vr - pi);
+                }
+            }
+        }
+    } else {
+        cplx<T> *Cs = As;   // [NF][d*d + 1]
+        const int ld = d * d + 1;
+#pragma unroll
+        for (int J = 0; J < WPF; ++J) {
+            const int j = J * 16 + (l & 15);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int i = I * 16 + Op::row(l, r);
+                if (i < d && j < d) Cs[f * ld + i * d + j] = mk<T>(accR[J][r], accI[J][r]);
+            }
+        }
+        __syncthreads();
+        for (int idx = tid; idx < NF * nl; idx += NT) {
+            const int ff = idx / nl, c = idx - ff * nl;
+            if (k0 + ff >= F) continue;
+            const int e = 2 * c;
+            const cplx<T> ce = Cs[ff * ld + e];
+            const cplx<T> co = (e + 1 < d * d) ? Cs[ff * ld + e + 1] : mk<T>(0, 0);
+            pack_store<T>(ZC, nl, rows1[ff], rows2[ff], c, ce, co);
+        }
+    }
+}
+
+template <typename T, int DP>
+__global__ void __launch_bounds__(MfCfg<DP>::THREADS)
+freq_gemm_mfma_kernel(const cplx<T> *__restrict__ ZA, const cplx<T> *__restrict__ ZB, cplx<T> *__restrict__ ZC,
+                      FftPlan plan, int d) {
+    freq_gemm_mfma_body<T, DP>(ZA, ZB, ZC, plan, d, blockIdx.x);
+}
+
+template <typename T, int DP>
+__global__ void __launch_bounds__(MfCfg<DP>::THREADS)
+freq_gemm_mfma_batched_kernel(const GemmProblem<T> *probs, int nprob, FftPlan plan) {
+    int lo = 0, hi = nprob - 1;
+    const int64_t bid = blockIdx.x;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (probs[mid].wg_begin <= bid) lo = mid;
+        else hi = mid - 1;
+    }
+    const GemmProblem<T> &pp = probs[lo];
+    freq_gemm_mfma_body<T, DP>(pp.A, pp.B, pp.C, plan, pp.d, bid - pp.wg_begin);
+}
+
+template <typename T, int DP>
+static hipError_t launch_gemm_mfma(const FftPlan &plan, int d, const cplx<T> *ZA, const cplx<T> *ZB, cplx<T> *ZC,
+                                   hipStream_t st) {
+    using Cfg = MfCfg<DP>;
+    const size_t lds = mf_lds_bytes<T, DP>((d & 1) ? d : 0);
+    auto kern = freq_gemm_mfma_kernel<T, DP>;
+    if (lds > 64 * 1024) {
+        (void)hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        (void)hipGetLastError();
+    }
+    const int64_t F = ((int64_t)1 << plan.lgL) / 2 + 1;
+    const int64_t blocks = (F + Cfg::NF - 1) / Cfg::NF;
+    char name[96];
+    snprintf(name, sizeof name, "freq_gemm_mfma_kernel<%s, %d>", sizeof(T) == 8 ? "double" : "float", DP);
+    const double Lr = (double)((int64_t)1 << plan.lgL);
+    const int nl = (d * d + 1) / 2;
+    launch_begin(name, Lr * 3.0 * nl * sizeof(cplx<T>), (double)F * 8.0 * d * d * d);
+    hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(Cfg::THREADS), lds, st, ZA, ZB, ZC, plan, d);
+    launch_end();
+    return hipGetLastError();
+}
+
+template <typename T, int DP>
+static hipError_t launch_gemm_mfma_batched(const FftPlan &plan, const GemmProblem<T> *probs, int nprob,
+                                           int64_t total, double bytes, double flops, hipStream_t st) {
+    using Cfg = MfCfg<DP>;
+    const size_t lds = mf_lds_bytes<T, DP>(DP - 1);
+    auto kern = freq_gemm_mfma_batched_kernel<T, DP>;
+    if (lds > 64 * 1024) {
+        (void)hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        (void)hipGetLastError();
+    }
+    char name[96];
+    snprintf(name, sizeof name, "freq_gemm_mfma_batched_kernel<%s, %d>", sizeof(T) == 8 ? "double" : "float", DP);
+    launch_begin(name, bytes, flops);
+    hipLaunchKernelGGL(kern, dim3((unsigned)total), dim3(Cfg::THREADS), lds, st, probs, nprob, plan);
+    launch_end();
+    return hipGetLastError();
+}
+
 template <typename T, int DP>
 static size_t sq_lds_bytes(int dmax_odd) {
     using Cfg = SqCfg<DP>;
@@ -350,15 +609,21 @@ static hipError_t launch_gemm_sq_batched(const FftPlan &plan, const GemmProblem<
     return hipGetLastError();
 }
 
-int gemm_sq_class(int d) { return (d + 7) / 8; }
+// Product class of dimension d: 1..8 = vector kernel padded to 8*cls,
+// 9..12 = matrix-core kernel padded to 16*(cls-8).  mfma: 0 never, 1 when the
+// 16-padding adds fewer than 8 rows and columns, 2 always (d > 8).
+int gemm_sq_class(int d, int mfma) {
+    if (d > 8 && d <= 64 && (mfma == 2 || (mfma == 1 && (d % 16 == 0 || d % 16 > 8)))) return 8 + (d + 15) / 16;
+    return (d + 7) / 8;
+}
 
 template <typename T>
-int64_t gemm_batch_layout(const FftPlan &plan, GemmProblem<T> *probs, int nprob) {
+int64_t gemm_batch_layout(const FftPlan &plan, GemmProblem<T> *probs, int nprob, int mfma) {
     const int64_t F = ((int64_t)1 << plan.lgL) / 2 + 1;
     int64_t acc = 0;
     for (int i = 0; i < nprob; ++i) {
         int nf = 1;
-        switch (gemm_sq_class(probs[i].d)) {
+        switch (gemm_sq_class(probs[i].d, mfma)) {
             case 1: nf = SqCfg<8>::NF; break;
             case 2: nf = SqCfg<16>::NF; break;
             case 3: nf = SqCfg<24>::NF; break;
@@ -366,7 +631,11 @@ int64_t gemm_batch_layout(const FftPlan &plan, GemmProblem<T> *probs, int nprob)
             case 5: nf = SqCfg<40>::NF; break;
             case 6: nf = SqCfg<48>::NF; break;
             case 7: nf = SqCfg<56>::NF; break;
-            default: nf = SqCfg<64>::NF; break;
+            case 8: nf = SqCfg<64>::NF; break;
+            case 9: nf = MfCfg<16>::NF; break;
+            case 10: nf = MfCfg<32>::NF; break;
+            case 11: nf = MfCfg<48>::NF; break;
+            default: nf = MfCfg<64>::NF; break;
         }
         probs[i].wg_begin = acc;
         acc += (F + nf - 1) / nf;
@@ -385,12 +654,16 @@ hipError_t freq_gemm_batched(const FftPlan &plan, int dclass, const GemmProblem<
         case 5: return launch_gemm_sq_batched<T, 40>(plan, probs, nprob, total, bytes, flops, st);
         case 6: return launch_gemm_sq_batched<T, 48>(plan, probs, nprob, total, bytes, flops, st);
         case 7: return launch_gemm_sq_batched<T, 56>(plan, probs, nprob, total, bytes, flops, st);
-        default: return launch_gemm_sq_batched<T, 64>(plan, probs, nprob, total, bytes, flops, st);
+        case 8: return launch_gemm_sq_batched<T, 64>(plan, probs, nprob, total, bytes, flops, st);
+        case 9: return launch_gemm_mfma_batched<T, 16>(plan, probs, nprob, total, bytes, flops, st);
+        case 10: return launch_gemm_mfma_batched<T, 32>(plan, probs, nprob, total, bytes, flops, st);
+        case 11: return launch_gemm_mfma_batched<T, 48>(plan, probs, nprob, total, bytes, flops, st);
+        default: return launch_gemm_mfma_batched<T, 64>(plan, probs, nprob, total, bytes, flops, st);
     }
 }
 
-template int64_t gemm_batch_layout<double>(const FftPlan &, GemmProblem<double> *, int);
-template int64_t gemm_batch_layout<float>(const FftPlan &, GemmProblem<float> *, int);
+template int64_t gemm_batch_layout<double>(const FftPlan &, GemmProblem<double> *, int, int);
+template int64_t gemm_batch_layout<float>(const FftPlan &, GemmProblem<float> *, int, int);
 template hipError_t freq_gemm_batched<double>(const FftPlan &, int, const GemmProblem<double> *, int, int64_t,
                                               double, double, hipStream_t);
 template hipError_t freq_gemm_batched<float>(const FftPlan &, int, const GemmProblem<float> *, int, int64_t, double,
@@ -415,9 +688,9 @@ static hipError_t launch_gemm_sq(const FftPlan &plan, int d, const cplx<T> *ZA, 
 }
 
 template <typename T>
-static hipError_t gemm_sq(const FftPlan &plan, int d, const cplx<T> *ZA, const cplx<T> *ZB, cplx<T> *ZC,
+static hipError_t gemm_sq(const FftPlan &plan, int d, int mfma, const cplx<T> *ZA, const cplx<T> *ZB, cplx<T> *ZC,
                           hipStream_t st) {
-    switch ((d + 7) / 8) {
+    switch (gemm_sq_class(d, mfma)) {
         case 1: return launch_gemm_sq<T, 8>(plan, d, ZA, ZB, ZC, st);
         case 2: return launch_gemm_sq<T, 16>(plan, d, ZA, ZB, ZC, st);
         case 3: return launch_gemm_sq<T, 24>(plan, d, ZA, ZB, ZC, st);
@@ -425,7 +698,11 @@ static hipError_t gemm_sq(const FftPlan &plan, int d, const cplx<T> *ZA, const c
         case 5: return launch_gemm_sq<T, 40>(plan, d, ZA, ZB, ZC, st);
         case 6: return launch_gemm_sq<T, 48>(plan, d, ZA, ZB, ZC, st);
         case 7: return launch_gemm_sq<T, 56>(plan, d, ZA, ZB, ZC, st);
-        default: return launch_gemm_sq<T, 64>(plan, d, ZA, ZB, ZC, st);
+        case 8: return launch_gemm_sq<T, 64>(plan, d, ZA, ZB, ZC, st);
+        case 9: return launch_gemm_mfma<T, 16>(plan, d, ZA, ZB, ZC, st);
+        case 10: return launch_gemm_mfma<T, 32>(plan, d, ZA, ZB, ZC, st);
+        case 11: return launch_gemm_mfma<T, 48>(plan, d, ZA, ZB, ZC, st);
+        default: return launch_gemm_mfma<T, 64>(plan, d, ZA, ZB, ZC, st);
     }
 }
 
@@ -433,7 +710,7 @@ template <typename T>
 hipError_t freq_gemm(const FftPlan &plan, const GemmDesc &g, const cplx<T> *ZA, const cplx<T> *ZB, cplx<T> *ZC,
                      hipStream_t st) {
     if (g.ra == g.m && g.m == g.cb && !g.transA && !g.transB && g.ra <= 64)
-        return gemm_sq<T>(plan, g.ra, ZA, ZB, ZC, st);
+        return gemm_sq<T>(plan, g.ra, g.mfma, ZA, ZB, ZC, st);
     const int dmax = g.ra > g.cb ? g.ra : g.cb;
     if (dmax <= 8) return launch_gemm<T, 1, 1>(plan, g, ZA, ZB, ZC, st);
     if (dmax <= 24) return launch_gemm<T, 2, 2>(plan, g, ZA, ZB, ZC, st);

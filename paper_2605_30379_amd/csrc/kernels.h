@@ -151,15 +151,17 @@ struct GemmDesc {
     int ra, m, cb;          // C[ra x cb] = A[ra x m] * B[m x cb]
     int transA, transB;     // operand stored transposed (A stored m x ra, B stored cb x m)
     int nlA, nlB, nlC;      // complex lanes of the stored sequences
+    int mfma;               // square products: 0 vector kernel, 1 matrix cores where the padding is small, 2 always
 };
 template <typename T>
 hipError_t freq_gemm(const FftPlan &plan, const GemmDesc &g, const cplx<T> *ZA, const cplx<T> *ZB, cplx<T> *ZC,
                      hipStream_t st);
-// Square products of many problems with the same padded dimension class
-// (d rounded up to a multiple of 8) in one launch.
-int gemm_sq_class(int d);
+// Square products of many problems with the same product class (vector
+// kernel with d rounded up to a multiple of 8, or matrix-core kernel with d
+// rounded up to a multiple of 16) in one launch.
+int gemm_sq_class(int d, int mfma);
 template <typename T>
-int64_t gemm_batch_layout(const FftPlan &plan, GemmProblem<T> *host_probs, int nprob);
+int64_t gemm_batch_layout(const FftPlan &plan, GemmProblem<T> *host_probs, int nprob, int mfma);
 template <typename T>
 hipError_t freq_gemm_batched(const FftPlan &plan, int dclass, const GemmProblem<T> *dev_probs, int nprob,
                              int64_t total_wg, double bytes, double flops, hipStream_t st);

@@ -361,3 +361,50 @@ def test_graph_replays_match_eager(mr, precision):
         mr.sync_status()
     finally:
         mr.set_tuning(**base)
+
+
+@pytest.mark.parametrize("d", [9, 12, 16, 24, 25, 31, 32, 40, 47, 48, 57, 63, 64])
+def test_matrix_core_products_match_oracle(mr, orc, d):
+    """Square frequency-domain products on the matrix cores (mfma = 2), on
+    the vector kernels (mfma = 0) and the default choice (mfma = 1), in FP64
+    and in the mixed form, odd and even d, all against the oracle; the two
+    FP64 kernels agree to rounding."""
+    n = 300
+    print(f"[mfma] d={d} n={n}", flush=True)
+    q = si.family_kernel("lognormal" if d % 2 else "weibull", d, n, 700 + d).q
+    ref = orc.psi(q.numpy())
+    qg = _gpu(q)
+    base = mr.get_tuning()
+    got = {}
+    try:
+        for mode in (0, 1, 2):
+            mr.set_tuning(mfma=mode)
+            for prec in ("fp64", "mixed"):
+                o = _np(mr.psi_inverse(qg, prec, check=True))
+                tol = FP64_TOL if prec == "fp64" else MIXED_TOL
+                assert _maxerr(o, ref) <= tol, (mode, prec)
+                got[mode, prec] = o
+    finally:
+        mr.set_tuning(**base)
+    assert _maxerr(got[0, "fp64"], got[2, "fp64"]) <= 1e-13
+
+
+def test_matrix_core_batched_matches_single_calls(mr, orc):
+    """With every product class on the matrix cores, the batched call still
+    equals the single-problem calls bitwise (same kernel bodies)."""
+    specs = [(9, 100), (16, 257), (23, 64), (32, 130), (41, 40), (64, 33), (5, 77)]
+    qs = [si.family_kernel("weibull", d, n, 800 + i).q.cuda() for i, (d, n) in enumerate(specs)]
+    base = mr.get_tuning()
+    try:
+        mr.set_tuning(mfma=2)
+        for prec in ("fp64", "mixed"):
+            outs = mr.psi_inverse_batched(qs, prec)
+            mr.sync_status()
+            for (d, n), q, o in zip(specs, qs, outs):
+                single = mr.psi_inverse(q, prec)
+                torch.cuda.synchronize()
+                assert torch.equal(o, single), (prec, d, n)
+                ref = orc.psi(q.cpu().numpy())
+                assert _maxerr(_np(o), ref) <= (FP64_TOL if prec == "fp64" else MIXED_TOL), (prec, d, n)
+    finally:
+        mr.set_tuning(**base)
