@@ -1150,7 +1150,7 @@ static void plan_fft(BatchPlan &bp, mrinv_handle_t h, int mode, const FftPlan &p
 
 template <typename T>
 static void plan_gemm(BatchPlan &bp, mrinv_handle_t h, const FftPlan &p, const std::vector<GemmProblem<T>> &probs) {
-    for (int cls = 1; cls <= 12; ++cls) {
+    for (int cls = 1; cls <= 16; ++cls) {
         std::vector<GemmProblem<T>> g;
         for (auto &q : probs)
             if (gemm_sq_class(q.d, h ? h->tune.mfma : 1) == cls) g.push_back(q);

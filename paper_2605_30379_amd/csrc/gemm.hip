@@ -381,7 +381,18 @@ static size_t mf_lds_bytes(int dmax_odd) {
     return cs > ab ? cs : ab;
 }
 
-template <typename T, int DP>
+// Value of lane l ^ 1 (a DPP quad permutation, no LDS traffic).
+__device__ __forceinline__ float lane_xor1(float x) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0xB1, 0xF, 0xF, false));
+}
+__device__ __forceinline__ double lane_xor1(double x) {
+    const long long u = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(u & 0xffffffffLL), 0xB1, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(u >> 32), 0xB1, 0xF, 0xF, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+template <typename T, int DP, bool ODD>
 __device__ __forceinline__ void freq_gemm_mfma_body(const cplx<T> *__restrict__ ZA, const cplx<T> *__restrict__ ZB,
                                                     cplx<T> *__restrict__ ZC, const FftPlan &plan, int d,
                                                     int64_t blk) {
@@ -390,6 +401,12 @@ __device__ __forceinline__ void freq_gemm_mfma_body(const cplx<T> *__restrict__ 
     using V = typename Op::V;
     constexpr int WPF = Cfg::WPF, NF = Cfg::NF, KC = Cfg::KC, NT = Cfg::THREADS;
     constexpr int LDA = Cfg::LDA, LDB = Cfg::LDB;
+    // Staging work per thread and chunk: entry pairs (even d) or entries
+    // (odd d) of A and of B; NT = 4 DP NF makes both counts exact.
+    constexpr int PA = DP * (KC / 2), PB = KC * (DP / 2);
+    constexpr int NPR = NF * PA / NT;                 // pairs of A (and of B) per thread
+    constexpr int NEN = NF * DP * KC / NT;            // entries of A (and of B) per thread
+    static_assert(NF * PA == NPR * NT && NF * PB == NPR * NT && NF * DP * KC == NEN * NT, "staging split");
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cplx<T> *As = reinterpret_cast<cplx<T> *>(smem_raw);
     cplx<T> *Bs = As + NF * Cfg::AS;
@@ -407,62 +424,118 @@ __device__ __forceinline__ void freq_gemm_mfma_body(const cplx<T> *__restrict__ 
     __syncthreads();
     const int l = tid & 63, w = tid >> 6;
     const int f = w / WPF, I = w - f * WPF;
-    const bool even = (d & 1) == 0;
+    constexpr bool even = !ODD;
     V accR[WPF], accI[WPF];
 #pragma unroll
     for (int J = 0; J < WPF; ++J)
 #pragma unroll
         for (int r = 0; r < 4; ++r) accR[J][r] = accI[J][r] = (T)0;
 
-    for (int kc = 0; kc < d; kc += KC) {
-        if (even) {
-            // Pairs of entries (e, e+1) share one packed lane: one load pair each.
-            constexpr int PA = DP * (KC / 2), PB = KC * (DP / 2);
-            for (int idx = tid; idx < NF * PA; idx += NT) {
+    // Packed values of the current chunk in flight: rows k and L-k of the
+    // lane holding each staged pair (even d) or entry (odd d).  Addresses of
+    // unused slots are clamped to lane 0 of row 0, so every load is issued
+    // unconditionally and the results are masked when staged.
+    constexpr int NR = ODD ? NEN : NPR;
+    cplx<T> xa1[NR], xa2[NR], xb1[NR], xb2[NR];
+    auto fetch = [&](int kc) {
+        if constexpr (even) {
+#pragma unroll
+            for (int u = 0; u < NPR; ++u) {
+                const int idx = tid + u * NT;
                 const int ff = idx / PA, p = idx - ff * PA;
                 const int i = p / (KC / 2), t = 2 * (p - i * (KC / 2));
-                cplx<T> ev = mk<T>(0, 0), od = mk<T>(0, 0);
-                if (i < d && kc + t < d && k0 + ff < F) {
-                    const int c = (i * d + kc + t) >> 1;
-                    const cplx<T> z1 = ZA[rows1[ff] * nl + c], z2 = ZA[rows2[ff] * nl + c];
-                    ev = mk<T>((z1.x + z2.x) * (T)0.5, (z1.y - z2.y) * (T)0.5);
-                    od = mk<T>((z1.y + z2.y) * (T)0.5, (z2.x - z1.x) * (T)0.5);
-                }
-                cplx<T> *dst = As + ff * Cfg::AS + i * LDA + t;
-                dst[0] = ev;
-                dst[1] = od;
-            }
-            for (int idx = tid; idx < NF * PB; idx += NT) {
-                const int ff = idx / PB, p = idx - ff * PB;
-                const int t = p / (DP / 2), j = 2 * (p - t * (DP / 2));
-                cplx<T> ev = mk<T>(0, 0), od = mk<T>(0, 0);
-                if (j < d && kc + t < d && k0 + ff < F) {
-                    const int c = ((kc + t) * d + j) >> 1;
-                    const cplx<T> z1 = ZB[rows1[ff] * nl + c], z2 = ZB[rows2[ff] * nl + c];
-                    ev = mk<T>((z1.x + z2.x) * (T)0.5, (z1.y - z2.y) * (T)0.5);
-                    od = mk<T>((z1.y + z2.y) * (T)0.5, (z2.x - z1.x) * (T)0.5);
-                }
-                cplx<T> *dst = Bs + ff * Cfg::BS + t * LDB + j;
-                dst[0] = ev;
-                dst[1] = od;
+                const bool ok = i < d && kc + t < d;
+                const int c = ok ? (i * d + kc + t) >> 1 : 0;
+                xa1[u] = ZA[rows1[ff] * nl + c];
+                xa2[u] = ZA[rows2[ff] * nl + c];
+                const int t2 = p / (DP / 2), jb = 2 * (p - t2 * (DP / 2));
+                const bool okb = jb < d && kc + t2 < d;
+                const int cb = okb ? ((kc + t2) * d + jb) >> 1 : 0;
+                xb1[u] = ZB[rows1[ff] * nl + cb];
+                xb2[u] = ZB[rows2[ff] * nl + cb];
             }
         } else {
-            for (int idx = tid; idx < NF * DP * KC; idx += NT) {
+#pragma unroll
+            for (int u = 0; u < NEN; ++u) {
+                const int idx = tid + u * NT;
                 const int ff = idx / (DP * KC), p = idx - ff * (DP * KC);
                 const int i = p / KC, t = p - i * KC;
-                cplx<T> v = mk<T>(0, 0);
-                if (i < d && kc + t < d && k0 + ff < F) v = unpack<T>(ZA, nl, rows1[ff], rows2[ff], i * d + kc + t);
-                As[ff * Cfg::AS + i * LDA + t] = v;
-            }
-            for (int idx = tid; idx < NF * KC * DP; idx += NT) {
-                const int ff = idx / (KC * DP), p = idx - ff * (KC * DP);
-                const int t = p / DP, j = p - t * DP;
-                cplx<T> v = mk<T>(0, 0);
-                if (j < d && kc + t < d && k0 + ff < F) v = unpack<T>(ZB, nl, rows1[ff], rows2[ff], (kc + t) * d + j);
-                Bs[ff * Cfg::BS + t * LDB + j] = v;
+                const bool ok = i < d && kc + t < d;
+                const int c = ok ? (i * d + kc + t) >> 1 : 0;
+                xa1[u] = ZA[rows1[ff] * nl + c];
+                xa2[u] = ZA[rows2[ff] * nl + c];
+                const int t2 = p / DP, j = p - t2 * DP;
+                const bool okb = j < d && kc + t2 < d;
+                const int cb = okb ? ((kc + t2) * d + j) >> 1 : 0;
+                xb1[u] = ZB[rows1[ff] * nl + cb];
+                xb2[u] = ZB[rows2[ff] * nl + cb];
             }
         }
+    };
+    // Separate the two real sequences of each packed lane (Hermitian
+    // symmetry) and write the chunk to LDS, zero outside the d x d block and
+    // past the last frequency.
+    auto stage = [&](int kc) {
+        if constexpr (even) {
+#pragma unroll
+            for (int u = 0; u < NPR; ++u) {
+                const int idx = tid + u * NT;
+                const int ff = idx / PA, p = idx - ff * PA;
+                const bool fok = k0 + ff < F;
+                {
+                    const int i = p / (KC / 2), t = 2 * (p - i * (KC / 2));
+                    const bool ok = fok && i < d && kc + t < d;
+                    const cplx<T> z1 = xa1[u], z2 = xa2[u];
+                    const cplx<T> ev = ok ? mk<T>((z1.x + z2.x) * (T)0.5, (z1.y - z2.y) * (T)0.5) : mk<T>(0, 0);
+                    const cplx<T> od = ok ? mk<T>((z1.y + z2.y) * (T)0.5, (z2.x - z1.x) * (T)0.5) : mk<T>(0, 0);
+                    cplx<T> *dst = As + ff * Cfg::AS + i * LDA + t;
+                    dst[0] = ev;
+                    dst[1] = od;
+                }
+                {
+                    const int t = p / (DP / 2), j = 2 * (p - t * (DP / 2));
+                    const bool ok = fok && j < d && kc + t < d;
+                    const cplx<T> z1 = xb1[u], z2 = xb2[u];
+                    const cplx<T> ev = ok ? mk<T>((z1.x + z2.x) * (T)0.5, (z1.y - z2.y) * (T)0.5) : mk<T>(0, 0);
+                    const cplx<T> od = ok ? mk<T>((z1.y + z2.y) * (T)0.5, (z2.x - z1.x) * (T)0.5) : mk<T>(0, 0);
+                    cplx<T> *dst = Bs + ff * Cfg::BS + t * LDB + j;
+                    dst[0] = ev;
+                    dst[1] = od;
+                }
+            }
+        } else {
+#pragma unroll
+            for (int u = 0; u < NEN; ++u) {
+                const int idx = tid + u * NT;
+                const int ff = idx / (DP * KC), p = idx - ff * (DP * KC);
+                const bool fok = k0 + ff < F;
+                {
+                    const int i = p / KC, t = p - i * KC;
+                    const int e = i * d + kc + t;
+                    const bool ok = fok && i < d && kc + t < d;
+                    const cplx<T> z1 = xa1[u], z2 = xa2[u];
+                    cplx<T> v = (e & 1) == 0 ? mk<T>((z1.x + z2.x) * (T)0.5, (z1.y - z2.y) * (T)0.5)
+                                             : mk<T>((z1.y + z2.y) * (T)0.5, (z2.x - z1.x) * (T)0.5);
+                    As[ff * Cfg::AS + i * LDA + t] = ok ? v : mk<T>(0, 0);
+                }
+                {
+                    const int t = p / DP, j = p - t * DP;
+                    const int e = (kc + t) * d + j;
+                    const bool ok = fok && j < d && kc + t < d;
+                    const cplx<T> z1 = xb1[u], z2 = xb2[u];
+                    cplx<T> v = (e & 1) == 0 ? mk<T>((z1.x + z2.x) * (T)0.5, (z1.y - z2.y) * (T)0.5)
+                                             : mk<T>((z1.y + z2.y) * (T)0.5, (z2.x - z1.x) * (T)0.5);
+                    Bs[ff * Cfg::BS + t * LDB + j] = ok ? v : mk<T>(0, 0);
+                }
+            }
+        }
+    };
+
+    fetch(0);
+    for (int kc = 0; kc < d; kc += KC) {
+        stage(kc);
         __syncthreads();
+        if (kc + KC < d) fetch(kc + KC);   // next chunk in flight during the products
         const cplx<T> *Af = As + f * Cfg::AS + (I * 16 + (l & 15)) * LDA;
         const cplx<T> *Bf = Bs + f * Cfg::BS + (l & 15);
 #pragma unroll
@@ -482,7 +555,7 @@ __device__ __forceinline__ void freq_gemm_mfma_body(const cplx<T> *__restrict__ 
     }
 
     const bool fok = k0 + f < F;
-    if (even) {
+    if constexpr (even) {
         // Entries (i, j) and (i, j^1) sit in lanes l and l^1 of the same
         // accumulator element: the even lane writes row k, the odd lane row L-k.
         const int64_t r1 = rows1[f], r2 = rows2[f];
@@ -494,7 +567,7 @@ __device__ __forceinline__ void freq_gemm_mfma_body(const cplx<T> *__restrict__ 
             for (int r = 0; r < 4; ++r) {
                 const int i = I * 16 + Op::row(l, r);
                 const T vr = accR[J][r], vi = accI[J][r];
-                const T pr = __shfl_xor(vr, 1), pi = __shfl_xor(vi, 1);
+                const T pr = lane_xor1(vr), pi = lane_xor1(vi);
                 if (fok && i < d && j < d) {
                     const int c = (i * d + (j & ~1)) >> 1;
                     if (!odd_lane) ZC[r1 * nl + c] = mk<T>(vr - pi, vi + pr);
@@ -526,14 +599,14 @@ __device__ __forceinline__ void freq_gemm_mfma_body(const cplx<T> *__restrict__ 
     }
 }
 
-template <typename T, int DP>
+template <typename T, int DP, bool ODD>
 __global__ void __launch_bounds__(MfCfg<DP>::THREADS)
 freq_gemm_mfma_kernel(const cplx<T> *__restrict__ ZA, const cplx<T> *__restrict__ ZB, cplx<T> *__restrict__ ZC,
                       FftPlan plan, int d) {
-    freq_gemm_mfma_body<T, DP>(ZA, ZB, ZC, plan, d, blockIdx.x);
+    freq_gemm_mfma_body<T, DP, ODD>(ZA, ZB, ZC, plan, d, blockIdx.x);
 }
 
-template <typename T, int DP>
+template <typename T, int DP, bool ODD>
 __global__ void __launch_bounds__(MfCfg<DP>::THREADS)
 freq_gemm_mfma_batched_kernel(const GemmProblem<T> *probs, int nprob, FftPlan plan) {
     int lo = 0, hi = nprob - 1;
@@ -544,15 +617,15 @@ freq_gemm_mfma_batched_kernel(const GemmProblem<T> *probs, int nprob, FftPlan pl
         else hi = mid - 1;
     }
     const GemmProblem<T> &pp = probs[lo];
-    freq_gemm_mfma_body<T, DP>(pp.A, pp.B, pp.C, plan, pp.d, bid - pp.wg_begin);
+    freq_gemm_mfma_body<T, DP, ODD>(pp.A, pp.B, pp.C, plan, pp.d, bid - pp.wg_begin);
 }
 
-template <typename T, int DP>
+template <typename T, int DP, bool ODD>
 static hipError_t launch_gemm_mfma(const FftPlan &plan, int d, const cplx<T> *ZA, const cplx<T> *ZB, cplx<T> *ZC,
                                    hipStream_t st) {
     using Cfg = MfCfg<DP>;
-    const size_t lds = mf_lds_bytes<T, DP>((d & 1) ? d : 0);
-    auto kern = freq_gemm_mfma_kernel<T, DP>;
+    const size_t lds = mf_lds_bytes<T, DP>(ODD ? d : 0);
+    auto kern = freq_gemm_mfma_kernel<T, DP, ODD>;
     if (lds > 64 * 1024) {
         (void)hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         (void)hipGetLastError();
@@ -560,7 +633,7 @@ static hipError_t launch_gemm_mfma(const FftPlan &plan, int d, const cplx<T> *ZA
     const int64_t F = ((int64_t)1 << plan.lgL) / 2 + 1;
     const int64_t blocks = (F + Cfg::NF - 1) / Cfg::NF;
     char name[96];
-    snprintf(name, sizeof name, "freq_gemm_mfma_kernel<%s, %d>", sizeof(T) == 8 ? "double" : "float", DP);
+    snprintf(name, sizeof name, "freq_gemm_mfma_kernel<%s, %d, %d>", sizeof(T) == 8 ? "double" : "float", DP, (int)ODD);
     const double Lr = (double)((int64_t)1 << plan.lgL);
     const int nl = (d * d + 1) / 2;
     launch_begin(name, Lr * 3.0 * nl * sizeof(cplx<T>), (double)F * 8.0 * d * d * d);
@@ -569,18 +642,19 @@ static hipError_t launch_gemm_mfma(const FftPlan &plan, int d, const cplx<T> *ZA
     return hipGetLastError();
 }
 
-template <typename T, int DP>
+template <typename T, int DP, bool ODD>
 static hipError_t launch_gemm_mfma_batched(const FftPlan &plan, const GemmProblem<T> *probs, int nprob,
                                            int64_t total, double bytes, double flops, hipStream_t st) {
     using Cfg = MfCfg<DP>;
-    const size_t lds = mf_lds_bytes<T, DP>(DP - 1);
-    auto kern = freq_gemm_mfma_batched_kernel<T, DP>;
+    const size_t lds = mf_lds_bytes<T, DP>(ODD ? DP - 1 : 0);
+    auto kern = freq_gemm_mfma_batched_kernel<T, DP, ODD>;
     if (lds > 64 * 1024) {
         (void)hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         (void)hipGetLastError();
     }
     char name[96];
-    snprintf(name, sizeof name, "freq_gemm_mfma_batched_kernel<%s, %d>", sizeof(T) == 8 ? "double" : "float", DP);
+    snprintf(name, sizeof name, "freq_gemm_mfma_batched_kernel<%s, %d, %d>", sizeof(T) == 8 ? "double" : "float", DP,
+             (int)ODD);
     launch_begin(name, bytes, flops);
     hipLaunchKernelGGL(kern, dim3((unsigned)total), dim3(Cfg::THREADS), lds, st, probs, nprob, plan);
     launch_end();
@@ -610,10 +684,12 @@ static hipError_t launch_gemm_sq_batched(const FftPlan &plan, const GemmProblem<
 }
 
 // Product class of dimension d: 1..8 = vector kernel padded to 8*cls,
-// 9..12 = matrix-core kernel padded to 16*(cls-8).  mfma: 0 never, 1 when the
-// 16-padding adds fewer than 8 rows and columns, 2 always (d > 8).
+// 9..12 = matrix-core kernel padded to 16*(cls-8) for even d, 13..16 the same
+// for odd d.  mfma: 0 never, 1 when the 16-padding adds fewer than 8 rows and
+// columns, 2 always (d > 8).
 int gemm_sq_class(int d, int mfma) {
-    if (d > 8 && d <= 64 && (mfma == 2 || (mfma == 1 && (d % 16 == 0 || d % 16 > 8)))) return 8 + (d + 15) / 16;
+    if (d > 8 && d <= 64 && (mfma == 2 || (mfma == 1 && (d % 16 == 0 || d % 16 > 8))))
+        return ((d & 1) ? 12 : 8) + (d + 15) / 16;
     return (d + 7) / 8;
 }
 
@@ -632,9 +708,9 @@ int64_t gemm_batch_layout(const FftPlan &plan, GemmProblem<T> *probs, int nprob,
             case 6: nf = SqCfg<48>::NF; break;
             case 7: nf = SqCfg<56>::NF; break;
             case 8: nf = SqCfg<64>::NF; break;
-            case 9: nf = MfCfg<16>::NF; break;
-            case 10: nf = MfCfg<32>::NF; break;
-            case 11: nf = MfCfg<48>::NF; break;
+            case 9: case 13: nf = MfCfg<16>::NF; break;
+            case 10: case 14: nf = MfCfg<32>::NF; break;
+            case 11: case 15: nf = MfCfg<48>::NF; break;
             default: nf = MfCfg<64>::NF; break;
         }
         probs[i].wg_begin = acc;
@@ -655,10 +731,14 @@ hipError_t freq_gemm_batched(const FftPlan &plan, int dclass, const GemmProblem<
         case 6: return launch_gemm_sq_batched<T, 48>(plan, probs, nprob, total, bytes, flops, st);
         case 7: return launch_gemm_sq_batched<T, 56>(plan, probs, nprob, total, bytes, flops, st);
         case 8: return launch_gemm_sq_batched<T, 64>(plan, probs, nprob, total, bytes, flops, st);
-        case 9: return launch_gemm_mfma_batched<T, 16>(plan, probs, nprob, total, bytes, flops, st);
-        case 10: return launch_gemm_mfma_batched<T, 32>(plan, probs, nprob, total, bytes, flops, st);
-        case 11: return launch_gemm_mfma_batched<T, 48>(plan, probs, nprob, total, bytes, flops, st);
-        default: return launch_gemm_mfma_batched<T, 64>(plan, probs, nprob, total, bytes, flops, st);
+        case 9: return launch_gemm_mfma_batched<T, 16, false>(plan, probs, nprob, total, bytes, flops, st);
+        case 10: return launch_gemm_mfma_batched<T, 32, false>(plan, probs, nprob, total, bytes, flops, st);
+        case 11: return launch_gemm_mfma_batched<T, 48, false>(plan, probs, nprob, total, bytes, flops, st);
+        case 12: return launch_gemm_mfma_batched<T, 64, false>(plan, probs, nprob, total, bytes, flops, st);
+        case 13: return launch_gemm_mfma_batched<T, 16, true>(plan, probs, nprob, total, bytes, flops, st);
+        case 14: return launch_gemm_mfma_batched<T, 32, true>(plan, probs, nprob, total, bytes, flops, st);
+        case 15: return launch_gemm_mfma_batched<T, 48, true>(plan, probs, nprob, total, bytes, flops, st);
+        default: return launch_gemm_mfma_batched<T, 64, true>(plan, probs, nprob, total, bytes, flops, st);
     }
 }
 
@@ -699,10 +779,14 @@ static hipError_t gemm_sq(const FftPlan &plan, int d, int mfma, const cplx<T> *Z
         case 6: return launch_gemm_sq<T, 48>(plan, d, ZA, ZB, ZC, st);
         case 7: return launch_gemm_sq<T, 56>(plan, d, ZA, ZB, ZC, st);
         case 8: return launch_gemm_sq<T, 64>(plan, d, ZA, ZB, ZC, st);
-        case 9: return launch_gemm_mfma<T, 16>(plan, d, ZA, ZB, ZC, st);
-        case 10: return launch_gemm_mfma<T, 32>(plan, d, ZA, ZB, ZC, st);
-        case 11: return launch_gemm_mfma<T, 48>(plan, d, ZA, ZB, ZC, st);
-        default: return launch_gemm_mfma<T, 64>(plan, d, ZA, ZB, ZC, st);
+        case 9: return launch_gemm_mfma<T, 16, false>(plan, d, ZA, ZB, ZC, st);
+        case 10: return launch_gemm_mfma<T, 32, false>(plan, d, ZA, ZB, ZC, st);
+        case 11: return launch_gemm_mfma<T, 48, false>(plan, d, ZA, ZB, ZC, st);
+        case 12: return launch_gemm_mfma<T, 64, false>(plan, d, ZA, ZB, ZC, st);
+        case 13: return launch_gemm_mfma<T, 16, true>(plan, d, ZA, ZB, ZC, st);
+        case 14: return launch_gemm_mfma<T, 32, true>(plan, d, ZA, ZB, ZC, st);
+        case 15: return launch_gemm_mfma<T, 48, true>(plan, d, ZA, ZB, ZC, st);
+        default: return launch_gemm_mfma<T, 64, true>(plan, d, ZA, ZB, ZC, st);
     }
 }
 
