@@ -370,13 +370,14 @@ template <int DP> struct MfCfg {
     static constexpr int LDB = DP + 1;                   // Bs[f][t][j]
     static constexpr int AS = DP * LDA;
     static constexpr int BS = KC * LDB;
+    static constexpr int NBUF = DP > KC ? 2 : 1;         // chunk buffers (double-buffered when d > 16)
 };
 
 // LDS bytes of one workgroup; odd d stages C (d*d complex per frequency).
 template <typename T, int DP>
 static size_t mf_lds_bytes(int dmax_odd) {
     using Cfg = MfCfg<DP>;
-    const size_t ab = (size_t)Cfg::NF * (Cfg::AS + Cfg::BS) * sizeof(cplx<T>);
+    const size_t ab = (size_t)Cfg::NBUF * Cfg::NF * (Cfg::AS + Cfg::BS) * sizeof(cplx<T>);
     const size_t cs = (size_t)Cfg::NF * ((size_t)dmax_odd * dmax_odd + 1) * sizeof(cplx<T>);
     return cs > ab ? cs : ab;
 }
@@ -408,8 +409,9 @@ __device__ __forceinline__ void freq_gemm_mfma_body(const cplx<T> *__restrict__ 
     constexpr int NEN = NF * DP * KC / NT;            // entries of A (and of B) per thread
     static_assert(NF * PA == NPR * NT && NF * PB == NPR * NT && NF * DP * KC == NEN * NT, "staging split");
     extern __shared__ __align__(16) unsigned char smem_raw[];
+    // Chunk buffer b: A part at As + b * NF * (AS + BS), B part right after it.
     cplx<T> *As = reinterpret_cast<cplx<T> *>(smem_raw);
-    cplx<T> *Bs = As + NF * Cfg::AS;
+    constexpr int BUF = NF * (Cfg::AS + Cfg::BS);
     __shared__ int64_t rows1[NF], rows2[NF];
     const int64_t L = (int64_t)1 << plan.lgL;
     const int64_t F = L / 2 + 1;
@@ -475,7 +477,9 @@ __device__ __forceinline__ void freq_gemm_mfma_body(const cplx<T> *__restrict__ 
     // Separate the two real sequences of each packed lane (Hermitian
     // symmetry) and write the chunk to LDS, zero outside the d x d block and
     // past the last frequency.
-    auto stage = [&](int kc) {
+    auto stage = [&](int kc, int buf) {
+        cplx<T> *Ab = As + buf * BUF;
+        cplx<T> *Bb = Ab + NF * Cfg::AS;
         if constexpr (even) {
 #pragma unroll
             for (int u = 0; u < NPR; ++u) {
@@ -488,7 +492,7 @@ __device__ __forceinline__ void freq_gemm_mfma_body(const cplx<T> *__restrict__ 
                     const cplx<T> z1 = xa1[u], z2 = xa2[u];
                     const cplx<T> ev = ok ? mk<T>((z1.x + z2.x) * (T)0.5, (z1.y - z2.y) * (T)0.5) : mk<T>(0, 0);
                     const cplx<T> od = ok ? mk<T>((z1.y + z2.y) * (T)0.5, (z2.x - z1.x) * (T)0.5) : mk<T>(0, 0);
-                    cplx<T> *dst = As + ff * Cfg::AS + i * LDA + t;
+                    cplx<T> *dst = Ab + ff * Cfg::AS + i * LDA + t;
                     dst[0] = ev;
                     dst[1] = od;
                 }
@@ -498,7 +502,7 @@ __device__ __forceinline__ void freq_gemm_mfma_body(const cplx<T> *__restrict__ 
                     const cplx<T> z1 = xb1[u], z2 = xb2[u];
                     const cplx<T> ev = ok ? mk<T>((z1.x + z2.x) * (T)0.5, (z1.y - z2.y) * (T)0.5) : mk<T>(0, 0);
                     const cplx<T> od = ok ? mk<T>((z1.y + z2.y) * (T)0.5, (z2.x - z1.x) * (T)0.5) : mk<T>(0, 0);
-                    cplx<T> *dst = Bs + ff * Cfg::BS + t * LDB + j;
+                    cplx<T> *dst = Bb + ff * Cfg::BS + t * LDB + j;
                     dst[0] = ev;
                     dst[1] = od;
                 }
@@ -516,7 +520,7 @@ __device__ __forceinline__ void freq_gemm_mfma_body(const cplx<T> *__restrict__ 
                     const cplx<T> z1 = xa1[u], z2 = xa2[u];
                     cplx<T> v = (e & 1) == 0 ? mk<T>((z1.x + z2.x) * (T)0.5, (z1.y - z2.y) * (T)0.5)
                                              : mk<T>((z1.y + z2.y) * (T)0.5, (z2.x - z1.x) * (T)0.5);
-                    As[ff * Cfg::AS + i * LDA + t] = ok ? v : mk<T>(0, 0);
+                    Ab[ff * Cfg::AS + i * LDA + t] = ok ? v : mk<T>(0, 0);
                 }
                 {
                     const int t = p / DP, j = p - t * DP;
@@ -525,19 +529,23 @@ __device__ __forceinline__ void freq_gemm_mfma_body(const cplx<T> *__restrict__ 
                     const cplx<T> z1 = xb1[u], z2 = xb2[u];
                     cplx<T> v = (e & 1) == 0 ? mk<T>((z1.x + z2.x) * (T)0.5, (z1.y - z2.y) * (T)0.5)
                                              : mk<T>((z1.y + z2.y) * (T)0.5, (z2.x - z1.x) * (T)0.5);
-                    Bs[ff * Cfg::BS + t * LDB + j] = ok ? v : mk<T>(0, 0);
+                    Bb[ff * Cfg::BS + t * LDB + j] = ok ? v : mk<T>(0, 0);
                 }
             }
         }
     };
 
+    // Chunk kc is read from buffer b while chunk kc + KC is fetched and
+    // staged into the other buffer; one barrier per chunk.
     fetch(0);
+    stage(0, 0);
+    __syncthreads();
+    int cur = 0;
     for (int kc = 0; kc < d; kc += KC) {
-        stage(kc);
-        __syncthreads();
-        if (kc + KC < d) fetch(kc + KC);   // next chunk in flight during the products
-        const cplx<T> *Af = As + f * Cfg::AS + (I * 16 + (l & 15)) * LDA;
-        const cplx<T> *Bf = Bs + f * Cfg::BS + (l & 15);
+        const bool more = kc + KC < d;   // only when d > KC, i.e. NBUF == 2
+        if (more) fetch(kc + KC);
+        const cplx<T> *Af = As + cur * BUF + f * Cfg::AS + (I * 16 + (l & 15)) * LDA;
+        const cplx<T> *Bf = As + cur * BUF + NF * Cfg::AS + f * Cfg::BS + (l & 15);
 #pragma unroll
         for (int ks = 0; ks < KC / 4; ++ks) {
             const int t = 4 * ks + (l >> 4);
@@ -551,7 +559,9 @@ __device__ __forceinline__ void freq_gemm_mfma_body(const cplx<T> *__restrict__ 
                 accI[J] = Op::mac(a.y, b.x, accI[J]);
             }
         }
+        if (more) stage(kc + KC, cur ^ 1);
         __syncthreads();
+        cur ^= 1;
     }
 
     const bool fok = k0 + f < F;
