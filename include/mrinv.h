@@ -207,16 +207,21 @@ mrinv_status_t mrinv_scatter_block_add(mrinv_handle_t h, const double *Y_bar, in
                                        int nc, double *X_bar_accum);
 
 /*
- * Batched inversion of many independent problems of uneven d and n in one
- * pass per Newton phase (persistent launches over a device task table).
+ * Batched inversion of many independent problems of uneven d and n: every
+ * phase of a Newton step (transform pass, product class, direct product) is
+ * one launch over all problems that take part in it, driven by a device table
+ * of per-problem descriptors.
  *   q_ptrs, psi_ptrs : host arrays of `count` device pointers;
- *   d, n             : host arrays of sizes (1 <= d <= 48 per problem).
- * Each problem's result equals the single-problem call with the same precision.
+ *   d, n             : host arrays of sizes (1 <= d <= 64, 1 <= n <= MRINV_MAX_N).
+ * Each problem's result equals the single-problem call with the same precision
+ * and tuning.  mrinv_batched_workspace_size gives the workspace bytes for the
+ * tuning of handle h (NULL: the tuning of a new handle), or 0 for invalid
+ * sizes; it needs no GPU.
  */
 mrinv_status_t mrinv_psi_inverse_batched(mrinv_handle_t h, int count, const double *const *q_ptrs,
                                          const int *d, const int64_t *n, mrinv_precision_t precision,
                                          double *const *psi_ptrs, void *ws, size_t ws_bytes);
-size_t mrinv_batched_workspace_size(int count, const int *d, const int64_t *n,
+size_t mrinv_batched_workspace_size(mrinv_handle_t h, int count, const int *d, const int64_t *n,
                                     mrinv_precision_t precision);
 
 /* Residual norms of a computed inverse X of A = e0 - q (Proposition 2.6,
@@ -234,7 +239,7 @@ typedef struct {
     int lanes_fp64;     /* complex lanes per FFT workgroup in float64: 8 or 16 (default 16) */
     int lanes_fp32;     /* complex lanes per FFT workgroup in float32: 8 or 16 (default 16) */
     int seed_m0;        /* coefficients formed by the coefficient recursion (Section 2.2) before
-                           Newton starts; rounded down to a power of two, 1..256 (default 16) */
+                           Newton starts; rounded down to a power of two, 1..256 (default 1: none) */
     int pair_forward;   /* nonzero: forward transforms of both Newton operands in one launch (default 1) */
     int twiddle_tables; /* 0: every twiddle is a product of two table entries formed on the fly;
                            1: in-workgroup twiddles from a 512-root table; 2: also per-pass outer
@@ -246,6 +251,9 @@ typedef struct {
     int mfma;           /* square frequency-domain products for d > 8 on the matrix cores (16x16x4 MFMA in
                            the working precision): 0 never (vector kernels), 1 when padding d to a multiple
                            of 16 adds fewer than 8 (default), 2 always.  Results agree to rounding. */
+    int direct_m;       /* Newton steps m -> m2 with m2 <= direct_m (rounded down to a power of two) form
+                           their two truncated products directly in the time domain on the matrix cores
+                           instead of through transforms: -1 automatic from d (default), 0 never. */
 } mrinv_tuning_t;
 
 mrinv_status_t mrinv_get_tuning(mrinv_handle_t h, mrinv_tuning_t *out);

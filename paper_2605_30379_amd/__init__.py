@@ -51,7 +51,8 @@ class Tuning(ctypes.Structure):
     """Launch-shape and schedule choices of a handle (mrinv_tuning_t)."""
     _fields_ = [("lgp_max", ctypes.c_int), ("lanes_fp64", ctypes.c_int), ("lanes_fp32", ctypes.c_int),
                 ("seed_m0", ctypes.c_int), ("pair_forward", ctypes.c_int), ("twiddle_tables", ctypes.c_int),
-                ("block_order", ctypes.c_int), ("use_graph", ctypes.c_int), ("mfma", ctypes.c_int)]
+                ("block_order", ctypes.c_int), ("use_graph", ctypes.c_int), ("mfma", ctypes.c_int),
+                ("direct_m", ctypes.c_int)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -107,7 +108,7 @@ def lib():
             "mrinv_scatter_block_add": (i32, [vp, vp, i64, i32, i32, vp, i32, vp, i32, vp]),
             "mrinv_psi_inverse_batched": (i32, [vp, i32, ctypes.POINTER(vp), ip, ctypes.POINTER(i64), i32,
                                                 ctypes.POINTER(vp), vp, sz]),
-            "mrinv_batched_workspace_size": (sz, [i32, ip, ctypes.POINTER(i64), i32]),
+            "mrinv_batched_workspace_size": (sz, [vp, i32, ip, ctypes.POINTER(i64), i32]),
             "mrinv_residual_norms": (i32, [vp, vp, vp, i32, i64, dp, vp, sz]),
             "mrinv_get_tuning": (i32, [vp, ctypes.POINTER(Tuning)]),
             "mrinv_set_tuning": (i32, [vp, ctypes.POINTER(Tuning)]),
@@ -383,7 +384,7 @@ def psi_inverse_batched(qs, precision="mixed"):
     qp = (ctypes.c_void_p * count)(*[q.data_ptr() for q in qs])
     op = (ctypes.c_void_p * count)(*[o.data_ptr() for o in outs])
     L = lib()
-    ws = _ws(L.mrinv_batched_workspace_size(count, d_arr, n_arr, prec), dev)
+    ws = _ws(L.mrinv_batched_workspace_size(_handle(dev), count, d_arr, n_arr, prec), dev)
     _check(L.mrinv_psi_inverse_batched(_handle(dev), count, qp, d_arr, n_arr, prec, op, _ptr(ws), ws.numel()))
     return outs
 

@@ -43,6 +43,10 @@ static mrinv_status_t fail(mrinv_status_t s, const char *fmt, ...) {
 // ---------------------------------------------------------------------------
 constexpr size_t SCRATCH_BYTES = (size_t)MRINV_MAX_N * sizeof(double) + 4096 * sizeof(double);
 
+// Tuning of a new handle, also used where no handle is given (workspace
+// queries), so that both plan the same launches.
+static const mrinv_tuning_t kDefaultTune = {9, 16, 16, 1, 1, 1, 0, 0, 1, -1};
+
 struct mrinv_handle_s {
     hipStream_t stream = nullptr;
     int device = 0;
@@ -51,7 +55,7 @@ struct mrinv_handle_s {
     double *scratch = nullptr;      // small per-handle scratch (index lists, vectors, 1-lane scans)
     void *timer = nullptr;          // launch timing records (mrinv_set_timing)
     bool timing = false;
-    mrinv_tuning_t tune{9, 16, 16, 16, 1, 1, 0, 0, 1};
+    mrinv_tuning_t tune = kDefaultTune;
     // Graph of the last captured psi inversion and the call it belongs to.
     struct {
         bool valid = false;
@@ -345,11 +349,12 @@ static DstDesc dst_real(void *p, bool dbl, int64_t ld, int nreal, int64_t lo, in
     return d;
 }
 
-static int order_of(mrinv_handle_t h) { return h ? h->tune.block_order : 0; }
+static const mrinv_tuning_t &tune_of(mrinv_handle_t h) { return h ? h->tune : kDefaultTune; }
+static int order_of(mrinv_handle_t h) { return tune_of(h).block_order; }
 template <typename T> static int lanes_of(mrinv_handle_t h) {
-    return h ? (sizeof(T) == 8 ? h->tune.lanes_fp64 : h->tune.lanes_fp32) : 0;
+    return sizeof(T) == 8 ? tune_of(h).lanes_fp64 : tune_of(h).lanes_fp32;
 }
-static FftPlan hplan(mrinv_handle_t h, int lgL) { return make_plan(lgL, h ? h->tune.lgp_max : LGP_MAX); }
+static FftPlan hplan(mrinv_handle_t h, int lgL) { return make_plan(lgL, tune_of(h).lgp_max); }
 
 // Forward transform of a real source into Z (all passes).
 template <typename T>
@@ -417,7 +422,7 @@ static hipError_t remask(mrinv_handle_t h, const FftPlan &p, int nl, cplx<T> *Z,
 
 static GemmDesc gdesc(mrinv_handle_t h, int ra, int m, int cb, int ta = 0, int tb = 0) {
     GemmDesc g{};
-    g.mfma = h ? h->tune.mfma : 1;
+    g.mfma = tune_of(h).mfma;
     g.ra = ra;
     g.m = m;
     g.cb = cb;
@@ -431,10 +436,29 @@ static GemmDesc gdesc(mrinv_handle_t h, int ra, int m, int cb, int ta = 0, int t
 
 // Length of the recursion seed: the largest power of two <= min(seed_m0, n).
 static int64_t seed_len(mrinv_handle_t h, int64_t n) {
-    const int64_t cap = std::min<int64_t>(h ? h->tune.seed_m0 : 16, n);
+    const int64_t cap = std::min<int64_t>(tune_of(h).seed_m0, n);
     int64_t m0 = 1;
     while (2 * m0 <= cap) m0 *= 2;
     return m0;
+}
+
+// Newton steps m -> m2 with m2 <= direct_limit run as direct products in the
+// time domain.  Automatic choice: the largest power of two M for which the
+// step M/2 -> M costs at most 1.2e8 multiply-adds (1.5 (M/2)^2 D^3 with D = d
+// rounded up to the 16-wide matrix tiles); below that the transform launches'
+// fixed latency costs more (measured crossover: M = 256 at d = 16).  0 turns
+// the direct steps off.
+static int64_t direct_limit(mrinv_handle_t h, int d) {
+    const int v = tune_of(h).direct_m;
+    if (v == 0) return 0;
+    int64_t M = 1;
+    if (v > 0) {
+        while (2 * M <= v) M *= 2;
+        return M;
+    }
+    const double D = 16.0 * ((d + 15) / 16);
+    while (1.5 * (double)M * (double)M * D * D * D <= 1.2e8) M *= 2;   // M is twice the step's m
+    return M;
 }
 
 // Register the outer-twiddle tables of plan p (every pass but the last,
@@ -476,8 +500,42 @@ static mrinv_status_t newton(mrinv_handle_t h, const double *src, int e0, int d,
     HIP_TRY(gj_inverse(src, d, e0, dbl ? (double *)out : nullptr, dbl ? nullptr : (float *)out, h->status, h->stream));
     // The first m0 coefficients by the coefficient recursion (one launch),
     // then Newton doubling from m0.
-    const int64_t m0 = seed_len(h, n);
+    int64_t m0 = seed_len(h, n);
     if (m0 > 1) HIP_TRY(seed_recursion<T>(src, e0, d, (int)m0, (T *)out, h->stream));
+    // Direct steps: E = -A*X on [m, m2) into scratch (SA), then X[m, m2) = X*E.
+    const int64_t dlim = direct_limit(h, d);
+    for (; m0 < n && std::min(2 * m0, n) <= dlim; m0 = std::min(2 * m0, n)) {
+        const int64_t m2 = std::min(2 * m0, n);
+        ConvDesc c{};
+        c.L = src;
+        c.l_f64 = 1;
+        c.R = out;
+        c.out = SA;
+        c.d = d;
+        c.sign = e0 ? 1.0 : -1.0;   // -A(l) = q(l) for l >= 1 in the renewal form
+        c.k0 = m0;
+        c.k1 = m2;
+        c.jlo = 0;
+        c.jhi = m0 - 1;
+        c.r_off = 0;
+        c.out_off = m0;
+        HIP_TRY(conv_direct<T>(c, h->stream));
+        ConvDesc u{};
+        u.L = out;
+        u.l_f64 = dbl;
+        u.R = SA;
+        u.out = out;
+        u.d = d;
+        u.sign = 1.0;
+        u.k0 = m0;
+        u.k1 = m2;
+        u.jlo = m0;
+        u.jhi = m2;
+        u.r_off = m0;
+        u.out_off = 0;
+        u.status = dbl ? h->status : nullptr;
+        HIP_TRY(conv_direct<T>(u, h->stream));
+    }
     const GemmDesc g = gdesc(h, d, d, d);
     // Plans of every step and their outer-twiddle tables (one launch).
     std::vector<FftPlan> plans;
@@ -687,6 +745,7 @@ static mrinv_status_t check_tuning(const mrinv_tuning_t &t) {
     if (t.block_order < 0 || t.block_order > 1) return fail(MRINV_E_ARG, "block_order must be 0 or 1");
     if (t.use_graph < 0 || t.use_graph > 1) return fail(MRINV_E_ARG, "use_graph must be 0 or 1");
     if (t.mfma < 0 || t.mfma > 2) return fail(MRINV_E_ARG, "mfma must be 0, 1 or 2");
+    if (t.direct_m < -1 || t.direct_m > 65536) return fail(MRINV_E_ARG, "direct_m %d not in -1..65536", t.direct_m);
     return MRINV_OK;
 }
 
@@ -748,12 +807,13 @@ extern "C" mrinv_status_t mrinv_autotune(mrinv_handle_t h, const double *q, int 
     for (int v : {8, 16}) { mrinv_tuning_t t = best; t.lanes_fp64 = v; CHECK(trial(t)); }
     if (precision != MRINV_FP64)
         for (int v : {8, 16}) { mrinv_tuning_t t = best; t.lanes_fp32 = v; CHECK(trial(t)); }
-    for (int v : {1, 16, 32, 64, 128}) { mrinv_tuning_t t = best; t.seed_m0 = v; CHECK(trial(t)); }
+    for (int v : {1, 16, 32, 64}) { mrinv_tuning_t t = best; t.seed_m0 = v; CHECK(trial(t)); }
     for (int v : {0, 1}) { mrinv_tuning_t t = best; t.pair_forward = v; CHECK(trial(t)); }
     for (int v : {0, 1, 2}) { mrinv_tuning_t t = best; t.twiddle_tables = v; CHECK(trial(t)); }
     for (int v : {0, 1}) { mrinv_tuning_t t = best; t.block_order = v; CHECK(trial(t)); }
     for (int v : {0, 1}) { mrinv_tuning_t t = best; t.use_graph = v; CHECK(trial(t)); }
     for (int v : {0, 1, 2}) { mrinv_tuning_t t = best; t.mfma = v; CHECK(trial(t)); }
+    for (int v : {0, -1, 64, 128, 256, 512, 1024}) { mrinv_tuning_t t = best; t.direct_m = v; CHECK(trial(t)); }
     h->tune = best;
     CHECK(mrinv_psi_inverse(h, q, d, n, precision, psi, ws, wsb));
     HIP_TRY(hipStreamSynchronize(h->stream));
@@ -1153,9 +1213,9 @@ static void plan_gemm(BatchPlan &bp, mrinv_handle_t h, const FftPlan &p, const s
     for (int cls = 1; cls <= 16; ++cls) {
         std::vector<GemmProblem<T>> g;
         for (auto &q : probs)
-            if (gemm_sq_class(q.d, h ? h->tune.mfma : 1) == cls) g.push_back(q);
+            if (gemm_sq_class(q.d, tune_of(h).mfma) == cls) g.push_back(q);
         if (g.empty()) continue;
-        const int64_t total = gemm_batch_layout<T>(p, g.data(), (int)g.size(), h ? h->tune.mfma : 1);
+        const int64_t total = gemm_batch_layout<T>(p, g.data(), (int)g.size(), tune_of(h).mfma);
         double bytes = 0, flops = 0;
         const double Lr = (double)((int64_t)1 << p.lgL);
         for (auto &q : g) {
@@ -1289,10 +1349,51 @@ static void plan_newton(BatchPlan &bp, mrinv_handle_t h, std::vector<BatchProble
     for (int64_t m = 1; m < nmax; m *= 2) {
         const FftPlan p = hplan(h, ceil_log2(2 * m));
         const int64_t L = (int64_t)1 << p.lgL;
+        // Direct steps of this m (as in the single-problem call), E scratch at
+        // the start of the spectrum region; the transform steps below reuse it
+        // after them in stream order.
+        {
+            std::vector<ConvDesc> ce[5], cu[5];
+            size_t used = 0;
+            for (int i = 0; i < (int)P.size(); ++i) {
+                const BatchProblem &b = P[i];
+                const int64_t m2 = std::min(2 * m, b.n);
+                if (!(b.n > m && m >= seed_len(h, b.n) && m2 <= direct_limit(h, b.d))) continue;
+                const int64_t d2 = (int64_t)b.d * b.d;
+                void *out = dbl ? (void *)b.psi : (void *)b.X;
+                void *E = spec + used;
+                used += align256((size_t)(m2 - m) * d2 * sizeof(T));
+                ConvDesc c{};
+                c.L = b.q; c.l_f64 = 1; c.R = out; c.out = E; c.d = b.d; c.sign = 1.0;
+                c.k0 = m; c.k1 = m2; c.jlo = 0; c.jhi = m - 1; c.r_off = 0; c.out_off = m;
+                ConvDesc u{};
+                u.L = out; u.l_f64 = dbl; u.R = E; u.out = out; u.d = b.d; u.sign = 1.0;
+                u.k0 = m; u.k1 = m2; u.jlo = m; u.jhi = m2; u.r_off = m; u.out_off = 0;
+                u.status = dbl ? status_of(h) : nullptr;
+                ce[conv_class(b.d)].push_back(c);
+                cu[conv_class(b.d)].push_back(u);
+            }
+            spec_max = std::max(spec_max, used);
+            for (int pass = 0; pass < 2; ++pass)
+                for (int cls = 1; cls <= 4; ++cls) {
+                    std::vector<ConvDesc> &v = pass == 0 ? ce[cls] : cu[cls];
+                    if (v.empty()) continue;
+                    const int64_t total = conv_batch_layout(v.data(), (int)v.size());
+                    double flops = 0;
+                    for (auto &x : v) flops += 1.5 * (double)(x.k1 - x.k0) * (double)(x.k1 - x.k0) * 2.0 * x.d * x.d * x.d;
+                    const size_t off = bp.put(v);
+                    const int cnt = (int)v.size();
+                    const int lf = pass == 0 ? 1 : (dbl ? 1 : 0);
+                    hipStream_t st = stream_of(h);
+                    bp.launches.push_back([=](char *base) {
+                        return conv_direct_batched<T>(cls, lf, (const ConvDesc *)(base + off), cnt, total, flops, st);
+                    });
+                }
+        }
         std::vector<int> act;
         std::vector<size_t> need;
         for (int i = 0; i < (int)P.size(); ++i)
-            if (P[i].n > m && m >= seed_len(h, P[i].n)) {
+            if (P[i].n > m && m >= seed_len(h, P[i].n) && std::min(2 * m, P[i].n) > direct_limit(h, P[i].d)) {
                 act.push_back(i);
                 need.push_back(3 * spec_bytes(p.lgL, (int64_t)P[i].d * P[i].d, dbl));
             }
@@ -1486,10 +1587,11 @@ static mrinv_status_t plan_batched(mrinv_handle_t h, int count, const double *co
     return MRINV_OK;
 }
 
-extern "C" size_t mrinv_batched_workspace_size(int count, const int *d, const int64_t *n, mrinv_precision_t prec) {
+extern "C" size_t mrinv_batched_workspace_size(mrinv_handle_t h, int count, const int *d, const int64_t *n,
+                                               mrinv_precision_t prec) {
     if (count < 1 || !d || !n) return 0;
     BatchPlan bp;
-    if (plan_batched(nullptr, count, nullptr, d, n, prec, nullptr, nullptr, bp) != MRINV_OK) return 0;
+    if (plan_batched(h, count, nullptr, d, n, prec, nullptr, nullptr, bp) != MRINV_OK) return 0;
     return bp.total;
 }
 

@@ -671,6 +671,181 @@ static hipError_t launch_gemm_mfma_batched(const FftPlan &plan, const GemmProble
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Direct truncated products of the first Newton steps (the definition of the
+// product in the truncated ring, Section 2.1, without transforms): for small m
+// the 1.5 m^2 d^3 multiply-adds of a step cost less than the latency of the
+// transform launches.  One workgroup per (k, 16x16 output tile); its four
+// waves take every fourth j and their tiles are summed through LDS.
+// ---------------------------------------------------------------------------
+constexpr int CONV_THREADS = 256;
+
+template <typename T, typename TL, int DP>
+__device__ __forceinline__ void conv_direct_body(const ConvDesc &c, int64_t blk) {
+    using Op = MfmaOp<T>;
+    using V = typename Op::V;
+    constexpr int NT = DP / 16;
+    const int64_t k = c.k0 + blk / (NT * NT);
+    const int tile = (int)(blk % (NT * NT));
+    const int I = tile / NT, J = tile - I * NT;
+    const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int d = c.d;
+    const int64_t dd = (int64_t)d * d;
+    const int64_t jhi = c.jhi < k ? c.jhi : k;
+    const int ia = I * 16 + (l & 15);         // row of the L operand
+    const int cb = J * 16 + (l & 15);         // column of the R operand
+    const int tq = l >> 4;
+    const TL *Lp = (const TL *)c.L;
+    const T *Rp = (const T *)c.R;
+    const T sg = (T)c.sign;
+    V acc;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) acc[r] = (T)0;
+    // Two values of j per iteration keep twice the loads in flight.
+    for (int64_t j = c.jlo + w; j <= jhi; j += 8) {
+        const bool two = j + 4 <= jhi;
+        T a0[DP / 4], b0[DP / 4], a1[DP / 4], b1[DP / 4];
+        const TL *L0 = Lp + (k - j) * dd, *L1 = Lp + (k - j - 4) * dd;
+        const T *R0 = Rp + (j - c.r_off) * dd, *R1 = Rp + (j + 4 - c.r_off) * dd;
+#pragma unroll
+        for (int tb = 0; tb < DP / 4; ++tb) {
+            const int t = 4 * tb + tq;
+            const bool okA = ia < d && t < d, okB = t < d && cb < d;
+            a0[tb] = okA ? (T)L0[ia * d + t] : (T)0;
+            b0[tb] = okB ? R0[t * d + cb] : (T)0;
+            a1[tb] = (two && okA) ? (T)L1[ia * d + t] : (T)0;
+            b1[tb] = (two && okB) ? R1[t * d + cb] : (T)0;
+        }
+#pragma unroll
+        for (int tb = 0; tb < DP / 4; ++tb) acc = Op::mac(a0[tb] * sg, b0[tb], acc);
+#pragma unroll
+        for (int tb = 0; tb < DP / 4; ++tb) acc = Op::mac(a1[tb] * sg, b1[tb], acc);
+    }
+    __shared__ T red[4][4][64];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) red[w][r][l] = acc[r];
+    __syncthreads();
+    if (w == 0) {
+        T *out = (T *)c.out + (k - c.out_off) * dd;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int row = I * 16 + Op::row(l, r), col = J * 16 + (l & 15);
+            const T v = (red[0][r][l] + red[1][r][l]) + (red[2][r][l] + red[3][r][l]);
+            if (row < d && col < d) {
+                out[row * d + col] = v;
+                if (c.status && !isfinite((double)v)) atomicOr(c.status, 2u);
+            }
+        }
+    }
+}
+
+template <typename T, typename TL, int DP>
+__global__ void __launch_bounds__(CONV_THREADS) conv_direct_kernel(ConvDesc c) {
+    conv_direct_body<T, TL, DP>(c, blockIdx.x);
+}
+
+template <typename T, typename TL, int DP>
+__global__ void __launch_bounds__(CONV_THREADS) conv_direct_batched_kernel(const ConvDesc *cs, int n) {
+    int lo = 0, hi = n - 1;
+    const int64_t bid = blockIdx.x;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (cs[mid].wg_begin <= bid) lo = mid;
+        else hi = mid - 1;
+    }
+    conv_direct_body<T, TL, DP>(cs[lo], bid - cs[lo].wg_begin);
+}
+
+int conv_class(int d) { return (d + 15) / 16; }
+
+static int64_t conv_blocks(const ConvDesc &c) {
+    const int nt = conv_class(c.d);
+    return (c.k1 - c.k0) * nt * nt;
+}
+
+static double conv_flops(const ConvDesc &c) {
+    double terms = 0;   // sum over k of the number of j
+    for (int64_t k = c.k0; k < c.k1; ++k) {
+        const int64_t hi = c.jhi < k ? c.jhi : k;
+        if (hi >= c.jlo) terms += (double)(hi - c.jlo + 1);
+    }
+    return terms * 2.0 * c.d * c.d * c.d;
+}
+
+template <typename T, typename TL, int DP>
+static hipError_t launch_conv(const ConvDesc &c, hipStream_t st) {
+    char name[96];
+    snprintf(name, sizeof name, "conv_direct_kernel<%s, %s, %d>", sizeof(T) == 8 ? "double" : "float",
+             sizeof(TL) == 8 ? "double" : "float", DP);
+    launch_begin(name, 0.0, conv_flops(c));
+    hipLaunchKernelGGL((conv_direct_kernel<T, TL, DP>), dim3((unsigned)conv_blocks(c)), dim3(CONV_THREADS), 0, st, c);
+    launch_end();
+    return hipGetLastError();
+}
+
+template <typename T, typename TL>
+static hipError_t conv_dispatch(const ConvDesc &c, hipStream_t st) {
+    switch (conv_class(c.d)) {
+        case 1: return launch_conv<T, TL, 16>(c, st);
+        case 2: return launch_conv<T, TL, 32>(c, st);
+        case 3: return launch_conv<T, TL, 48>(c, st);
+        default: return launch_conv<T, TL, 64>(c, st);
+    }
+}
+
+template <typename T>
+hipError_t conv_direct(const ConvDesc &c, hipStream_t st) {
+    if (c.k1 <= c.k0) return hipSuccess;
+    if constexpr (sizeof(T) == 8) return conv_dispatch<T, double>(c, st);
+    else return c.l_f64 ? conv_dispatch<T, double>(c, st) : conv_dispatch<T, float>(c, st);
+}
+
+int64_t conv_batch_layout(ConvDesc *cs, int n) {
+    int64_t acc = 0;
+    for (int i = 0; i < n; ++i) {
+        cs[i].wg_begin = acc;
+        acc += conv_blocks(cs[i]);
+    }
+    return acc;
+}
+
+template <typename T, typename TL, int DP>
+static hipError_t launch_conv_batched(const ConvDesc *cs, int n, int64_t total, double flops, hipStream_t st) {
+    char name[96];
+    snprintf(name, sizeof name, "conv_direct_batched_kernel<%s, %s, %d>", sizeof(T) == 8 ? "double" : "float",
+             sizeof(TL) == 8 ? "double" : "float", DP);
+    launch_begin(name, 0.0, flops);
+    hipLaunchKernelGGL((conv_direct_batched_kernel<T, TL, DP>), dim3((unsigned)total), dim3(CONV_THREADS), 0, st, cs,
+                       n);
+    launch_end();
+    return hipGetLastError();
+}
+
+template <typename T, typename TL>
+static hipError_t conv_batched_dispatch(int cls, const ConvDesc *cs, int n, int64_t total, double flops,
+                                        hipStream_t st) {
+    switch (cls) {
+        case 1: return launch_conv_batched<T, TL, 16>(cs, n, total, flops, st);
+        case 2: return launch_conv_batched<T, TL, 32>(cs, n, total, flops, st);
+        case 3: return launch_conv_batched<T, TL, 48>(cs, n, total, flops, st);
+        default: return launch_conv_batched<T, TL, 64>(cs, n, total, flops, st);
+    }
+}
+
+template <typename T>
+hipError_t conv_direct_batched(int cls, int l_f64, const ConvDesc *cs, int n, int64_t total, double flops,
+                               hipStream_t st) {
+    if (total <= 0) return hipSuccess;
+    if constexpr (sizeof(T) == 8) return conv_batched_dispatch<T, double>(cls, cs, n, total, flops, st);
+    else return l_f64 ? conv_batched_dispatch<T, double>(cls, cs, n, total, flops, st)
+                      : conv_batched_dispatch<T, float>(cls, cs, n, total, flops, st);
+}
+
+template hipError_t conv_direct<double>(const ConvDesc &, hipStream_t);
+template hipError_t conv_direct<float>(const ConvDesc &, hipStream_t);
+template hipError_t conv_direct_batched<double>(int, int, const ConvDesc *, int, int64_t, double, hipStream_t);
+template hipError_t conv_direct_batched<float>(int, int, const ConvDesc *, int, int64_t, double, hipStream_t);
+
 template <typename T, int DP>
 static size_t sq_lds_bytes(int dmax_odd) {
     using Cfg = SqCfg<DP>;

@@ -112,6 +112,23 @@ template <typename T> struct GemmProblem {
     int64_t wg_begin;
 };
 
+// One truncated product in the time domain (the first Newton steps):
+//     out(k) = sign * sum_{j = jlo}^{min(jhi, k)} L(k - j) R(j),  k in [k0, k1),
+// d x d matrices, L(l) at L + l d^2 (float64 or the working precision),
+// R(j) at R + (j - r_off) d^2, out(k) at out + (k - out_off) d^2.  The
+// workgroups of a batched launch from wg_begin on belong to it.
+struct ConvDesc {
+    const void *L;
+    const void *R;
+    void *out;
+    int l_f64;
+    int d;
+    double sign;
+    int64_t k0, k1, jlo, jhi, r_off, out_off;
+    unsigned int *status;   // optional: STATUS_NONFINITE on a non-finite output
+    int64_t wg_begin;
+};
+
 // One problem of a batched Gauss-Jordan launch (one workgroup each).
 struct GjProblem {
     const double *A0;
@@ -194,6 +211,16 @@ hipError_t seed_recursion_batched(const SeedProblem *probs, int nprob, int total
 // e0 != 0 means the source is q and A = e0 - q.
 template <typename T>
 hipError_t seed_recursion(const double *A, int e0, int d, int m0, T *out, hipStream_t st);
+// Direct products (ConvDesc) on the matrix cores: one launch, or one launch
+// over many descriptors of the same padded dimension 16 * cls (device table,
+// wg_begin from conv_batch_layout).
+int conv_class(int d);
+template <typename T>
+hipError_t conv_direct(const ConvDesc &c, hipStream_t st);
+int64_t conv_batch_layout(ConvDesc *host_descs, int n);
+template <typename T>
+hipError_t conv_direct_batched(int cls, int l_f64, const ConvDesc *dev_descs, int n, int64_t total, double flops,
+                               hipStream_t st);
 
 hipError_t gj_inverse_batched(const GjProblem *dev_probs, int nprob, int dmax, unsigned int *status,
                               hipStream_t st);

@@ -83,9 +83,9 @@ def test_batched_workspace_query_without_a_handle(L):
     d = (ctypes.c_int * 512)(*[x["d"] for x in w])
     n = (ctypes.c_int64 * 512)(*[x["n"] for x in w])
     L.mrinv_batched_workspace_size.restype = ctypes.c_size_t
-    fp64 = L.mrinv_batched_workspace_size(512, d, n, 0)
-    mixed = L.mrinv_batched_workspace_size(512, d, n, 1)
+    fp64 = L.mrinv_batched_workspace_size(None, 512, d, n, 0)
+    mixed = L.mrinv_batched_workspace_size(None, 512, d, n, 1)
     assert 0 < fp64 < mixed < (96 << 30)
     bad = (ctypes.c_int * 1)(65)
     one = (ctypes.c_int64 * 1)(10)
-    assert L.mrinv_batched_workspace_size(1, bad, one, 0) == 0
+    assert L.mrinv_batched_workspace_size(None, 1, bad, one, 0) == 0

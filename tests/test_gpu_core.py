@@ -389,14 +389,17 @@ def test_matrix_core_products_match_oracle(mr, orc, d):
     assert _maxerr(got[0, "fp64"], got[2, "fp64"]) <= 1e-13
 
 
-def test_matrix_core_batched_matches_single_calls(mr, orc):
-    """With every product class on the matrix cores, the batched call still
-    equals the single-problem calls bitwise (same kernel bodies)."""
+@pytest.mark.parametrize("tuning", [dict(mfma=2), dict(seed_m0=16, direct_m=0), dict(direct_m=1024, mfma=0)])
+def test_matrix_core_batched_matches_single_calls(mr, orc, tuning):
+    """Under non-default tunings (all products on the matrix cores; recursion
+    seed and transforms only; direct steps up to 1024 with vector products)
+    the batched call, planned and sized for the handle's tuning, still equals
+    the single-problem calls bitwise (same kernel bodies) and the oracle."""
     specs = [(9, 100), (16, 257), (23, 64), (32, 130), (41, 40), (64, 33), (5, 77)]
     qs = [si.family_kernel("weibull", d, n, 800 + i).q.cuda() for i, (d, n) in enumerate(specs)]
     base = mr.get_tuning()
     try:
-        mr.set_tuning(mfma=2)
+        mr.set_tuning(**tuning)
         for prec in ("fp64", "mixed"):
             outs = mr.psi_inverse_batched(qs, prec)
             mr.sync_status()
@@ -408,3 +411,41 @@ def test_matrix_core_batched_matches_single_calls(mr, orc):
                 assert _maxerr(_np(o), ref) <= (FP64_TOL if prec == "fp64" else MIXED_TOL), (prec, d, n)
     finally:
         mr.set_tuning(**base)
+
+
+@pytest.mark.parametrize("d", [1, 3, 4, 16, 17, 33, 64])
+def test_direct_steps_match_oracle(mr, orc, d):
+    """Newton steps formed directly in the time domain (direct_m), none of
+    them (0), the automatic choice (-1) and all of them, with and without the
+    recursion seed, FP64 and mixed, against the oracle."""
+    n = 200 if d <= 33 else 90
+    print(f"[direct] d={d} n={n}", flush=True)
+    q = si.family_kernel("weibull" if d % 2 == 0 else "lognormal", d, n, 900 + d).q
+    ref = orc.psi(q.numpy())
+    qg = _gpu(q)
+    base = mr.get_tuning()
+    try:
+        for direct_m, seed in ((0, 1), (-1, 1), (65536, 1), (65536, 16), (64, 8)):
+            mr.set_tuning(direct_m=direct_m, seed_m0=seed)
+            for prec in ("fp64", "mixed"):
+                o = _np(mr.psi_inverse(qg, prec, check=True))
+                tol = FP64_TOL if prec == "fp64" else MIXED_TOL
+                assert _maxerr(o, ref) <= tol, (direct_m, seed, prec)
+    finally:
+        mr.set_tuning(**base)
+
+
+def test_direct_steps_series_inverse_general_a0(mr, orc):
+    """series_inverse with a general A(0) through direct steps only."""
+    d, n = 5, 120
+    rng = np.random.default_rng(41)
+    A = rng.standard_normal((n, d, d)) / (d * (1 + np.arange(n))[:, None, None] ** 2)
+    A[0] = rng.standard_normal((d, d)) + 0.5 * np.eye(d)
+    ref = orc.series_inverse_left(A)
+    base = mr.get_tuning()
+    try:
+        mr.set_tuning(direct_m=65536)
+        got = _np(mr.series_inverse(_gpu(A), check=True))
+    finally:
+        mr.set_tuning(**base)
+    assert _maxerr(got, ref) <= 1e-11 * max(1.0, np.max(np.abs(ref)))
