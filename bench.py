@@ -151,6 +151,42 @@ def roofline_of(stats, traffic_file=None):
     return roof, breakdown
 
 
+def write_traffic(args, kernel: str, fetch_csv: str, write_csv: str) -> None:
+    """HBM traffic of one launch of `kernel` from rocprofv3 counter runs.
+
+    FETCH_SIZE and WRITE_SIZE (KiB per dispatch) are scaled so that the 1 GiB
+    device-to-device copy of --calibrate-copy (the largest copyBuffer
+    dispatch) reads and writes exactly 1 GiB, then averaged over the kernel's
+    dispatches.  The file carries the kernel source hash; bench.py ignores it
+    once the kernels change."""
+    import csv
+    import re
+
+    def rows(path, counter):
+        return [r for r in csv.DictReader(open(path)) if r["Counter_Name"] == counter]
+
+    def short(name):
+        return re.sub(r"\(.*", "", re.sub(r"^void mrinv::", "", name)).strip()
+
+    out = {"kernel": kernel, "source_hash": source_hash(), "config": args.config, "form": CONFIGS[args.config]["form"]}
+    for counter, path in (("FETCH_SIZE", fetch_csv), ("WRITE_SIZE", write_csv)):
+        rr = rows(path, counter)
+        cal = max(float(r["Counter_Value"]) for r in rr if "copyBuffer" in r["Kernel_Name"])
+        scale = float(1 << 30) / (cal * 1024.0)
+        vals = [float(r["Counter_Value"]) * 1024.0 * scale for r in rr if short(r["Kernel_Name"]) == kernel]
+        if not vals:
+            raise SystemExit(f"no dispatch of {kernel} in {path}")
+        key = counter.split("_")[0].lower()
+        out[f"{key}_scale"] = scale
+        out[f"{key}_bytes_per_launch"] = sum(vals) / len(vals)
+        out["dispatches"] = len(vals)
+    out["bytes_per_launch"] = out["fetch_bytes_per_launch"] + out["write_bytes_per_launch"]
+    path = os.path.join(ROOT, "profiles", f"traffic_{args.config}_{out['form']}.json")
+    with open(path, "w") as f:
+        json.dump(out, f, indent=1)
+    print(json.dumps(out))
+
+
 def cpu_baseline(cfg, budget_s: float):
     """The oracle's left recursion on a prefix n' of the same kernel (finite-
     horizon exactness makes the prefix a valid sub-problem), sized to about
@@ -262,7 +298,13 @@ def main():
     ap.add_argument("--forms", default="fp64,mixed", help="comma-separated forms to time (value form first)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one 1 GiB device-to-device copy first (reference for HBM counter runs)")
+    ap.add_argument("--traffic", nargs=3, metavar=("KERNEL", "FETCH_CSV", "WRITE_CSV"),
+                    help="write profiles/traffic_<config>_<form>.json for KERNEL from two rocprofv3 --pmc runs "
+                         "(FETCH_SIZE, then WRITE_SIZE) of a --calibrate-copy bench command, then exit")
     args = ap.parse_args()
+
+    if args.traffic:
+        return write_traffic(args, *args.traffic)
 
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the path is single-GPU by design "

@@ -643,7 +643,8 @@ static hipError_t launch_gemm_mfma(const FftPlan &plan, int d, const cplx<T> *ZA
     const int64_t F = ((int64_t)1 << plan.lgL) / 2 + 1;
     const int64_t blocks = (F + Cfg::NF - 1) / Cfg::NF;
     char name[96];
-    snprintf(name, sizeof name, "freq_gemm_mfma_kernel<%s, %d, %d>", sizeof(T) == 8 ? "double" : "float", DP, (int)ODD);
+    snprintf(name, sizeof name, "freq_gemm_mfma_kernel<%s, %d, %s>", sizeof(T) == 8 ? "double" : "float", DP,
+             ODD ? "true" : "false");
     const double Lr = (double)((int64_t)1 << plan.lgL);
     const int nl = (d * d + 1) / 2;
     launch_begin(name, Lr * 3.0 * nl * sizeof(cplx<T>), (double)F * 8.0 * d * d * d);
@@ -663,8 +664,8 @@ static hipError_t launch_gemm_mfma_batched(const FftPlan &plan, const GemmProble
         (void)hipGetLastError();
     }
     char name[96];
-    snprintf(name, sizeof name, "freq_gemm_mfma_batched_kernel<%s, %d, %d>", sizeof(T) == 8 ? "double" : "float", DP,
-             (int)ODD);
+    snprintf(name, sizeof name, "freq_gemm_mfma_batched_kernel<%s, %d, %s>", sizeof(T) == 8 ? "double" : "float",
+             DP, ODD ? "true" : "false");
     launch_begin(name, bytes, flops);
     hipLaunchKernelGGL(kern, dim3((unsigned)total), dim3(Cfg::THREADS), lds, st, probs, nprob, plan);
     launch_end();
