@@ -41,7 +41,11 @@ static mrinv_status_t fail(mrinv_status_t s, const char *fmt, ...) {
 // ---------------------------------------------------------------------------
 // Handle
 // ---------------------------------------------------------------------------
-constexpr size_t SCRATCH_BYTES = (size_t)MRINV_MAX_N * sizeof(double) + 4096 * sizeof(double);
+// Handle scratch: MRINV_MAX_N doubles (1-lane scan input copies), 4096
+// doubles of small vectors, then the time-scan workspace for up to 256 lanes.
+constexpr size_t SCRATCH_SCAN_OFF = (size_t)MRINV_MAX_N + 4096;   // in doubles
+constexpr size_t SCRATCH_BYTES =
+    SCRATCH_SCAN_OFF * sizeof(double) + ((MRINV_MAX_N + 1023) / 1024) * 256 * sizeof(double);
 
 // Tuning of a new handle, also used where no handle is given (workspace
 // queries), so that both plan the same launches.
@@ -849,7 +853,7 @@ extern "C" mrinv_status_t mrinv_survival(mrinv_handle_t h, const double *q, int 
     TimerScope _ts(h);
     if (!h || !q || !hb) return fail(MRINV_E_ARG, "NULL handle or pointer");
     CHECK(check_dn(d, n));
-    HIP_TRY(survival(q, d, n, hb, h->stream));
+    HIP_TRY(survival(q, d, n, hb, h->scratch + SCRATCH_SCAN_OFF, h->stream));
     return MRINV_OK;
 }
 
@@ -865,7 +869,7 @@ extern "C" mrinv_status_t mrinv_transition(mrinv_handle_t h, const double *psi, 
     double *hb = cv.take<double>((size_t)n * d * sizeof(double));
     auto *SP = cv.take<cplx<double>>(spec_bytes(p.lgL, d2, true));
     auto *SH = cv.take<cplx<double>>(spec_bytes(p.lgL, d, true));
-    HIP_TRY(survival(q, d, n, hb, h->stream));
+    HIP_TRY(survival(q, d, n, hb, h->scratch + SCRATCH_SCAN_OFF, h->stream));
     HIP_TRY(fwd<double>(h, p, nl_of(d2), SP, src_real(psi, true, d2, (int)d2, 0, n)));
     HIP_TRY(fwd<double>(h, p, nl_of(d), SH, src_real(hb, true, d, d, 0, n)));
     HIP_TRY(freq_diag<double>(p, d, d, SP, SH, SP, h->stream));
@@ -880,7 +884,8 @@ extern "C" mrinv_status_t mrinv_contract(mrinv_handle_t h, const double *X, int6
     TimerScope _ts(h);
     if (!h || !X || !u || !v || !out) return fail(MRINV_E_ARG, "NULL handle or pointer");
     if (n < 1 || rows < 1 || cols < 1 || n > MRINV_MAX_N) return fail(MRINV_E_ARG, "bad sizes");
-    HIP_TRY(contract(X, n, rows, cols, u, v, cumulative, offset, scale, out, h->stream));
+    HIP_TRY(contract(X, n, rows, cols, u, v, cumulative, offset, scale, out, h->scratch + SCRATCH_SCAN_OFF,
+                     h->stream));
     return MRINV_OK;
 }
 
@@ -895,7 +900,8 @@ extern "C" mrinv_status_t mrinv_contract_backward(mrinv_handle_t h, const double
         HIP_TRY(hipMemcpyAsync(h->scratch, out_bar, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, h->stream));
         w = h->scratch;
     }
-    HIP_TRY(contract_backward(w, n, rows, cols, u, v, cumulative, scale, X_bar_accum, h->stream));
+    HIP_TRY(contract_backward(w, n, rows, cols, u, v, cumulative, scale, X_bar_accum, h->scratch + SCRATCH_SCAN_OFF,
+                              h->stream));
     return MRINV_OK;
 }
 
@@ -983,8 +989,9 @@ static mrinv_status_t first_entrance_impl(mrinv_handle_t h, const double *q, int
     if (rest_b < psib + std::max(need_inv, need_app)) return fail(MRINV_E_WORKSPACE, "workspace too small");
     CHECK(mrinv_psi_inverse(h, qCC, nC, n, prec, psiC, ws2, rest_b - psib));
     CHECK(mrinv_markov_renewal_apply(h, psiC, nC, n, qCD, nD, gD, ws2, rest_b - psib));
-    if (g) HIP_TRY(contract(gD, n, nC, nD, sv.alpha, sv.ones, 0, 0.0, 1.0, g, h->stream));
-    HIP_TRY(contract(gD, n, nC, nD, sv.alpha, sv.ones, 1, offset, scale, F, h->stream));
+    if (g)
+        HIP_TRY(contract(gD, n, nC, nD, sv.alpha, sv.ones, 0, 0.0, 1.0, g, h->scratch + SCRATCH_SCAN_OFF, h->stream));
+    HIP_TRY(contract(gD, n, nC, nD, sv.alpha, sv.ones, 1, offset, scale, F, h->scratch + SCRATCH_SCAN_OFF, h->stream));
     return MRINV_OK;
 }
 
@@ -1017,7 +1024,7 @@ extern "C" mrinv_status_t mrinv_availability(mrinv_handle_t h, const double *P, 
     CHECK(put_small(h, {}, {}, al, d, sv));
     HIP_TRY(hipMemcpyAsync(sv.ones, ind.data(), d * sizeof(double), hipMemcpyHostToDevice, h->stream));
     HIP_TRY(hipStreamSynchronize(h->stream));
-    HIP_TRY(contract(P, n, d, d, sv.alpha, sv.ones, 0, 0.0, 1.0, A, h->stream));
+    HIP_TRY(contract(P, n, d, d, sv.alpha, sv.ones, 0, 0.0, 1.0, A, h->scratch + SCRATCH_SCAN_OFF, h->stream));
     return MRINV_OK;
 }
 
@@ -1101,7 +1108,7 @@ extern "C" mrinv_status_t mrinv_transition_backward(mrinv_handle_t h, const doub
     const double invL = 1.0 / (double)((int64_t)1 << p.lgL);
     HIP_TRY(fwd<double>(h, p, nl_of(d2), S1, src_real(P_bar, true, d2, (int)d2, 0, n, n - 1)));
     if (psi_bar_accum) {
-        HIP_TRY(survival(q, d, n, hb, h->stream));
+        HIP_TRY(survival(q, d, n, hb, h->scratch + SCRATCH_SCAN_OFF, h->stream));
         HIP_TRY(fwd<double>(h, p, nl_of(d), SH, src_real(hb, true, d, d, 0, n)));
         HIP_TRY(freq_diag<double>(p, d, d, S1, SH, S2, h->stream));
         HIP_TRY(inv<double>(h, p, nl_of(d2), S2,
@@ -1111,7 +1118,7 @@ extern "C" mrinv_status_t mrinv_transition_backward(mrinv_handle_t h, const doub
         HIP_TRY(fwd<double>(h, p, nl_of(d2), S2, src_real(psi, true, d2, (int)d2, 0, n)));
         HIP_TRY(freq_coldot<double>(p, d, d, S2, S1, SH, h->stream));
         HIP_TRY(inv<double>(h, p, nl_of(d), SH, dst_real(hbb, true, d, d, 0, n, invL, OP_STORE, n - 1)));
-        HIP_TRY(survival_backward(hbb, d, n, q_bar_accum, h->stream));
+        HIP_TRY(survival_backward(hbb, d, n, q_bar_accum, h->scratch + SCRATCH_SCAN_OFF, h->stream));
     }
     return MRINV_OK;
 }

@@ -206,67 +206,127 @@ template hipError_t seed_recursion<float>(const double *, int, int, int, float *
 
 // ---------------------------------------------------------------------------
 // Inclusive scan over time of w lanes, Y[k][i] <- a + b * sum_{l<=k} Y[l][i]
-// (reverse != 0: sum over l >= k).  One workgroup per lane; each thread scans
-// a contiguous segment, segment totals are scanned in LDS.
+// (reverse != 0: sum over l >= k), w <= 256.  Three launches: chunk totals,
+// an exclusive scan of the totals, and the rescan of every chunk from its
+// offset.  Inside a chunk of SCAN_ROWS time steps, thread (s, i) of a
+// workgroup handles lane i over sub-segment s; reads of one time step are
+// contiguous across lanes.
 // ---------------------------------------------------------------------------
-constexpr int SCAN_THREADS = 1024;
+constexpr int SCAN_THREADS = 256;
+constexpr int SCAN_ROWS = 1024;
 
-__global__ void __launch_bounds__(SCAN_THREADS) scan_lanes_kernel(double *Y, int64_t n, int w, int reverse,
-                                                                  double a, double b) {
+__device__ __forceinline__ int64_t scan_row(int64_t k, int64_t n, int reverse) { return reverse ? n - 1 - k : k; }
+
+// Thread layout of one chunk: lanes i < w, sub-segments s < nsub = 256 / w.
+struct ScanGeom {
+    int w, nsub, i, s;
+    int64_t k0, k1;     // rows of this thread's sub-segment
+    bool ok;
+};
+
+__device__ __forceinline__ ScanGeom scan_geom(int64_t n, int w, int64_t chunk) {
+    ScanGeom g;
+    g.w = w;
+    g.nsub = SCAN_THREADS / w;
+    g.i = threadIdx.x % w;
+    g.s = threadIdx.x / w;
+    g.ok = g.s < g.nsub;
+    const int64_t c0 = chunk * SCAN_ROWS, c1 = min(n, c0 + SCAN_ROWS);
+    const int64_t seg = (SCAN_ROWS + g.nsub - 1) / g.nsub;
+    g.k0 = min(c1, c0 + g.s * seg);
+    g.k1 = min(c1, g.k0 + seg);
+    return g;
+}
+
+__global__ void __launch_bounds__(SCAN_THREADS) scan_totals_kernel(const double *Y, int64_t n, int w, int reverse,
+                                                                   double *tot) {
     __shared__ double part[SCAN_THREADS];
-    const int i = blockIdx.x;
-    const int t = threadIdx.x;
-    const int64_t seg = (n + SCAN_THREADS - 1) / SCAN_THREADS;
-    const int64_t lo = t * seg, hi = min(n, lo + seg);
-    auto at = [&](int64_t k) -> double & { return Y[(reverse ? (n - 1 - k) : k) * w + i]; };
+    const ScanGeom g = scan_geom(n, w, blockIdx.x);
     double s = 0.0;
-    for (int64_t k = lo; k < hi; ++k) s += at(k);
-    part[t] = s;
+    if (g.ok)
+        for (int64_t k = g.k0; k < g.k1; ++k) s += Y[scan_row(k, n, reverse) * w + g.i];
+    part[threadIdx.x] = s;
     __syncthreads();
-    // Hillis-Steele inclusive scan of the segment totals.
-    for (int off = 1; off < SCAN_THREADS; off <<= 1) {
-        const double v = t >= off ? part[t - off] : 0.0;
-        __syncthreads();
-        part[t] += v;
-        __syncthreads();
-    }
-    double run = t > 0 ? part[t - 1] : 0.0;
-    for (int64_t k = lo; k < hi; ++k) {
-        run += at(k);
-        at(k) = a + b * run;
+    if (threadIdx.x < w) {
+        double t = 0.0;
+        for (int u = 0; u < g.nsub; ++u) t += part[u * w + threadIdx.x];
+        tot[(int64_t)blockIdx.x * w + threadIdx.x] = t;
     }
 }
 
-static hipError_t scan_lanes(double *Y, int64_t n, int w, int reverse, double a, double b, hipStream_t st) {
-    launch_begin("scan_lanes_kernel", 2.0 * n * w * 8.0, 0.0);
-    hipLaunchKernelGGL(scan_lanes_kernel, dim3(w), dim3(SCAN_THREADS), 0, st, Y, n, w, reverse, a, b);
+// Exclusive scan of the chunk totals per lane, in place (one thread per lane).
+__global__ void __launch_bounds__(SCAN_THREADS) scan_offsets_kernel(double *tot, int64_t nchunks, int w) {
+    const int i = threadIdx.x;
+    if (i >= w) return;
+    double run = 0.0;
+    for (int64_t c = 0; c < nchunks; ++c) {
+        const double v = tot[c * w + i];
+        tot[c * w + i] = run;
+        run += v;
+    }
+}
+
+__global__ void __launch_bounds__(SCAN_THREADS) scan_apply_kernel(double *Y, int64_t n, int w, int reverse,
+                                                                  const double *off, double a, double b) {
+    __shared__ double part[SCAN_THREADS];
+    const ScanGeom g = scan_geom(n, w, blockIdx.x);
+    double s = 0.0;
+    if (g.ok)
+        for (int64_t k = g.k0; k < g.k1; ++k) s += Y[scan_row(k, n, reverse) * w + g.i];
+    part[threadIdx.x] = s;
+    __syncthreads();
+    if (!g.ok) return;
+    double run = off[(int64_t)blockIdx.x * w + g.i];
+    for (int u = 0; u < g.s; ++u) run += part[u * w + g.i];
+    for (int64_t k = g.k0; k < g.k1; ++k) {
+        double &y = Y[scan_row(k, n, reverse) * w + g.i];
+        run += y;
+        y = a + b * run;
+    }
+}
+
+// tmp: ceil(n / SCAN_ROWS) * w doubles.
+static hipError_t scan_lanes(double *Y, int64_t n, int w, int reverse, double a, double b, double *tmp,
+                             hipStream_t st) {
+    if (w < 1 || w > SCAN_THREADS) return hipErrorInvalidValue;
+    const int64_t nch = (n + SCAN_ROWS - 1) / SCAN_ROWS;
+    launch_begin("scan_lanes_kernel", 3.0 * n * w * 8.0, 0.0);
+    hipLaunchKernelGGL(scan_totals_kernel, dim3((unsigned)nch), dim3(SCAN_THREADS), 0, st, Y, n, w, reverse, tmp);
+    hipLaunchKernelGGL(scan_offsets_kernel, dim3(1), dim3(SCAN_THREADS), 0, st, tmp, nch, w);
+    hipLaunchKernelGGL(scan_apply_kernel, dim3((unsigned)nch), dim3(SCAN_THREADS), 0, st, Y, n, w, reverse,
+                       (const double *)tmp, a, b);
     launch_end();
     return hipGetLastError();
 }
 
-// rho[k][i] = sum_j q_ij(k) for k >= 1, rho[0][i] = 0.
-__global__ void rowsum_kernel(const double *q, int d, int64_t n, double *rho) {
+size_t scan_tmp_bytes(int64_t n, int w) { return (size_t)((n + SCAN_ROWS - 1) / SCAN_ROWS) * w * sizeof(double); }
+
+// rho[k][i] = sum_j q_ij(k) for k >= 1, rho[0][i] = 0.  Row (k, i) is summed
+// by a group of G = 2^ceil(log2 d) lanes of one wavefront (coalesced reads,
+// butterfly reduction).
+__global__ void rowsum_kernel(const double *q, int d, int lgG, int64_t n, double *rho) {
+    const int G = 1 << lgG;
     const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (gid >= n * d) return;
-    const int64_t k = gid / d;
-    const int i = (int)(gid - k * d);
-    double s = 0.0;
-    if (k > 0) {
-        const double *row = q + (k * d + i) * d;
-        for (int j = 0; j < d; ++j) s += row[j];
-    }
-    rho[gid] = s;
+    const int64_t row = gid >> lgG;            // (k, i) flattened
+    const int j = (int)(gid & (G - 1));
+    const bool in = row < n * d;
+    double v = 0.0;
+    if (in && j < d && row >= d) v = q[row * d + j];
+    for (int o = G >> 1; o > 0; o >>= 1) v += __shfl_xor(v, o, G);
+    if (in && j == 0) rho[row] = v;
 }
 
 // Survival sequence Hbar(k)_ii = 1 - sum_j sum_{l=1..k} q_ij(l) (Section 4.1).
-hipError_t survival(const double *q, int d, int64_t n, double *hb, hipStream_t st) {
-    const int64_t total = n * d;
+hipError_t survival(const double *q, int d, int64_t n, double *hb, double *tmp, hipStream_t st) {
+    int lgG = 0;
+    while ((1 << lgG) < d) ++lgG;
+    const int64_t total = (n * d) << lgG;
     launch_begin("rowsum_kernel", (double)n * d * (d + 1) * 8.0, 0.0);
-    hipLaunchKernelGGL(rowsum_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, q, d, n, hb);
+    hipLaunchKernelGGL(rowsum_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, q, d, lgG, n, hb);
     launch_end();
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    return scan_lanes(hb, n, d, 0, 1.0, -1.0, st);
+    return scan_lanes(hb, n, d, 0, 1.0, -1.0, tmp, st);
 }
 
 // q_bar(l)[i][j] += -sum_{k>=l} hb_bar(k)[i] for l >= 1.  hbb is scanned in place.
@@ -279,8 +339,8 @@ __global__ void bcast_sub_kernel(const double *s, int d, int64_t n, double *qb) 
     qb[gid] -= s[k * d + i];
 }
 
-hipError_t survival_backward(const double *hbb, int d, int64_t n, double *qb, hipStream_t st) {
-    hipError_t e = scan_lanes(const_cast<double *>(hbb), n, d, 1, 0.0, 1.0, st);
+hipError_t survival_backward(const double *hbb, int d, int64_t n, double *qb, double *tmp, hipStream_t st) {
+    hipError_t e = scan_lanes(const_cast<double *>(hbb), n, d, 1, 0.0, 1.0, tmp, st);
     if (e != hipSuccess) return e;
     const int64_t total = n * d * d;
     hipLaunchKernelGGL(bcast_sub_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, hbb, d, n, qb);
@@ -313,13 +373,13 @@ __global__ void affine_kernel(double *y, int64_t n, double a, double b) {
 }
 
 hipError_t contract(const double *X, int64_t n, int rows, int cols, const double *u, const double *v,
-                    int cumulative, double offset, double scale, double *out, hipStream_t st) {
+                    int cumulative, double offset, double scale, double *out, double *tmp, hipStream_t st) {
     const int64_t threads = n * 64;
     hipLaunchKernelGGL(contract_kernel, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, st, X, n, rows, cols,
                        u, v, out);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    if (cumulative) return scan_lanes(out, n, 1, 0, offset, scale, st);
+    if (cumulative) return scan_lanes(out, n, 1, 0, offset, scale, tmp, st);
     hipLaunchKernelGGL(affine_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, out, n, offset, scale);
     return hipGetLastError();
 }
@@ -337,11 +397,11 @@ __global__ void outer_accum_kernel(const double *w, int64_t n, int rows, int col
 }
 
 hipError_t contract_backward(const double *ob, int64_t n, int rows, int cols, const double *u, const double *v,
-                             int cumulative, double scale, double *Xb, hipStream_t st) {
+                             int cumulative, double scale, double *Xb, double *tmp, hipStream_t st) {
     // The cumulative form needs the reverse cumulative sum of out_bar; it is
     // formed in place in the caller's out_bar buffer copy (see api).
     if (cumulative) {
-        hipError_t e = scan_lanes(const_cast<double *>(ob), n, 1, 1, 0.0, 1.0, st);
+        hipError_t e = scan_lanes(const_cast<double *>(ob), n, 1, 1, 0.0, 1.0, tmp, st);
         if (e != hipSuccess) return e;
     }
     const int64_t total = n * rows * cols;

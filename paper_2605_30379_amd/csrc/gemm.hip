@@ -393,7 +393,9 @@ __device__ __forceinline__ double lane_xor1(double x) {
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
-template <typename T, int DP, bool ODD>
+// TA / TB: operand stored transposed (A(i, t) at entry t d + i, B(t, j) at
+// entry j d + t), staged entry by entry.
+template <typename T, int DP, bool ODD, bool TA = false, bool TB = false>
 __device__ __forceinline__ void freq_gemm_mfma_body(const cplx<T> *__restrict__ ZA, const cplx<T> *__restrict__ ZB,
                                                     cplx<T> *__restrict__ ZC, const FftPlan &plan, int d,
                                                     int64_t blk) {
@@ -426,7 +428,8 @@ __device__ __forceinline__ void freq_gemm_mfma_body(const cplx<T> *__restrict__ 
     __syncthreads();
     const int l = tid & 63, w = tid >> 6;
     const int f = w / WPF, I = w - f * WPF;
-    constexpr bool even = !ODD;
+    constexpr bool even = !ODD;               // C entries (i, j), (i, j^1) share a packed lane
+    constexpr bool pairs = !ODD && !TA && !TB; // operands staged by packed lanes
     V accR[WPF], accI[WPF];
 #pragma unroll
     for (int J = 0; J < WPF; ++J)
@@ -437,10 +440,10 @@ __device__ __forceinline__ void freq_gemm_mfma_body(const cplx<T> *__restrict__ 
     // lane holding each staged pair (even d) or entry (odd d).  Addresses of
     // unused slots are clamped to lane 0 of row 0, so every load is issued
     // unconditionally and the results are masked when staged.
-    constexpr int NR = ODD ? NEN : NPR;
+    constexpr int NR = pairs ? NPR : NEN;
     cplx<T> xa1[NR], xa2[NR], xb1[NR], xb2[NR];
     auto fetch = [&](int kc) {
-        if constexpr (even) {
+        if constexpr (pairs) {
 #pragma unroll
             for (int u = 0; u < NPR; ++u) {
                 const int idx = tid + u * NT;
@@ -463,12 +466,12 @@ __device__ __forceinline__ void freq_gemm_mfma_body(const cplx<T> *__restrict__ 
                 const int ff = idx / (DP * KC), p = idx - ff * (DP * KC);
                 const int i = p / KC, t = p - i * KC;
                 const bool ok = i < d && kc + t < d;
-                const int c = ok ? (i * d + kc + t) >> 1 : 0;
+                const int c = ok ? (TA ? (kc + t) * d + i : i * d + kc + t) >> 1 : 0;
                 xa1[u] = ZA[rows1[ff] * nl + c];
                 xa2[u] = ZA[rows2[ff] * nl + c];
                 const int t2 = p / DP, j = p - t2 * DP;
                 const bool okb = j < d && kc + t2 < d;
-                const int cb = okb ? ((kc + t2) * d + j) >> 1 : 0;
+                const int cb = okb ? (TB ? j * d + kc + t2 : (kc + t2) * d + j) >> 1 : 0;
                 xb1[u] = ZB[rows1[ff] * nl + cb];
                 xb2[u] = ZB[rows2[ff] * nl + cb];
             }
@@ -480,7 +483,7 @@ __device__ __forceinline__ void freq_gemm_mfma_body(const cplx<T> *__restrict__ 
     auto stage = [&](int kc, int buf) {
         cplx<T> *Ab = As + buf * BUF;
         cplx<T> *Bb = Ab + NF * Cfg::AS;
-        if constexpr (even) {
+        if constexpr (pairs) {
 #pragma unroll
             for (int u = 0; u < NPR; ++u) {
                 const int idx = tid + u * NT;
@@ -515,7 +518,7 @@ __device__ __forceinline__ void freq_gemm_mfma_body(const cplx<T> *__restrict__ 
                 const bool fok = k0 + ff < F;
                 {
                     const int i = p / KC, t = p - i * KC;
-                    const int e = i * d + kc + t;
+                    const int e = TA ? (kc + t) * d + i : i * d + kc + t;
                     const bool ok = fok && i < d && kc + t < d;
                     const cplx<T> z1 = xa1[u], z2 = xa2[u];
                     cplx<T> v = (e & 1) == 0 ? mk<T>((z1.x + z2.x) * (T)0.5, (z1.y - z2.y) * (T)0.5)
@@ -524,7 +527,7 @@ __device__ __forceinline__ void freq_gemm_mfma_body(const cplx<T> *__restrict__ 
                 }
                 {
                     const int t = p / DP, j = p - t * DP;
-                    const int e = (kc + t) * d + j;
+                    const int e = TB ? j * d + kc + t : (kc + t) * d + j;
                     const bool ok = fok && j < d && kc + t < d;
                     const cplx<T> z1 = xb1[u], z2 = xb2[u];
                     cplx<T> v = (e & 1) == 0 ? mk<T>((z1.x + z2.x) * (T)0.5, (z1.y - z2.y) * (T)0.5)
@@ -609,11 +612,11 @@ __device__ __forceinline__ void freq_gemm_mfma_body(const cplx<T> *__restrict__ 
     }
 }
 
-template <typename T, int DP, bool ODD>
+template <typename T, int DP, bool ODD, bool TA, bool TB>
 __global__ void __launch_bounds__(MfCfg<DP>::THREADS)
 freq_gemm_mfma_kernel(const cplx<T> *__restrict__ ZA, const cplx<T> *__restrict__ ZB, cplx<T> *__restrict__ ZC,
                       FftPlan plan, int d) {
-    freq_gemm_mfma_body<T, DP, ODD>(ZA, ZB, ZC, plan, d, blockIdx.x);
+    freq_gemm_mfma_body<T, DP, ODD, TA, TB>(ZA, ZB, ZC, plan, d, blockIdx.x);
 }
 
 template <typename T, int DP, bool ODD>
@@ -630,12 +633,12 @@ freq_gemm_mfma_batched_kernel(const GemmProblem<T> *probs, int nprob, FftPlan pl
     freq_gemm_mfma_body<T, DP, ODD>(pp.A, pp.B, pp.C, plan, pp.d, bid - pp.wg_begin);
 }
 
-template <typename T, int DP, bool ODD>
+template <typename T, int DP, bool ODD, bool TA = false, bool TB = false>
 static hipError_t launch_gemm_mfma(const FftPlan &plan, int d, const cplx<T> *ZA, const cplx<T> *ZB, cplx<T> *ZC,
                                    hipStream_t st) {
     using Cfg = MfCfg<DP>;
     const size_t lds = mf_lds_bytes<T, DP>(ODD ? d : 0);
-    auto kern = freq_gemm_mfma_kernel<T, DP, ODD>;
+    auto kern = freq_gemm_mfma_kernel<T, DP, ODD, TA, TB>;
     if (lds > 64 * 1024) {
         (void)hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         (void)hipGetLastError();
@@ -643,8 +646,12 @@ static hipError_t launch_gemm_mfma(const FftPlan &plan, int d, const cplx<T> *ZA
     const int64_t F = ((int64_t)1 << plan.lgL) / 2 + 1;
     const int64_t blocks = (F + Cfg::NF - 1) / Cfg::NF;
     char name[96];
-    snprintf(name, sizeof name, "freq_gemm_mfma_kernel<%s, %d, %s>", sizeof(T) == 8 ? "double" : "float", DP,
-             ODD ? "true" : "false");
+    if (TA || TB)
+        snprintf(name, sizeof name, "freq_gemm_mfma_kernel<%s, %d, %s, %s, %s>", sizeof(T) == 8 ? "double" : "float",
+                 DP, ODD ? "true" : "false", TA ? "true" : "false", TB ? "true" : "false");
+    else
+        snprintf(name, sizeof name, "freq_gemm_mfma_kernel<%s, %d, %s, false, false>",
+                 sizeof(T) == 8 ? "double" : "float", DP, ODD ? "true" : "false");
     const double Lr = (double)((int64_t)1 << plan.lgL);
     const int nl = (d * d + 1) / 2;
     launch_begin(name, Lr * 3.0 * nl * sizeof(cplx<T>), (double)F * 8.0 * d * d * d);
@@ -976,11 +983,34 @@ static hipError_t gemm_sq(const FftPlan &plan, int d, int mfma, const cplx<T> *Z
     }
 }
 
+// Square products with one operand stored transposed (the adjoints), on the
+// matrix cores.
+template <typename T, bool TA, bool TB>
+static hipError_t gemm_sq_t(const FftPlan &plan, int d, const cplx<T> *ZA, const cplx<T> *ZB, cplx<T> *ZC,
+                            hipStream_t st) {
+    const bool odd = d & 1;
+    switch ((d + 15) / 16) {
+        case 1: return odd ? launch_gemm_mfma<T, 16, true, TA, TB>(plan, d, ZA, ZB, ZC, st)
+                           : launch_gemm_mfma<T, 16, false, TA, TB>(plan, d, ZA, ZB, ZC, st);
+        case 2: return odd ? launch_gemm_mfma<T, 32, true, TA, TB>(plan, d, ZA, ZB, ZC, st)
+                           : launch_gemm_mfma<T, 32, false, TA, TB>(plan, d, ZA, ZB, ZC, st);
+        case 3: return odd ? launch_gemm_mfma<T, 48, true, TA, TB>(plan, d, ZA, ZB, ZC, st)
+                           : launch_gemm_mfma<T, 48, false, TA, TB>(plan, d, ZA, ZB, ZC, st);
+        default: return odd ? launch_gemm_mfma<T, 64, true, TA, TB>(plan, d, ZA, ZB, ZC, st)
+                            : launch_gemm_mfma<T, 64, false, TA, TB>(plan, d, ZA, ZB, ZC, st);
+    }
+}
+
 template <typename T>
 hipError_t freq_gemm(const FftPlan &plan, const GemmDesc &g, const cplx<T> *ZA, const cplx<T> *ZB, cplx<T> *ZC,
                      hipStream_t st) {
     if (g.ra == g.m && g.m == g.cb && !g.transA && !g.transB && g.ra <= 64)
         return gemm_sq<T>(plan, g.ra, g.mfma, ZA, ZB, ZC, st);
+    const bool sq = g.ra == g.m && g.m == g.cb && g.ra <= 64 && !(g.transA && g.transB);
+    if (sq && gemm_sq_class(g.ra, g.mfma) >= 9) {
+        if (g.transA) return gemm_sq_t<T, true, false>(plan, g.ra, ZA, ZB, ZC, st);
+        return gemm_sq_t<T, false, true>(plan, g.ra, ZA, ZB, ZC, st);
+    }
     const int dmax = g.ra > g.cb ? g.ra : g.cb;
     if (dmax <= 8) return launch_gemm<T, 1, 1>(plan, g, ZA, ZB, ZC, st);
     if (dmax <= 24) return launch_gemm<T, 2, 2>(plan, g, ZA, ZB, ZC, st);

@@ -225,17 +225,19 @@ hipError_t conv_direct_batched(int cls, int l_f64, const ConvDesc *dev_descs, in
 hipError_t gj_inverse_batched(const GjProblem *dev_probs, int nprob, int dmax, unsigned int *status,
                               hipStream_t st);
 
-hipError_t survival(const double *q, int d, int64_t n, double *hb, hipStream_t st);
+// tmp: scan workspace of scan_tmp_bytes(n, lanes) bytes.
+size_t scan_tmp_bytes(int64_t n, int w);
+hipError_t survival(const double *q, int d, int64_t n, double *hb, double *tmp, hipStream_t st);
 hipError_t contract(const double *X, int64_t n, int rows, int cols, const double *u, const double *v,
-                    int cumulative, double offset, double scale, double *out, hipStream_t st);
+                    int cumulative, double offset, double scale, double *out, double *tmp, hipStream_t st);
 hipError_t contract_backward(const double *ob, int64_t n, int rows, int cols, const double *u, const double *v,
-                             int cumulative, double scale, double *Xb, hipStream_t st);
+                             int cumulative, double scale, double *Xb, double *tmp, hipStream_t st);
 hipError_t gather_block(const double *X, int64_t n, int rows, int cols, const int *ri, int nr, const int *ci,
                         int nc, double *Y, hipStream_t st);
 hipError_t scatter_block_add(const double *Yb, int64_t n, int rows, int cols, const int *ri, int nr,
                              const int *ci, int nc, double *Xb, hipStream_t st);
 // q_bar(l)[i][j] += -sum_{k>=l} hb_bar(k)[i] for l >= 1.
-hipError_t survival_backward(const double *hbb, int d, int64_t n, double *qb, hipStream_t st);
+hipError_t survival_backward(const double *hbb, int d, int64_t n, double *qb, double *tmp, hipStream_t st);
 hipError_t fill_f64(double *p, int64_t count, double v, hipStream_t st);
 hipError_t fill_u32(unsigned int *p, int64_t count, unsigned int v, hipStream_t st);
 hipError_t residual_norms(const double *R_L, const double *R_R, int d, int64_t n, double *acc, hipStream_t st);

@@ -218,6 +218,52 @@ def test_psi_backward_matches_oracle_adjoint(mr, orc):
     assert _maxerr(got, ref) <= 1e-11 * max(1.0, np.max(np.abs(ref)))
 
 
+@pytest.mark.parametrize("d", [12, 17, 32, 33])
+def test_psi_backward_transposed_products_match_oracle(mr, orc, d):
+    """The adjoint's products with a transposed operand on the matrix cores
+    (mfma = 1, 2) and on the vector kernel (mfma = 0) against the oracle."""
+    rng = np.random.default_rng(40 + d)
+    n = 150
+    q = si.weibull_kernel(d, n, 60 + d).q.numpy()
+    psi = orc.psi(q)
+    pb = rng.standard_normal((n, d, d))
+    ref = orc.adjoint(psi, pb)
+    base = mr.get_tuning()
+    try:
+        for mode in (0, 1, 2):
+            mr.set_tuning(mfma=mode)
+            got = _np(mr.psi_inverse_backward(_gpu(psi), _gpu(pb)))
+            assert _maxerr(got, ref) <= 1e-11 * max(1.0, np.max(np.abs(ref))), mode
+    finally:
+        mr.set_tuning(**base)
+
+
+@pytest.mark.parametrize("w,n,reverse", [(1, 1, 0), (1, 5000, 1), (16, 1025, 0), (31, 3000, 1), (64, 2049, 0)])
+def test_time_scans(mr, w, n, reverse):
+    """Survival sequence H-bar (a scan over time of d lanes, Section 4.1) and
+    the cumulative contraction against numpy cumulative sums."""
+    rng = np.random.default_rng(w + n)
+    if reverse == 0:
+        q = rng.random((n, w, w)) / (w * n)
+        q[0] = 0.0
+        hb = _np(mr.survival(_gpu(q)))
+        ref = 1.0 - np.cumsum(q.sum(axis=2), axis=0)
+        assert hb.shape == (n, w)
+        assert _maxerr(hb, ref) <= 1e-13
+    X = rng.standard_normal((n, w, 2))
+    u = rng.standard_normal(w)
+    v = rng.standard_normal(2)
+    out = _np(mr.contract(_gpu(X), torch.tensor(u), torch.tensor(v), cumulative=True))
+    ref = np.cumsum(np.einsum("kij,i,j->k", X, u, v))
+    assert _maxerr(out, ref) <= 1e-10 * max(1.0, np.max(np.abs(ref)))
+    if reverse:
+        ob = rng.standard_normal(n)
+        Xb = _np(mr.contract_backward(_gpu(ob), w, 2, u, v, cumulative=True))
+        rs = np.cumsum(ob[::-1])[::-1]
+        refb = rs[:, None, None] * u[None, :, None] * v[None, None, :]
+        assert _maxerr(Xb, refb) <= 1e-10 * max(1.0, np.max(np.abs(refb)))
+
+
 def test_apply_backward_matches_direct(mr, orc):
     """psi_bar(l) = sum_k M_bar(k) L(k-l)^T and L_bar(j) = sum_l psi(l)^T M_bar(l+j),
     evaluated with the oracle's direct convolution on reversed sequences."""
