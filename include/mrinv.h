@@ -249,8 +249,8 @@ typedef struct {
     int use_graph;      /* nonzero: mrinv_psi_inverse records its launches once into a HIP graph per
                            (pointers, sizes, tuning) and replays it on later identical calls (default 0) */
     int mfma;           /* square frequency-domain products for d > 8 on the matrix cores (16x16x4 MFMA in
-                           the working precision): 0 never (vector kernels), 1 when padding d to a multiple
-                           of 16 adds fewer than 8 (default), 2 always.  Results agree to rounding. */
+                           the working precision, d padded to a multiple of 16): 0 never (vector kernels),
+                           1 or 2 always (default 1).  Results agree to rounding. */
     int direct_m;       /* Newton steps m -> m2 with m2 <= direct_m (rounded down to a power of two) form
                            their two truncated products directly in the time domain on the matrix cores
                            instead of through transforms: -1 automatic from d (default), 0 never. */

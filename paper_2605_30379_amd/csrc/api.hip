@@ -1196,11 +1196,13 @@ static void plan_fft(BatchPlan &bp, mrinv_handle_t h, int mode, const FftPlan &p
                      const std::vector<PassProblem<T>> &probs) {
     if (probs.empty()) return;
     const bool dbl = sizeof(T) == 8;
-    // group by lanes per workgroup
+    // Group by lanes per workgroup: the handle's choice (at most 16 here), 2
+    // for problems of at most 2 lanes.
+    const int lanes = std::min(16, lanes_of<T>(h));
     for (int C : {2, 8, 16}) {
         std::vector<PassProblem<T>> g;
         for (auto &q : probs)
-            if (fft_lanes_per_block(dbl, q.nl) == C) g.push_back(q);
+            if ((q.nl <= 2 ? 2 : lanes) == C) g.push_back(q);
         if (g.empty()) continue;
         const int64_t total = fft_batch_layout<T>(p, pass, g.data(), (int)g.size(), C);
         double bytes = 0;
