@@ -205,31 +205,56 @@ __device__ __forceinline__ void fft_pass_body(cplx<T> *z, const PassGeom &g, int
             const bool two = e + 1 < src.nreal;
             const int64_t rstep = (src.rev >= 0 ? -dt : dt) * src.ld;
             const int64_t row0 = src.rev >= 0 ? src.rev - t0 : t0;
+            // With an even row length and entry count every lane is an aligned
+            // pair: one vector load per element.
+            const bool vec = ((src.ld | src.nreal) & 1) == 0;
             if (src.kind == SRC_REAL64) {
                 const double *q = (const double *)src.p + row0 * src.ld + e;
+                if (vec) {
 #pragma unroll
-                for (int r = 0; r < R; ++r) {
-                    const int64_t t = t0 + r * dt;
-                    T a = 0, bb = 0;
-                    if (t >= src.lo && t < src.hi) {
-                        a = (T)q[0];
-                        if (two) bb = (T)q[1];
+                    for (int r = 0; r < R; ++r) {
+                        const int64_t t = t0 + r * dt;
+                        double2 w = make_double2(0.0, 0.0);
+                        if (t >= src.lo && t < src.hi) w = *(const double2 *)q;
+                        v[r] = mk<T>((T)w.x, (T)w.y);
+                        q += rstep;
                     }
-                    v[r] = mk<T>(a, bb);
-                    q += rstep;
+                } else {
+#pragma unroll
+                    for (int r = 0; r < R; ++r) {
+                        const int64_t t = t0 + r * dt;
+                        T a = 0, bb = 0;
+                        if (t >= src.lo && t < src.hi) {
+                            a = (T)q[0];
+                            if (two) bb = (T)q[1];
+                        }
+                        v[r] = mk<T>(a, bb);
+                        q += rstep;
+                    }
                 }
             } else {
                 const float *q = (const float *)src.p + row0 * src.ld + e;
+                if (vec) {
 #pragma unroll
-                for (int r = 0; r < R; ++r) {
-                    const int64_t t = t0 + r * dt;
-                    T a = 0, bb = 0;
-                    if (t >= src.lo && t < src.hi) {
-                        a = (T)q[0];
-                        if (two) bb = (T)q[1];
+                    for (int r = 0; r < R; ++r) {
+                        const int64_t t = t0 + r * dt;
+                        float2 w = make_float2(0.f, 0.f);
+                        if (t >= src.lo && t < src.hi) w = *(const float2 *)q;
+                        v[r] = mk<T>((T)w.x, (T)w.y);
+                        q += rstep;
                     }
-                    v[r] = mk<T>(a, bb);
-                    q += rstep;
+                } else {
+#pragma unroll
+                    for (int r = 0; r < R; ++r) {
+                        const int64_t t = t0 + r * dt;
+                        T a = 0, bb = 0;
+                        if (t >= src.lo && t < src.hi) {
+                            a = (T)q[0];
+                            if (two) bb = (T)q[1];
+                        }
+                        v[r] = mk<T>(a, bb);
+                        q += rstep;
+                    }
                 }
             }
             if (src.e0_d > 0) {
@@ -261,6 +286,7 @@ __device__ __forceinline__ void fft_pass_body(cplx<T> *z, const PassGeom &g, int
             const int e = 2 * lane;
             const bool two = e + 1 < dst.nreal;
             const bool dbl = dst.kind == DST_REAL64;
+            const bool vec = ((dst.ld | dst.nreal) & 1) == 0;   // aligned pairs (see the loads)
             double ax[R], bx[R];
 #pragma unroll
             for (int r = 0; r < R; ++r) {
@@ -301,12 +327,20 @@ __device__ __forceinline__ void fft_pass_body(cplx<T> *z, const PassGeom &g, int
                 bb += bx[r];
                 if (dbl) {
                     double *p = (double *)dst.p + row * dst.ld + e;
-                    p[0] = a;
-                    if (two) p[1] = bb;
+                    if (vec) {
+                        *(double2 *)p = make_double2(a, bb);
+                    } else {
+                        p[0] = a;
+                        if (two) p[1] = bb;
+                    }
                 } else {
                     float *p = (float *)dst.p + row * dst.ld + e;
-                    p[0] = (float)a;
-                    if (two) p[1] = (float)bb;
+                    if (vec) {
+                        *(float2 *)p = make_float2((float)a, (float)bb);
+                    } else {
+                        p[0] = (float)a;
+                        if (two) p[1] = (float)bb;
+                    }
                 }
                 flag_nonfinite(dst.status, a, two ? bb : 0.0);
             }
