@@ -107,6 +107,83 @@ __device__ __forceinline__ void flag_nonfinite(unsigned int *status, double a, d
     if (status && (!isfinite(a) || !isfinite(b))) atomicOr(status, STATUS_NONFINITE);
 }
 
+// LDS layout of a pass workgroup.  The data tile holds P rows of C lanes
+// (stride C + 1), or, for 512-row FP64 passes, P rows of C/2 lanes that the
+// two lane halves use in turn (stride C/2): 80 KB instead of 155 KB, so two
+// workgroups share a CU.  P outer twiddles and P stage roots follow the tile.
+// Forward passes only: the inverse and fused passes need more than the 64
+// VGPRs that two 1024-thread workgroups per CU allow, so they keep the full
+// tile.
+template <typename T, int LGP, int C, int MODE>
+__host__ __device__ constexpr int pass_split() {
+    return (sizeof(T) == 8 && LGP == 9 && C == 16 && MODE == 0) ? 2 : 1;
+}
+template <typename T, int LGP, int C, int MODE>
+__host__ __device__ constexpr int pass_lds_stride() {
+    return pass_split<T, LGP, C, MODE>() == 2 ? C / 2 : C + 1;
+}
+template <typename T, int LGP, int C, int MODE>
+__host__ __device__ constexpr size_t pass_lds_bytes() {
+    return ((size_t)1 << LGP) * (pass_lds_stride<T, LGP, C, MODE>() + 2) * sizeof(cplx<T>);
+}
+
+__device__ __forceinline__ int stage_store_base(int j, int lgNs, int LGR) {
+    return ((j >> lgNs) << (lgNs + LGR)) + (j & ((1 << lgNs) - 1));
+}
+
+// Stage twiddles and DFT of one stage, in registers (see fft_stage).
+template <typename T, int LGR, bool INV>
+__device__ __forceinline__ void stage_math(int LGP, int lgNs, int j, cplx<T> (&v)[1 << LGR], const cplx<T> *roots) {
+    constexpr int R = 1 << LGR;
+    if (lgNs > 0) {
+        const int k0 = j & ((1 << lgNs) - 1);
+        const int sh = LGP - lgNs - LGR;
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+            const cplx<T> w = roots[(k0 * r) << sh];
+            v[r] = INV ? cmulc<T>(v[r], w) : cmul<T>(v[r], w);
+        }
+    }
+    Dft<T, R, INV>::run(v);
+}
+
+// Moves v from one stage's store layout (elements b + r 2^lgs_out) to the
+// next stage's load layout (elements j + r 2^lgs_in) through a tile holding
+// HC lanes: lanes [h HC, (h + 1) HC) in round h.
+template <typename T, int R, int HC>
+__device__ __forceinline__ void split_exchange(cplx<T> *tile, int half, int ch, int b, int lgs_out, int j, int lgs_in,
+                                               cplx<T> (&v)[R]) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        if (half == h) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) tile[(b + (r << lgs_out)) * HC + ch] = v[r];
+        }
+        __syncthreads();
+        if (half == h) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) v[r] = tile[(j + (r << lgs_in)) * HC + ch];
+        }
+        __syncthreads();
+    }
+}
+
+// All stages of a 2^LGP-point DFT whose stages share one register radix, from
+// v in stage 0's load layout of group j to v in the last stage's store layout.
+template <typename T, int LGP, bool INV, int HC>
+__device__ __forceinline__ void split_stages(cplx<T> *tile, int half, int ch, int j,
+                                             cplx<T> (&v)[1 << stage_lg(LGP, 0)], const cplx<T> *roots) {
+    constexpr int LGR = stage_lg(LGP, 0), NS = num_stages(LGP), R = 1 << LGR;
+    static_assert(stage_lg(LGP, 1) == LGR && (NS < 3 || stage_lg(LGP, 2) == LGR), "uniform radix");
+    stage_math<T, LGR, INV>(LGP, 0, j, v, roots);
+#pragma unroll
+    for (int st = 1; st < NS; ++st) {
+        const int lo = (st - 1) * LGR;
+        split_exchange<T, R, HC>(tile, half, ch, stage_store_base(j, lo, LGR), lo, j, LGP - LGR, v);
+        stage_math<T, LGR, INV>(LGP, st * LGR, j, v, roots);
+    }
+}
+
 // MODE 0: forward pass; MODE 1: inverse pass; MODE 2: inverse pass, then the
 // mask/scale/negate of `dst` (rows outside [lo, hi) become zero), then the
 // forward pass of the same geometry, in place.
@@ -117,7 +194,8 @@ __device__ __forceinline__ void fft_pass_body(cplx<T> *z, const PassGeom &g, int
     constexpr int P = 1 << LGP;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cplx<T> *lds = reinterpret_cast<cplx<T> *>(smem_raw);
-    constexpr int LDS_STRIDE = C + 1;
+    constexpr int SPLIT = pass_split<T, LGP, C, MODE>();
+    constexpr int LDS_STRIDE = pass_lds_stride<T, LGP, C, MODE>();
     cplx<T> *tws = lds + P * LDS_STRIDE;   // outer twiddles of this column
     cplx<T> *roots = tws + P;              // roots[i] = W_P^i
     const int c = threadIdx.x % C;
@@ -194,6 +272,17 @@ __device__ __forceinline__ void fft_pass_body(cplx<T> *z, const PassGeom &g, int
             for (int r = 0; r < MR_RADIX(v); ++r) v[r] = cmulc<T>(v[r], tws[j + (r << lgs)]);
         }
     };
+
+    // Two lane halves sharing the tile: all stages in registers, exchanges
+    // in two rounds.
+    constexpr int LGR = stage_lg(LGP, 0);
+    constexpr int LGL = (num_stages(LGP) - 1) * LGR;   // last stage's store stride exponent
+    const int half = c / (C / 2 > 0 ? C / 2 : 1), ch = c % (C / 2 > 0 ? C / 2 : 1);
+    const int jb = grp, bl = stage_store_base(grp, LGL, LGR);
+    (void)half;
+    (void)ch;
+    (void)bl;
+    (void)jb;
 
     if constexpr (MODE == 0) {
         // Real source: complex lane = entries (2 lane, 2 lane + 1) of row t
@@ -275,7 +364,14 @@ __device__ __forceinline__ void fft_pass_body(cplx<T> *z, const PassGeom &g, int
             if (src.kind == SRC_Z) z_load_all(j, lgs, v);
             else real_load_all(j, lgs, v);
         };
-        wg_fft<T, LGP, false>(lds, LDS_STRIDE, c, grp, gload_all, fwd_store_all, false, false, roots);
+        if constexpr (SPLIT == 2) {
+            cplx<T> v[1 << LGR];
+            gload_all(jb, LGP - LGR, v);
+            split_stages<T, LGP, false, C / 2>(lds, half, ch, jb, v, roots);
+            fwd_store_all(bl, LGL, v);
+        } else {
+            wg_fft<T, LGP, false>(lds, LDS_STRIDE, c, grp, gload_all, fwd_store_all, false, false, roots);
+        }
     } else if constexpr (MODE == 1) {
         // Real destination: value = op(scale * v) (+ the old value or the
         // float32 aux entry), rows t in [lo, hi) of row t (or rev - t).
@@ -287,29 +383,6 @@ __device__ __forceinline__ void fft_pass_body(cplx<T> *z, const PassGeom &g, int
             const bool two = e + 1 < dst.nreal;
             const bool dbl = dst.kind == DST_REAL64;
             const bool vec = ((dst.ld | dst.nreal) & 1) == 0;   // aligned pairs (see the loads)
-            double ax[R], bx[R];
-#pragma unroll
-            for (int r = 0; r < R; ++r) {
-                ax[r] = 0.0;
-                bx[r] = 0.0;
-            }
-            if (dst.op == OP_ADD || dst.op == OP_XPLUS) {
-#pragma unroll
-                for (int r = 0; r < R; ++r) {
-                    const int64_t t = t0 + r * dt;
-                    if (t < dst.lo || t >= dst.hi) continue;
-                    const int64_t row = dst.rev >= 0 ? dst.rev - t : t;
-                    if (dst.op == OP_XPLUS || !dbl) {
-                        const float *x = (const float *)(dst.op == OP_XPLUS ? dst.aux : dst.p) + row * dst.ld + e;
-                        ax[r] = (double)x[0];
-                        if (two) bx[r] = (double)x[1];
-                    } else {
-                        const double *x = (const double *)dst.p + row * dst.ld + e;
-                        ax[r] = x[0];
-                        if (two) bx[r] = x[1];
-                    }
-                }
-            }
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 const int64_t t = t0 + r * dt;
@@ -323,8 +396,18 @@ __device__ __forceinline__ void fft_pass_body(cplx<T> *z, const PassGeom &g, int
                     a = (t == 0 && is_diag_lane(e, dst.e0_d) ? 1.0 : 0.0) - a;
                     bb = (t == 0 && is_diag_lane(e + 1, dst.e0_d) ? 1.0 : 0.0) - bb;
                 }
-                a += ax[r];
-                bb += bx[r];
+                if (dst.op == OP_ADD || dst.op == OP_XPLUS) {
+                    // the old value (OP_ADD) or the float32 aux entry (OP_XPLUS)
+                    if (dst.op == OP_XPLUS || !dbl) {
+                        const float *x = (const float *)(dst.op == OP_XPLUS ? dst.aux : dst.p) + row * dst.ld + e;
+                        a += (double)x[0];
+                        if (two) bb += (double)x[1];
+                    } else {
+                        const double *x = (const double *)dst.p + row * dst.ld + e;
+                        a += x[0];
+                        if (two) bb += x[1];
+                    }
+                }
                 if (dbl) {
                     double *p = (double *)dst.p + row * dst.ld + e;
                     if (vec) {
@@ -349,9 +432,31 @@ __device__ __forceinline__ void fft_pass_body(cplx<T> *z, const PassGeom &g, int
             if (dst.kind == DST_Z) z_store_all(b0, lgs, v);
             else real_store_all(b0, lgs, v);
         };
-        wg_fft<T, LGP, true>(lds, LDS_STRIDE, c, grp, inv_load_all, gstore_all, false, false, roots);
+        if constexpr (SPLIT == 2) {
+            cplx<T> v[1 << LGR];
+            inv_load_all(jb, LGP - LGR, v);
+            split_stages<T, LGP, true, C / 2>(lds, half, ch, jb, v, roots);
+            gstore_all(bl, LGL, v);
+        } else {
+            wg_fft<T, LGP, true>(lds, LDS_STRIDE, c, grp, inv_load_all, gstore_all, false, false, roots);
+        }
     } else {
         const T sc = dst.op == OP_NEG ? -(T)dst.scale : (T)dst.scale;
+        if constexpr (SPLIT == 2) {
+            cplx<T> v[1 << LGR];
+            inv_load_all(jb, LGP - LGR, v);
+            split_stages<T, LGP, true, C / 2>(lds, half, ch, jb, v, roots);
+#pragma unroll
+            for (int r = 0; r < (1 << LGR); ++r) {
+                const int64_t t = base + (int64_t)(bl + (r << LGL)) * S;
+                const bool keep = t >= dst.lo && t < dst.hi;
+                v[r] = keep ? cscale<T>(v[r], sc) : mk<T>(0, 0);
+            }
+            split_exchange<T, 1 << LGR, C / 2>(lds, half, ch, bl, LGL, jb, LGP - LGR, v);
+            split_stages<T, LGP, false, C / 2>(lds, half, ch, jb, v, roots);
+            fwd_store_all(bl, LGL, v);
+            return;
+        }
         auto mask_store_all = [&](int b0, int lgs, auto &v) {
 #pragma unroll
             for (int r = 0; r < MR_RADIX(v); ++r) {
@@ -428,18 +533,11 @@ static double pass_bytes(int mode, const PassGeom &g, const SrcDesc &src, const 
     return rd + wr;
 }
 
-// LDS of one pass workgroup: the P x C data tile (stride C + 1), the P outer
-// twiddles of its column and the P roots of its in-workgroup stages.
-template <typename T, int LGP, int C>
-static constexpr size_t pass_lds_bytes() {
-    return ((size_t)1 << LGP) * (C + 3) * sizeof(cplx<T>);
-}
-
 template <typename T, int LGP, int C, int MODE>
 static hipError_t launch_pass_t(cplx<T> *z, const PassGeom &g, const SrcDesc &src, const DstDesc &dst,
                                 const Twiddles<T> &tw, hipStream_t st) {
     const int threads = C << (LGP - min_stage_lg(LGP));
-    const size_t lds = pass_lds_bytes<T, LGP, C>();
+    const size_t lds = pass_lds_bytes<T, LGP, C, MODE>();
     auto kern = fft_pass_kernel<T, LGP, C, MODE>;
     static bool attr_set = false;
     if (!attr_set && lds > 64 * 1024) {
@@ -537,7 +635,7 @@ template <typename T, int LGP, int C, int MODE>
 static hipError_t launch_batched_t(const PassProblem<T> *probs, int nprob, int64_t total, const PassGeom &g,
                                    double bytes, const Twiddles<T> &tw, hipStream_t st) {
     const int threads = C << (LGP - min_stage_lg(LGP));
-    const size_t lds = pass_lds_bytes<T, LGP, C>();
+    const size_t lds = pass_lds_bytes<T, LGP, C, MODE>();
     auto kern = fft_pass_batched_kernel<T, LGP, C, MODE>;
     static bool attr_set = false;
     if (!attr_set && lds > 64 * 1024) {
@@ -558,7 +656,7 @@ template <typename T, int LGP, int C, int MODE>
 static hipError_t launch_pair_t(const PassProblem<T> &a, const PassProblem<T> &b, int64_t total, const PassGeom &g,
                                 double bytes, const Twiddles<T> &tw, hipStream_t st) {
     const int threads = C << (LGP - min_stage_lg(LGP));
-    const size_t lds = pass_lds_bytes<T, LGP, C>();
+    const size_t lds = pass_lds_bytes<T, LGP, C, MODE>();
     auto kern = fft_pass_pair_kernel<T, LGP, C, MODE>;
     static bool attr_set = false;
     if (!attr_set && lds > 64 * 1024) {
