@@ -110,13 +110,12 @@ __device__ __forceinline__ void flag_nonfinite(unsigned int *status, double a, d
 // LDS layout of a pass workgroup.  The data tile holds P rows of C lanes
 // (stride C + 1), or, for 512-row FP64 passes, P rows of C/2 lanes that the
 // two lane halves use in turn (stride C/2): 80 KB instead of 155 KB, so two
-// workgroups share a CU.  P outer twiddles and P stage roots follow the tile.
-// Forward passes only: the inverse and fused passes need more than the 64
-// VGPRs that two 1024-thread workgroups per CU allow, so they keep the full
-// tile.
+// 1024-thread workgroups share a CU (their kernels are compiled for 8 waves
+// per SIMD, i.e. at most 64 VGPRs).  P outer twiddles and P stage roots follow
+// the tile.
 template <typename T, int LGP, int C, int MODE>
 __host__ __device__ constexpr int pass_split() {
-    return (sizeof(T) == 8 && LGP == 9 && C == 16 && MODE == 0) ? 2 : 1;
+    return (sizeof(T) == 8 && LGP == 9 && C == 16) ? 2 : 1;
 }
 template <typename T, int LGP, int C, int MODE>
 __host__ __device__ constexpr int pass_lds_stride() {
@@ -478,6 +477,7 @@ __device__ __forceinline__ void fft_pass_body(cplx<T> *z, const PassGeom &g, int
 
 template <typename T, int LGP, int C, int MODE>
 __global__ void __launch_bounds__(C << (LGP - min_stage_lg(LGP)))
+__attribute__((amdgpu_waves_per_eu(pass_split<T, LGP, C, MODE>() == 2 ? 8 : 1)))
 fft_pass_kernel(cplx<T> *z, PassGeom g, SrcDesc src, DstDesc dst, Twiddles<T> tw) {
     fft_pass_body<T, LGP, C, MODE>(z, g, g.nl, g.nchunks, blockIdx.x, src, dst, tw);
 }
@@ -486,6 +486,7 @@ fft_pass_kernel(cplx<T> *z, PassGeom g, SrcDesc src, DstDesc dst, Twiddles<T> tw
 // operands of a product in one launch).
 template <typename T, int LGP, int C, int MODE>
 __global__ void __launch_bounds__(C << (LGP - min_stage_lg(LGP)))
+__attribute__((amdgpu_waves_per_eu(pass_split<T, LGP, C, MODE>() == 2 ? 8 : 1)))
 fft_pass_pair_kernel(PassProblem<T> a, PassProblem<T> b, PassGeom g, Twiddles<T> tw) {
     const int64_t bid = blockIdx.x;
     if (bid < b.wg_begin) fft_pass_body<T, LGP, C, MODE>(a.z, g, a.nl, a.nchunks, bid, a.src, a.dst, tw);
@@ -495,6 +496,7 @@ fft_pass_pair_kernel(PassProblem<T> a, PassProblem<T> b, PassGeom g, Twiddles<T>
 // Batched: the workgroup's problem is found by binary search over wg_begin.
 template <typename T, int LGP, int C, int MODE>
 __global__ void __launch_bounds__(C << (LGP - min_stage_lg(LGP)))
+__attribute__((amdgpu_waves_per_eu(pass_split<T, LGP, C, MODE>() == 2 ? 8 : 1)))
 fft_pass_batched_kernel(const PassProblem<T> *probs, int nprob, PassGeom g, Twiddles<T> tw) {
     int lo = 0, hi = nprob - 1;
     const int64_t bid = blockIdx.x;
