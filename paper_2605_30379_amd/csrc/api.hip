@@ -638,16 +638,20 @@ static mrinv_status_t inverse_impl(mrinv_handle_t h, const double *src, int e0, 
     }
     const double invL = 1.0 / (double)((int64_t)1 << p2.lgL);
     const GemmDesc g = gdesc(h, d, d, d);
+    // The float64 spectrum of A is formed once and kept for every sweep when
+    // the float32 spectra fit behind it (always but for tiny sizes).
+    const size_t s64 = spec_bytes(p2.lgL, d2, true), s32 = spec_bytes(p2.lgL, d2, false);
+    const bool keepA = s64 + 3 * s32 <= 3 * s64;
     for (int sweep = 0; sweep < MIXED_SWEEPS; ++sweep) {
         const bool last = sweep == MIXED_SWEEPS - 1;
         {
             // R = e0 - A*X on [0, n) in float64 (full product, no wrap-around at L >= 2n-1).
-            const size_t sb = spec_bytes(p2.lgL, d2, true);
             auto *SA = (cplx<double> *)spec;
-            auto *SB = (cplx<double> *)(spec + sb);
-            auto *ST = (cplx<double> *)(spec + 2 * sb);
-            HIP_TRY(fwd2<double>(h, p2, nl, SA, src_real(src, true, d2, d2, 0, n, -1, e0 ? d : 0), SB,
-                                 src_real(X, false, d2, d2, 0, n)));
+            auto *SB = (cplx<double> *)(spec + s64);
+            auto *ST = (cplx<double> *)(spec + 2 * s64);
+            const SrcDesc sa = src_real(src, true, d2, d2, 0, n, -1, e0 ? d : 0), sx = src_real(X, false, d2, d2, 0, n);
+            if (sweep == 0 || !keepA) HIP_TRY(fwd2<double>(h, p2, nl, SA, sa, SB, sx));
+            else HIP_TRY(fwd<double>(h, p2, nl, SB, sx));
             HIP_TRY(freq_gemm<double>(p2, g, SA, SB, ST, h->stream));
             DstDesc dr = dst_real(R, false, d2, d2, 0, n, invL, OP_E0MINUS);
             dr.e0_d = d;
@@ -656,10 +660,10 @@ static mrinv_status_t inverse_impl(mrinv_handle_t h, const double *src, int e0, 
         {
             // X <- X + X*R, the correction product in float32; the last sweep
             // writes the float64 result, earlier ones update X in place.
-            const size_t sb = spec_bytes(p2.lgL, d2, false);
-            auto *SA = (cplx<float> *)spec;
-            auto *SB = (cplx<float> *)(spec + sb);
-            auto *ST = (cplx<float> *)(spec + 2 * sb);
+            char *f32 = keepA ? spec + s64 : spec;
+            auto *SA = (cplx<float> *)f32;
+            auto *SB = (cplx<float> *)(f32 + s32);
+            auto *ST = (cplx<float> *)(f32 + 2 * s32);
             HIP_TRY(fwd2<float>(h, p2f, nl, SA, src_real(X, false, d2, d2, 0, n), SB, src_real(R, false, d2, d2, 0, n)));
             HIP_TRY(freq_gemm<float>(p2f, g, SA, SB, ST, h->stream));
             DstDesc dx = last ? dst_real(out, true, d2, d2, 0, n, invL, OP_XPLUS, -1, h->status)
@@ -1469,28 +1473,36 @@ static void plan_sweeps(BatchPlan &bp, mrinv_handle_t h, std::vector<BatchProble
         for (auto &sub : split_by_cap(grp, need)) {
             for (int sweep = 0; sweep < MIXED_SWEEPS; ++sweep) {
                 const bool last = sweep == MIXED_SWEEPS - 1;
-                std::vector<cplx<double> *> A64, B64, T64;
+                std::vector<cplx<double> *> A64, B64, T64, A64r;
                 std::vector<cplx<float> *> A32, B32, T32;
-                std::vector<int> nl;
-                std::vector<SrcDesc> sq, sx, sr;
+                std::vector<int> nl, nlr;
+                std::vector<SrcDesc> sq, sx, sr, sqr;
                 std::vector<DstDesc> dr, dx;
                 std::vector<GemmProblem<double>> g64;
                 std::vector<GemmProblem<float>> g32;
-                size_t used = 0, used32 = 0;
+                size_t used = 0;
                 for (int i : sub) {
                     const BatchProblem &b = P[i];
                     const int64_t d2 = (int64_t)b.d * b.d;
                     const size_t s64 = spec_bytes(lg, d2, true), s32 = spec_bytes(lg, d2, false);
+                    // As in the single-problem call: A's float64 spectrum is kept
+                    // across sweeps when the float32 spectra fit behind it.
+                    const bool keepA = s64 + 3 * s32 <= 3 * s64;
                     A64.push_back((cplx<double> *)(spec + used));
                     B64.push_back((cplx<double> *)(spec + used + s64));
                     T64.push_back((cplx<double> *)(spec + used + 2 * s64));
+                    char *f32 = spec + used + (keepA ? s64 : 0);
+                    A32.push_back((cplx<float> *)f32);
+                    B32.push_back((cplx<float> *)(f32 + s32));
+                    T32.push_back((cplx<float> *)(f32 + 2 * s32));
                     used += 3 * s64;
-                    A32.push_back((cplx<float> *)(spec + used32));
-                    B32.push_back((cplx<float> *)(spec + used32 + s32));
-                    T32.push_back((cplx<float> *)(spec + used32 + 2 * s32));
-                    used32 += 3 * s32;
                     nl.push_back(nl_of(d2));
                     sq.push_back(src_real(b.q, true, d2, (int)d2, 0, b.n, -1, b.d));
+                    if (sweep == 0 || !keepA) {
+                        A64r.push_back(A64.back());
+                        nlr.push_back(nl.back());
+                        sqr.push_back(sq.back());
+                    }
                     sx.push_back(src_real(b.X, false, d2, (int)d2, 0, b.n));
                     sr.push_back(src_real(b.R, false, d2, (int)d2, 0, b.n));
                     DstDesc r = dst_real(b.R, false, d2, (int)d2, 0, b.n, invL, OP_E0MINUS);
@@ -1508,7 +1520,7 @@ static void plan_sweeps(BatchPlan &bp, mrinv_handle_t h, std::vector<BatchProble
                     g32.push_back(w);
                 }
                 spec_max = std::max(spec_max, used);
-                plan_fwd<double>(bp, h, p, A64, nl, sq);
+                if (!A64r.empty()) plan_fwd<double>(bp, h, p, A64r, nlr, sqr);
                 plan_fwd<double>(bp, h, p, B64, nl, sx);
                 plan_gemm<double>(bp, h, p, g64);
                 plan_inv<double>(bp, h, p, T64, nl, dr);
