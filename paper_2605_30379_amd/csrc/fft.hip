@@ -603,6 +603,15 @@ static hipError_t launch_pass_m(int lgP, int C, cplx<T> *z, const PassGeom &g, c
     }
 }
 
+// Small transforms (the first Newton steps) have too few workgroups to fill
+// the GPU; fewer lanes per workgroup give more, shorter workgroups.  Halves
+// C (16 -> 8 -> 2) while fewer than 512 workgroups would run.
+static int fewer_lanes_when_small(int C, int64_t cols, int nl_a, int nl_b) {
+    auto blocks = [&](int c) { return cols * ((nl_a + c - 1) / c + (nl_b + c - 1) / c); };
+    while (C > 2 && blocks(C) < 512) C = C == 32 ? 16 : C == 16 ? 8 : 2;
+    return C;
+}
+
 int fft_lanes_per_block(bool dbl, int nl) {
     if (nl <= 2) return 2;
     if (dbl) return 8;
@@ -623,6 +632,7 @@ hipError_t fft_pass(int mode, const FftPlan &plan, int pass, int nl, cplx<T> *z,
     const int lgP = plan.lgP[pass];
     int C = nl <= 2 ? 2 : (lanes ? lanes : fft_lanes_per_block(sizeof(T) == 8, nl));
     if (C == 32 && (lgP > 8 || nl <= 16)) C = 16;
+    C = fewer_lanes_when_small(C, g.L >> lgP, nl, 0);
     g.nchunks = (nl + C - 1) / C;
     Twiddles<T> t = tw;
     t.outer = plan.outer[pass];
@@ -797,6 +807,7 @@ hipError_t fft_pass_pair(const FftPlan &plan, int pass, PassProblem<T> a, PassPr
     int C = nlmin <= 2 ? 2 : (lanes ? lanes : fft_lanes_per_block(sizeof(T) == 8, a.nl > b.nl ? a.nl : b.nl));
     if (C == 32 && (plan.lgP[pass] > 8 || nlmin <= 16)) C = 16;
     const int64_t cols = g.L >> plan.lgP[pass];
+    C = fewer_lanes_when_small(C, cols, a.nl, b.nl);
     a.nchunks = (a.nl + C - 1) / C;
     b.nchunks = (b.nl + C - 1) / C;
     a.wg_begin = 0;
