@@ -683,10 +683,11 @@ static hipError_t launch_gemm_mfma_batched(const FftPlan &plan, const GemmProble
 // Direct truncated products of the first Newton steps (the definition of the
 // product in the truncated ring, Section 2.1, without transforms): for small m
 // the 1.5 m^2 d^3 multiply-adds of a step cost less than the latency of the
-// transform launches.  One workgroup per (k, 16x16 output tile); its four
-// waves take every fourth j and their tiles are summed through LDS.
+// transform launches.  One workgroup per (k, 16x16 output tile); its CONV_WAVES
+// waves take every CONV_WAVES-th j and their tiles are summed through LDS.
 // ---------------------------------------------------------------------------
-constexpr int CONV_THREADS = 256;
+constexpr int CONV_WAVES = 16;
+constexpr int CONV_THREADS = 64 * CONV_WAVES;
 
 template <typename T, typename TL, int DP>
 __device__ __forceinline__ void conv_direct_body(const ConvDesc &c, int64_t blk) {
@@ -710,11 +711,11 @@ __device__ __forceinline__ void conv_direct_body(const ConvDesc &c, int64_t blk)
 #pragma unroll
     for (int r = 0; r < 4; ++r) acc[r] = (T)0;
     // Two values of j per iteration keep twice the loads in flight.
-    for (int64_t j = c.jlo + w; j <= jhi; j += 8) {
-        const bool two = j + 4 <= jhi;
+    for (int64_t j = c.jlo + w; j <= jhi; j += 2 * CONV_WAVES) {
+        const bool two = j + CONV_WAVES <= jhi;
         T a0[DP / 4], b0[DP / 4], a1[DP / 4], b1[DP / 4];
-        const TL *L0 = Lp + (k - j) * dd, *L1 = Lp + (k - j - 4) * dd;
-        const T *R0 = Rp + (j - c.r_off) * dd, *R1 = Rp + (j + 4 - c.r_off) * dd;
+        const TL *L0 = Lp + (k - j) * dd, *L1 = Lp + (k - j - CONV_WAVES) * dd;
+        const T *R0 = Rp + (j - c.r_off) * dd, *R1 = Rp + (j + CONV_WAVES - c.r_off) * dd;
 #pragma unroll
         for (int tb = 0; tb < DP / 4; ++tb) {
             const int t = 4 * tb + tq;
@@ -729,7 +730,7 @@ __device__ __forceinline__ void conv_direct_body(const ConvDesc &c, int64_t blk)
 #pragma unroll
         for (int tb = 0; tb < DP / 4; ++tb) acc = Op::mac(a1[tb] * sg, b1[tb], acc);
     }
-    __shared__ T red[4][4][64];
+    __shared__ T red[CONV_WAVES][4][64];
 #pragma unroll
     for (int r = 0; r < 4; ++r) red[w][r][l] = acc[r];
     __syncthreads();
@@ -738,7 +739,9 @@ __device__ __forceinline__ void conv_direct_body(const ConvDesc &c, int64_t blk)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int row = I * 16 + Op::row(l, r), col = J * 16 + (l & 15);
-            const T v = (red[0][r][l] + red[1][r][l]) + (red[2][r][l] + red[3][r][l]);
+            T v = (T)0;
+#pragma unroll
+            for (int u = 0; u < CONV_WAVES; ++u) v += red[u][r][l];
             if (row < d && col < d) {
                 out[row * d + col] = v;
                 if (c.status && !isfinite((double)v)) atomicOr(c.status, 2u);
