@@ -177,12 +177,17 @@ def get_tuning(device=None) -> dict:
 
 
 def set_tuning(device=None, **kw):
-    """Change tuning fields (lgp_max, lanes_fp64, lanes_fp32, seed_m0, pair_forward)."""
+    """Change tuning fields of the device's handle (the fields of mrinv_tuning_t:
+    lgp_max, lanes_fp64, lanes_fp32, seed_m0, pair_forward, twiddle_tables,
+    block_order, use_graph, mfma, direct_m); unknown names raise."""
     dev = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
     t = Tuning()
     h = _handle(dev)
     _check(lib().mrinv_get_tuning(h, ctypes.byref(t)))
+    names = {f for f, _ in Tuning._fields_}
     for k, v in kw.items():
+        if k not in names:
+            raise MrinvError(1, f"unknown tuning field {k!r}")
         setattr(t, k, int(v))
     _check(lib().mrinv_set_tuning(h, ctypes.byref(t)))
 
