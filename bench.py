@@ -347,7 +347,8 @@ def main():
         print(f"[bench] {form}: {ms:.4f} ms/inversion, {res[form]['tflops']:.3f} effective TFLOP/s",
               file=sys.stderr, flush=True)
 
-    # Per-kernel timing of the value form (separate run, events around each launch).
+    # Per-kernel timing of the value form (separate run; the library stamps each
+    # launch with dispatch-packet events).
     value_form = cfg["form"]
     enable, collect = kernel_stats(mr, torch, dev)
     enable(True)

@@ -269,14 +269,15 @@ mrinv_status_t mrinv_autotune(mrinv_handle_t h, const double *q, int d, int64_t 
                               mrinv_tuning_t *chosen);
 
 /* Per-kernel timing, a profiling aid that is off by default.  While enabled,
- * every kernel launch of the library is bracketed by HIP events on the
- * handle's stream and tagged with the algorithmic bytes (one read of each
- * input element the launch needs, one write of each output element) and
- * flops of that launch.  mrinv_set_timing also clears earlier records. */
+ * every kernel launch of the library carries a start and a stop HIP event
+ * that the runtime stamps at the kernel's own start and end
+ * (hipExtLaunchKernelGGL), and is tagged with the algorithmic bytes (one read
+ * of each input element the launch needs, one write of each output element)
+ * and flops of that launch.  mrinv_set_timing also clears earlier records. */
 typedef struct {
     char name[96];      /* kernel name with its template arguments */
     int64_t launches;
-    double total_ms;    /* sum of event-measured launch durations */
+    double total_ms;    /* sum of the launches' execution times */
     double bytes;       /* sum of algorithmic bytes */
     double flops;       /* sum of algorithmic flops (0 for pure data movement) */
 } mrinv_kernel_stat_t;

@@ -86,18 +86,16 @@ __global__ void __launch_bounds__(64) gj_batched_kernel(const GjProblem *probs, 
 
 hipError_t gj_inverse_batched(const GjProblem *probs, int nprob, int dmax, unsigned int *status, hipStream_t st) {
     const size_t lds = (size_t)dmax * 2 * dmax * sizeof(double);
-    launch_begin("gj_batched_kernel", (double)nprob * dmax * dmax * 16.0, 2.0 * nprob * dmax * dmax * dmax);
-    hipLaunchKernelGGL(gj_batched_kernel, dim3(nprob), dim3(64), lds, st, probs, status);
-    launch_end();
+    launch_kernel("gj_batched_kernel", (double)nprob * dmax * dmax * 16.0, 2.0 * nprob * dmax * dmax * dmax,
+                  gj_batched_kernel, dim3(nprob), dim3(64), lds, st, probs, status);
     return hipGetLastError();
 }
 
 hipError_t gj_inverse(const double *A0, int d, int e0_minus, double *out64, float *out32, unsigned int *status,
                       hipStream_t st) {
     const size_t lds = (size_t)d * 2 * d * sizeof(double);
-    launch_begin("gj_kernel", (double)d * d * 8.0 * 2, 2.0 * d * d * d);
-    hipLaunchKernelGGL(gj_kernel, dim3(1), dim3(64), lds, st, A0, d, e0_minus, out64, out32, status);
-    launch_end();
+    launch_kernel("gj_kernel", (double)d * d * 8.0 * 2, 2.0 * d * d * d,
+                  gj_kernel, dim3(1), dim3(64), lds, st, A0, d, e0_minus, out64, out32, status);
     return hipGetLastError();
 }
 
@@ -182,10 +180,9 @@ template <typename T>
 hipError_t seed_recursion_batched(const SeedProblem *probs, int nprob, int total_cols, int dmax, int m0max,
                                   hipStream_t st) {
     const size_t lds = ((size_t)m0max * dmax + (size_t)dmax * dmax + SEED_THREADS + dmax) * sizeof(double);
-    launch_begin(sizeof(T) == 8 ? "seed_recursion_batched_kernel<double>" : "seed_recursion_batched_kernel<float>",
-                 0.0, 0.0);
-    hipLaunchKernelGGL(seed_recursion_batched_kernel<T>, dim3(total_cols), dim3(SEED_THREADS), lds, st, probs, nprob);
-    launch_end();
+    launch_kernel(sizeof(T) == 8 ? "seed_recursion_batched_kernel<double>" : "seed_recursion_batched_kernel<float>",
+                  0.0, 0.0, seed_recursion_batched_kernel<T>, dim3(total_cols), dim3(SEED_THREADS), lds, st, probs,
+                  nprob);
     return hipGetLastError();
 }
 template hipError_t seed_recursion_batched<double>(const SeedProblem *, int, int, int, int, hipStream_t);
@@ -194,10 +191,9 @@ template hipError_t seed_recursion_batched<float>(const SeedProblem *, int, int,
 template <typename T>
 hipError_t seed_recursion(const double *A, int e0, int d, int m0, T *out, hipStream_t st) {
     const size_t lds = ((size_t)m0 * d + (size_t)d * d + SEED_THREADS + d) * sizeof(double);
-    launch_begin(sizeof(T) == 8 ? "seed_recursion_kernel<double>" : "seed_recursion_kernel<float>",
-                 (double)m0 * d * d * 8.0 * 2, (double)m0 * m0 * d * d * d);
-    hipLaunchKernelGGL(seed_recursion_kernel<T>, dim3(d), dim3(SEED_THREADS), lds, st, A, e0, d, m0, out);
-    launch_end();
+    launch_kernel(sizeof(T) == 8 ? "seed_recursion_kernel<double>" : "seed_recursion_kernel<float>",
+                  (double)m0 * d * d * 8.0 * 2, (double)m0 * m0 * d * d * d, seed_recursion_kernel<T>, dim3(d),
+                  dim3(SEED_THREADS), lds, st, A, e0, d, m0, out);
     return hipGetLastError();
 }
 
@@ -290,12 +286,12 @@ static hipError_t scan_lanes(double *Y, int64_t n, int w, int reverse, double a,
                              hipStream_t st) {
     if (w < 1 || w > SCAN_THREADS) return hipErrorInvalidValue;
     const int64_t nch = (n + SCAN_ROWS - 1) / SCAN_ROWS;
-    launch_begin("scan_lanes_kernel", 3.0 * n * w * 8.0, 0.0);
-    hipLaunchKernelGGL(scan_totals_kernel, dim3((unsigned)nch), dim3(SCAN_THREADS), 0, st, Y, n, w, reverse, tmp);
-    hipLaunchKernelGGL(scan_offsets_kernel, dim3(1), dim3(SCAN_THREADS), 0, st, tmp, nch, w);
-    hipLaunchKernelGGL(scan_apply_kernel, dim3((unsigned)nch), dim3(SCAN_THREADS), 0, st, Y, n, w, reverse,
-                       (const double *)tmp, a, b);
-    launch_end();
+    launch_kernel("scan_totals_kernel", (double)n * w * 8.0, 0.0, scan_totals_kernel, dim3((unsigned)nch),
+                  dim3(SCAN_THREADS), 0, st, Y, n, w, reverse, tmp);
+    launch_kernel("scan_offsets_kernel", 2.0 * nch * w * 8.0, 0.0, scan_offsets_kernel, dim3(1), dim3(SCAN_THREADS), 0,
+                  st, tmp, nch, w);
+    launch_kernel("scan_apply_kernel", 2.0 * n * w * 8.0, 0.0, scan_apply_kernel, dim3((unsigned)nch),
+                  dim3(SCAN_THREADS), 0, st, Y, n, w, reverse, (const double *)tmp, a, b);
     return hipGetLastError();
 }
 
@@ -321,9 +317,8 @@ hipError_t survival(const double *q, int d, int64_t n, double *hb, double *tmp, 
     int lgG = 0;
     while ((1 << lgG) < d) ++lgG;
     const int64_t total = (n * d) << lgG;
-    launch_begin("rowsum_kernel", (double)n * d * (d + 1) * 8.0, 0.0);
-    hipLaunchKernelGGL(rowsum_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, q, d, lgG, n, hb);
-    launch_end();
+    launch_kernel("rowsum_kernel", (double)n * d * (d + 1) * 8.0, 0.0,
+                  rowsum_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, q, d, lgG, n, hb);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     return scan_lanes(hb, n, d, 0, 1.0, -1.0, tmp, st);

@@ -551,9 +551,8 @@ static hipError_t launch_pass_t(cplx<T> *z, const PassGeom &g, const SrcDesc &sr
     const int64_t blocks = cols * g.nchunks;
     char name[96];
     snprintf(name, sizeof name, "fft_pass_kernel<%s, %d, %d, %d>", sizeof(T) == 8 ? "double" : "float", LGP, C, MODE);
-    launch_begin(name, pass_bytes<T>(MODE, g, src, dst), 0.0);
-    hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(threads), lds, st, z, g, src, dst, tw);
-    launch_end();
+    launch_kernel(name, pass_bytes<T>(MODE, g, src, dst), 0.0,
+                  kern, dim3((unsigned)blocks), dim3(threads), lds, st, z, g, src, dst, tw);
     return hipGetLastError();
 }
 
@@ -658,9 +657,8 @@ static hipError_t launch_batched_t(const PassProblem<T> *probs, int nprob, int64
     char name[96];
     snprintf(name, sizeof name, "fft_pass_batched_kernel<%s, %d, %d, %d>", sizeof(T) == 8 ? "double" : "float", LGP,
              C, MODE);
-    launch_begin(name, bytes, 0.0);
-    hipLaunchKernelGGL(kern, dim3((unsigned)total), dim3(threads), lds, st, probs, nprob, g, tw);
-    launch_end();
+    launch_kernel(name, bytes, 0.0,
+                  kern, dim3((unsigned)total), dim3(threads), lds, st, probs, nprob, g, tw);
     return hipGetLastError();
 }
 
@@ -679,9 +677,8 @@ static hipError_t launch_pair_t(const PassProblem<T> &a, const PassProblem<T> &b
     char name[96];
     snprintf(name, sizeof name, "fft_pass_pair_kernel<%s, %d, %d, %d>", sizeof(T) == 8 ? "double" : "float", LGP, C,
              MODE);
-    launch_begin(name, bytes, 0.0);
-    hipLaunchKernelGGL(kern, dim3((unsigned)total), dim3(threads), lds, st, a, b, g, tw);
-    launch_end();
+    launch_kernel(name, bytes, 0.0,
+                  kern, dim3((unsigned)total), dim3(threads), lds, st, a, b, g, tw);
     return hipGetLastError();
 }
 
@@ -787,9 +784,8 @@ __global__ void gen_outer_twiddles_kernel(TwGen g, const double2 *hi, const doub
 
 hipError_t gen_outer_twiddles(const TwGen &g, const double2 *hi, const double2 *lo, hipStream_t st) {
     if (g.count == 0 || g.total == 0) return hipSuccess;
-    launch_begin("gen_outer_twiddles_kernel", 0.0, 0.0);
-    hipLaunchKernelGGL(gen_outer_twiddles_kernel, dim3((unsigned)((g.total + 255) / 256)), dim3(256), 0, st, g, hi, lo);
-    launch_end();
+    launch_kernel("gen_outer_twiddles_kernel", 0.0, 0.0,
+                  gen_outer_twiddles_kernel, dim3((unsigned)((g.total + 255) / 256)), dim3(256), 0, st, g, hi, lo);
     return hipGetLastError();
 }
 

@@ -182,10 +182,9 @@ static hipError_t launch_gemm(const FftPlan &plan, const GemmDesc &g, const cplx
     char name[96];
     snprintf(name, sizeof name, "freq_gemm_kernel<%s, %d, %d>", sizeof(T) == 8 ? "double" : "float", TM, TN);
     const double Lr = (double)((int64_t)1 << plan.lgL);
-    launch_begin(name, Lr * (g.nlA + g.nlB + g.nlC) * sizeof(cplx<T>), (double)F * 8.0 * g.ra * g.m * g.cb);
-    hipLaunchKernelGGL((freq_gemm_kernel<T, TM, TN>), dim3((unsigned)blocks), dim3(GEMM_THREADS), bytes(NF), st, ZA,
-                       ZB, ZC, plan, g, NF, KC, tiles_j, tiles);
-    launch_end();
+    launch_kernel(name, Lr * (g.nlA + g.nlB + g.nlC) * sizeof(cplx<T>), (double)F * 8.0 * g.ra * g.m * g.cb,
+                  (freq_gemm_kernel<T, TM, TN>), dim3((unsigned)blocks), dim3(GEMM_THREADS), bytes(NF), st, ZA, ZB,
+                  ZC, plan, g, NF, KC, tiles_j, tiles);
     return hipGetLastError();
 }
 
@@ -654,9 +653,8 @@ static hipError_t launch_gemm_mfma(const FftPlan &plan, int d, const cplx<T> *ZA
                  sizeof(T) == 8 ? "double" : "float", DP, ODD ? "true" : "false");
     const double Lr = (double)((int64_t)1 << plan.lgL);
     const int nl = (d * d + 1) / 2;
-    launch_begin(name, Lr * 3.0 * nl * sizeof(cplx<T>), (double)F * 8.0 * d * d * d);
-    hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(Cfg::THREADS), lds, st, ZA, ZB, ZC, plan, d);
-    launch_end();
+    launch_kernel(name, Lr * 3.0 * nl * sizeof(cplx<T>), (double)F * 8.0 * d * d * d,
+                  kern, dim3((unsigned)blocks), dim3(Cfg::THREADS), lds, st, ZA, ZB, ZC, plan, d);
     return hipGetLastError();
 }
 
@@ -673,9 +671,8 @@ static hipError_t launch_gemm_mfma_batched(const FftPlan &plan, const GemmProble
     char name[96];
     snprintf(name, sizeof name, "freq_gemm_mfma_batched_kernel<%s, %d, %s>", sizeof(T) == 8 ? "double" : "float",
              DP, ODD ? "true" : "false");
-    launch_begin(name, bytes, flops);
-    hipLaunchKernelGGL(kern, dim3((unsigned)total), dim3(Cfg::THREADS), lds, st, probs, nprob, plan);
-    launch_end();
+    launch_kernel(name, bytes, flops,
+                  kern, dim3((unsigned)total), dim3(Cfg::THREADS), lds, st, probs, nprob, plan);
     return hipGetLastError();
 }
 
@@ -788,9 +785,8 @@ static hipError_t launch_conv(const ConvDesc &c, hipStream_t st) {
     char name[96];
     snprintf(name, sizeof name, "conv_direct_kernel<%s, %s, %d>", sizeof(T) == 8 ? "double" : "float",
              sizeof(TL) == 8 ? "double" : "float", DP);
-    launch_begin(name, 0.0, conv_flops(c));
-    hipLaunchKernelGGL((conv_direct_kernel<T, TL, DP>), dim3((unsigned)conv_blocks(c)), dim3(CONV_THREADS), 0, st, c);
-    launch_end();
+    launch_kernel(name, 0.0, conv_flops(c),
+                  (conv_direct_kernel<T, TL, DP>), dim3((unsigned)conv_blocks(c)), dim3(CONV_THREADS), 0, st, c);
     return hipGetLastError();
 }
 
@@ -825,10 +821,8 @@ static hipError_t launch_conv_batched(const ConvDesc *cs, int n, int64_t total, 
     char name[96];
     snprintf(name, sizeof name, "conv_direct_batched_kernel<%s, %s, %d>", sizeof(T) == 8 ? "double" : "float",
              sizeof(TL) == 8 ? "double" : "float", DP);
-    launch_begin(name, 0.0, flops);
-    hipLaunchKernelGGL((conv_direct_batched_kernel<T, TL, DP>), dim3((unsigned)total), dim3(CONV_THREADS), 0, st, cs,
-                       n);
-    launch_end();
+    launch_kernel(name, 0.0, flops,
+                  (conv_direct_batched_kernel<T, TL, DP>), dim3((unsigned)total), dim3(CONV_THREADS), 0, st, cs, n);
     return hipGetLastError();
 }
 
@@ -872,10 +866,9 @@ static hipError_t launch_gemm_sq_batched(const FftPlan &plan, const GemmProblem<
     const size_t lds = sq_lds_bytes<T, DP>(DP - 1);
     char name[96];
     snprintf(name, sizeof name, "freq_gemm_sq_batched_kernel<%s, %d>", sizeof(T) == 8 ? "double" : "float", DP);
-    launch_begin(name, bytes, flops);
-    hipLaunchKernelGGL((freq_gemm_sq_batched_kernel<T, DP>), dim3((unsigned)total), dim3(Cfg::THREADS), lds, st,
-                       probs, nprob, plan);
-    launch_end();
+    launch_kernel(name, bytes, flops,
+                  (freq_gemm_sq_batched_kernel<T, DP>), dim3((unsigned)total), dim3(Cfg::THREADS), lds, st, probs,
+                  nprob, plan);
     return hipGetLastError();
 }
 
@@ -956,10 +949,9 @@ static hipError_t launch_gemm_sq(const FftPlan &plan, int d, const cplx<T> *ZA, 
     snprintf(name, sizeof name, "freq_gemm_sq_kernel<%s, %d>", sizeof(T) == 8 ? "double" : "float", DP);
     const double Lr = (double)((int64_t)1 << plan.lgL);
     const int nl = (d * d + 1) / 2;
-    launch_begin(name, Lr * 3.0 * nl * sizeof(cplx<T>), (double)F * 8.0 * d * d * d);
-    hipLaunchKernelGGL((freq_gemm_sq_kernel<T, DP>), dim3((unsigned)blocks), dim3(Cfg::THREADS), lds, st, ZA, ZB, ZC,
-                       plan, d);
-    launch_end();
+    launch_kernel(name, Lr * 3.0 * nl * sizeof(cplx<T>), (double)F * 8.0 * d * d * d,
+                  (freq_gemm_sq_kernel<T, DP>), dim3((unsigned)blocks), dim3(Cfg::THREADS), lds, st, ZA, ZB, ZC, plan,
+                  d);
     return hipGetLastError();
 }
 
@@ -1045,11 +1037,10 @@ hipError_t freq_diag(const FftPlan &plan, int ra, int cb, const cplx<T> *ZA, con
     const int64_t F = ((int64_t)1 << plan.lgL) / 2 + 1;
     const int64_t total = F * nl;
     const int threads = 256;
-    launch_begin(sizeof(T) == 8 ? "freq_diag_kernel<double>" : "freq_diag_kernel<float>",
-                 (double)((int64_t)1 << plan.lgL) * (2 * nl + nlh) * sizeof(cplx<T>), (double)F * ra * cb * 6.0);
-    hipLaunchKernelGGL(freq_diag_kernel<T>, dim3((unsigned)((total + threads - 1) / threads)), dim3(threads), 0, st,
-                       ZA, ZH, ZC, plan, ra, cb, nl, nlh);
-    launch_end();
+    launch_kernel(sizeof(T) == 8 ? "freq_diag_kernel<double>" : "freq_diag_kernel<float>",
+                  (double)((int64_t)1 << plan.lgL) * (2 * nl + nlh) * sizeof(cplx<T>), (double)F * ra * cb * 6.0,
+                  freq_diag_kernel<T>, dim3((unsigned)((total + threads - 1) / threads)), dim3(threads), 0, st, ZA, ZH,
+                  ZC, plan, ra, cb, nl, nlh);
     return hipGetLastError();
 }
 

@@ -1,6 +1,7 @@
 // Kernel launch interface of the mrinv library (internal).
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -10,14 +11,29 @@
 
 namespace mrinv {
 
-// Optional launch timing (see mrinv_set_timing).  launch_begin/launch_end
-// bracket one kernel launch; they do nothing unless a timer is active.
+// Optional launch timing (see mrinv_set_timing).  While a timer is active,
+// timed_events() records one launch (name, algorithmic bytes and flops) and
+// hands out the start/stop events that the launch carries; otherwise it
+// returns false and the kernel is launched without events.
 void timer_activate(void *timer, hipStream_t st);
-void launch_begin(const char *name, double bytes, double flops);
-void launch_end();
+bool timed_events(const char *name, double bytes, double flops, hipEvent_t *start, hipEvent_t *stop);
 void *timer_create();
 void timer_destroy(void *t);
 void timer_reset(void *t);
+
+// Launches kernel(args...) on st.  A timed launch goes through
+// hipExtLaunchKernelGGL, whose events the runtime stamps from the kernel's own
+// dispatch packet, so their difference is the kernel's execution time (an
+// event pair recorded around the launch would add the packet gaps).
+template <typename F, typename... Args>
+inline void launch_kernel(const char *name, double bytes, double flops, F kernel, dim3 grid, dim3 block, size_t lds,
+                          hipStream_t st, Args... args) {
+    hipEvent_t a = nullptr, b = nullptr;
+    if (timed_events(name, bytes, flops, &a, &b))
+        hipExtLaunchKernelGGL(kernel, grid, block, (uint32_t)lds, st, a, b, 0u, args...);
+    else
+        hipLaunchKernelGGL(kernel, grid, block, lds, st, args...);
+}
 
 constexpr unsigned int STATUS_SINGULAR = 1u;
 constexpr unsigned int STATUS_NONFINITE = 2u;

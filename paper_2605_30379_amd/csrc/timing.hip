@@ -1,7 +1,8 @@
 // Optional per-kernel timing.  When a handle enables it, every kernel launch
-// of the library is bracketed by HIP events on the launch stream and tagged
-// with the kernel's name and the algorithmic bytes and flops of that launch;
-// mrinv_kernel_stats() aggregates them per kernel name.
+// of the library carries a start and a stop event stamped at the kernel's own
+// start and end (hipExtLaunchKernelGGL) and is tagged with the kernel's name
+// and the algorithmic bytes and flops of that launch; mrinv_kernel_stats()
+// aggregates them per kernel name.
 #include <string.h>
 
 #include <map>
@@ -35,16 +36,11 @@ struct Timer {
 };
 
 static thread_local Timer *g_timer = nullptr;
-static thread_local hipStream_t g_timer_stream = nullptr;
-static thread_local TimedLaunch *g_open = nullptr;
 
-void timer_activate(void *timer, hipStream_t st) {
-    g_timer = (Timer *)timer;
-    g_timer_stream = st;
-}
+void timer_activate(void *timer, hipStream_t) { g_timer = (Timer *)timer; }
 
-void launch_begin(const char *name, double bytes, double flops) {
-    if (!g_timer) return;
+bool timed_events(const char *name, double bytes, double flops, hipEvent_t *start, hipEvent_t *stop) {
+    if (!g_timer) return false;
     TimedLaunch t;
     t.name = name;
     t.start = g_timer->get();
@@ -52,14 +48,9 @@ void launch_begin(const char *name, double bytes, double flops) {
     t.bytes = bytes;
     t.flops = flops;
     g_timer->launches.push_back(t);
-    g_open = &g_timer->launches.back();
-    (void)hipEventRecord(g_open->start, g_timer_stream);
-}
-
-void launch_end() {
-    if (!g_timer || !g_open) return;
-    (void)hipEventRecord(g_open->stop, g_timer_stream);
-    g_open = nullptr;
+    *start = t.start;
+    *stop = t.stop;
+    return true;
 }
 
 void *timer_create() { return new Timer(); }

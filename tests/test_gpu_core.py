@@ -495,3 +495,49 @@ def test_direct_steps_series_inverse_general_a0(mr, orc):
     finally:
         mr.set_tuning(**base)
     assert _maxerr(got, ref) <= 1e-11 * max(1.0, np.max(np.abs(ref)))
+
+
+def test_kernel_timing_records_every_launch(mr):
+    """Timed launches (events stamped by the kernels' own dispatch packets)
+    change no result, and their summed execution times fit inside the wall
+    time of the calls they cover."""
+    import ctypes
+
+    class Stat(ctypes.Structure):
+        _fields_ = [("name", ctypes.c_char * 96), ("launches", ctypes.c_int64), ("total_ms", ctypes.c_double),
+                    ("bytes", ctypes.c_double), ("flops", ctypes.c_double)]
+
+    L = mr.lib()
+    L.mrinv_set_timing.argtypes = [ctypes.c_void_p, ctypes.c_int]
+    L.mrinv_set_timing.restype = ctypes.c_int
+    L.mrinv_kernel_stats.argtypes = [ctypes.c_void_p, ctypes.POINTER(Stat), ctypes.c_int]
+    L.mrinv_kernel_stats.restype = ctypes.c_int
+    dev = torch.device("cuda:0")
+    h = mr._handle(dev)
+    q = _gpu(si.family_kernel("weibull", 16, 8192, 77).q)
+    plain = _np(mr.psi_inverse(q, "fp64", check=True))
+    calls = 3
+    assert L.mrinv_set_timing(h, 1) == 0
+    try:
+        t0 = torch.cuda.Event(enable_timing=True)
+        t1 = torch.cuda.Event(enable_timing=True)
+        t0.record()
+        outs = [mr.psi_inverse(q, "fp64") for _ in range(calls)]
+        t1.record()
+        torch.cuda.synchronize()
+        wall_ms = t0.elapsed_time(t1)
+        buf = (Stat * 64)()
+        k = L.mrinv_kernel_stats(h, buf, 64)
+    finally:
+        L.mrinv_set_timing(h, 0)
+    assert 0 < k <= 64
+    stats = [buf[i] for i in range(k)]
+    names = [s.name.decode() for s in stats]
+    assert any(n.startswith("fft_pass") for n in names), names
+    assert any(n.startswith("freq_gemm") for n in names), names
+    for s in stats:
+        assert s.launches > 0 and s.launches % calls == 0, (s.name, s.launches)
+        assert 0.0 < s.total_ms < wall_ms, (s.name, s.total_ms, wall_ms)
+    assert sum(s.total_ms for s in stats) <= wall_ms
+    for o in outs:
+        assert np.array_equal(_np(o), plain)
