@@ -14,19 +14,25 @@ namespace mrinv {
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void gj_body(const double *A0, int d, int e0_minus, double *out64, float *out32,
                                         unsigned int *status) {
-    // One wavefront; lane r owns row r of W = [A(0) | I] (kept in LDS).
+    // One wavefront; lane r owns row r of W = [A(0) | I] (kept in LDS).  Row r
+    // is stored rotated by r (column j at slot (j + r) mod 2d), so the lanes'
+    // simultaneous accesses to one column fall into different LDS banks.
     extern __shared__ __align__(16) unsigned char smem_raw[];
     double *W = reinterpret_cast<double *>(smem_raw);   // [d][2d]
     const int lane = threadIdx.x;
     const int w = 2 * d;
+    auto at = [&](int r, int j) {
+        const int s = j + r;
+        return r * w + (s >= w ? s - w : s);
+    };
     double amax = 0.0;
     bool finite = true;
     if (lane < d) {
         for (int j = 0; j < d; ++j) {
             const double a = A0[lane * d + j];
             const double v = e0_minus ? ((lane == j ? 1.0 : 0.0) - a) : a;
-            W[lane * w + j] = v;
-            W[lane * w + d + j] = lane == j ? 1.0 : 0.0;
+            W[at(lane, j)] = v;
+            W[at(lane, d + j)] = lane == j ? 1.0 : 0.0;
             finite = finite && isfinite(v);
             amax = fmax(amax, fabs(v));
         }
@@ -34,10 +40,30 @@ __device__ __forceinline__ void gj_body(const double *A0, int d, int e0_minus, d
     for (int off = 32; off > 0; off >>= 1) amax = fmax(amax, __shfl_xor(amax, off, 64));
     int sing = __any(!finite) ? 2 : 0;
     const double tol = d * 0x1p-53 * amax;
+    // A diagonal A(0) (the identity when q(0) = 0) needs no elimination: the
+    // pivots are the diagonal entries in order, and row r of the result is
+    // row r of I scaled by 1 / a_rr, exactly what the general sweep computes.
+    bool offdiag = false;
+    if (lane < d)
+        for (int j = 0; j < d; ++j) offdiag = offdiag || (j != lane && W[at(lane, j)] != 0.0);
+    if (!sing && !__any(offdiag)) {
+        const double arr = lane < d ? W[at(lane, lane)] : 1.0;
+        const bool bad = __any(lane < d && !(fabs(arr) > tol));
+        if (bad && lane == 0 && status) atomicOr(status, STATUS_SINGULAR);
+        if (lane < d) {
+            const double inv = 1.0 / arr;
+            for (int j = 0; j < d; ++j) {
+                const double v = bad ? __longlong_as_double(0x7ff8000000000000LL) : (j == lane ? 1.0 : 0.0) * inv;
+                if (out64) out64[lane * d + j] = v;
+                if (out32) out32[lane * d + j] = (float)v;
+            }
+        }
+        return;
+    }
     __syncthreads();
     for (int c = 0; c < d && !sing; ++c) {
         // Partial pivoting: argmax over rows c..d-1 of |W[r][c]| (lowest row on ties).
-        double best = (lane >= c && lane < d) ? fabs(W[lane * w + c]) : -1.0;
+        double best = (lane >= c && lane < d) ? fabs(W[at(lane, c)]) : -1.0;
         int piv = lane;
         for (int off = 32; off > 0; off >>= 1) {
             const double ob = __shfl_xor(best, off, 64);
@@ -47,20 +73,20 @@ __device__ __forceinline__ void gj_body(const double *A0, int d, int e0_minus, d
         if (!(best > tol)) { sing = 1; break; }
         if (piv != c) {
             for (int j = lane; j < w; j += 64) {
-                const double t = W[c * w + j];
-                W[c * w + j] = W[piv * w + j];
-                W[piv * w + j] = t;
+                const double t = W[at(c, j)];
+                W[at(c, j)] = W[at(piv, j)];
+                W[at(piv, j)] = t;
             }
         }
         __syncthreads();
-        const double inv = 1.0 / W[c * w + c];
+        const double inv = 1.0 / W[at(c, c)];
         __syncthreads();
-        for (int j = lane; j < w; j += 64) W[c * w + j] *= inv;
+        for (int j = lane; j < w; j += 64) W[at(c, j)] *= inv;
         __syncthreads();
         if (lane < d && lane != c) {
-            const double f = W[lane * w + c];
+            const double f = W[at(lane, c)];
             if (f != 0.0)
-                for (int j = 0; j < w; ++j) W[lane * w + j] = fma(-f, W[c * w + j], W[lane * w + j]);
+                for (int j = 0; j < w; ++j) W[at(lane, j)] = fma(-f, W[at(c, j)], W[at(lane, j)]);
         }
         __syncthreads();
     }
@@ -68,7 +94,7 @@ __device__ __forceinline__ void gj_body(const double *A0, int d, int e0_minus, d
     if (bad && lane == 0 && status) atomicOr(status, sing == 1 ? STATUS_SINGULAR : STATUS_NONFINITE);
     for (int idx = lane; idx < d * d; idx += 64) {
         const int i = idx / d, j = idx - i * d;
-        const double v = bad ? __longlong_as_double(0x7ff8000000000000LL) : W[i * w + d + j];
+        const double v = bad ? __longlong_as_double(0x7ff8000000000000LL) : W[at(i, d + j)];
         if (out64) out64[idx] = v;
         if (out32) out32[idx] = (float)v;
     }

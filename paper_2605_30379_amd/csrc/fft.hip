@@ -22,6 +22,11 @@
 // up to three register-radix stages (radix <= 16); the first stage reads global
 // memory directly, the last stage writes global memory directly, and LDS holds
 // the data between stages.
+// No multiply-add contraction in this file: a pass computes the same bits
+// whatever its lanes per workgroup or LDS tiling, so batched and single
+// transforms of one problem agree exactly.
+#pragma clang fp contract(off)
+
 #include <stdio.h>
 
 #include <type_traits>
@@ -115,7 +120,12 @@ __device__ __forceinline__ void flag_nonfinite(unsigned int *status, double a, d
 // the tile.
 template <typename T, int LGP, int C, int MODE>
 __host__ __device__ constexpr int pass_split() {
-    return (sizeof(T) == 8 && LGP == 9 && C == 16) ? 2 : 1;
+    return (sizeof(T) == 8 && (LGP == 9 || LGP == 8) && C == 16) ? 2 : 1;
+}
+// Waves per SIMD the pass kernels are compiled for (VGPR budget 512 / waves).
+template <typename T, int LGP, int C, int MODE>
+__host__ __device__ constexpr int pass_waves() {
+    return pass_split<T, LGP, C, MODE>() == 2 ? (LGP == 9 ? 8 : 4) : 1;
 }
 template <typename T, int LGP, int C, int MODE>
 __host__ __device__ constexpr int pass_lds_stride() {
@@ -477,7 +487,7 @@ __device__ __forceinline__ void fft_pass_body(cplx<T> *z, const PassGeom &g, int
 
 template <typename T, int LGP, int C, int MODE>
 __global__ void __launch_bounds__(C << (LGP - min_stage_lg(LGP)))
-__attribute__((amdgpu_waves_per_eu(pass_split<T, LGP, C, MODE>() == 2 ? 8 : 1)))
+__attribute__((amdgpu_waves_per_eu(pass_waves<T, LGP, C, MODE>())))
 fft_pass_kernel(cplx<T> *z, PassGeom g, SrcDesc src, DstDesc dst, Twiddles<T> tw) {
     fft_pass_body<T, LGP, C, MODE>(z, g, g.nl, g.nchunks, blockIdx.x, src, dst, tw);
 }
@@ -486,7 +496,7 @@ fft_pass_kernel(cplx<T> *z, PassGeom g, SrcDesc src, DstDesc dst, Twiddles<T> tw
 // operands of a product in one launch).
 template <typename T, int LGP, int C, int MODE>
 __global__ void __launch_bounds__(C << (LGP - min_stage_lg(LGP)))
-__attribute__((amdgpu_waves_per_eu(pass_split<T, LGP, C, MODE>() == 2 ? 8 : 1)))
+__attribute__((amdgpu_waves_per_eu(pass_waves<T, LGP, C, MODE>())))
 fft_pass_pair_kernel(PassProblem<T> a, PassProblem<T> b, PassGeom g, Twiddles<T> tw) {
     const int64_t bid = blockIdx.x;
     if (bid < b.wg_begin) fft_pass_body<T, LGP, C, MODE>(a.z, g, a.nl, a.nchunks, bid, a.src, a.dst, tw);
@@ -496,7 +506,7 @@ fft_pass_pair_kernel(PassProblem<T> a, PassProblem<T> b, PassGeom g, Twiddles<T>
 // Batched: the workgroup's problem is found by binary search over wg_begin.
 template <typename T, int LGP, int C, int MODE>
 __global__ void __launch_bounds__(C << (LGP - min_stage_lg(LGP)))
-__attribute__((amdgpu_waves_per_eu(pass_split<T, LGP, C, MODE>() == 2 ? 8 : 1)))
+__attribute__((amdgpu_waves_per_eu(pass_waves<T, LGP, C, MODE>())))
 fft_pass_batched_kernel(const PassProblem<T> *probs, int nprob, PassGeom g, Twiddles<T> tw) {
     int lo = 0, hi = nprob - 1;
     const int64_t bid = blockIdx.x;

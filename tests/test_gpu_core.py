@@ -131,6 +131,25 @@ def test_series_inverse_general_A0(mr, orc):
     assert _maxerr(got, ref) <= 1e-11 * max(1.0, np.max(np.abs(ref)))
 
 
+@pytest.mark.parametrize("a0", ["diagonal", "permuted"])
+def test_series_inverse_diagonal_and_permuted_A0(mr, orc, a0):
+    """A diagonal A(0) with negative entries takes the Gauss-Jordan shortcut;
+    a row-permuted diagonal one needs pivoting.  Both match the oracle, and
+    the constant coefficient of the diagonal case is exactly 1 / a_rr."""
+    rng = np.random.default_rng(5)
+    d, n = 6, 200
+    A = rng.standard_normal((n, d, d)) / (d * (1 + np.arange(n))[:, None, None] ** 2)
+    diag = np.array([-2.0, 0.5, 3.0, -0.25, 7.0, 1.0])
+    A[0] = np.diag(diag)
+    if a0 == "permuted":
+        A[0] = A[0][[2, 0, 1, 5, 3, 4]]
+    ref = orc.series_inverse_left(A)
+    got = _np(mr.series_inverse(_gpu(A), check=True))
+    assert _maxerr(got, ref) <= 1e-11 * max(1.0, np.max(np.abs(ref)))
+    if a0 == "diagonal":
+        assert np.array_equal(got[0], np.diag(1.0 / diag))
+
+
 @pytest.mark.parametrize("d,n,r", [(4, 100, 3), (5, 257, 1), (3, 64, 6)])
 def test_apply_matches_oracle(mr, orc, d, n, r):
     rng = np.random.default_rng(d * n + r)
