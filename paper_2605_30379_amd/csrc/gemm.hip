@@ -360,11 +360,15 @@ template <> struct MfmaOp<float> {
     __device__ static __forceinline__ int row(int l, int r) { return 4 * (l >> 4) + r; }
 };
 
-template <int DP> struct MfCfg {
+template <typename T, int DP> struct MfCfg {
     static constexpr int WPF = DP / 16;                  // waves per frequency
     static constexpr int NF = WPF >= 3 ? 1 : 4 / WPF;    // frequencies per workgroup
     static constexpr int THREADS = 64 * WPF * NF;
-    static constexpr int KC = 16;                        // contraction chunk
+    // Contraction chunk and register budget.  FP64 products with d > 16 take
+    // 8-wide chunks (half the LDS of 16-wide ones) and a register budget of
+    // 4 (d <= 32) or 3 (d <= 64) waves per SIMD, so more workgroups share a CU.
+    static constexpr int WAVES = sizeof(T) == 8 && DP >= 32 ? (DP == 32 ? 4 : 3) : 1;
+    static constexpr int KC = WAVES > 1 ? 8 : 16;
     static constexpr int LDA = KC + 1;                   // As[f][i][t], i < DP, t < KC
     static constexpr int LDB = DP + 1;                   // Bs[f][t][j]
     static constexpr int AS = DP * LDA;
@@ -375,7 +379,7 @@ template <int DP> struct MfCfg {
 // LDS bytes of one workgroup; odd d stages C (d*d complex per frequency).
 template <typename T, int DP>
 static size_t mf_lds_bytes(int dmax_odd) {
-    using Cfg = MfCfg<DP>;
+    using Cfg = MfCfg<T, DP>;
     const size_t ab = (size_t)Cfg::NBUF * Cfg::NF * (Cfg::AS + Cfg::BS) * sizeof(cplx<T>);
     const size_t cs = (size_t)Cfg::NF * ((size_t)dmax_odd * dmax_odd + 1) * sizeof(cplx<T>);
     return cs > ab ? cs : ab;
@@ -398,7 +402,7 @@ template <typename T, int DP, bool ODD, bool TA = false, bool TB = false>
 __device__ __forceinline__ void freq_gemm_mfma_body(const cplx<T> *__restrict__ ZA, const cplx<T> *__restrict__ ZB,
                                                     cplx<T> *__restrict__ ZC, const FftPlan &plan, int d,
                                                     int64_t blk) {
-    using Cfg = MfCfg<DP>;
+    using Cfg = MfCfg<T, DP>;
     using Op = MfmaOp<T>;
     using V = typename Op::V;
     constexpr int WPF = Cfg::WPF, NF = Cfg::NF, KC = Cfg::KC, NT = Cfg::THREADS;
@@ -612,14 +616,16 @@ __device__ __forceinline__ void freq_gemm_mfma_body(const cplx<T> *__restrict__ 
 }
 
 template <typename T, int DP, bool ODD, bool TA, bool TB>
-__global__ void __launch_bounds__(MfCfg<DP>::THREADS)
+__global__ void __launch_bounds__((MfCfg<T, DP>::THREADS))
+__attribute__((amdgpu_waves_per_eu(MfCfg<T, DP>::WAVES)))
 freq_gemm_mfma_kernel(const cplx<T> *__restrict__ ZA, const cplx<T> *__restrict__ ZB, cplx<T> *__restrict__ ZC,
                       FftPlan plan, int d) {
     freq_gemm_mfma_body<T, DP, ODD, TA, TB>(ZA, ZB, ZC, plan, d, blockIdx.x);
 }
 
 template <typename T, int DP, bool ODD>
-__global__ void __launch_bounds__(MfCfg<DP>::THREADS)
+__global__ void __launch_bounds__((MfCfg<T, DP>::THREADS))
+__attribute__((amdgpu_waves_per_eu(MfCfg<T, DP>::WAVES)))
 freq_gemm_mfma_batched_kernel(const GemmProblem<T> *probs, int nprob, FftPlan plan) {
     int lo = 0, hi = nprob - 1;
     const int64_t bid = blockIdx.x;
@@ -635,7 +641,7 @@ freq_gemm_mfma_batched_kernel(const GemmProblem<T> *probs, int nprob, FftPlan pl
 template <typename T, int DP, bool ODD, bool TA = false, bool TB = false>
 static hipError_t launch_gemm_mfma(const FftPlan &plan, int d, const cplx<T> *ZA, const cplx<T> *ZB, cplx<T> *ZC,
                                    hipStream_t st) {
-    using Cfg = MfCfg<DP>;
+    using Cfg = MfCfg<T, DP>;
     const size_t lds = mf_lds_bytes<T, DP>(ODD ? d : 0);
     auto kern = freq_gemm_mfma_kernel<T, DP, ODD, TA, TB>;
     if (lds > 64 * 1024) {
@@ -661,7 +667,7 @@ static hipError_t launch_gemm_mfma(const FftPlan &plan, int d, const cplx<T> *ZA
 template <typename T, int DP, bool ODD>
 static hipError_t launch_gemm_mfma_batched(const FftPlan &plan, const GemmProblem<T> *probs, int nprob,
                                            int64_t total, double bytes, double flops, hipStream_t st) {
-    using Cfg = MfCfg<DP>;
+    using Cfg = MfCfg<T, DP>;
     const size_t lds = mf_lds_bytes<T, DP>(ODD ? DP - 1 : 0);
     auto kern = freq_gemm_mfma_batched_kernel<T, DP, ODD>;
     if (lds > 64 * 1024) {
@@ -897,10 +903,10 @@ int64_t gemm_batch_layout(const FftPlan &plan, GemmProblem<T> *probs, int nprob,
             case 6: nf = SqCfg<48>::NF; break;
             case 7: nf = SqCfg<56>::NF; break;
             case 8: nf = SqCfg<64>::NF; break;
-            case 9: case 13: nf = MfCfg<16>::NF; break;
-            case 10: case 14: nf = MfCfg<32>::NF; break;
-            case 11: case 15: nf = MfCfg<48>::NF; break;
-            default: nf = MfCfg<64>::NF; break;
+            case 9: case 13: nf = MfCfg<double, 16>::NF; break;
+            case 10: case 14: nf = MfCfg<double, 32>::NF; break;
+            case 11: case 15: nf = MfCfg<double, 48>::NF; break;
+            default: nf = MfCfg<double, 64>::NF; break;
         }
         probs[i].wg_begin = acc;
         acc += (F + nf - 1) / nf;
