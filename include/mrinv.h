@@ -236,9 +236,11 @@ mrinv_status_t mrinv_residual_norms(mrinv_handle_t h, const double *q, const dou
  * keeps the fastest.  None of them changes what is computed. */
 typedef struct {
     int lgp_max;        /* largest FFT pass radix exponent, 5..9 (default 9: passes of <= 512 rows) */
-    int lanes_fp64;     /* complex lanes per FFT workgroup in float64: 8, 16 or 32 (default 16; 32 only for
-                           passes of <= 256 rows; fewer for transforms too small to fill the GPU) */
-    int lanes_fp32;     /* the same in float32 (default 16) */
+    int lanes_fp64;     /* complex lanes per FFT workgroup in float64: 8, 16 or 32 (32 only for passes
+                           of <= 256 rows; fewer for transforms too small to fill the GPU), or 0
+                           (default): automatic, 32 for passes of <= 128 rows when d >= 32, else 16.
+                           Batched calls use at most 16 (16 for 0). */
+    int lanes_fp32;     /* the same in float32; automatic: 32 for passes of <= 256 rows when d >= 32 */
     int seed_m0;        /* coefficients formed by the coefficient recursion (Section 2.2) before
                            Newton starts; rounded down to a power of two, 1..256 (default 1: none) */
     int pair_forward;   /* nonzero: forward transforms of both Newton operands in one launch (default 1) */

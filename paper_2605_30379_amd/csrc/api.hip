@@ -49,7 +49,7 @@ constexpr size_t SCRATCH_BYTES =
 
 // Tuning of a new handle, also used where no handle is given (workspace
 // queries), so that both plan the same launches.
-static const mrinv_tuning_t kDefaultTune = {9, 16, 16, 1, 1, 1, 0, 0, 1, -1};
+static const mrinv_tuning_t kDefaultTune = {9, 0, 0, 1, 1, 1, 0, 0, 1, -1};
 
 struct mrinv_handle_s {
     hipStream_t stream = nullptr;
@@ -744,10 +744,10 @@ extern "C" mrinv_status_t mrinv_series_inverse(mrinv_handle_t h, const double *A
 // ---------------------------------------------------------------------------
 static mrinv_status_t check_tuning(const mrinv_tuning_t &t) {
     if (t.lgp_max < 5 || t.lgp_max > LGP_MAX) return fail(MRINV_E_ARG, "lgp_max %d not in 5..%d", t.lgp_max, LGP_MAX);
-    if (t.lanes_fp64 != 8 && t.lanes_fp64 != 16 && t.lanes_fp64 != 32)
-        return fail(MRINV_E_ARG, "lanes_fp64 must be 8, 16 or 32");
-    if (t.lanes_fp32 != 8 && t.lanes_fp32 != 16 && t.lanes_fp32 != 32)
-        return fail(MRINV_E_ARG, "lanes_fp32 must be 8, 16 or 32");
+    if (t.lanes_fp64 != 0 && t.lanes_fp64 != 8 && t.lanes_fp64 != 16 && t.lanes_fp64 != 32)
+        return fail(MRINV_E_ARG, "lanes_fp64 must be 0 (automatic), 8, 16 or 32");
+    if (t.lanes_fp32 != 0 && t.lanes_fp32 != 8 && t.lanes_fp32 != 16 && t.lanes_fp32 != 32)
+        return fail(MRINV_E_ARG, "lanes_fp32 must be 0 (automatic), 8, 16 or 32");
     if (t.seed_m0 < 1 || t.seed_m0 > 256) return fail(MRINV_E_ARG, "seed_m0 %d not in 1..256", t.seed_m0);
     if (t.twiddle_tables < 0 || t.twiddle_tables > 2) return fail(MRINV_E_ARG, "twiddle_tables must be 0, 1 or 2");
     if (t.block_order < 0 || t.block_order > 1) return fail(MRINV_E_ARG, "block_order must be 0 or 1");
@@ -812,9 +812,9 @@ extern "C" mrinv_status_t mrinv_autotune(mrinv_handle_t h, const double *q, int 
         return MRINV_OK;
     };
     for (int v : {7, 8, 9}) { mrinv_tuning_t t = best; t.lgp_max = v; CHECK(trial(t)); }
-    for (int v : {8, 16}) { mrinv_tuning_t t = best; t.lanes_fp64 = v; CHECK(trial(t)); }
+    for (int v : {0, 8, 16, 32}) { mrinv_tuning_t t = best; t.lanes_fp64 = v; CHECK(trial(t)); }
     if (precision != MRINV_FP64)
-        for (int v : {8, 16}) { mrinv_tuning_t t = best; t.lanes_fp32 = v; CHECK(trial(t)); }
+        for (int v : {0, 8, 16, 32}) { mrinv_tuning_t t = best; t.lanes_fp32 = v; CHECK(trial(t)); }
     for (int v : {1, 16, 32, 64}) { mrinv_tuning_t t = best; t.seed_m0 = v; CHECK(trial(t)); }
     for (int v : {0, 1}) { mrinv_tuning_t t = best; t.pair_forward = v; CHECK(trial(t)); }
     for (int v : {0, 1, 2}) { mrinv_tuning_t t = best; t.twiddle_tables = v; CHECK(trial(t)); }
@@ -1202,7 +1202,7 @@ static void plan_fft(BatchPlan &bp, mrinv_handle_t h, int mode, const FftPlan &p
     const bool dbl = sizeof(T) == 8;
     // Group by lanes per workgroup: the handle's choice (at most 16 here), 2
     // for problems of at most 2 lanes.
-    const int lanes = std::min(16, lanes_of<T>(h));
+    const int lanes = lanes_of<T>(h) == 0 ? 16 : std::min(16, lanes_of<T>(h));
     for (int C : {2, 8, 16}) {
         std::vector<PassProblem<T>> g;
         for (auto &q : probs)

@@ -621,10 +621,14 @@ static int fewer_lanes_when_small(int C, int64_t cols, int nl_a, int nl_b) {
     return C;
 }
 
-int fft_lanes_per_block(bool dbl, int nl) {
+// Automatic lanes per workgroup (tuning value 0): 32 lanes (256 contiguous
+// bytes of a float64 row, 128 of a float32 one) where the 32-lane tile stays
+// small enough for two workgroups per CU (float64 passes of at most 128 rows,
+// float32 passes of at most 256) and there are at least 512 lanes (d >= 32);
+// 16 otherwise.
+int fft_lanes_per_block(bool dbl, int nl, int lgP) {
     if (nl <= 2) return 2;
-    if (dbl) return 8;
-    return nl <= 8 ? 8 : 16;
+    return nl >= 512 && lgP <= (dbl ? 7 : 8) ? 32 : 16;
 }
 
 template <typename T>
@@ -639,7 +643,7 @@ hipError_t fft_pass(int mode, const FftPlan &plan, int pass, int nl, cplx<T> *z,
     g.S = (int64_t)1 << (lgB - plan.lgP[pass]);
     g.nl = nl;
     const int lgP = plan.lgP[pass];
-    int C = nl <= 2 ? 2 : (lanes ? lanes : fft_lanes_per_block(sizeof(T) == 8, nl));
+    int C = nl <= 2 ? 2 : (lanes ? lanes : fft_lanes_per_block(sizeof(T) == 8, nl, lgP));
     if (C == 32 && (lgP > 8 || nl <= 16)) C = 16;
     C = fewer_lanes_when_small(C, g.L >> lgP, nl, 0);
     g.nchunks = (nl + C - 1) / C;
@@ -810,7 +814,7 @@ hipError_t fft_pass_pair(const FftPlan &plan, int pass, PassProblem<T> a, PassPr
     PassGeom g = pass_geom(plan, pass);
     g.col_fastest = order;
     const int nlmin = a.nl < b.nl ? a.nl : b.nl;
-    int C = nlmin <= 2 ? 2 : (lanes ? lanes : fft_lanes_per_block(sizeof(T) == 8, a.nl > b.nl ? a.nl : b.nl));
+    int C = nlmin <= 2 ? 2 : (lanes ? lanes : fft_lanes_per_block(sizeof(T) == 8, nlmin, plan.lgP[pass]));
     if (C == 32 && (plan.lgP[pass] > 8 || nlmin <= 16)) C = 16;
     const int64_t cols = g.L >> plan.lgP[pass];
     C = fewer_lanes_when_small(C, cols, a.nl, b.nl);

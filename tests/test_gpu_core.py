@@ -454,23 +454,24 @@ def test_matrix_core_products_match_oracle(mr, orc, d):
     assert _maxerr(got[0, "fp64"], got[2, "fp64"]) <= 1e-13
 
 
-@pytest.mark.parametrize("d,n", [(16, 8192), (33, 2048), (4, 40000)])
+@pytest.mark.parametrize("d,n", [(16, 8192), (33, 2048), (64, 1500), (4, 40000)])
 def test_lanes_per_workgroup_do_not_change_the_bits(mr, d, n):
     """The transform passes compute the same bits whatever their lanes per
-    workgroup (8, 16 or 32; 16 takes the half-lane LDS tile for 256- and
-    512-row FP64 passes), so every lane setting gives one result."""
+    workgroup (8, 16 or 32, or the automatic choice 0; 16 takes the half-lane
+    LDS tile for 256- and 512-row FP64 passes), so every lane setting gives
+    one result."""
     q = _gpu(si.family_kernel("weibull", d, n, 60 + d).q)
     base = mr.get_tuning()
     outs = {}
     try:
-        for lanes in (8, 16, 32):
+        for lanes in (0, 8, 16, 32):
             mr.set_tuning(lanes_fp64=lanes, lanes_fp32=lanes)
             for prec in ("fp64", "mixed"):
                 outs[lanes, prec] = _np(mr.psi_inverse(q, prec, check=True))
     finally:
         mr.set_tuning(**base)
     for prec in ("fp64", "mixed"):
-        for lanes in (8, 32):
+        for lanes in (0, 8, 32):
             assert np.array_equal(outs[lanes, prec], outs[16, prec]), (lanes, prec)
 
 
