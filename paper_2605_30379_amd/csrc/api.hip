@@ -251,12 +251,19 @@ static size_t ws_twiddles(int lgN, int lg2, mrinv_precision_t prec) {
     return align256(3 * L * 8) + align256(2 * ((size_t)1 << lg2) * 16) + align256(2 * ((size_t)1 << lg2) * 8) + 4096;
 }
 
+// Spectra of one problem's residual sweeps at length 2^lg: A, X and the
+// products in float64 (slots 0-2), then X's spectrum in float32 (slot 3).
+// The float32 spectra of R and of the correction reuse slots 1-2 once the
+// float64 residual is formed.
+static size_t sweep_bytes(int lg, int64_t d2) { return 3 * spec_bytes(lg, d2, true) + spec_bytes(lg, d2, false); }
+
 static size_t ws_psi(int d, int64_t n, mrinv_precision_t prec) {
     const int64_t d2 = (int64_t)d * d;
     const int lgN = std::max(1, ceil_log2(n));
     const int lg2 = lg_full(n);
     if (prec == MRINV_FP64) return 3 * spec_bytes(lgN, d2, true) + ws_twiddles(lgN, lg2, prec);
-    size_t spec = std::max(3 * spec_bytes(lgN, d2, false), 3 * spec_bytes(lg2, d2, true));
+    // Sweeps: three float64 spectra at 2^lg2 plus the float32 copy of X's spectrum.
+    size_t spec = std::max(3 * spec_bytes(lgN, d2, false), sweep_bytes(lg2, d2));
     return spec + 2 * align256((size_t)n * d2 * sizeof(float)) + ws_twiddles(lgN, lg2, prec);
 }
 
@@ -360,14 +367,23 @@ template <typename T> static int lanes_of(mrinv_handle_t h) {
 }
 static FftPlan hplan(mrinv_handle_t h, int lgL) { return make_plan(lgL, tune_of(h).lgp_max); }
 
+// Destination of forward pass j: in place, and for the last pass of a float64
+// transform optionally also a float32 copy of the spectrum at aux32.
+static DstDesc fwd_dst(const FftPlan &p, int j, const void *aux32) {
+    DstDesc d = dst_z();
+    if (j == p.npass - 1) d.aux = aux32;
+    return d;
+}
+
 // Forward transform of a real source into Z (all passes).
 template <typename T>
-static hipError_t fwd(mrinv_handle_t h, const FftPlan &p, int nl, cplx<T> *Z, const SrcDesc &src) {
+static hipError_t fwd(mrinv_handle_t h, const FftPlan &p, int nl, cplx<T> *Z, const SrcDesc &src,
+                      const void *aux32 = nullptr) {
     const Twiddles<T> tw = tw_of<T>(h);
     const int ln = lanes_of<T>(h);
-    hipError_t e = fft_pass<T>(0, p, 0, nl, Z, src, dst_z(), tw, h->stream, ln, order_of(h));
+    hipError_t e = fft_pass<T>(0, p, 0, nl, Z, src, fwd_dst(p, 0, aux32), tw, h->stream, ln, order_of(h));
     for (int j = 1; j < p.npass && e == hipSuccess; ++j)
-        e = fft_pass<T>(0, p, j, nl, Z, src_z(), dst_z(), tw, h->stream, ln, order_of(h));
+        e = fft_pass<T>(0, p, j, nl, Z, src_z(), fwd_dst(p, j, aux32), tw, h->stream, ln, order_of(h));
     return e;
 }
 
@@ -375,20 +391,22 @@ static hipError_t fwd(mrinv_handle_t h, const FftPlan &p, int nl, cplx<T> *Z, co
 // pair_forward each pass of both is one launch.
 template <typename T>
 static hipError_t fwd2(mrinv_handle_t h, const FftPlan &p, int nl, cplx<T> *ZA, const SrcDesc &sa, cplx<T> *ZB,
-                       const SrcDesc &sb) {
+                       const SrcDesc &sb, const void *aux32_b = nullptr) {
     if (!h->tune.pair_forward) {
         hipError_t e = fwd<T>(h, p, nl, ZA, sa);
-        return e == hipSuccess ? fwd<T>(h, p, nl, ZB, sb) : e;
+        return e == hipSuccess ? fwd<T>(h, p, nl, ZB, sb, aux32_b) : e;
     }
     const Twiddles<T> tw = tw_of<T>(h);
     PassProblem<T> a{}, b{};
     a.z = ZA; a.nl = nl; a.src = sa; a.dst = dst_z();
-    b.z = ZB; b.nl = nl; b.src = sb; b.dst = dst_z();
+    b.z = ZB; b.nl = nl; b.src = sb; b.dst = fwd_dst(p, 0, aux32_b);
     hipError_t e = fft_pass_pair<T>(p, 0, a, b, tw, h->stream, lanes_of<T>(h), order_of(h));
     a.src = src_z();
     b.src = src_z();
-    for (int j = 1; j < p.npass && e == hipSuccess; ++j)
+    for (int j = 1; j < p.npass && e == hipSuccess; ++j) {
+        b.dst = fwd_dst(p, j, aux32_b);
         e = fft_pass_pair<T>(p, j, a, b, tw, h->stream, lanes_of<T>(h), order_of(h));
+    }
     return e;
 }
 
@@ -638,39 +656,36 @@ static mrinv_status_t inverse_impl(mrinv_handle_t h, const double *src, int e0, 
     }
     const double invL = 1.0 / (double)((int64_t)1 << p2.lgL);
     const GemmDesc g = gdesc(h, d, d, d);
-    // The float64 spectrum of A is formed once and kept for every sweep when
-    // the float32 spectra fit behind it (always but for tiny sizes).
+    // Slots (sweep_bytes): A's float64 spectrum, formed once and kept for
+    // every sweep; X's float64 spectrum, whose last forward pass also writes
+    // the float32 copy into slot 3 for the correction product; the float64
+    // product.  The float32 spectra of R and of the correction take slots 1-2
+    // once R is formed.
     const size_t s64 = spec_bytes(p2.lgL, d2, true), s32 = spec_bytes(p2.lgL, d2, false);
-    const bool keepA = s64 + 3 * s32 <= 3 * s64;
+    auto *SA = (cplx<double> *)spec;
+    auto *SB = (cplx<double> *)(spec + s64);
+    auto *ST = (cplx<double> *)(spec + 2 * s64);
+    auto *X32 = (cplx<float> *)(spec + 3 * s64);
+    auto *R32 = (cplx<float> *)(spec + s64);
+    auto *T32 = (cplx<float> *)(spec + s64 + s32);
     for (int sweep = 0; sweep < MIXED_SWEEPS; ++sweep) {
         const bool last = sweep == MIXED_SWEEPS - 1;
-        {
-            // R = e0 - A*X on [0, n) in float64 (full product, no wrap-around at L >= 2n-1).
-            auto *SA = (cplx<double> *)spec;
-            auto *SB = (cplx<double> *)(spec + s64);
-            auto *ST = (cplx<double> *)(spec + 2 * s64);
-            const SrcDesc sa = src_real(src, true, d2, d2, 0, n, -1, e0 ? d : 0), sx = src_real(X, false, d2, d2, 0, n);
-            if (sweep == 0 || !keepA) HIP_TRY(fwd2<double>(h, p2, nl, SA, sa, SB, sx));
-            else HIP_TRY(fwd<double>(h, p2, nl, SB, sx));
-            HIP_TRY(freq_gemm<double>(p2, g, SA, SB, ST, h->stream));
-            DstDesc dr = dst_real(R, false, d2, d2, 0, n, invL, OP_E0MINUS);
-            dr.e0_d = d;
-            HIP_TRY(inv<double>(h, p2, nl, ST, dr));
-        }
-        {
-            // X <- X + X*R, the correction product in float32; the last sweep
-            // writes the float64 result, earlier ones update X in place.
-            char *f32 = keepA ? spec + s64 : spec;
-            auto *SA = (cplx<float> *)f32;
-            auto *SB = (cplx<float> *)(f32 + s32);
-            auto *ST = (cplx<float> *)(f32 + 2 * s32);
-            HIP_TRY(fwd2<float>(h, p2f, nl, SA, src_real(X, false, d2, d2, 0, n), SB, src_real(R, false, d2, d2, 0, n)));
-            HIP_TRY(freq_gemm<float>(p2f, g, SA, SB, ST, h->stream));
-            DstDesc dx = last ? dst_real(out, true, d2, d2, 0, n, invL, OP_XPLUS, -1, h->status)
-                              : dst_real(X, false, d2, d2, 0, n, invL, OP_XPLUS);
-            dx.aux = X;
-            HIP_TRY(inv<float>(h, p2f, nl, ST, dx));
-        }
+        // R = e0 - A*X on [0, n) in float64 (full product, no wrap-around at L >= 2n-1).
+        const SrcDesc sa = src_real(src, true, d2, d2, 0, n, -1, e0 ? d : 0), sx = src_real(X, false, d2, d2, 0, n);
+        if (sweep == 0) HIP_TRY(fwd2<double>(h, p2, nl, SA, sa, SB, sx, X32));
+        else HIP_TRY(fwd<double>(h, p2, nl, SB, sx, X32));
+        HIP_TRY(freq_gemm<double>(p2, g, SA, SB, ST, h->stream));
+        DstDesc dr = dst_real(R, false, d2, d2, 0, n, invL, OP_E0MINUS);
+        dr.e0_d = d;
+        HIP_TRY(inv<double>(h, p2, nl, ST, dr));
+        // X <- X + X*R, the correction product in float32; the last sweep
+        // writes the float64 result, earlier ones update X in place.
+        HIP_TRY(fwd<float>(h, p2f, nl, R32, src_real(R, false, d2, d2, 0, n)));
+        HIP_TRY(freq_gemm<float>(p2f, g, X32, R32, T32, h->stream));
+        DstDesc dx = last ? dst_real(out, true, d2, d2, 0, n, invL, OP_XPLUS, -1, h->status)
+                          : dst_real(X, false, d2, d2, 0, n, invL, OP_XPLUS);
+        dx.aux = X;
+        HIP_TRY(inv<float>(h, p2f, nl, T32, dx));
     }
     return MRINV_OK;
 }
@@ -1244,21 +1259,30 @@ static void plan_gemm(BatchPlan &bp, mrinv_handle_t h, const FftPlan &p, const s
     }
 }
 
-// Forward transform of a real source per problem into its spectrum.
+// Forward transform of a real source per problem into its spectrum.  aux32
+// (optional, float64 only): per problem, where the last pass also writes a
+// float32 copy of the spectrum.
 template <typename T>
 static void plan_fwd(BatchPlan &bp, mrinv_handle_t h, const FftPlan &p, const std::vector<cplx<T> *> &Z,
-                     const std::vector<int> &nl, const std::vector<SrcDesc> &src) {
+                     const std::vector<int> &nl, const std::vector<SrcDesc> &src,
+                     const std::vector<const void *> *aux32 = nullptr) {
     std::vector<PassProblem<T>> v(Z.size());
+    auto dsts = [&](int j) {
+        for (size_t i = 0; i < Z.size(); ++i) v[i].dst = fwd_dst(p, j, aux32 ? (*aux32)[i] : nullptr);
+    };
     for (size_t i = 0; i < Z.size(); ++i) {
         v[i] = PassProblem<T>{};
         v[i].z = Z[i];
         v[i].nl = nl[i];
         v[i].src = src[i];
-        v[i].dst = dst_z();
     }
+    dsts(0);
     plan_fft<T>(bp, h, 0, p, 0, v);
     for (auto &x : v) x.src = src_z();
-    for (int j = 1; j < p.npass; ++j) plan_fft<T>(bp, h, 0, p, j, v);
+    for (int j = 1; j < p.npass; ++j) {
+        dsts(j);
+        plan_fft<T>(bp, h, 0, p, j, v);
+    }
 }
 
 template <typename T>
@@ -1468,15 +1492,16 @@ static void plan_sweeps(BatchPlan &bp, mrinv_handle_t h, std::vector<BatchProble
         for (int i = 0; i < (int)P.size(); ++i)
             if (lgs[i] == lg) {
                 grp.push_back(i);
-                need.push_back(3 * spec_bytes(lg, (int64_t)P[i].d * P[i].d, true));
+                need.push_back(sweep_bytes(lg, (int64_t)P[i].d * P[i].d));
             }
         for (auto &sub : split_by_cap(grp, need)) {
             for (int sweep = 0; sweep < MIXED_SWEEPS; ++sweep) {
                 const bool last = sweep == MIXED_SWEEPS - 1;
-                std::vector<cplx<double> *> A64, B64, T64, A64r;
-                std::vector<cplx<float> *> A32, B32, T32;
-                std::vector<int> nl, nlr;
-                std::vector<SrcDesc> sq, sx, sr, sqr;
+                std::vector<cplx<double> *> A64, B64, T64;
+                std::vector<cplx<float> *> X32, R32, T32;
+                std::vector<const void *> X32c;
+                std::vector<int> nl;
+                std::vector<SrcDesc> sq, sx, sr;
                 std::vector<DstDesc> dr, dx;
                 std::vector<GemmProblem<double>> g64;
                 std::vector<GemmProblem<float>> g32;
@@ -1485,24 +1510,17 @@ static void plan_sweeps(BatchPlan &bp, mrinv_handle_t h, std::vector<BatchProble
                     const BatchProblem &b = P[i];
                     const int64_t d2 = (int64_t)b.d * b.d;
                     const size_t s64 = spec_bytes(lg, d2, true), s32 = spec_bytes(lg, d2, false);
-                    // As in the single-problem call: A's float64 spectrum is kept
-                    // across sweeps when the float32 spectra fit behind it.
-                    const bool keepA = s64 + 3 * s32 <= 3 * s64;
+                    // The slots of the single-problem call (sweep_bytes).
                     A64.push_back((cplx<double> *)(spec + used));
                     B64.push_back((cplx<double> *)(spec + used + s64));
                     T64.push_back((cplx<double> *)(spec + used + 2 * s64));
-                    char *f32 = spec + used + (keepA ? s64 : 0);
-                    A32.push_back((cplx<float> *)f32);
-                    B32.push_back((cplx<float> *)(f32 + s32));
-                    T32.push_back((cplx<float> *)(f32 + 2 * s32));
-                    used += 3 * s64;
+                    X32.push_back((cplx<float> *)(spec + used + 3 * s64));
+                    X32c.push_back(X32.back());
+                    R32.push_back((cplx<float> *)(spec + used + s64));
+                    T32.push_back((cplx<float> *)(spec + used + s64 + s32));
+                    used += sweep_bytes(lg, d2);
                     nl.push_back(nl_of(d2));
                     sq.push_back(src_real(b.q, true, d2, (int)d2, 0, b.n, -1, b.d));
-                    if (sweep == 0 || !keepA) {
-                        A64r.push_back(A64.back());
-                        nlr.push_back(nl.back());
-                        sqr.push_back(sq.back());
-                    }
                     sx.push_back(src_real(b.X, false, d2, (int)d2, 0, b.n));
                     sr.push_back(src_real(b.R, false, d2, (int)d2, 0, b.n));
                     DstDesc r = dst_real(b.R, false, d2, (int)d2, 0, b.n, invL, OP_E0MINUS);
@@ -1516,16 +1534,15 @@ static void plan_sweeps(BatchPlan &bp, mrinv_handle_t h, std::vector<BatchProble
                     u.A = A64.back(); u.B = B64.back(); u.C = T64.back(); u.d = b.d;
                     g64.push_back(u);
                     GemmProblem<float> w{};
-                    w.A = A32.back(); w.B = B32.back(); w.C = T32.back(); w.d = b.d;
+                    w.A = X32.back(); w.B = R32.back(); w.C = T32.back(); w.d = b.d;
                     g32.push_back(w);
                 }
                 spec_max = std::max(spec_max, used);
-                if (!A64r.empty()) plan_fwd<double>(bp, h, p, A64r, nlr, sqr);
-                plan_fwd<double>(bp, h, p, B64, nl, sx);
+                if (sweep == 0) plan_fwd<double>(bp, h, p, A64, nl, sq);
+                plan_fwd<double>(bp, h, p, B64, nl, sx, &X32c);
                 plan_gemm<double>(bp, h, p, g64);
                 plan_inv<double>(bp, h, p, T64, nl, dr);
-                plan_fwd<float>(bp, h, p, A32, nl, sx);
-                plan_fwd<float>(bp, h, p, B32, nl, sr);
+                plan_fwd<float>(bp, h, p, R32, nl, sr);
                 plan_gemm<float>(bp, h, p, g32);
                 plan_inv<float>(bp, h, p, T32, nl, dx);
             }

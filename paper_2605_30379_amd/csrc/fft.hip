@@ -273,6 +273,18 @@ __device__ __forceinline__ void fft_pass_body(cplx<T> *z, const PassGeom &g, int
             for (int r = 0; r < MR_RADIX(v); ++r) v[r] = cmul<T>(v[r], tws[b0 + (r << lgs)]);
         }
         z_store_all(b0, lgs, v);
+        if constexpr (MODE == 0 && sizeof(T) == 8) {
+            // Optional float32 copy of the float64 output, same layout.
+            if (dst.aux && lane_ok) {
+                float2 *qa = (float2 *)dst.aux + (zc - z) + (int64_t)b0 * rs;
+                const int64_t step = rs << lgs;
+#pragma unroll
+                for (int r = 0; r < MR_RADIX(v); ++r) {
+                    *qa = make_float2((float)v[r].x, (float)v[r].y);
+                    qa += step;
+                }
+            }
+        }
     };
     auto inv_load_all = [&](int j, int lgs, auto &v) {
         z_load_all(j, lgs, v);
@@ -535,6 +547,7 @@ static double pass_bytes(int mode, const PassGeom &g, const SrcDesc &src, const 
     double rd = zc, wr = zc;
     if (mode == 0 && src.kind != SRC_Z)
         rd = window_rows(g.L, src.lo, src.hi) * src.nreal * (src.kind == SRC_REAL64 ? 8.0 : 4.0);
+    if (mode == 0 && sizeof(T) == 8 && dst.kind == DST_Z && dst.aux) wr += (double)g.L * g.nl * 8.0;
     if (mode == 1 && dst.kind != DST_Z) {
         const double rows = window_rows(g.L, dst.lo, dst.hi);
         const double w = dst.kind == DST_REAL64 ? 8.0 : 4.0;

@@ -102,7 +102,8 @@ struct DstDesc {
     int64_t rev;
     int op;
     int e0_d;
-    const void *aux;       // OP_XPLUS: float32 array with the same layout, added to the result
+    const void *aux;       // OP_XPLUS: float32 array with the same layout, added to the result;
+                           // a float64 forward pass to DST_Z: float32 copy of its output
     double scale;
     unsigned int *status;  // optional: set STATUS_NONFINITE on non-finite output
 };
