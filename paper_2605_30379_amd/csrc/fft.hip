@@ -627,7 +627,7 @@ static hipError_t launch_pass_m(int lgP, int C, cplx<T> *z, const PassGeom &g, c
 
 // Small transforms (the first Newton steps) have too few workgroups to fill
 // the GPU; fewer lanes per workgroup give more, shorter workgroups.  Halves
-// C (16 -> 8 -> 2) while fewer than 512 workgroups would run.
+// C (32 -> 16 -> 8 -> 2) while fewer than 512 workgroups would run.
 static int fewer_lanes_when_small(int C, int64_t cols, int nl_a, int nl_b) {
     auto blocks = [&](int c) { return cols * ((nl_a + c - 1) / c + (nl_b + c - 1) / c); };
     while (C > 2 && blocks(C) < 512) C = C == 32 ? 16 : C == 16 ? 8 : 2;
