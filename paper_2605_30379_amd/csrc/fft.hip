@@ -113,19 +113,21 @@ __device__ __forceinline__ void flag_nonfinite(unsigned int *status, double a, d
 }
 
 // LDS layout of a pass workgroup.  The data tile holds P rows of C lanes
-// (stride C + 1), or, for 512-row FP64 passes, P rows of C/2 lanes that the
-// two lane halves use in turn (stride C/2): 80 KB instead of 155 KB, so two
-// 1024-thread workgroups share a CU (their kernels are compiled for 8 waves
-// per SIMD, i.e. at most 64 VGPRs).  P outer twiddles and P stage roots follow
-// the tile.
+// (stride C + 1), or, for the float64 passes of 256 rows (16 lanes) and 512
+// rows (8 or 16 lanes), P rows of C/2 lanes that the two lane halves use in
+// turn (stride C/2).  512 rows, 16 lanes: 80 KB instead of 155 KB, two
+// 1024-thread workgroups per CU, compiled for 8 waves per SIMD (64 VGPRs);
+// 512 rows, 8 lanes: 48 KB, three 512-thread workgroups, 6 waves (80 VGPRs);
+// 256 rows, 16 lanes: 40 KB, four 256-thread workgroups, 4 waves (128 VGPRs).
+// P outer twiddles and P stage roots follow the tile.
 template <typename T, int LGP, int C, int MODE>
 __host__ __device__ constexpr int pass_split() {
-    return (sizeof(T) == 8 && (LGP == 9 || LGP == 8) && C == 16) ? 2 : 1;
+    return (sizeof(T) == 8 && (((LGP == 9 || LGP == 8) && C == 16) || (LGP == 9 && C == 8))) ? 2 : 1;
 }
 // Waves per SIMD the pass kernels are compiled for (VGPR budget 512 / waves).
 template <typename T, int LGP, int C, int MODE>
 __host__ __device__ constexpr int pass_waves() {
-    return pass_split<T, LGP, C, MODE>() == 2 ? (LGP == 9 ? 8 : 4) : 1;
+    return pass_split<T, LGP, C, MODE>() == 2 ? (LGP == 9 ? (C == 8 ? 6 : 8) : 4) : 1;
 }
 template <typename T, int LGP, int C, int MODE>
 __host__ __device__ constexpr int pass_lds_stride() {
@@ -639,8 +641,12 @@ static int fewer_lanes_when_small(int C, int64_t cols, int nl_a, int nl_b) {
 // small enough for two workgroups per CU (float64 passes of at most 128 rows,
 // float32 passes of at most 256) and there are at least 512 lanes (d >= 32);
 // 16 otherwise.
-int fft_lanes_per_block(bool dbl, int nl, int lgP) {
+int fft_lanes_per_block(bool dbl, int nl, int lgP, int mode) {
     if (nl <= 2) return 2;
+    // The fused 512-row float64 pass (inverse, mask, forward) runs at 8 lanes:
+    // 512 threads and a 48 KB half-lane tile, three workgroups per CU with 80
+    // registers instead of two with 64 (no spills).
+    if (dbl && lgP == 9 && mode == 2) return 8;
     return nl >= 512 && lgP <= (dbl ? 7 : 8) ? 32 : 16;
 }
 
@@ -656,7 +662,7 @@ hipError_t fft_pass(int mode, const FftPlan &plan, int pass, int nl, cplx<T> *z,
     g.S = (int64_t)1 << (lgB - plan.lgP[pass]);
     g.nl = nl;
     const int lgP = plan.lgP[pass];
-    int C = nl <= 2 ? 2 : (lanes ? lanes : fft_lanes_per_block(sizeof(T) == 8, nl, lgP));
+    int C = nl <= 2 ? 2 : (lanes ? lanes : fft_lanes_per_block(sizeof(T) == 8, nl, lgP, mode));
     if (C == 32 && (lgP > 8 || nl <= 16)) C = 16;
     C = fewer_lanes_when_small(C, g.L >> lgP, nl, 0);
     g.nchunks = (nl + C - 1) / C;
@@ -827,7 +833,7 @@ hipError_t fft_pass_pair(const FftPlan &plan, int pass, PassProblem<T> a, PassPr
     PassGeom g = pass_geom(plan, pass);
     g.col_fastest = order;
     const int nlmin = a.nl < b.nl ? a.nl : b.nl;
-    int C = nlmin <= 2 ? 2 : (lanes ? lanes : fft_lanes_per_block(sizeof(T) == 8, nlmin, plan.lgP[pass]));
+    int C = nlmin <= 2 ? 2 : (lanes ? lanes : fft_lanes_per_block(sizeof(T) == 8, nlmin, plan.lgP[pass], 0));
     if (C == 32 && (plan.lgP[pass] > 8 || nlmin <= 16)) C = 16;
     const int64_t cols = g.L >> plan.lgP[pass];
     C = fewer_lanes_when_small(C, cols, a.nl, b.nl);

@@ -158,7 +158,7 @@ struct GjProblem {
 inline SrcDesc src_z() { SrcDesc s{}; s.kind = SRC_Z; s.rev = -1; return s; }
 inline DstDesc dst_z() { DstDesc d{}; d.kind = DST_Z; d.rev = -1; d.scale = 1.0; return d; }
 
-int fft_lanes_per_block(bool dbl, int nl, int lgP);
+int fft_lanes_per_block(bool dbl, int nl, int lgP, int mode);
 
 // mode 0 forward, 1 inverse, 2 inverse + mask + forward (same pass).
 // lanes: complex lanes per workgroup (8 or 16), 0 for the default;
