@@ -63,13 +63,28 @@ def model_bytes(d: int, n: int, w: int) -> float:
     return sum(14.0 * L * d * d * w for L in newton_lengths(n))
 
 
-def source_hash() -> str:
+CSRC = os.path.join(ROOT, "paper_2605_30379_amd", "csrc")
+
+
+def source_hash(files=None) -> str:
+    """Hash of the HIP sources (all of them, or the named files)."""
     h = hashlib.sha256()
-    csrc = os.path.join(ROOT, "paper_2605_30379_amd", "csrc")
-    for f in sorted(os.listdir(csrc)):
-        if f.endswith((".hip", ".h")):
-            h.update(open(os.path.join(csrc, f), "rb").read())
+    names = files if files is not None else [f for f in os.listdir(CSRC) if f.endswith((".hip", ".h"))]
+    for f in sorted(names):
+        h.update(open(os.path.join(CSRC, f), "rb").read())
     return h.hexdigest()[:16]
+
+
+def kernel_source_hash(kernel: str) -> str:
+    """Hash of what determines one kernel's memory traffic: the file that
+    defines it and the shared headers (host-side driver code is not part)."""
+    if kernel.startswith(("fft_pass", "gen_outer")):
+        f = "fft.hip"
+    elif kernel.startswith(("freq_", "conv_direct")):
+        f = "gemm.hip"
+    else:
+        f = "aux.hip"
+    return source_hash([f, "common.h", "kernels.h"])
 
 
 def kernel_stats(mr, torch, dev):
@@ -138,7 +153,7 @@ def roofline_of(stats, traffic_file=None):
     roof["traffic"] = None
     if traffic_file and os.path.exists(traffic_file):
         tr = json.load(open(traffic_file))
-        if tr.get("kernel") == top["name"] and tr.get("source_hash") == source_hash():
+        if tr.get("kernel") == top["name"] and tr.get("source_hash") == kernel_source_hash(top["name"]):
             roof["traffic"] = tr.get("bytes_per_launch")
     breakdown = []
     for s in stats[:12]:
@@ -168,7 +183,8 @@ def write_traffic(args, kernel: str, fetch_csv: str, write_csv: str) -> None:
     def short(name):
         return re.sub(r"\(.*", "", re.sub(r"^void mrinv::", "", name)).strip()
 
-    out = {"kernel": kernel, "source_hash": source_hash(), "config": args.config, "form": CONFIGS[args.config]["form"]}
+    out = {"kernel": kernel, "source_hash": kernel_source_hash(kernel), "config": args.config,
+           "form": CONFIGS[args.config]["form"]}
     for counter, path in (("FETCH_SIZE", fetch_csv), ("WRITE_SIZE", write_csv)):
         rr = rows(path, counter)
         cal = max(float(r["Counter_Value"]) for r in rr if "copyBuffer" in r["Kernel_Name"])

@@ -262,10 +262,11 @@ typedef struct {
 mrinv_status_t mrinv_get_tuning(mrinv_handle_t h, mrinv_tuning_t *out);
 mrinv_status_t mrinv_set_tuning(mrinv_handle_t h, const mrinv_tuning_t *t);
 
-/* Time mrinv_psi_inverse on q (device [n][d][d]) under a set of candidate
- * tunings (pass radix cap, lanes per workgroup, recursion seed length), keep
- * the fastest in the handle and report it in *chosen (may be NULL).  psi
- * receives the result; ws as for mrinv_psi_inverse.  Synchronises. */
+/* Time mrinv_psi_inverse on q (device [n][d][d]) under candidate tunings,
+ * one field of mrinv_tuning_t at a time starting from the handle's current
+ * tuning (a coordinate search), keep the fastest in the handle and report it
+ * in *chosen (may be NULL).  psi receives the result; ws as for
+ * mrinv_psi_inverse.  Synchronises. */
 mrinv_status_t mrinv_autotune(mrinv_handle_t h, const double *q, int d, int64_t n,
                               mrinv_precision_t precision, double *psi, void *ws, size_t ws_bytes,
                               mrinv_tuning_t *chosen);

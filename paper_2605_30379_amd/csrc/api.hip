@@ -822,7 +822,10 @@ extern "C" mrinv_status_t mrinv_autotune(mrinv_handle_t h, const double *q, int 
         h->tune = t;
         float ms = 0.f;
         mrinv_status_t st = time_inverse(h, q, d, n, precision, psi, ws, wsb, 3, &ms);
-        if (st != MRINV_OK) return st;
+        if (st != MRINV_OK) {
+            h->tune = best;   // a failed trial leaves the best tuning so far in the handle
+            return st;
+        }
         if (ms < best_ms) { best_ms = ms; best = t; }
         return MRINV_OK;
     };

@@ -537,6 +537,29 @@ def test_direct_steps_series_inverse_general_a0(mr, orc):
     assert _maxerr(got, ref) <= 1e-11 * max(1.0, np.max(np.abs(ref)))
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_autotune_keeps_a_valid_tuning(mr, orc, precision):
+    """The autotuner's choice is a valid tuning (it can be set again), stays
+    in the handle, and the inverse under it still matches the oracle."""
+    d, n = 12, 3000
+    q = si.family_kernel("weibull", d, n, 88).q
+    ref = orc.psi(q.numpy())
+    qg = _gpu(q)
+    base = mr.get_tuning()
+    try:
+        chosen = mr.autotune(qg, precision)
+        assert set(chosen) == set(base)
+        assert chosen == mr.get_tuning()
+        assert chosen["lanes_fp64"] in (0, 8, 16, 32) and chosen["lanes_fp32"] in (0, 8, 16, 32)
+        assert 5 <= chosen["lgp_max"] <= 9 and chosen["mfma"] in (0, 1, 2)
+        mr.set_tuning(**chosen)
+        got = _np(mr.psi_inverse(qg, precision, check=True))
+        tol = FP64_TOL if precision == "fp64" else MIXED_TOL
+        assert _maxerr(got, ref) <= tol
+    finally:
+        mr.set_tuning(**base)
+
+
 def test_kernel_timing_records_every_launch(mr):
     """Timed launches (events stamped by the kernels' own dispatch packets)
     change no result, and their summed execution times fit inside the wall
