@@ -1013,7 +1013,11 @@ hipError_t freq_gemm(const FftPlan &plan, const GemmDesc &g, const cplx<T> *ZA, 
         return gemm_sq_t<T, false, true>(plan, g.ra, ZA, ZB, ZC, st);
     }
     const int dmax = g.ra > g.cb ? g.ra : g.cb;
-    if (dmax <= 8) return launch_gemm<T, 1, 1>(plan, g, ZA, ZB, ZC, st);
+    // Thin products (a matrix times a vector, and its adjoints) take 1 x 1
+    // register tiles: with wider tiles a frequency has too few of them, and
+    // the A operand's LDS share caps the frequencies per workgroup, so most
+    // threads would idle.
+    if (dmax <= 8 || g.ra <= 2 || g.cb <= 2) return launch_gemm<T, 1, 1>(plan, g, ZA, ZB, ZC, st);
     if (dmax <= 24) return launch_gemm<T, 2, 2>(plan, g, ZA, ZB, ZC, st);
     return launch_gemm<T, 4, 4>(plan, g, ZA, ZB, ZC, st);
 }
