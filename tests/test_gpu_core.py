@@ -96,6 +96,29 @@ def test_psi_three_pass_geometric_closed_form(mr, orc):
     assert _maxerr(_np(got[torch.as_tensor(ks).cuda()]), ref) <= fp64_tol(n)
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_maximum_horizon_geometric_closed_form(mr, orc, precision):
+    """The largest supported horizon, n = 2^21 (three-pass transforms up to
+    L = 2^21, mixed sweeps at 2^22): Markov closed form at sampled k,
+    including the last coefficient."""
+    n, d = 1 << 21, 2   # MRINV_MAX_N
+    k = si.geometric_kernel(d, n, 41)
+    print(f"[max-horizon] d={d} n={n} {precision}", flush=True)
+    got = mr.psi_inverse(k.q.cuda(), precision, check=True)
+    ks = np.array([0, 1, 2, 5, 1000, 65537, 1 << 20, n - 2, n - 1])
+    ref = orc.geometric_psi(k.params["M"], k.params["a"], ks)
+    tol = fp64_tol(2 * n) if precision == "fp64" else MIXED_TOL
+    assert _maxerr(_np(got[torch.as_tensor(ks).cuda()]), ref) <= tol
+
+
+def test_empty_and_oversized_horizons_are_rejected(mr):
+    with pytest.raises((mr.MrinvError, ValueError)):
+        mr.psi_inverse(torch.zeros((0, 3, 3), dtype=torch.float64).cuda())
+    with pytest.raises(mr.MrinvError):
+        mr.psi_inverse(torch.zeros(((1 << 21) + 1, 1, 1), dtype=torch.float64).cuda())
+    mr.sync_status()
+
+
 def test_prefix_exactness_and_causality(mr):
     """Proposition 2.3 on the GPU: the first n' coefficients do not depend on
     q(k >= n') and equal the horizon-n' inverse (within rounding)."""
