@@ -707,25 +707,58 @@ __device__ __forceinline__ void conv_direct_body(const ConvDesc &c, int64_t blk)
     const int ia = I * 16 + (l & 15);         // row of the L operand
     const int cb = J * 16 + (l & 15);         // column of the R operand
     const int tq = l >> 4;
+    // Lane quarter tq holds the contraction indices t = tq KQ + tb (tb < KQ):
+    // a contiguous piece of row ia of L, read with 16-byte loads when the
+    // tiles cover the matrix exactly (d == DP: aligned, no padding).
+    constexpr int KQ = DP / 4;
+    const bool vecA = d == DP;
     const TL *Lp = (const TL *)c.L;
     const T *Rp = (const T *)c.R;
     const T sg = (T)c.sign;
     V acc;
 #pragma unroll
     for (int r = 0; r < 4; ++r) acc[r] = (T)0;
+    auto load_l = [&](const TL *Lrow, bool ok, T (&a)[KQ]) {
+        if (vecA) {
+            if constexpr (sizeof(TL) == 8) {
+#pragma unroll
+                for (int u = 0; u < KQ / 2; ++u) {
+                    const double2 v = ok ? reinterpret_cast<const double2 *>(Lrow)[u] : make_double2(0.0, 0.0);
+                    a[2 * u] = (T)v.x;
+                    a[2 * u + 1] = (T)v.y;
+                }
+            } else {
+#pragma unroll
+                for (int u = 0; u < KQ / 4; ++u) {
+                    const float4 v = ok ? reinterpret_cast<const float4 *>(Lrow)[u] : make_float4(0.f, 0.f, 0.f, 0.f);
+                    a[4 * u] = (T)v.x;
+                    a[4 * u + 1] = (T)v.y;
+                    a[4 * u + 2] = (T)v.z;
+                    a[4 * u + 3] = (T)v.w;
+                }
+            }
+        } else {
+#pragma unroll
+            for (int tb = 0; tb < KQ; ++tb) {
+                const int t = tq * KQ + tb;
+                a[tb] = (ok && ia < d && t < d) ? (T)Lrow[tb] : (T)0;
+            }
+        }
+    };
     // Two values of j per iteration keep twice the loads in flight.
     for (int64_t j = c.jlo + w; j <= jhi; j += 2 * CONV_WAVES) {
         const bool two = j + CONV_WAVES <= jhi;
-        T a0[DP / 4], b0[DP / 4], a1[DP / 4], b1[DP / 4];
-        const TL *L0 = Lp + (k - j) * dd, *L1 = Lp + (k - j - CONV_WAVES) * dd;
+        T a0[KQ], b0[KQ], a1[KQ], b1[KQ];
+        const int64_t lrow = (int64_t)ia * d + tq * KQ;
+        const TL *L0 = Lp + (k - j) * dd + lrow, *L1 = Lp + (k - j - CONV_WAVES) * dd + lrow;
         const T *R0 = Rp + (j - c.r_off) * dd, *R1 = Rp + (j + CONV_WAVES - c.r_off) * dd;
+        load_l(L0, true, a0);
+        load_l(L1, two, a1);
 #pragma unroll
-        for (int tb = 0; tb < DP / 4; ++tb) {
-            const int t = 4 * tb + tq;
-            const bool okA = ia < d && t < d, okB = t < d && cb < d;
-            a0[tb] = okA ? (T)L0[ia * d + t] : (T)0;
+        for (int tb = 0; tb < KQ; ++tb) {
+            const int t = tq * KQ + tb;
+            const bool okB = t < d && cb < d;
             b0[tb] = okB ? R0[t * d + cb] : (T)0;
-            a1[tb] = (two && okA) ? (T)L1[ia * d + t] : (T)0;
             b1[tb] = (two && okB) ? R1[t * d + cb] : (T)0;
         }
 #pragma unroll
