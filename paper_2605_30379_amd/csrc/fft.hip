@@ -128,6 +128,7 @@ __host__ __device__ constexpr int pass_split() {
 template <typename T, int LGP, int C, int MODE>
 __host__ __device__ constexpr int pass_waves() {
     if (sizeof(T) == 4 && LGP == 9 && C == 16) return 8;   // two 1024-thread workgroups per CU
+    if (sizeof(T) == 4 && LGP == 7 && C >= 16) return 8;   // as many workgroups as the LDS allows
     return pass_split<T, LGP, C, MODE>() == 2 ? (LGP == 9 ? (C == 8 ? 6 : 8) : 4) : 1;
 }
 template <typename T, int LGP, int C, int MODE>
