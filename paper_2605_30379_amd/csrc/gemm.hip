@@ -707,9 +707,11 @@ __device__ __forceinline__ void conv_direct_body(const ConvDesc &c, int64_t blk)
     const int ia = I * 16 + (l & 15);         // row of the L operand
     const int cb = J * 16 + (l & 15);         // column of the R operand
     const int tq = l >> 4;
-    // Lane quarter tq holds the contraction indices t = tq KQ + tb (tb < KQ):
-    // a contiguous piece of row ia of L, read with 16-byte loads when the
-    // tiles cover the matrix exactly (d == DP: aligned, no padding).
+    // When the tiles cover the matrix exactly (d == DP: aligned rows, no
+    // padding), lane quarter tq holds the contraction indices t = tq KQ + tb
+    // (tb < KQ), a contiguous piece of row ia of L read with 16-byte loads;
+    // otherwise t = 4 tb + tq with masked scalar loads.  Both operands use the
+    // same assignment, so each MFMA contracts matching indices.
     constexpr int KQ = DP / 4;
     const bool vecA = d == DP;
     const TL *Lp = (const TL *)c.L;
@@ -718,8 +720,10 @@ __device__ __forceinline__ void conv_direct_body(const ConvDesc &c, int64_t blk)
     V acc;
 #pragma unroll
     for (int r = 0; r < 4; ++r) acc[r] = (T)0;
-    auto load_l = [&](const TL *Lrow, bool ok, T (&a)[KQ]) {
+    auto tix = [&](int tb) { return vecA ? tq * KQ + tb : 4 * tb + tq; };
+    auto load_l = [&](const TL *Lmat, bool ok, T (&a)[KQ]) {
         if (vecA) {
+            const TL *Lrow = Lmat + (int64_t)ia * d + tq * KQ;
             if constexpr (sizeof(TL) == 8) {
 #pragma unroll
                 for (int u = 0; u < KQ / 2; ++u) {
@@ -740,8 +744,8 @@ __device__ __forceinline__ void conv_direct_body(const ConvDesc &c, int64_t blk)
         } else {
 #pragma unroll
             for (int tb = 0; tb < KQ; ++tb) {
-                const int t = tq * KQ + tb;
-                a[tb] = (ok && ia < d && t < d) ? (T)Lrow[tb] : (T)0;
+                const int t = 4 * tb + tq;
+                a[tb] = (ok && ia < d && t < d) ? (T)Lmat[ia * d + t] : (T)0;
             }
         }
     };
@@ -749,14 +753,13 @@ __device__ __forceinline__ void conv_direct_body(const ConvDesc &c, int64_t blk)
     for (int64_t j = c.jlo + w; j <= jhi; j += 2 * CONV_WAVES) {
         const bool two = j + CONV_WAVES <= jhi;
         T a0[KQ], b0[KQ], a1[KQ], b1[KQ];
-        const int64_t lrow = (int64_t)ia * d + tq * KQ;
-        const TL *L0 = Lp + (k - j) * dd + lrow, *L1 = Lp + (k - j - CONV_WAVES) * dd + lrow;
+        const TL *L0 = Lp + (k - j) * dd, *L1 = Lp + (k - j - CONV_WAVES) * dd;
         const T *R0 = Rp + (j - c.r_off) * dd, *R1 = Rp + (j + CONV_WAVES - c.r_off) * dd;
         load_l(L0, true, a0);
         load_l(L1, two, a1);
 #pragma unroll
         for (int tb = 0; tb < KQ; ++tb) {
-            const int t = tq * KQ + tb;
+            const int t = tix(tb);
             const bool okB = t < d && cb < d;
             b0[tb] = okB ? R0[t * d + cb] : (T)0;
             b1[tb] = (two && okB) ? R1[t * d + cb] : (T)0;
