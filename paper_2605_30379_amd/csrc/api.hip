@@ -99,26 +99,35 @@ extern "C" mrinv_status_t mrinv_create(mrinv_handle_t *handle, void *stream) {
     auto *h = new (std::nothrow) mrinv_handle_s();
     if (!h) return fail(MRINV_E_ARG, "out of host memory");
     h->stream = (hipStream_t)stream;
-    HIP_TRY(hipGetDevice(&h->device));
-    std::vector<double2> hi, lo;
-    host_twiddles(hi, lo);
-    const size_t n64 = (TW_HI_SIZE + TW_LO_SIZE + 512) * sizeof(double2);
-    // 512th roots W_512^j = W_{2^22}^{j 2^13} = hi[4j] (the lo factor is 1).
-    std::vector<double2> root(512);
-    for (int j = 0; j < 512; ++j) root[j] = hi[4 * j];
-    if (hipMalloc((void **)&h->tw64, n64) != hipSuccess ||
-        hipMalloc((void **)&h->status, 256) != hipSuccess ||
-        hipMalloc((void **)&h->scratch, SCRATCH_BYTES) != hipSuccess) {
+    // Any failure below releases what was made so far.
+    auto init = [&]() -> mrinv_status_t {
+        HIP_TRY(hipGetDevice(&h->device));
+        std::vector<double2> hi, lo;
+        host_twiddles(hi, lo);
+        const size_t n64 = (TW_HI_SIZE + TW_LO_SIZE + 512) * sizeof(double2);
+        // 512th roots W_512^j = W_{2^22}^{j 2^13} = hi[4j] (the lo factor is 1).
+        std::vector<double2> root(512);
+        for (int j = 0; j < 512; ++j) root[j] = hi[4 * j];
+        HIP_TRY(hipMalloc((void **)&h->tw64, n64));
+        HIP_TRY(hipMalloc((void **)&h->status, 256));
+        HIP_TRY(hipMalloc((void **)&h->scratch, SCRATCH_BYTES));
+        HIP_TRY(hipMemcpy(h->tw64, hi.data(), TW_HI_SIZE * sizeof(double2), hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(h->tw64 + TW_HI_SIZE, lo.data(), TW_LO_SIZE * sizeof(double2), hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(h->tw64 + TW_HI_SIZE + TW_LO_SIZE, root.data(), 512 * sizeof(double2),
+                          hipMemcpyHostToDevice));
+        HIP_TRY(hipMemset(h->status, 0, 256));
+        HIP_TRY(hipEventCreateWithFlags(&h->pinned_done, hipEventDisableTiming));
+        HIP_TRY(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
+        HIP_TRY(hipDeviceSynchronize());
+        return MRINV_OK;
+    };
+    const mrinv_status_t st = init();
+    if (st != MRINV_OK) {
+        const std::string msg = g_last_error;
         mrinv_destroy(h);
-        return fail(MRINV_E_HIP, "device allocation failed in mrinv_create");
+        g_last_error = msg;
+        return st;
     }
-    HIP_TRY(hipMemcpy(h->tw64, hi.data(), TW_HI_SIZE * sizeof(double2), hipMemcpyHostToDevice));
-    HIP_TRY(hipMemcpy(h->tw64 + TW_HI_SIZE, lo.data(), TW_LO_SIZE * sizeof(double2), hipMemcpyHostToDevice));
-    HIP_TRY(hipMemcpy(h->tw64 + TW_HI_SIZE + TW_LO_SIZE, root.data(), 512 * sizeof(double2), hipMemcpyHostToDevice));
-    HIP_TRY(hipMemset(h->status, 0, 256));
-    HIP_TRY(hipEventCreateWithFlags(&h->pinned_done, hipEventDisableTiming));
-    HIP_TRY(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
-    HIP_TRY(hipDeviceSynchronize());
     *handle = h;
     g_last_error.clear();
     return MRINV_OK;
