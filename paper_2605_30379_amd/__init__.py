@@ -233,7 +233,9 @@ def psi_inverse(q: torch.Tensor, precision="fp64", check: bool = False) -> torch
 def series_inverse(A: torch.Tensor, precision="fp64", check: bool = False) -> torch.Tensor:
     """A^(-1) on the horizon for a general sequence with A(0) nonsingular (Theorem 2.1)."""
     A = _seq(A, "A")
-    n, d, _ = A.shape
+    n, d, d2 = A.shape
+    if d != d2:
+        raise MrinvError(1, "A must be square")
     prec = _PREC[precision]
     out = torch.empty_like(A)
     ws = _ws(lib().mrinv_workspace_size(0, d, n, 0, prec), A.device)
