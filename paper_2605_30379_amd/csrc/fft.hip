@@ -237,8 +237,10 @@ __device__ __forceinline__ void fft_pass_body(cplx<T> *z, const PassGeom &g, int
     // Forward twiddle on output r: W_B^{m r}; inverse on input r: W_B^{-m r}.
     // They depend on the column only, so the workgroup forms its P outer
     // twiddles (from the pass's table when there is one) and the P roots of
-    // its in-workgroup stages once; every lane reads them from LDS.
-    {
+    // its in-workgroup stages once; every lane reads them from LDS.  Each
+    // thread issues its first stage's data loads before filling the tables,
+    // so the two memory latencies overlap.
+    auto fill_tables = [&]() {
         const cplx<T> *otw = reinterpret_cast<const cplx<T> *>(tw.outer) + ((size_t)m << LGP);
         for (int i = threadIdx.x; i < P; i += blockDim.x) {
             if (m) tws[i] = tw.outer ? otw[i] : twiddle<T, false>(tw, m * (uint32_t)i, g.lgB);
@@ -249,8 +251,10 @@ __device__ __forceinline__ void fft_pass_body(cplx<T> *z, const PassGeom &g, int
                 roots[i] = twiddle<T, false>(tw, (uint32_t)i, LGP);
             }
         }
-    }
-    __syncthreads();
+    };
+    constexpr int LG0 = stage_lg(LGP, 0);              // first stage: radix 2^LG0
+    const bool first_active = grp < (P >> LG0);
+    cplx<T> pre[1 << LG0];                              // its elements, loaded early
 
     auto z_load_all = [&](int j, int lgs, auto &v) {
         const cplx<T> *q = zc + (int64_t)j * rs;
@@ -290,12 +294,25 @@ __device__ __forceinline__ void fft_pass_body(cplx<T> *z, const PassGeom &g, int
             }
         }
     };
-    auto inv_load_all = [&](int j, int lgs, auto &v) {
-        z_load_all(j, lgs, v);
+    // First-stage loads from the early copy (the forward stage has no input
+    // twiddle; the inverse one multiplies by the conjugate outer twiddles).
+    auto pre_load = [&](int, int, auto &v) {
+#pragma unroll
+        for (int r = 0; r < MR_RADIX(v); ++r) v[r] = pre[r];
+    };
+    auto pre_inv_load = [&](int j, int lgs, auto &v) {
+#pragma unroll
+        for (int r = 0; r < MR_RADIX(v); ++r) v[r] = pre[r];
         if (m) {
 #pragma unroll
             for (int r = 0; r < MR_RADIX(v); ++r) v[r] = cmulc<T>(v[r], tws[j + (r << lgs)]);
         }
+    };
+    // Inverse first stages: raw early loads, then the tables.
+    auto start_inverse = [&]() {
+        if (first_active) z_load_all(grp, LGP - LG0, pre);
+        fill_tables();
+        __syncthreads();
     };
 
     // Two lane halves sharing the tile: all stages in registers, exchanges
@@ -389,13 +406,16 @@ __device__ __forceinline__ void fft_pass_body(cplx<T> *z, const PassGeom &g, int
             if (src.kind == SRC_Z) z_load_all(j, lgs, v);
             else real_load_all(j, lgs, v);
         };
+        if (first_active) gload_all(grp, LGP - LG0, pre);
+        fill_tables();
+        __syncthreads();
         if constexpr (SPLIT == 2) {
             cplx<T> v[1 << LGR];
-            gload_all(jb, LGP - LGR, v);
+            pre_load(jb, LGP - LGR, v);
             split_stages<T, LGP, false, C / 2>(lds, half, ch, jb, v, roots);
             fwd_store_all(bl, LGL, v);
         } else {
-            wg_fft<T, LGP, false>(lds, LDS_STRIDE, c, grp, gload_all, fwd_store_all, false, false, roots);
+            wg_fft<T, LGP, false>(lds, LDS_STRIDE, c, grp, pre_load, fwd_store_all, false, false, roots);
         }
     } else if constexpr (MODE == 1) {
         // Real destination: value = op(scale * v) (+ the old value or the
@@ -457,19 +477,21 @@ __device__ __forceinline__ void fft_pass_body(cplx<T> *z, const PassGeom &g, int
             if (dst.kind == DST_Z) z_store_all(b0, lgs, v);
             else real_store_all(b0, lgs, v);
         };
+        start_inverse();
         if constexpr (SPLIT == 2) {
             cplx<T> v[1 << LGR];
-            inv_load_all(jb, LGP - LGR, v);
+            pre_inv_load(jb, LGP - LGR, v);
             split_stages<T, LGP, true, C / 2>(lds, half, ch, jb, v, roots);
             gstore_all(bl, LGL, v);
         } else {
-            wg_fft<T, LGP, true>(lds, LDS_STRIDE, c, grp, inv_load_all, gstore_all, false, false, roots);
+            wg_fft<T, LGP, true>(lds, LDS_STRIDE, c, grp, pre_inv_load, gstore_all, false, false, roots);
         }
     } else {
         const T sc = dst.op == OP_NEG ? -(T)dst.scale : (T)dst.scale;
+        start_inverse();
         if constexpr (SPLIT == 2) {
             cplx<T> v[1 << LGR];
-            inv_load_all(jb, LGP - LGR, v);
+            pre_inv_load(jb, LGP - LGR, v);
             split_stages<T, LGP, true, C / 2>(lds, half, ch, jb, v, roots);
 #pragma unroll
             for (int r = 0; r < (1 << LGR); ++r) {
@@ -491,7 +513,7 @@ __device__ __forceinline__ void fft_pass_body(cplx<T> *z, const PassGeom &g, int
                 lds[idx * LDS_STRIDE + c] = keep ? cscale<T>(v[r], sc) : mk<T>(0, 0);
             }
         };
-        wg_fft<T, LGP, true>(lds, LDS_STRIDE, c, grp, inv_load_all, mask_store_all, false, true, roots);
+        wg_fft<T, LGP, true>(lds, LDS_STRIDE, c, grp, pre_inv_load, mask_store_all, false, true, roots);
         __syncthreads();
         auto lds_load_all = [&](int j, int lgs, auto &v) {
 #pragma unroll
