@@ -67,7 +67,8 @@ typedef enum {
     MRINV_OP_APPLY_BACKWARD = 4,    /* mrinv_markov_renewal_apply_backward */
     MRINV_OP_TRANSITION_BACKWARD = 5,
     MRINV_OP_FIRST_ENTRANCE = 6,    /* mrinv_first_entrance / mrinv_reliability (r = |D|) */
-    MRINV_OP_AVAILABILITY = 7
+    MRINV_OP_AVAILABILITY = 7,
+    MRINV_OP_RESIDUAL = 8           /* mrinv_residual_norms */
 } mrinv_op_t;
 
 typedef struct mrinv_handle_s *mrinv_handle_t;

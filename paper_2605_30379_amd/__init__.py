@@ -366,12 +366,7 @@ def residual_norms(q: torch.Tensor, X: torch.Tensor):
     n, d, _ = q.shape
     X = _seq(X, "X", d, d)
     L = lib()
-    import math
-    lg = max(1, math.ceil(math.log2(2 * n - 1))) if n > 1 else 1
-    nl = (d * d + 1) // 2
-    spec = ((1 << lg) * nl * 16 + 255) // 256 * 256
-    need = 3 * spec + 2 * ((n * d * d * 8 + 255) // 256 * 256)
-    ws = _ws(need, q.device)
+    ws = _ws(L.mrinv_workspace_size(8, d, n, 0, 0), q.device)
     out = (ctypes.c_double * 3)()
     _check(L.mrinv_residual_norms(_handle(q.device), _ptr(q), _ptr(X), d, n, out, _ptr(ws), ws.numel()))
     return float(out[0]), float(out[1]), float(out[2])

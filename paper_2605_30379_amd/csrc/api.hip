@@ -286,6 +286,11 @@ static size_t ws_transition(int d, int64_t n) {
     return align256((size_t)n * d * sizeof(double)) + spec_bytes(lg, (int64_t)d * d, true) + spec_bytes(lg, d, true);
 }
 
+static size_t ws_residual(int d, int64_t n) {
+    const int64_t d2 = (int64_t)d * d;
+    return 3 * spec_bytes(lg_full(n), d2, true) + 2 * align256((size_t)n * d2 * 8);
+}
+
 static size_t ws_psi_backward(int d, int64_t n) { return 3 * spec_bytes(lg_full(n), (int64_t)d * d, true); }
 
 static size_t ws_apply_backward(int d, int64_t n, int r) {
@@ -318,6 +323,7 @@ extern "C" size_t mrinv_workspace_size(mrinv_op_t op, int d, int64_t n, int r, m
         case MRINV_OP_TRANSITION_BACKWARD: return ws_transition_backward(d, n);
         case MRINV_OP_FIRST_ENTRANCE: return (r < 1 || r > d) ? 0 : ws_first_entrance(d, n, r, prec);
         case MRINV_OP_AVAILABILITY: return 256;
+        case MRINV_OP_RESIDUAL: return ws_residual(d, n);
     }
     return 0;
 }
@@ -1165,8 +1171,7 @@ extern "C" mrinv_status_t mrinv_residual_norms(mrinv_handle_t h, const double *q
     const FftPlan p = hplan(h, lg_full(n));
     const int64_t d2 = (int64_t)d * d;
     const int nl = nl_of(d2);
-    const size_t need = 3 * spec_bytes(p.lgL, d2, true) + 2 * align256((size_t)n * d2 * 8);
-    CHECK(check_ws(ws, wsb, need));
+    CHECK(check_ws(ws, wsb, ws_residual(d, n)));
     Carve cv(ws);
     const size_t sb = spec_bytes(p.lgL, d2, true);
     auto *SA = cv.take<cplx<double>>(sb);

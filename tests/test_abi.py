@@ -48,6 +48,8 @@ def test_workspace_sizes(L):
     ws = L.mrinv_workspace_size(0, 16, 65536, 0, 0)
     assert spectra <= ws <= spectra + 3 * 65536 * 16 + 8192
     assert L.mrinv_workspace_size(0, 16, 65536, 0, 1) > L.mrinv_workspace_size(0, 16, 65536, 0, 0)
+    # residual diagnostics (op 8): three float64 spectra at 2^ceil(log2(2n-1)) plus two copies of the input
+    assert L.mrinv_workspace_size(8, 4, 100, 0, 0) >= 3 * 256 * 8 * 16 + 2 * 100 * 16 * 8
 
 
 def test_argument_validation_without_gpu(L):

@@ -583,6 +583,23 @@ def test_autotune_keeps_a_valid_tuning(mr, orc, precision):
         mr.set_tuning(**base)
 
 
+def test_residual_norms_match_oracle(mr, orc):
+    """Residual diagnostics (Proposition 2.6): the library's FFT-based sums of
+    ||e0 - A*X||_F and ||e0 - X*A||_F and max |e0 - A*X| against the oracle's
+    direct convolutions, on a perturbed inverse so the residuals are far above
+    rounding."""
+    d, n = 5, 300
+    q = si.family_kernel("weibull", d, n, 71).q
+    psi = orc.psi(q.numpy())
+    X = psi + 1e-6 * np.random.default_rng(3).standard_normal(psi.shape)
+    rl, rr = orc.residuals(orc.e0_minus(q.numpy()), X)
+    ref = (float(np.sum(np.linalg.norm(rl, axis=(1, 2)))), float(np.sum(np.linalg.norm(rr, axis=(1, 2)))),
+           float(np.max(np.abs(rl))))
+    got = mr.residual_norms(_gpu(q), _gpu(X))
+    for g, r in zip(got, ref):
+        assert abs(g - r) <= 1e-8 * r, (got, ref)
+
+
 def test_kernel_timing_records_every_launch(mr):
     """Timed launches (events stamped by the kernels' own dispatch packets)
     change no result, and their summed execution times fit inside the wall
