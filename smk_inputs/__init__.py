@@ -273,6 +273,25 @@ def paper_uniform_poisson(s: int, n: int) -> Kernel:
     return Kernel(torch.from_numpy(q), p, {"family": "poisson_uniform"})
 
 
+
+def exponential_semi_markov(G: np.ndarray, h: float, count: int):
+    """Exponential semi-Markov model of a generator G (Section 5.2) sampled on
+    the grid t_m = m h, m = 0 .. count - 1.
+
+    The embedded matrix is P_ij = G_ij / lambda_i (i != j) with lambda_i = -G_ii;
+    the kernel is Q_ij(t) = P_ij (1 - exp(-lambda_i t)) and the survival is
+    Hbar(t) = diag(exp(-lambda_i t)).  Returns (Q [count, s, s],
+    Hbar [count, s, s]), both float64 numpy arrays."""
+    G = np.asarray(G, dtype=np.float64)
+    s = G.shape[0]
+    lam = -np.diag(G)
+    pemb = G / lam[:, None]
+    np.fill_diagonal(pemb, 0.0)
+    t = h * np.arange(count)
+    Q = pemb[None] * -np.expm1(-lam[None, :, None] * t[:, None, None])
+    Hbar = np.exp(-lam[None, :] * t[:, None])[:, :, None] * np.eye(s)
+    return Q, Hbar
+
 # ---------------------------------------------------------------------------
 # Differentiable parameterisation (input construction for gradient studies).
 # ---------------------------------------------------------------------------

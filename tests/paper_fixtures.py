@@ -1,0 +1,46 @@
+"""Readers of the text fixtures under tests/golden/ (values printed in the
+paper, each file naming the passage it comes from)."""
+import pathlib
+from fractions import Fraction
+
+import numpy as np
+
+GOLDEN = pathlib.Path(__file__).parent / "golden"
+
+
+def read_blocks(name: str) -> dict:
+    """Parse a fixture of named blocks.  A line with a single word opens a
+    block whose rows follow; a line 'key value' sets a scalar; '#' starts a
+    comment."""
+    blocks, cur = {}, None
+    for raw in (GOLDEN / name).read_text().splitlines():
+        line = raw.split("#", 1)[0].strip()
+        if not line:
+            continue
+        tok = line.split()
+        if len(tok) == 1:
+            cur = blocks.setdefault(tok[0], [])
+        elif cur is None or tok[0] in ("horizon", "h", "N"):
+            blocks[tok[0]], cur = tok[1], None
+        else:
+            cur.append(tok)
+    return blocks
+
+
+def generator(blocks) -> np.ndarray:
+    return np.array([[float(x) for x in r] for r in blocks["generator"]])
+
+
+def embedded(blocks):
+    return [[Fraction(x) for x in r] for r in blocks["embedded"]]
+
+
+def same_digits(x: float, printed: str, decimals: int | None = None) -> bool:
+    """True when x rounds to the printed value: to `decimals` decimals, else
+    to as many significant digits as the printed mantissa shows."""
+    v = float(printed)
+    if decimals is None:
+        mant = printed.lower().split("e")[0].lstrip("-")
+        digits = len(mant.replace(".", "").lstrip("0"))
+        decimals = digits - 1 - int(np.floor(np.log10(abs(v))))
+    return abs(x - v) <= 0.5 * 10.0 ** -decimals * 1.001

@@ -4,12 +4,12 @@ mathematics, independent of the oracle's own formulas.
 Each test names what pins it: a brute-force enumeration, a closed form, an
 exact identity, a library routine, or a worked example printed in the paper.
 """
-import pathlib
 from fractions import Fraction
 
 import numpy as np
 import pytest
 
+import paper_fixtures as pf
 import smk_inputs as si
 from oracle import exact
 
@@ -316,65 +316,44 @@ def test_paper_residual_orders(orc):
     assert orc.norm_1N(rR) < 5.91e-15 * 10
 
 
-GOLDEN = pathlib.Path(__file__).parent / "golden"
+
+UP, DOWN = [0, 1, 2], [3]
+ALPHA = np.array([1.0, 0.0, 0.0, 0.0])
 
 
-def _read_convergence_fixture():
-    blocks, cur = {}, None
-    for raw in (GOLDEN / "exponential_convergence.txt").read_text().splitlines():
-        line = raw.split("#", 1)[0].strip()
-        if not line:
-            continue
-        tok = line.split()
-        if tok[0] == "horizon":
-            blocks["horizon"], cur = float(tok[1]), None
-        elif tok[0] in ("generator", "embedded", "table"):
-            cur = blocks.setdefault(tok[0], [])
-        else:
-            cur.append(tok)
-    G = np.array([[float(x) for x in r] for r in blocks["generator"]])
-    emb = [[Fraction(x) for x in r] for r in blocks["embedded"]]
-    return G, emb, blocks["horizon"], blocks["table"]
-
-
-def _mean_value_errors(orc, G, T, h):
-    """Maximum errors over m <= floor(T/h) of the mean-value approximation
-    (Section 4.2) of the exponential semi-Markov model with generator G, for
-    the transition matrix, reliability (first entrance into D = {3}) and
-    availability, against the exact Markov solution exp(G t) (Section 5.2)."""
+def _exact(G, t):
+    """Exact Markov availability alpha exp(G t) 1_U and reliability
+    alpha_U exp(G_UU t) 1_U (Section 5.2), by scipy's matrix exponential."""
     from scipy.linalg import expm
+    P = np.stack([expm(G * tm) for tm in t])
+    R = np.array([expm(G[np.ix_(UP, UP)] * tm)[0].sum() for tm in t])
+    return P, P[:, 0, UP].sum(1), R
+
+
+def _mean_value(orc, G, h, n):
+    """Mean-value approximation (Section 4.2) of P, reliability and
+    availability on t_0 .. t_{n-1}:
+    K_h = (e0 - Qbar_h)^-1 * [L_h - 1/2 Delta^+Q_h * (L_h(0) e0)], with
+    L = Hbar for P and L = Q_UD (first entrance into D = {3}) for reliability.
+    Qbar_h(0) = Delta Q_h(1) / 2 is not zero, so this runs the general-A(0)
+    inverse."""
+    Q, Hb = si.exponential_semi_markov(G, h, n + 1)
     s = G.shape[0]
-    lam = -np.diag(G)
-    pemb = G / lam[:, None]
-    np.fill_diagonal(pemb, 0.0)
-    N = int(np.floor(T / h + 1e-9))
-    n = N + 1
-    t = h * np.arange(N + 2)
-    # Q_ij(t) = P_ij (1 - exp(-lam_i t)), sampled at t_0 .. t_{N+1}.
-    Qh = pemb[None] * -np.expm1(-lam[None, :, None] * t[:, None, None])
-    dQ = np.zeros_like(Qh)
-    dQ[1:] = Qh[1:] - Qh[:-1]
-    dQp = dQ[1:n + 1]                      # Delta^+ Q_h(m) = Delta Q_h(m + 1)
-    Qbar = 0.5 * (dQ[:n] + dQp)            # Qbar_h(0) = Delta Q_h(1) / 2, not zero
-    U, D = [0, 1, 2], [3]
+    dQ = np.zeros_like(Q)
+    dQ[1:] = Q[1:] - Q[:-1]
+    dQp = dQ[1:]                           # Delta^+ Q_h(m) = Delta Q_h(m + 1)
+    Qbar = 0.5 * (dQ[:n] + dQp)
 
     def solve(rows, L, L0):
-        """K_h = (e0 - Qbar)^-1 * [L_h - 1/2 Delta^+Q_h * (L_h(0) e0)] on `rows`."""
         A = -Qbar[:, rows][:, :, rows]
         A[0] += np.eye(len(rows))
         X = orc.series_inverse_left(A)
         corr = np.einsum("kij,jl->kil", dQp[:, rows][:, :, rows], L0)
         return orc.conv(X, L - 0.5 * corr)
 
-    Hb = np.exp(-lam[None, :] * t[:n, None])[:, :, None] * np.eye(s)
-    P = solve(list(range(s)), Hb, np.eye(s))
-    GD = solve(U, Qh[:n][:, U][:, :, D], np.zeros((len(U), len(D))))
-    Pex = np.stack([expm(G * tm) for tm in t[:n]])
-    Rex = np.stack([expm(G[np.ix_(U, U)] * tm)[0].sum() for tm in t[:n]])
-    e_p = np.max(np.linalg.norm(P - Pex, axis=(1, 2)))
-    e_r = np.max(np.abs((1.0 - GD[:, 0, 0]) - Rex))
-    e_a = np.max(np.abs(P[:, 0, U].sum(1) - Pex[:, 0, U].sum(1)))
-    return e_p, e_r, e_a
+    P = solve(list(range(s)), Hb[:n], np.eye(s))
+    GD = solve(UP, Q[:n][:, UP][:, :, DOWN], np.zeros((len(UP), len(DOWN))))
+    return P, P[:, 0, UP].sum(1), 1.0 - GD[:, 0, 0]
 
 
 def test_paper_exponential_convergence_table(orc):
@@ -382,27 +361,47 @@ def test_paper_exponential_convergence_table(orc):
     mean-value scheme for the four-state exponential model, run through the
     oracle's general-A(0) inverse and rectangular convolutions, reproduces
     every printed error to its five significant digits and every printed
-    order to three decimals (fixture: tests/golden/exponential_convergence.txt).
+    order to three decimals (fixture golden/exponential_convergence.txt).
     The embedded matrix derived from the generator is the printed one."""
-    G, emb, T, table = _read_convergence_fixture()
+    fx = pf.read_blocks("exponential_convergence.txt")
+    G, T = pf.generator(fx), float(fx["horizon"])
     lam = [-Fraction(str(G[i, i])) for i in range(4)]
     derived = [[Fraction(0) if i == j else Fraction(str(G[i, j])) / lam[i] for j in range(4)] for i in range(4)]
-    assert derived == emb
-
-    def same_digits(x, printed, decimals=None):
-        v = float(printed)
-        if decimals is not None:
-            return abs(x - v) <= 0.5 * 10.0 ** -decimals * 1.001
-        return abs(x - v) <= 0.5 * 10.0 ** (np.floor(np.log10(v)) - 4) * 1.001
-
+    assert derived == pf.embedded(fx)
     prev = None
-    for row in table:
+    for row in fx["table"]:
         h = float(row[0])
-        errs = _mean_value_errors(orc, G, T, h)
+        n = int(np.floor(T / h + 1e-9)) + 1
+        P, A, R = _mean_value(orc, G, h, n)
+        Pex, Aex, Rex = _exact(G, h * np.arange(n))
+        errs = (np.max(np.linalg.norm(P - Pex, axis=(1, 2))), np.max(np.abs(R - Rex)), np.max(np.abs(A - Aex)))
         for c, e in enumerate(errs):
-            assert same_digits(e, row[1 + 2 * c]), (h, c, e, row[1 + 2 * c])
-            if prev is not None:
-                assert same_digits(np.log2(prev[c] / e), row[2 + 2 * c], 3), (h, c, row[2 + 2 * c])
-            else:
+            assert pf.same_digits(e, row[1 + 2 * c]), (h, c, e, row[1 + 2 * c])
+            if prev is None:
                 assert row[2 + 2 * c] == "-"
+            else:
+                assert pf.same_digits(np.log2(prev[c] / e), row[2 + 2 * c], 3), (h, c, row[2 + 2 * c])
         prev = errs
+
+
+def test_paper_exponential_long_horizon(orc):
+    """The paper's long-horizon errors for the same model (Section 5.2,
+    N = 2^15, h = 0.005; fixture golden/exponential_figure.txt), to the
+    printed three digits.  The process discretization is the discrete path
+    itself: the renewal sequence of q = Delta Q_h (q(0) = 0) with the oracle's
+    availability and reliability functions (Section 4.1)."""
+    fx = pf.read_blocks("exponential_figure.txt")
+    G, h, n = pf.generator(fx), float(fx["h"]), int(fx["N"])
+    printed = {r[0]: r[1:] for r in fx["errors"]}
+    _, Aex, Rex = _exact(G, h * np.arange(n))
+    Q, _ = si.exponential_semi_markov(G, h, n)
+    q = np.zeros_like(Q)
+    q[1:] = Q[1:] - Q[:-1]
+    up = np.array([1, 1, 1, 0])
+    A = orc.availability(q, up, ALPHA)
+    R = orc.reliability(q, up, ALPHA)
+    for e, v in zip((np.max(np.abs(A - Aex)), np.max(np.abs(R - Rex))), printed["process"]):
+        assert pf.same_digits(e, v), (e, v)
+    _, A, R = _mean_value(orc, G, h, n)
+    for e, v in zip((np.max(np.abs(A - Aex)), np.max(np.abs(R - Rex))), printed["mean_value"]):
+        assert pf.same_digits(e, v), (e, v)
