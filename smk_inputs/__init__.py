@@ -292,6 +292,23 @@ def exponential_semi_markov(G: np.ndarray, h: float, count: int):
     Hbar = np.exp(-lam[None, :] * t[:, None])[:, :, None] * np.eye(s)
     return Q, Hbar
 
+
+def lognormal_semi_markov(pemb, mu, sigma, h: float, count: int):
+    """Lognormal semi-Markov model (Section 5.2 and the parameter appendix)
+    sampled on the grid t_m = m h, m = 0 .. count - 1: the kernel
+    Q_ij(t) = P_ij Phi((ln t - mu_ij) / sigma_ij) for t > 0, Q(0) = 0, and the
+    survival Hbar(t) = diag(1 - sum_j Q_ij(t)).  Entries with P_ij = 0 may
+    carry any mu, sigma > 0.  Returns (Q [count, s, s], Hbar [count, s, s])."""
+    pemb = np.asarray(pemb, dtype=np.float64)
+    s = pemb.shape[0]
+    t = torch.as_tensor(h * np.arange(1, count), dtype=torch.float64)
+    z = (torch.log(t)[:, None, None] - torch.as_tensor(mu, dtype=torch.float64)) / torch.as_tensor(
+        sigma, dtype=torch.float64)
+    Q = np.zeros((count, s, s))
+    Q[1:] = pemb[None] * _norm_cdf(z).numpy()
+    Hbar = (1.0 - Q.sum(axis=2))[:, :, None] * np.eye(s)
+    return Q, Hbar
+
 # ---------------------------------------------------------------------------
 # Differentiable parameterisation (input construction for gradient studies).
 # ---------------------------------------------------------------------------

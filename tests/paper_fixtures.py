@@ -44,3 +44,17 @@ def same_digits(x: float, printed: str, decimals: int | None = None) -> bool:
         digits = len(mant.replace(".", "").lstrip("0"))
         decimals = digits - 1 - int(np.floor(np.log10(abs(v))))
     return abs(x - v) <= 0.5 * 10.0 ** -decimals * 1.001
+
+
+def lognormal_params(blocks, s: int):
+    """(mu, sigma) as s x s arrays from rows 'i-j mu sigma'; entries not
+    listed get mu = 0, sigma = 1 (their embedded probability is zero)."""
+    mu, sigma = np.zeros((s, s)), np.ones((s, s))
+    for pair, m, sg in blocks["lognormal"]:
+        i, j = (int(x) for x in pair.split("-"))
+        mu[i, j], sigma[i, j] = float(m), float(sg)
+    return mu, sigma
+
+
+def embedded_matrix(blocks) -> np.ndarray:
+    return np.array([[float(x) for x in r] for r in embedded(blocks)])

@@ -235,44 +235,29 @@ def test_c4_batched_uneven_workload(mr, orc):
         assert float(o[1:].sum(dim=2).max()) <= 1 + 1e-10, w
 
 
-def test_paper_exponential_long_horizon(mr, orc):
-    """The four-state exponential model of Section 5.2 at N = 2^15, h = 0.005
-    (fixture golden/exponential_figure.txt), through the library:
-      * process discretization: psi of q = Delta Q_h (FP64), P = psi*Hbar,
-        availability, and reliability by first entrance (Section 4.1);
-      * mean-value scheme (Section 4.2): the general-A(0) inverse of
-        e0 - Qbar_h and the rectangular products with its right-hand sides.
-    Each maximum error against the exact Markov solution (scipy's expm)
-    rounds to the value the paper prints, and the inverses agree with the
-    oracle on a 2048-step prefix (an exact sub-problem, Proposition 2.3)."""
-    from scipy.linalg import expm
 
-    import paper_fixtures as pf
-
-    fx = pf.read_blocks("exponential_figure.txt")
-    G, h, n = pf.generator(fx), float(fx["h"]), int(fx["N"])
-    printed = {r[0]: r[1:] for r in fx["errors"]}
+def _continuous_schemes(mr, orc, Q, Hb, n):
+    """Both discretizations of Section 4.2 through the library, for a kernel Q
+    sampled on t_0 .. t_n and its survival Hb; returns availability and
+    reliability on t_0 .. t_{n-1} as {scheme: (A, R)}.
+      * process: psi of q = Delta Q_h (FP64), P = psi*Hbar, availability, and
+        reliability by first entrance (Section 4.1);
+      * mean_value: K_h = (e0 - Qbar_h)^-1 * [L_h - 1/2 Delta^+Q_h * (L_h(0) e0)]
+        with the general-A(0) inverse and the rectangular products.
+    Every inverse is checked against the oracle on a 2048-step prefix (an
+    exact sub-problem, Proposition 2.3)."""
     up, U, D = [1, 1, 1, 0], [0, 1, 2], [3]
     alpha = [1.0, 0.0, 0.0, 0.0]
-    t = h * np.arange(n)
-    Aex = np.array([expm(G * tm)[0, U].sum() for tm in t])
-    Rex = np.array([expm(G[np.ix_(U, U)] * tm)[0].sum() for tm in t])
     dev = torch.device("cuda")
-
-    Q, Hb = si.exponential_semi_markov(G, h, n + 1)
     dQ = np.zeros_like(Q)
     dQ[1:] = Q[1:] - Q[:-1]
+    out = {}
 
-    # Process discretization: q = Delta Q_h, q(0) = 0.
     q = torch.from_numpy(np.ascontiguousarray(dQ[:n])).to(dev)
     psi = mr.psi_inverse(q, "fp64")
-    A = mr.availability(mr.transition(psi, q), up, alpha)
-    R = mr.reliability(q, up, alpha)
     assert _maxerr(_np(psi[:2048]), orc.psi(dQ[:2048])) <= 1e-12
-    for e, v in zip((_maxerr(_np(A), Aex), _maxerr(_np(R), Rex)), printed["process"]):
-        assert pf.same_digits(e, v), ("process", e, v)
+    out["process"] = (_np(mr.availability(mr.transition(psi, q), up, alpha)), _np(mr.reliability(q, up, alpha)))
 
-    # Mean-value scheme: K_h = (e0 - Qbar_h)^-1 * [L_h - 1/2 Delta^+Q_h * (L_h(0) e0)].
     dQp = dQ[1:n + 1]
     Qbar = 0.5 * (dQ[:n] + dQp)
 
@@ -283,11 +268,48 @@ def test_paper_exponential_long_horizon(mr, orc):
         assert _maxerr(_np(X[:2048]), orc.series_inverse_left(Am[:2048])) <= 1e-12
         return X
 
-    L = Hb[:n] - 0.5 * dQp                                  # L = Hbar, L(0) = I
-    P = mr.markov_renewal_apply(inverse([0, 1, 2, 3]), torch.from_numpy(np.ascontiguousarray(L)).to(dev))
-    A = mr.availability(P, up, alpha)
+    L = np.ascontiguousarray(Hb[:n] - 0.5 * dQp)            # L = Hbar, L(0) = I
+    P = mr.markov_renewal_apply(inverse([0, 1, 2, 3]), torch.from_numpy(L).to(dev))
     QUD = np.ascontiguousarray(Q[:n][:, U][:, :, D])        # L = Q_UD, L(0) = 0
     GD = mr.markov_renewal_apply(inverse(U), torch.from_numpy(QUD).to(dev))
-    R = 1.0 - _np(GD)[:, 0, 0]
-    for e, v in zip((_maxerr(_np(A), Aex), _maxerr(R, Rex)), printed["mean_value"]):
-        assert pf.same_digits(e, v), ("mean_value", e, v)
+    out["mean_value"] = (_np(mr.availability(P, up, alpha)), 1.0 - _np(GD)[:, 0, 0])
+    return out
+
+
+def test_paper_exponential_long_horizon(mr, orc):
+    """The four-state exponential model of Section 5.2 at N = 2^15, h = 0.005
+    (fixture golden/exponential_figure.txt): through the library, each
+    scheme's maximum availability and reliability error against the exact
+    Markov solution (scipy's expm) rounds to the value the paper prints."""
+    from scipy.linalg import expm
+
+    import paper_fixtures as pf
+
+    fx = pf.read_blocks("exponential_figure.txt")
+    G, h, n = pf.generator(fx), float(fx["h"]), int(fx["N"])
+    U = [0, 1, 2]
+    t = h * np.arange(n)
+    Aex = np.array([expm(G * tm)[0, U].sum() for tm in t])
+    Rex = np.array([expm(G[np.ix_(U, U)] * tm)[0].sum() for tm in t])
+    res = _continuous_schemes(mr, orc, *si.exponential_semi_markov(G, h, n + 1), n)
+    for r in fx["errors"]:
+        A, R = res[r[0]]
+        for e, v in zip((_maxerr(A, Aex), _maxerr(R, Rex)), r[1:]):
+            assert pf.same_digits(e, v), (r[0], e, v)
+
+
+def test_paper_lognormal_scheme_difference(mr, orc):
+    """The lognormal model of Section 5.2 (appendix parameters; fixture
+    golden/lognormal_figure.txt) at N = 2^15, h = 0.005: through the library,
+    the largest differences between the two schemes in availability and
+    reliability round to the printed values."""
+    import paper_fixtures as pf
+
+    fx = pf.read_blocks("lognormal_figure.txt")
+    mu, sigma = pf.lognormal_params(fx, 4)
+    h, n = float(fx["h"]), int(fx["N"])
+    printed = dict(fx["differences"])
+    res = _continuous_schemes(mr, orc, *si.lognormal_semi_markov(pf.embedded_matrix(fx), mu, sigma, h, n + 1), n)
+    (A_pd, R_pd), (A_mv, R_mv) = res["process"], res["mean_value"]
+    assert pf.same_digits(_maxerr(A_mv, A_pd), printed["max_dA"])
+    assert pf.same_digits(_maxerr(R_mv, R_pd), printed["max_dR"])

@@ -330,18 +330,18 @@ def _exact(G, t):
     return P, P[:, 0, UP].sum(1), R
 
 
-def _mean_value(orc, G, h, n):
-    """Mean-value approximation (Section 4.2) of P, reliability and
-    availability on t_0 .. t_{n-1}:
+def _mean_value(orc, Q, Hb, n):
+    """Mean-value approximation (Section 4.2) of P, availability and
+    reliability on t_0 .. t_{n-1}, from the kernel Q sampled on t_0 .. t_n and
+    the survival Hb:
     K_h = (e0 - Qbar_h)^-1 * [L_h - 1/2 Delta^+Q_h * (L_h(0) e0)], with
     L = Hbar for P and L = Q_UD (first entrance into D = {3}) for reliability.
     Qbar_h(0) = Delta Q_h(1) / 2 is not zero, so this runs the general-A(0)
     inverse."""
-    Q, Hb = si.exponential_semi_markov(G, h, n + 1)
-    s = G.shape[0]
+    s = Q.shape[1]
     dQ = np.zeros_like(Q)
     dQ[1:] = Q[1:] - Q[:-1]
-    dQp = dQ[1:]                           # Delta^+ Q_h(m) = Delta Q_h(m + 1)
+    dQp = dQ[1:n + 1]                      # Delta^+ Q_h(m) = Delta Q_h(m + 1)
     Qbar = 0.5 * (dQ[:n] + dQp)
 
     def solve(rows, L, L0):
@@ -354,6 +354,16 @@ def _mean_value(orc, G, h, n):
     P = solve(list(range(s)), Hb[:n], np.eye(s))
     GD = solve(UP, Q[:n][:, UP][:, :, DOWN], np.zeros((len(UP), len(DOWN))))
     return P, P[:, 0, UP].sum(1), 1.0 - GD[:, 0, 0]
+
+
+def _process(orc, Q, n):
+    """Process discretization (Section 4.2): the discrete renewal sequence of
+    q = Delta Q_h (q(0) = 0) and the oracle's availability and reliability
+    (Section 4.1) on t_0 .. t_{n-1}."""
+    q = np.zeros((n,) + Q.shape[1:])
+    q[1:] = Q[1:n] - Q[:n - 1]
+    up = np.array([1, 1, 1, 0])
+    return orc.availability(q, up, ALPHA), orc.reliability(q, up, ALPHA)
 
 
 def test_paper_exponential_convergence_table(orc):
@@ -372,7 +382,7 @@ def test_paper_exponential_convergence_table(orc):
     for row in fx["table"]:
         h = float(row[0])
         n = int(np.floor(T / h + 1e-9)) + 1
-        P, A, R = _mean_value(orc, G, h, n)
+        P, A, R = _mean_value(orc, *si.exponential_semi_markov(G, h, n + 1), n)
         Pex, Aex, Rex = _exact(G, h * np.arange(n))
         errs = (np.max(np.linalg.norm(P - Pex, axis=(1, 2))), np.max(np.abs(R - Rex)), np.max(np.abs(A - Aex)))
         for c, e in enumerate(errs):
@@ -394,14 +404,28 @@ def test_paper_exponential_long_horizon(orc):
     G, h, n = pf.generator(fx), float(fx["h"]), int(fx["N"])
     printed = {r[0]: r[1:] for r in fx["errors"]}
     _, Aex, Rex = _exact(G, h * np.arange(n))
-    Q, _ = si.exponential_semi_markov(G, h, n)
-    q = np.zeros_like(Q)
-    q[1:] = Q[1:] - Q[:-1]
-    up = np.array([1, 1, 1, 0])
-    A = orc.availability(q, up, ALPHA)
-    R = orc.reliability(q, up, ALPHA)
+    Q, Hb = si.exponential_semi_markov(G, h, n + 1)
+    A, R = _process(orc, Q, n)
     for e, v in zip((np.max(np.abs(A - Aex)), np.max(np.abs(R - Rex))), printed["process"]):
         assert pf.same_digits(e, v), (e, v)
-    _, A, R = _mean_value(orc, G, h, n)
+    _, A, R = _mean_value(orc, Q, Hb, n)
     for e, v in zip((np.max(np.abs(A - Aex)), np.max(np.abs(R - Rex))), printed["mean_value"]):
         assert pf.same_digits(e, v), (e, v)
+
+
+def test_paper_lognormal_scheme_difference(orc):
+    """The heavy-tailed lognormal model of Section 5.2 (parameters from the
+    appendix; fixture golden/lognormal_figure.txt): on the N = 2^15,
+    h = 0.005 grid the mean-value approximation and the process
+    discretization differ by at most the printed amounts in availability and
+    reliability, to the printed three digits."""
+    fx = pf.read_blocks("lognormal_figure.txt")
+    pemb = pf.embedded_matrix(fx)
+    mu, sigma = pf.lognormal_params(fx, 4)
+    h, n = float(fx["h"]), int(fx["N"])
+    printed = dict(fx["differences"])
+    Q, Hb = si.lognormal_semi_markov(pemb, mu, sigma, h, n + 1)
+    A_pd, R_pd = _process(orc, Q, n)
+    _, A_mv, R_mv = _mean_value(orc, Q, Hb, n)
+    assert pf.same_digits(np.max(np.abs(A_mv - A_pd)), printed["max_dA"])
+    assert pf.same_digits(np.max(np.abs(R_mv - R_pd)), printed["max_dR"])
