@@ -208,6 +208,27 @@ def test_paper_first_entrance_example(mr, orc):
     assert abs(_np(F)[-1] - 1.0) <= 1e-14
 
 
+
+def test_paper_horizon_scaling_accuracy(mr, orc):
+    """The paper's horizon-scaling model (Section 5.1; fixture
+    golden/inverse_accuracy.txt) at N = 128, 512, 2048: the library's FP64
+    inverse is at least as accurate as the FFT-Newton figures the paper
+    prints: scaled discrepancy d_N from the coefficient recursion (the
+    oracle's right recursion, the paper's eq. (inverse-recursion)) and the
+    left and right residuals in the norm ||.||_{1,N} (Section 2), both formed
+    by the oracle with direct convolutions."""
+    import paper_fixtures as pf
+
+    for N, dN, left, right in pf.read_blocks("inverse_accuracy.txt")["fft_newton"]:
+        q = si.paper_three_state_gamma(int(N)).q.numpy()
+        psi = _np(mr.psi_inverse(_gpu(q)))
+        got_d = orc.scaled_discrepancy(psi, orc.psi_right(q))
+        rL, rR = orc.residuals(orc.e0_minus(q), psi)
+        got = (got_d, orc.norm_1N(rL), orc.norm_1N(rR))
+        print(f"N={N}: d_N={got[0]:.3g} left={got[1]:.3g} right={got[2]:.3g}", flush=True)
+        for g, v in zip(got, (dN, left, right)):
+            assert g <= float(v), (N, g, v)
+
 def test_reliability_and_availability_match_oracle(mr, orc):
     d, n = 6, 400
     q = si.weibull_kernel(d, n, 12).q.numpy()
