@@ -203,6 +203,78 @@ def write_traffic(args, kernel: str, fetch_csv: str, write_csv: str) -> None:
     print(json.dumps(out))
 
 
+
+def stage_table(trace_csv: str, fetch_csv: str, write_csv: str, mfma_csv: str) -> None:
+    """Per-stage counter evidence from four rocprofv3 runs of one bench
+    command: a kernel trace (durations), FETCH_SIZE, WRITE_SIZE, and MfmaUtil
+    with SQ_INSTS_VALU_MFMA_MOPS_F64 / _F32.  Dispatches are grouped by kernel
+    and grid size (one group per launch shape); for each group it prints the
+    mean duration, the scaled HBM bytes (FETCH and WRITE calibrated on the
+    1 GiB copy of --calibrate-copy, as for --traffic), the achieved HBM
+    bandwidth and its fraction of the 8 TB/s peak, the MFMA busy percentage
+    and the matrix-core flop rate (MOPS x 512 flops).  Prints markdown."""
+    import collections
+    import csv
+    import re
+
+    def short(name):
+        return re.sub(r"\(.*", "", re.sub(r"^void mrinv::", "", name)).strip()
+
+    def keep(name):
+        return "copyBuffer" not in name and "mrinv" in name
+
+    dur = collections.defaultdict(list)
+    for r in csv.DictReader(open(trace_csv)):
+        if keep(r["Kernel_Name"]):
+            g = int(r["Grid_Size_X"]) * int(r["Grid_Size_Y"]) * int(r["Grid_Size_Z"])
+            dur[(short(r["Kernel_Name"]), g)].append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-9)
+
+    def counters(path, names):
+        out = collections.defaultdict(lambda: collections.defaultdict(list))
+        rows = list(csv.DictReader(open(path)))
+        for r in rows:
+            if r["Counter_Name"] in names and keep(r["Kernel_Name"]):
+                out[(short(r["Kernel_Name"]), int(r["Grid_Size"]))][r["Counter_Name"]].append(float(r["Counter_Value"]))
+        return rows, out
+
+    scaled = {}
+    for counter, path in (("FETCH_SIZE", fetch_csv), ("WRITE_SIZE", write_csv)):
+        rows, c = counters(path, {counter})
+        cal = max(float(r["Counter_Value"]) for r in rows if r["Counter_Name"] == counter and "copyBuffer" in r["Kernel_Name"])
+        scale = float(1 << 30) / (cal * 1024.0)
+        for k, v in c.items():
+            vals = v[counter]
+            scaled.setdefault(k, {})[counter] = sum(vals) / len(vals) * 1024.0 * scale
+    _, mf = counters(mfma_csv, {"MfmaUtil", "SQ_INSTS_VALU_MFMA_MOPS_F64", "SQ_INSTS_VALU_MFMA_MOPS_F32"})
+
+    def mean(xs):
+        return sum(xs) / len(xs) if xs else 0.0
+
+    total = sum(sum(v) for v in dur.values())
+    print("| kernel | grid | dispatches | avg us | share of kernel time | FETCH MB | WRITE MB | HBM GB/s | of 8 TB/s "
+          "| MFMA busy % | MFMA TFLOP/s |")
+    print("|---|---|---|---|---|---|---|---|---|---|---|")
+    for k in sorted(dur, key=lambda k: -sum(dur[k])):
+        t = sum(dur[k]) / len(dur[k])
+        share = sum(dur[k]) / total
+        if share < 0.01:
+            continue
+        f = scaled.get(k, {}).get("FETCH_SIZE")
+        w = scaled.get(k, {}).get("WRITE_SIZE")
+        bw = (f + w) / t / 1e9 if f is not None and w is not None else None
+        m = mf.get(k, {})
+        util = mean(m["MfmaUtil"]) if m.get("MfmaUtil") else None
+        mops = mean(m.get("SQ_INSTS_VALU_MFMA_MOPS_F64", [])) + mean(m.get("SQ_INSTS_VALU_MFMA_MOPS_F32", []))
+        tf = mops * 512 / t / 1e12 if mops > 0 else None
+
+        def fmt(x, spec):
+            return "—" if x is None else format(x, spec)
+        print(f"| `{k[0]}` | {k[1]} | {len(dur[k])} | {t * 1e6:.2f} | {share:.3f} | {fmt(f and f / 1e6, '.2f')} "
+              f"| {fmt(w and w / 1e6, '.2f')} | {fmt(bw, '.0f')} | {fmt(bw and bw / 8000.0, '.3f')} "
+              f"| {fmt(util, '.1f')} | {fmt(tf, '.2f')} |")
+    print(f"\nKernel time over the trace: {total * 1e3:.3f} ms in {sum(len(v) for v in dur.values())} dispatches; "
+          "groups under 1% of it are not listed.")
+
 def cpu_baseline(cfg, budget_s: float):
     """The oracle's left recursion on a prefix n' of the same kernel (finite-
     horizon exactness makes the prefix a valid sub-problem), sized to about
@@ -314,11 +386,16 @@ def main():
     ap.add_argument("--forms", default="fp64,mixed", help="comma-separated forms to time (value form first)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one 1 GiB device-to-device copy first (reference for HBM counter runs)")
+    ap.add_argument("--stage-table", nargs=4, metavar=("TRACE_CSV", "FETCH_CSV", "WRITE_CSV", "MFMA_CSV"),
+                    help="print per-stage counter evidence (duration, HBM bytes and bandwidth, MFMA busy) from four "
+                         "rocprofv3 runs of one --calibrate-copy bench command, then exit")
     ap.add_argument("--traffic", nargs=3, metavar=("KERNEL", "FETCH_CSV", "WRITE_CSV"),
                     help="write profiles/traffic_<config>_<form>.json for KERNEL from two rocprofv3 --pmc runs "
                          "(FETCH_SIZE, then WRITE_SIZE) of a --calibrate-copy bench command, then exit")
     args = ap.parse_args()
 
+    if args.stage_table:
+        return stage_table(*args.stage_table)
     if args.traffic:
         return write_traffic(args, *args.traffic)
 
