@@ -9,19 +9,23 @@ GOLDEN = pathlib.Path(__file__).parent / "golden"
 
 
 def read_blocks(name: str) -> dict:
-    """Parse a fixture of named blocks.  A line with a single word opens a
-    block whose rows follow; a line 'key value' sets a scalar; '#' starts a
-    comment."""
+    """Parse a fixture.  '#' starts a comment; 'name = value' sets a scalar
+    (kept as text); a line holding a single word opens a block, and every
+    other line is a row (list of words) of the block opened last."""
     blocks, cur = {}, None
     for raw in (GOLDEN / name).read_text().splitlines():
         line = raw.split("#", 1)[0].strip()
         if not line:
             continue
+        if "=" in line:
+            key, value = (x.strip() for x in line.split("=", 1))
+            blocks[key], cur = value, None
+            continue
         tok = line.split()
         if len(tok) == 1:
             cur = blocks.setdefault(tok[0], [])
-        elif cur is None or tok[0] in ("horizon", "h", "N"):
-            blocks[tok[0]], cur = tok[1], None
+        elif cur is None:
+            raise ValueError(f"{name}: row outside a block: {raw!r}")
         else:
             cur.append(tok)
     return blocks
