@@ -71,3 +71,34 @@ def test_stage_table_arithmetic(tmp_path, capsys):
     assert abs(float(cells[8]) - 0.5) < 1e-3
     assert float(cells[9]) == 40.0
     assert abs(float(cells[10]) - 1.024e9 / 20e-6 / 1e12) < 0.01    # 51.2 TFLOP/s
+
+
+def test_write_traffic_scaling_and_hash(tmp_path, monkeypatch):
+    """--traffic: scaled FETCH/WRITE bytes per launch of one kernel, keyed to
+    the hash of the kernel's source; the bench line accepts the file only
+    while that hash matches."""
+    import argparse
+    import json
+
+    name = "freq_gemm_mfma_kernel<double, 16, false, false, false>"
+    gib_kib = float(1 << 20)
+
+    def pmc(counter, copy_kib, kern_kib):
+        return [{"Dispatch_Id": 1, "Kernel_Name": COPY, "Grid_Size": 512, "Counter_Name": counter,
+                 "Counter_Value": copy_kib}] + [
+            {"Dispatch_Id": i, "Kernel_Name": KERNEL, "Grid_Size": 4096, "Counter_Name": counter,
+             "Counter_Value": v} for i, v in ((2, kern_kib), (3, 3 * kern_kib))]
+
+    fpath, wpath = str(tmp_path / "fetch.csv"), str(tmp_path / "write.csv")
+    _write(fpath, PMC_COLS, pmc("FETCH_SIZE", gib_kib / 2, 10e6 / 1024))   # 10 and 30 MB counted
+    _write(wpath, PMC_COLS, pmc("WRITE_SIZE", gib_kib, 5e6 / 1024))        # 5 and 15 MB
+    (tmp_path / "profiles").mkdir()
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    bench.write_traffic(argparse.Namespace(config="c2"), name, fpath, wpath)
+    out = json.load(open(tmp_path / "profiles" / "traffic_c2_fp64.json"))
+    assert out["dispatches"] == 2
+    assert abs(out["fetch_scale"] - 2.0) < 1e-12 and abs(out["write_scale"] - 1.0) < 1e-12
+    assert abs(out["fetch_bytes_per_launch"] - 40e6) < 1 and abs(out["write_bytes_per_launch"] - 10e6) < 1
+    assert abs(out["bytes_per_launch"] - 50e6) < 1
+    assert out["source_hash"] == bench.kernel_source_hash(name)
+    assert bench.kernel_source_hash(name) != bench.kernel_source_hash("fft_pass_kernel<double, 8, 16, 0>")
