@@ -51,6 +51,7 @@ def _load():
         "orc_inverse_row": (I, [dp, I, L, dp, dp]),
         "orc_inverse_right": (I, [dp, I, L, dp]),
         "orc_conv": (None, [dp, dp, I, I, I, L, dp]),
+        "orc_residual_at": (None, [dp, I, dp, I, ctypes.POINTER(ctypes.c_long), I, dp]),
         "orc_hbar": (None, [dp, I, L, dp]),
         "orc_transition": (None, [dp, dp, I, L, dp]),
         "orc_availability": (I, [dp, I, L, dp, ip, dp]),
@@ -247,6 +248,23 @@ def residuals(A, X):
     E = np.zeros((n, d, d))
     E[0] = np.eye(d)
     return E - conv(A, X), E - conv(X, A)
+
+
+def residual_at(A, X, ks, e0_minus: bool = False) -> np.ndarray:
+    """Left residual e0 - A*X at the coefficients ks only, each by the direct
+    sum over l = 0..k (no transform); returns [len(ks), d, d].  With e0_minus
+    the first argument is q and A = e0 - q.  A and X may be longer than
+    max(ks) + 1; only their first max(ks) + 1 coefficients are read."""
+    A = _f64(A)
+    X = _f64(X)
+    n, d, _ = A.shape
+    kk = np.ascontiguousarray(ks, dtype=np.int64)
+    if kk.size and (kk.min() < 0 or kk.max() >= min(n, X.shape[0])):
+        raise ValueError("coefficient index out of range")
+    out = np.empty((kk.size, d, d))
+    _load().orc_residual_at(_p(A), int(bool(e0_minus)), _p(X), d,
+                            kk.ctypes.data_as(ctypes.POINTER(ctypes.c_long)), int(kk.size), _p(out))
+    return out
 
 
 def norm_1N(R, spectral: bool = True) -> float:

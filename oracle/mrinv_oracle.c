@@ -77,6 +77,16 @@ int orc_gj_inverse(const double *A, int d, double *Ainv)
     return 0;
 }
 
+/* Summation chunks of the recursions' inner sums: one chunk (a plain sum in
+   increasing index) while the order-k sum is small, else ORC_CHUNKS (or k, if
+   fewer) contiguous chunks.  The count never depends on the thread count. */
+#define ORC_CHUNKS 64
+static int chunks_for(double work, long k)
+{
+    if (work <= 2e5) return 1;
+    return k < ORC_CHUNKS ? (int)k : ORC_CHUNKS;
+}
+
 /* ------------------------------------------------------------------------- */
 /* Left (column-decoupled) coefficient recursion.  From the order-k          */
 /* coefficient of A*X = e0:  X(0) = A(0)^-1 and, for k >= 1,                 */
@@ -97,24 +107,21 @@ int orc_inverse_left_cols(const double *A, int d, long n, const int *cols, int n
     for (long l = 0; l < n; ++l)
         for (int r = 0; r < d; ++r)
             for (int t = 0; t < d; ++t) AT[IDX3(l, t, r, d, d)] = A[IDX3(l, r, t, d, d)];
-    int nth = orc_num_threads();
     size_t blk = (size_t)nc * d;
-    double *part = (double *)malloc(sizeof(double) * blk * (size_t)nth);
+    double *part = (double *)malloc(sizeof(double) * blk * (size_t)ORC_CHUNKS);
     double *S = (double *)malloc(sizeof(double) * blk);   /* S[c][r] */
     for (long k = 1; k < n; ++k) {
-        /* S[c][r] = sum_{l=1..k} sum_t A(l)[r][t] X(k-l)[t][c], the l-range split
-           into one contiguous chunk per thread; chunks are added in thread order. */
-        int use = ((double)k * d * d * nc > 2e5) ? nth : 1;
-#pragma omp parallel num_threads(use)
-        {
-            int me = 0, cnt = 1;
-#ifdef _OPENMP
-            me = omp_get_thread_num();
-            cnt = omp_get_num_threads();
-#endif
-            double *P = part + (size_t)me * blk;
+        /* S[c][r] = sum_{l=1..k} sum_t A(l)[r][t] X(k-l)[t][c].  The l-range is
+           cut into a number of contiguous chunks that depends on k, d and nc
+           only (never on the thread count); each chunk sums in increasing l
+           and the chunk sums are added in chunk order, so the rounding is the
+           same on every host. */
+        const int nch = chunks_for((double)k * d * d * nc, k);
+#pragma omp parallel for schedule(static)
+        for (int ch = 0; ch < nch; ++ch) {
+            double *P = part + (size_t)ch * blk;
             memset(P, 0, sizeof(double) * blk);
-            long lo = 1 + (k * me) / cnt, hi = 1 + (k * (me + 1)) / cnt;
+            long lo = 1 + (k * ch) / nch, hi = 1 + (k * (ch + 1)) / nch;
             for (long l = lo; l < hi; ++l)
                 for (int t = 0; t < d; ++t) {
                     const double *at = AT + IDX3(l, t, 0, d, d);
@@ -127,7 +134,7 @@ int orc_inverse_left_cols(const double *A, int d, long n, const int *cols, int n
         }
         for (size_t e = 0; e < blk; ++e) {
             double s = 0.0;
-            for (int th = 0; th < use; ++th) s += part[(size_t)th * blk + e];
+            for (int ch = 0; ch < nch; ++ch) s += part[(size_t)ch * blk + e];
             S[e] = s;
         }
         for (int i = 0; i < d; ++i)
@@ -165,22 +172,17 @@ int orc_inverse_row(const double *A, int d, long n, const double *alpha, double 
         for (int i = 0; i < d; ++i) s += alpha[i] * A0inv[i * d + j];
         r[j] = s;
     }
-    int nth = orc_num_threads();
-    double *part = (double *)malloc(sizeof(double) * (size_t)d * nth);
+    double *part = (double *)malloc(sizeof(double) * (size_t)d * ORC_CHUNKS);
     double *S = (double *)malloc(sizeof(double) * (size_t)d);
     for (long k = 1; k < n; ++k) {
-        /* S = sum_{l=0..k-1} r(l) A(k-l), l split into per-thread chunks added in order */
-        int use = ((double)k * d * d > 2e5) ? nth : 1;
-#pragma omp parallel num_threads(use)
-        {
-            int me = 0, cnt = 1;
-#ifdef _OPENMP
-            me = omp_get_thread_num();
-            cnt = omp_get_num_threads();
-#endif
-            double *P = part + (size_t)me * d;
+        /* S = sum_{l=0..k-1} r(l) A(k-l); fixed chunks of the l-range as in
+           orc_inverse_left_cols, added in chunk order. */
+        const int nch = chunks_for((double)k * d * d, k);
+#pragma omp parallel for schedule(static)
+        for (int ch = 0; ch < nch; ++ch) {
+            double *P = part + (size_t)ch * d;
             memset(P, 0, sizeof(double) * (size_t)d);
-            long lo = (k * me) / cnt, hi = (k * (me + 1)) / cnt;
+            long lo = (k * ch) / nch, hi = (k * (ch + 1)) / nch;
             for (long l = lo; l < hi; ++l)
                 for (int u = 0; u < d; ++u) {
                     const double a = r[(size_t)l * d + u];
@@ -190,7 +192,7 @@ int orc_inverse_row(const double *A, int d, long n, const double *alpha, double 
         }
         for (int t = 0; t < d; ++t) {
             double s = 0.0;
-            for (int th = 0; th < use; ++th) s += part[(size_t)th * d + t];
+            for (int ch = 0; ch < nch; ++ch) s += part[(size_t)ch * d + t];
             S[t] = s;
         }
         for (int j = 0; j < d; ++j) {
@@ -239,6 +241,40 @@ void orc_conv(const double *A, const double *B, int ra, int m, int cb, long n, d
                     double *crow = ck + (size_t)i * cb;
                     for (int j = 0; j < cb; ++j) crow[j] += a * brow[j];
                 }
+    }
+}
+
+/* ------------------------------------------------------------------------- */
+/* Left residual of a candidate inverse X of A at selected coefficients:     */
+/*     rho(k) = e0(k) - sum_{l=0..k} A(l) X(k-l)   for k in ks[0..nk),        */
+/* e0(0) = I, e0(k) = 0 otherwise (Section 2, eq. (convolution); Proposition  */
+/* 2.6 bounds the inverse's error by this residual).  With e0_minus != 0 the  */
+/* array holds q and A = e0 - q is formed entry by entry (A(0) = I - q(0),    */
+/* A(l) = -q(l)).  A, X are [n][d][d] with n > max ks; out is [nk][d][d].     */
+/* Each rho(k) is its own plain sum in increasing l; OpenMP runs the sampled  */
+/* coefficients in parallel.                                                 */
+/* ------------------------------------------------------------------------- */
+void orc_residual_at(const double *A, int e0_minus, const double *X, int d, const long *ks, int nk, double *out)
+{
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int s = 0; s < nk; ++s) {
+        const long k = ks[s];
+        double *rk = out + IDX3(s, 0, 0, d, d);
+        memset(rk, 0, sizeof(double) * (size_t)d * d);
+        for (long l = 0; l <= k; ++l)
+            for (int i = 0; i < d; ++i)
+                for (int t = 0; t < d; ++t) {
+                    double a = A[IDX3(l, i, t, d, d)];
+                    if (e0_minus) a = (l == 0 && i == t ? 1.0 : 0.0) - a;
+                    const double *xrow = X + IDX3(k - l, t, 0, d, d);
+                    double *rrow = rk + (size_t)i * d;
+                    for (int j = 0; j < d; ++j) rrow[j] += a * xrow[j];
+                }
+        for (int i = 0; i < d; ++i)
+            for (int j = 0; j < d; ++j) {
+                const double e = (k == 0 && i == j) ? 1.0 : 0.0;
+                rk[i * d + j] = e - rk[i * d + j];
+            }
     }
 }
 

@@ -14,22 +14,7 @@ import smk_inputs as si
 
 pytestmark = pytest.mark.gpu
 
-FP64_TOL = 1e-12
-MIXED_TOL = 1e-10
-
-
-def fp64_tol(n: int) -> float:
-    """FP64 bound for horizon n.  The rounding of an FFT product grows like
-    sqrt(L) log2(L) times the coefficient size (Proposition 2.1), and a
-    renewal sequence keeps a non-decaying plateau, so the last Newton
-    products carry it in full.  Up to n = 65536 the 1e-12 target holds;
-    beyond it the bound is scaled by sqrt(L / 2^16) * log2(L) / 16 with a
-    factor 2 of headroom (numpy's FFT-Newton reaches 2.6e-12 at n = 300000)."""
-    import math
-    lg = max(1, math.ceil(math.log2(n)))
-    if lg <= 16:
-        return FP64_TOL
-    return 2 * FP64_TOL * math.sqrt(2.0 ** (lg - 16)) * lg / 16
+from tolerances import FP64_TOL, MIXED_TOL, fp64_tol  # noqa: E402
 
 
 @pytest.fixture(scope="module")

@@ -429,3 +429,98 @@ def test_paper_lognormal_scheme_difference(orc):
     _, A_mv, R_mv = _mean_value(orc, Q, Hb, n)
     assert pf.same_digits(np.max(np.abs(A_mv - A_pd)), printed["max_dA"])
     assert pf.same_digits(np.max(np.abs(R_mv - R_pd)), printed["max_dR"])
+
+
+def test_geometric_helpers_match_the_pinned_recursion(orc):
+    """The closed-form helpers used as checkers at full size (geometric_psi,
+    geometric_P) against the left recursion and P = psi*Hbar, which the path
+    enumeration and the inline closed form above pin.  A helper with a wrong
+    power (M^k instead of M^(k-1)), a missing -diag(a) or a transposed M fails."""
+    d, n = 5, 60
+    k = si.geometric_kernel(d, n, 12)
+    q = k.q.numpy()
+    M, a = k.params["M"], k.params["a"]
+    ks = np.arange(n)
+    ps = orc.psi(q)
+    assert np.max(np.abs(orc.geometric_psi(M, a, ks) - ps)) <= 1e-14
+    assert np.max(np.abs(orc.geometric_P(M, ks) - orc.transition(ps, q))) <= 1e-13
+    # Sampled, out-of-order coefficient lists return the same values.
+    sub = np.array([37, 0, 5, 59, 1])
+    assert np.max(np.abs(orc.geometric_psi(M, a, sub) - ps[sub])) <= 1e-14
+    # The planted mistakes named above are all visible at this size.
+    wrong = [np.linalg.matrix_power(M, t) @ (M - np.diag(a)) for t in range(1, 8)]
+    assert np.max(np.abs(np.array(wrong) - ps[1:8])) > 1e-3
+    wrong = [np.linalg.matrix_power(M, t - 1) @ M for t in range(1, 8)]
+    assert np.max(np.abs(np.array(wrong) - ps[1:8])) > 1e-3
+    wrong = [np.linalg.matrix_power(M.T, t - 1) @ (M.T - np.diag(a)) for t in range(1, 8)]
+    assert np.max(np.abs(np.array(wrong) - ps[1:8])) > 1e-3
+
+
+def test_residuals_fft_matches_direct_residuals(orc):
+    """The numpy-FFT residual checker (residuals_fft) against the direct
+    residual sequences e0 - A*X and e0 - X*A of eq. (convolution) on a
+    perturbed inverse, where left and right residuals differ (matrix products
+    do not commute), so a swapped operand order or a dropped e0 fails."""
+    rng = np.random.default_rng(21)
+    d, n = 4, 50
+    q = si.weibull_kernel(d, n, 21).q.numpy()
+    X = orc.psi(q) + 1e-6 * rng.standard_normal((n, d, d))
+    RL, RR = orc.residuals(orc.e0_minus(q), X)
+    rl, rr, ml, mr_ = orc.residuals_fft(q, X, row_block=3)
+    fro = lambda R: float(np.sum(np.linalg.norm(R, axis=(1, 2))))
+    assert abs(rl - fro(RL)) <= 1e-12 * fro(RL)
+    assert abs(rr - fro(RR)) <= 1e-12 * fro(RR)
+    assert abs(ml - np.max(np.abs(RL))) <= 1e-15 and abs(mr_ - np.max(np.abs(RR))) <= 1e-15
+    assert abs(rl - rr) > 1e-3 * rl
+    # The exact inverse has residuals at rounding level.
+    rl0, rr0, ml0, mr0 = orc.residuals_fft(q, orc.psi(q))
+    assert ml0 <= 1e-15 and mr0 <= 1e-15
+
+
+def test_sampled_residual_closed_form(orc):
+    """residual_at: e0 - A*X at chosen coefficients by the direct sum.  Pins:
+    the exact inverse leaves rounding only; a perturbation eps at X(k0) alone
+    gives rho(k) = -A(k - k0) eps for k >= k0 and leaves rho(k < k0) unchanged;
+    the values at every k equal the direct residual sequence."""
+    rng = np.random.default_rng(22)
+    d, n = 3, 40
+    A = _rand_series(rng, n, d)
+    X = orc.series_inverse_left(A)
+    ks = np.array([0, 1, 7, 20, 39])
+    assert np.max(np.abs(orc.residual_at(A, X, ks))) <= 1e-14
+    eps = rng.standard_normal((d, d)) * 1e-3
+    k0 = 7
+    Xp = X.copy()
+    Xp[k0] += eps
+    got = orc.residual_at(A, Xp, ks)
+    for s, k in enumerate(ks):
+        ref = -A[k - k0] @ eps if k >= k0 else np.zeros((d, d))
+        assert np.max(np.abs(got[s] - ref)) <= 1e-14
+    RL, _ = orc.residuals(A, Xp)
+    assert np.max(np.abs(orc.residual_at(A, Xp, np.arange(n)) - RL)) <= 1e-15
+    # With e0_minus the first argument is q and A = e0 - q.
+    q = si.weibull_kernel(d, n, 23).q.numpy()
+    ps = orc.psi(q) + 1e-5
+    assert np.max(np.abs(orc.residual_at(q, ps, ks, e0_minus=True)
+                         - orc.residual_at(orc.e0_minus(q), ps, ks))) <= 1e-16
+    with pytest.raises(ValueError):
+        orc.residual_at(A, X, [n])
+
+
+def test_recursion_sums_do_not_depend_on_the_thread_count(orc):
+    """The recursions cut their inner sums into a fixed number of chunks, so
+    the oracle gives the same bits whatever OpenMP team it runs on."""
+    import subprocess
+    import sys
+    code = ("import hashlib, numpy as np, smk_inputs as si, oracle; "
+            "q = si.weibull_kernel(6, 1500, 24).q.numpy(); "
+            "x = oracle.psi(q); r = oracle.series_inverse_row(oracle.e0_minus(q), np.eye(6)[1]); "
+            "print(hashlib.sha256(x.tobytes() + r.tobytes()).hexdigest())")
+    import os
+    outs = []
+    for th in ("1", "3"):
+        env = dict(os.environ, OMP_NUM_THREADS=th)
+        outs.append(subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True,
+                                   cwd=os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                                   check=True).stdout.strip())
+    assert outs[0] == outs[1]
