@@ -16,16 +16,24 @@
  *   arrays: X[k][i][j] at X[(k*rows + i)*cols + j], k = 0..n-1, IEEE float64.
  *   Small vectors/masks documented as "host" are host pointers.
  * - Horizon: n coefficients, k = 0..n-1 (I_N of Section 2).
- * - The library never allocates device memory after mrinv_create.  Scratch
- *   memory is a caller-provided device workspace `ws` of at least
- *   mrinv_workspace_size(...) bytes (256-byte aligned).
- * - Every call only enqueues work on the handle's HIP stream and returns.
+ * - The library allocates device memory only in mrinv_create (twiddle
+ *   tables, the status word and a 16 MiB per-handle scratch area for small
+ *   vectors and time scans).  Every other buffer is the caller's: scratch
+ *   memory is a device workspace `ws` of at least mrinv_workspace_size(...)
+ *   bytes (256-byte aligned).
+ * - Calls only enqueue work on the handle's HIP stream and return, with these
+ *   exceptions, each stated at its declaration: mrinv_sync_status,
+ *   mrinv_residual_norms, mrinv_autotune, mrinv_kernel_stats and
+ *   mrinv_psi_inverse_batched_prepare (hence mrinv_psi_inverse_batched) wait
+ *   for the stream.  Calls that only enqueue can be recorded into a HIP graph
+ *   (stream capture) and replayed; the mrinv_create of the handle must come
+ *   before the capture.
  *   Argument errors are reported synchronously and enqueue nothing.
  *   Conditions found on the device (singular A(0), non-finite values) set a
  *   sticky device status word that mrinv_sync_status() reads and clears;
  *   affected outputs are NaN.
- * - Outputs must not alias inputs.  A handle is not thread-safe; use one
- *   handle per stream.
+ * - Outputs must not alias inputs.  A handle is not thread-safe and its
+ *   scratch area is used in stream order: use one handle per stream.
  * - No C++ exception crosses this interface.
  */
 #ifndef MRINV_H
@@ -74,8 +82,10 @@ typedef enum {
 typedef struct mrinv_handle_s *mrinv_handle_t;
 
 /* Create a handle bound to `stream` (a hipStream_t; NULL = default stream)
- * on the current device.  Allocates the twiddle tables and the device status
- * word (the only device allocations the library makes). */
+ * on the current device.  Allocates the twiddle tables, the device status
+ * word and the 16 MiB scratch area (the only device allocations the library
+ * makes) and waits for the device.  mrinv_destroy waits for the stream and
+ * frees them. */
 mrinv_status_t mrinv_create(mrinv_handle_t *handle, void *stream);
 mrinv_status_t mrinv_destroy(mrinv_handle_t handle);
 mrinv_status_t mrinv_set_stream(mrinv_handle_t handle, void *stream);
@@ -103,9 +113,11 @@ size_t mrinv_workspace_size(mrinv_op_t op, int d, int64_t n, int r, mrinv_precis
  * B <- B*(2 e0 - A*B) (eq. (newton)) doubling the number of exact
  * coefficients each step, the final step truncated to n.
  * MRINV_MIXED_FP32 runs the Newton steps with float32 transforms and products,
- * then forms the residual R = e0 - A*X in float64 over the whole horizon and
- * returns X + X*R (one Newton sweep whose residual is float64; Proposition 2.6
- * bounds the remaining error by the residual).
+ * then two residual sweeps: each forms R = e0 - A*X in float64 over the whole
+ * horizon (transforms of length 2^ceil(log2(2n-1)), no wrap-around) and sets
+ * X <- X + X*R with the correction product in float32.  Each sweep squares
+ * the residual (Appendix, algorithmic details: e0 - A*B_{r+1} =
+ * (e0 - A*B_r)^2); Proposition 2.6 bounds the remaining error by it.
  * 1 <= d <= 64, 1 <= n <= MRINV_MAX_N.
  */
 mrinv_status_t mrinv_psi_inverse(mrinv_handle_t h, const double *q, int d, int64_t n,
@@ -153,7 +165,9 @@ mrinv_status_t mrinv_gather_block(mrinv_handle_t h, const double *X, int64_t n, 
 
 /* Composite functionals (Section 4.1 / Table 2), all float64 outputs [n].
  * in_D / up : host int masks of length d; alpha : host float64 [d] initial
- * law (entries outside C, resp. U, are ignored).
+ * law (entries outside C, resp. U, are ignored).  The host arrays are read
+ * during the call and travel to the device as kernel arguments: they may be
+ * reused as soon as the call returns, and a recorded graph keeps their values.
  *   first entrance: g(k) = alpha_C g_D(k) 1_D and F(k) = sum_{l<=k} g(l) with
  *     g_D = (e0^C - q_CC)^-1 * q_CD  (eqs. (first-entrance-mass), (first-entrance-cdf)).
  *   reliability:    R(k) = 1 - F_D(k) with D = complement of `up`.
@@ -222,6 +236,19 @@ mrinv_status_t mrinv_scatter_block_add(mrinv_handle_t h, const double *Y_bar, in
 mrinv_status_t mrinv_psi_inverse_batched(mrinv_handle_t h, int count, const double *const *q_ptrs,
                                          const int *d, const int64_t *n, mrinv_precision_t precision,
                                          double *const *psi_ptrs, void *ws, size_t ws_bytes);
+/* mrinv_psi_inverse_batched in two parts.  _prepare plans every launch, writes
+ * the descriptor table into the head of ws (from host memory the plan owns)
+ * and waits for the stream until it is there; the plan is kept in the handle,
+ * replacing an earlier one.  _launch enqueues the prepared launches on the
+ * handle's current stream and only enqueues, so it can be recorded into a HIP
+ * graph and replayed; ws must still hold the table (the launches do not
+ * write it), q must hold the inputs and psi receives the results each time.
+ * mrinv_psi_inverse_batched = _prepare, then _launch.  _launch without a
+ * prepared plan returns MRINV_E_ARG. */
+mrinv_status_t mrinv_psi_inverse_batched_prepare(mrinv_handle_t h, int count, const double *const *q_ptrs,
+                                                 const int *d, const int64_t *n, mrinv_precision_t precision,
+                                                 double *const *psi_ptrs, void *ws, size_t ws_bytes);
+mrinv_status_t mrinv_psi_inverse_batched_launch(mrinv_handle_t h);
 size_t mrinv_batched_workspace_size(mrinv_handle_t h, int count, const int *d, const int64_t *n,
                                     mrinv_precision_t precision);
 
@@ -243,7 +270,9 @@ typedef struct {
                            Batched calls use at most 16 (16 for 0). */
     int lanes_fp32;     /* the same in float32; automatic: 32 for passes of <= 256 rows when d >= 32 */
     int seed_m0;        /* coefficients formed by the coefficient recursion (Section 2.2) before
-                           Newton starts; rounded down to a power of two, 1..256 (default 1: none) */
+                           Newton starts; rounded down to a power of two, 1..256 (default 1: none).
+                           A call whose seed needs more than 64 KiB of LDS ((m0 d + d^2 + 256 + d) * 8
+                           bytes; at d = 64 that is m0 > 32) returns MRINV_E_UNSUPPORTED. */
     int pair_forward;   /* nonzero: forward transforms of both Newton operands in one launch (default 1) */
     int twiddle_tables; /* 0: every twiddle is a product of two table entries formed on the fly;
                            1: in-workgroup twiddles from a 512-root table; 2: also per-pass outer

@@ -31,7 +31,7 @@ __all__ = [
     "gather_block", "psi_inverse_backward", "markov_renewal_apply_backward", "transition_backward",
     "contract_backward", "scatter_block_add", "psi_inverse_batched", "residual_norms", "sync_status",
     "PsiInverse", "RenewalApply", "Transition", "Contract", "GatherBlock", "workspace_size",
-    "FP64", "MIXED_FP32", "OPS", "Tuning", "get_tuning", "set_tuning", "autotune",
+    "FP64", "MIXED_FP32", "OPS", "Tuning", "get_tuning", "set_tuning", "autotune", "BatchedPlan",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -108,6 +108,9 @@ def lib():
             "mrinv_scatter_block_add": (i32, [vp, vp, i64, i32, i32, vp, i32, vp, i32, vp]),
             "mrinv_psi_inverse_batched": (i32, [vp, i32, ctypes.POINTER(vp), ip, ctypes.POINTER(i64), i32,
                                                 ctypes.POINTER(vp), vp, sz]),
+            "mrinv_psi_inverse_batched_prepare": (i32, [vp, i32, ctypes.POINTER(vp), ip, ctypes.POINTER(i64), i32,
+                                                        ctypes.POINTER(vp), vp, sz]),
+            "mrinv_psi_inverse_batched_launch": (i32, [vp]),
             "mrinv_batched_workspace_size": (sz, [vp, i32, ip, ctypes.POINTER(i64), i32]),
             "mrinv_residual_norms": (i32, [vp, vp, vp, i32, i64, dp, vp, sz]),
             "mrinv_get_tuning": (i32, [vp, ctypes.POINTER(Tuning)]),
@@ -129,17 +132,27 @@ def _check(status: int):
 
 
 def _handle(device: torch.device):
-    """Per-device library handle bound to torch's current stream."""
+    """The library handle of (device, torch's current stream on it).
+
+    A handle's scratch area is used in stream order, so each stream gets its
+    own handle (the library's contract: one handle per stream).  Handles live
+    until the process ends.  mrinv_create allocates and waits for the device:
+    a stream that is being captured into a graph must have made one call
+    before the capture."""
     idx = device.index if device.index is not None else torch.cuda.current_device()
+    stream = torch.cuda.current_stream(idx).cuda_stream
     L = lib()
-    h = _handles.get(idx)
+    key = (idx, stream)
+    h = _handles.get(key)
     if h is None:
-        with torch.cuda.device(idx):
-            hv = ctypes.c_void_p()
-            _check(L.mrinv_create(ctypes.byref(hv), ctypes.c_void_p(torch.cuda.current_stream(idx).cuda_stream)))
-        h = hv
-        _handles[idx] = h
-    _check(L.mrinv_set_stream(h, ctypes.c_void_p(torch.cuda.current_stream(idx).cuda_stream)))
+        with _lock:
+            h = _handles.get(key)
+            if h is None:
+                with torch.cuda.device(idx):
+                    hv = ctypes.c_void_p()
+                    _check(L.mrinv_create(ctypes.byref(hv), ctypes.c_void_p(stream)))
+                h = hv
+                _handles[key] = h
     return h
 
 
@@ -147,7 +160,7 @@ def _ptr(t):
     return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
 
 
-def _seq(x: torch.Tensor, name: str, rows=None, cols=None) -> torch.Tensor:
+def _seq(x: torch.Tensor, name: str, rows=None, cols=None, n=None) -> torch.Tensor:
     if not isinstance(x, torch.Tensor):
         raise TypeError(f"{name} must be a torch.Tensor")
     if x.device.type != "cuda":
@@ -158,6 +171,8 @@ def _seq(x: torch.Tensor, name: str, rows=None, cols=None) -> torch.Tensor:
         raise MrinvError(1, f"{name} must have shape [n, rows, cols]")
     if rows is not None and x.shape[1] != rows or cols is not None and x.shape[2] != cols:
         raise MrinvError(1, f"{name} has shape {tuple(x.shape)}")
+    if n is not None and x.shape[0] != n:
+        raise MrinvError(1, f"{name} has horizon {x.shape[0]}, expected {n}")
     return x.contiguous()
 
 
@@ -247,11 +262,9 @@ def series_inverse(A: torch.Tensor, precision="fp64", check: bool = False) -> to
 
 def markov_renewal_apply(psi: torch.Tensor, L: torch.Tensor) -> torch.Tensor:
     """M = psi * L truncated at n (L: [n, d, r])."""
-    psi = _seq(psi, "psi")
+    psi = _square(psi, "psi")
     n, d, _ = psi.shape
-    L = _seq(L, "L", rows=d)
-    if L.shape[0] != n:
-        raise MrinvError(1, "L horizon differs from psi")
+    L = _seq(L, "L", rows=d, n=n)
     r = L.shape[2]
     M = torch.empty_like(L)
     ws = _ws(lib().mrinv_workspace_size(1, d, n, r, 0), psi.device)
@@ -262,9 +275,9 @@ def markov_renewal_apply(psi: torch.Tensor, L: torch.Tensor) -> torch.Tensor:
 
 def transition(psi: torch.Tensor, q: torch.Tensor) -> torch.Tensor:
     """P = psi * Hbar(q) (eq. (transition-discrete))."""
-    psi = _seq(psi, "psi")
+    psi = _square(psi, "psi")
     n, d, _ = psi.shape
-    q = _seq(q, "q", d, d)
+    q = _seq(q, "q", d, d, n=n)
     P = torch.empty_like(psi)
     ws = _ws(lib().mrinv_workspace_size(2, d, n, 0, 0), psi.device)
     _check(lib().mrinv_transition(_handle(psi.device), _ptr(psi), _ptr(q), d, n, _ptr(P), _ptr(ws), ws.numel()))
@@ -273,7 +286,7 @@ def transition(psi: torch.Tensor, q: torch.Tensor) -> torch.Tensor:
 
 def survival(q: torch.Tensor) -> torch.Tensor:
     """Diagonal of Hbar: [n, d]."""
-    q = _seq(q, "q")
+    q = _square(q, "q")
     n, d, _ = q.shape
     hb = torch.empty((n, d), dtype=torch.float64, device=q.device)
     _check(lib().mrinv_survival(_handle(q.device), _ptr(q), d, n, _ptr(hb)))
@@ -299,9 +312,22 @@ def contract(X: torch.Tensor, u, v, cumulative: bool = False, offset: float = 0.
     return out
 
 
+def _indices(idx, bound: int, name: str, distinct: bool = False) -> torch.Tensor:
+    t = torch.as_tensor(idx, dtype=torch.int64).reshape(-1)
+    if t.numel() < 1:
+        raise MrinvError(1, f"{name} is empty")
+    if int(t.min()) < 0 or int(t.max()) >= bound:
+        raise MrinvError(1, f"{name} has an index outside [0, {bound})")
+    if distinct and torch.unique(t).numel() != t.numel():
+        raise MrinvError(1, f"{name} has repeated indices")
+    return t.to(torch.int32)
+
+
 def gather_block(X: torch.Tensor, rows_idx, cols_idx) -> torch.Tensor:
     X = _seq(X, "X")
     n, r, c = X.shape
+    rows_idx = _indices(rows_idx, r, "rows_idx")
+    cols_idx = _indices(cols_idx, c, "cols_idx")
     ri = torch.as_tensor(rows_idx, dtype=torch.int32).to(X.device).contiguous()
     ci = torch.as_tensor(cols_idx, dtype=torch.int32).to(X.device).contiguous()
     Y = torch.empty((n, ri.numel(), ci.numel()), dtype=torch.float64, device=X.device)
@@ -326,7 +352,7 @@ def _dalpha(alpha, d):
 
 def first_entrance(q: torch.Tensor, in_D, alpha, precision="fp64"):
     """(g, F): first-entrance mass alpha_C g_D(k) 1_D and cdf F_D(k) (eqs. (first-entrance-mass, -cdf))."""
-    q = _seq(q, "q")
+    q = _square(q, "q")
     n, d, _ = q.shape
     mask = [int(bool(x)) for x in list(in_D)]
     prec = _PREC[precision]
@@ -340,7 +366,7 @@ def first_entrance(q: torch.Tensor, in_D, alpha, precision="fp64"):
 
 def reliability(q: torch.Tensor, up, alpha, precision="fp64") -> torch.Tensor:
     """R(k) = 1 - F_D(k) with D the complement of the up set."""
-    q = _seq(q, "q")
+    q = _square(q, "q")
     n, d, _ = q.shape
     mask = [int(bool(x)) for x in list(up)]
     prec = _PREC[precision]
@@ -353,7 +379,7 @@ def reliability(q: torch.Tensor, up, alpha, precision="fp64") -> torch.Tensor:
 
 def availability(P: torch.Tensor, up, alpha) -> torch.Tensor:
     """A(k) = alpha P(k) 1_U."""
-    P = _seq(P, "P")
+    P = _square(P, "P")
     n, d, _ = P.shape
     A = torch.empty(n, dtype=torch.float64, device=P.device)
     _check(lib().mrinv_availability(_handle(P.device), _ptr(P), d, n, _imask(up, d), _dalpha(alpha, d), _ptr(A)))
@@ -362,9 +388,9 @@ def availability(P: torch.Tensor, up, alpha) -> torch.Tensor:
 
 def residual_norms(q: torch.Tensor, X: torch.Tensor):
     """(sum_k ||e0 - A*X||_F, sum_k ||e0 - X*A||_F, max |e0 - A*X|) with A = e0 - q."""
-    q = _seq(q, "q")
+    q = _square(q, "q")
     n, d, _ = q.shape
-    X = _seq(X, "X", d, d)
+    X = _seq(X, "X", d, d, n=n)
     L = lib()
     ws = _ws(L.mrinv_workspace_size(8, d, n, 0, 0), q.device)
     out = (ctypes.c_double * 3)()
@@ -376,7 +402,7 @@ def psi_inverse_batched(qs, precision="mixed"):
     """Invert a list of kernels of uneven (d, n); returns the list of psi."""
     if not qs:
         return []
-    qs = [_seq(q, f"q[{i}]") for i, q in enumerate(qs)]
+    qs = [_square(q, f"q[{i}]") for i, q in enumerate(qs)]
     dev = qs[0].device
     count = len(qs)
     prec = _PREC[precision]
@@ -387,18 +413,73 @@ def psi_inverse_batched(qs, precision="mixed"):
     op = (ctypes.c_void_p * count)(*[o.data_ptr() for o in outs])
     L = lib()
     ws = _ws(L.mrinv_batched_workspace_size(_handle(dev), count, d_arr, n_arr, prec), dev)
-    _check(L.mrinv_psi_inverse_batched(_handle(dev), count, qp, d_arr, n_arr, prec, op, _ptr(ws), ws.numel()))
+    h = _handle(dev)
+    _batched_owner[h.value] = None      # this call's plan replaces any prepared BatchedPlan on the stream
+    _check(L.mrinv_psi_inverse_batched(h, count, qp, d_arr, n_arr, prec, op, _ptr(ws), ws.numel()))
     return outs
+
+
+class BatchedPlan:
+    """A prepared batched inversion (mrinv_psi_inverse_batched_prepare).
+
+    The constructor plans every launch for the kernels ``qs`` and writes the
+    descriptor table into its own workspace (it waits for the stream);
+    :meth:`launch` only enqueues the launches, so it can be recorded into a
+    CUDA/HIP graph on the same stream and replayed.  ``outs`` receive the
+    inverses each time; ``qs`` must keep holding the inputs.  The library
+    keeps one prepared plan per handle (per stream): preparing another plan on
+    the same stream retires this one."""
+
+    def __init__(self, qs, precision="mixed"):
+        if not qs:
+            raise MrinvError(1, "empty batch")
+        self.qs = [_seq(q, f"q[{i}]") for i, q in enumerate(qs)]
+        for i, q in enumerate(self.qs):
+            if q.shape[1] != q.shape[2]:
+                raise MrinvError(1, f"q[{i}] must be square")
+        self.device = self.qs[0].device
+        self.stream = torch.cuda.current_stream(self.device).cuda_stream
+        count = len(self.qs)
+        prec = _PREC[precision]
+        self.outs = [torch.empty_like(q) for q in self.qs]
+        d_arr = (ctypes.c_int * count)(*[q.shape[1] for q in self.qs])
+        n_arr = (ctypes.c_int64 * count)(*[q.shape[0] for q in self.qs])
+        qp = (ctypes.c_void_p * count)(*[q.data_ptr() for q in self.qs])
+        op = (ctypes.c_void_p * count)(*[o.data_ptr() for o in self.outs])
+        L = lib()
+        self.h = _handle(self.device)
+        self.ws = _ws(L.mrinv_batched_workspace_size(self.h, count, d_arr, n_arr, prec), self.device)
+        _check(L.mrinv_psi_inverse_batched_prepare(self.h, count, qp, d_arr, n_arr, prec, op, _ptr(self.ws),
+                                                   self.ws.numel()))
+        _batched_owner[self.h.value] = id(self)
+
+    def launch(self):
+        if torch.cuda.current_stream(self.device).cuda_stream != self.stream:
+            raise MrinvError(1, "launch on the stream the plan was prepared on")
+        if _batched_owner.get(self.h.value) != id(self):
+            raise MrinvError(1, "another batched plan was prepared on this stream since")
+        _check(lib().mrinv_psi_inverse_batched_launch(self.h))
+        return self.outs
+
+
+_batched_owner: dict = {}
 
 
 # ---------------------------------------------------------------------------
 # Adjoint entry points
 # ---------------------------------------------------------------------------
 
+def _square(x: torch.Tensor, name: str) -> torch.Tensor:
+    x = _seq(x, name)
+    if x.shape[1] != x.shape[2]:
+        raise MrinvError(1, f"{name} must be square, got {tuple(x.shape)}")
+    return x
+
+
 def psi_inverse_backward(psi: torch.Tensor, psi_bar: torch.Tensor) -> torch.Tensor:
-    psi = _seq(psi, "psi")
+    psi = _square(psi, "psi")
     n, d, _ = psi.shape
-    psi_bar = _seq(psi_bar, "psi_bar", d, d)
+    psi_bar = _seq(psi_bar, "psi_bar", d, d, n=n)
     qb = torch.empty_like(psi)
     ws = _ws(lib().mrinv_workspace_size(3, d, n, 0, 0), psi.device)
     _check(lib().mrinv_psi_inverse_backward(_handle(psi.device), _ptr(psi), _ptr(psi_bar), d, n, _ptr(qb), _ptr(ws),
@@ -407,11 +488,11 @@ def psi_inverse_backward(psi: torch.Tensor, psi_bar: torch.Tensor) -> torch.Tens
 
 
 def markov_renewal_apply_backward(psi, L, M_bar, need_psi=True, need_L=True):
-    psi = _seq(psi, "psi")
+    psi = _square(psi, "psi")
     n, d, _ = psi.shape
-    L = _seq(L, "L", rows=d)
+    L = _seq(L, "L", rows=d, n=n)
     r = L.shape[2]
-    M_bar = _seq(M_bar, "M_bar", d, r)
+    M_bar = _seq(M_bar, "M_bar", d, r, n=n)
     pb = torch.zeros_like(psi) if need_psi else None
     lb = torch.empty_like(L) if need_L else None
     ws = _ws(lib().mrinv_workspace_size(4, d, n, r, 0), psi.device)
@@ -421,10 +502,10 @@ def markov_renewal_apply_backward(psi, L, M_bar, need_psi=True, need_L=True):
 
 
 def transition_backward(psi, q, P_bar, need_psi=True, need_q=True):
-    psi = _seq(psi, "psi")
+    psi = _square(psi, "psi")
     n, d, _ = psi.shape
-    q = _seq(q, "q", d, d)
-    P_bar = _seq(P_bar, "P_bar", d, d)
+    q = _seq(q, "q", d, d, n=n)
+    P_bar = _seq(P_bar, "P_bar", d, d, n=n)
     pb = torch.zeros_like(psi) if need_psi else None
     qb = torch.zeros_like(q) if need_q else None
     ws = _ws(lib().mrinv_workspace_size(5, d, n, 0, 0), psi.device)
@@ -434,6 +515,8 @@ def transition_backward(psi, q, P_bar, need_psi=True, need_q=True):
 
 
 def contract_backward(out_bar, rows, cols, u, v, cumulative=False, scale=1.0) -> torch.Tensor:
+    if out_bar.device.type != "cuda" or out_bar.dtype != torch.float64 or out_bar.dim() != 1:
+        raise MrinvError(1, "out_bar must be a 1-D float64 GPU tensor")
     out_bar = out_bar.contiguous()
     n = out_bar.numel()
     dev = out_bar.device
@@ -446,11 +529,15 @@ def contract_backward(out_bar, rows, cols, u, v, cumulative=False, scale=1.0) ->
 
 
 def scatter_block_add(Y_bar, rows, cols, rows_idx, cols_idx, X_bar=None) -> torch.Tensor:
-    Y_bar = Y_bar.contiguous()
+    rows_idx = _indices(rows_idx, rows, "rows_idx", distinct=True)
+    cols_idx = _indices(cols_idx, cols, "cols_idx", distinct=True)
+    Y_bar = _seq(Y_bar, "Y_bar", rows_idx.numel(), cols_idx.numel())
     n = Y_bar.shape[0]
     dev = Y_bar.device
     if X_bar is None:
         X_bar = torch.zeros((n, rows, cols), dtype=torch.float64, device=dev)
+    elif tuple(X_bar.shape) != (n, rows, cols) or not X_bar.is_contiguous() or X_bar.dtype != torch.float64:
+        raise MrinvError(1, f"X_bar must be a contiguous float64 [{n}, {rows}, {cols}] tensor")
     ri = torch.as_tensor(rows_idx, dtype=torch.int32).to(dev).contiguous()
     ci = torch.as_tensor(cols_idx, dtype=torch.int32).to(dev).contiguous()
     _check(lib().mrinv_scatter_block_add(_handle(dev), _ptr(Y_bar), n, rows, cols, _ptr(ri), ri.numel(), _ptr(ci),

@@ -72,9 +72,7 @@ struct mrinv_handle_s {
         hipGraphExec_t exec = nullptr;
     } gc;
     hipStream_t cap_stream = nullptr;
-    void *pinned = nullptr;         // pinned staging buffer of batched descriptor tables
-    size_t pinned_bytes = 0;
-    hipEvent_t pinned_done = nullptr;   // recorded after the last transfer out of `pinned`
+    void *batch = nullptr;          // plan of the last mrinv_psi_inverse_batched_prepare (BatchPlan)
     Twiddles<double> t64() const { return {tw64, tw64 + TW_HI_SIZE, tw64 + TW_HI_SIZE + TW_LO_SIZE, nullptr}; }
     Twiddles<float> t32() const { return {tw64, tw64 + TW_HI_SIZE, tw64 + TW_HI_SIZE + TW_LO_SIZE, nullptr}; }
 };
@@ -92,6 +90,8 @@ static void host_twiddles(std::vector<double2> &hi, std::vector<double2> &lo) {
     for (int j = 0; j < TW_HI_SIZE; ++j) hi[j] = w((int64_t)j << TW_LO_BITS);
     for (int j = 0; j < TW_LO_SIZE; ++j) lo[j] = w(j);
 }
+
+static void batch_plan_free(void *plan);
 
 extern "C" mrinv_status_t mrinv_create(mrinv_handle_t *handle, void *stream) {
     if (!handle) return fail(MRINV_E_ARG, "handle is NULL");
@@ -116,7 +116,6 @@ extern "C" mrinv_status_t mrinv_create(mrinv_handle_t *handle, void *stream) {
         HIP_TRY(hipMemcpy(h->tw64 + TW_HI_SIZE + TW_LO_SIZE, root.data(), 512 * sizeof(double2),
                           hipMemcpyHostToDevice));
         HIP_TRY(hipMemset(h->status, 0, 256));
-        HIP_TRY(hipEventCreateWithFlags(&h->pinned_done, hipEventDisableTiming));
         HIP_TRY(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
         HIP_TRY(hipDeviceSynchronize());
         return MRINV_OK;
@@ -144,8 +143,7 @@ extern "C" mrinv_status_t mrinv_destroy(mrinv_handle_t h) {
     if (h->gc.exec) (void)hipGraphExecDestroy(h->gc.exec);
     if (h->gc.graph) (void)hipGraphDestroy(h->gc.graph);
     if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
-    if (h->pinned) (void)hipHostFree(h->pinned);
-    if (h->pinned_done) (void)hipEventDestroy(h->pinned_done);
+    batch_plan_free(h->batch);
     delete h;
     return MRINV_OK;
 }
@@ -605,6 +603,18 @@ static mrinv_status_t check_dn(int d, int64_t n) {
     return MRINV_OK;
 }
 
+// The recursion seed keeps a column's history, A(0)^-1 and its partial sums in
+// LDS; launches stay within the 64 KiB of dynamic LDS a kernel gets without
+// a raised limit (at d = 64 that allows seeds of up to 32 coefficients).
+constexpr size_t SEED_LDS_MAX = 64 * 1024;
+
+static mrinv_status_t check_seed(int64_t m0, int d) {
+    if (m0 > 1 && seed_lds_bytes((int)m0, d) > SEED_LDS_MAX)
+        return fail(MRINV_E_UNSUPPORTED, "seed_m0=%lld at d=%d needs %zu bytes of LDS (limit %zu)", (long long)m0, d,
+                    seed_lds_bytes((int)m0, d), SEED_LDS_MAX);
+    return MRINV_OK;
+}
+
 static mrinv_status_t check_ws(void *ws, size_t have, size_t need) {
     if (need > have) return fail(MRINV_E_WORKSPACE, "workspace %zu bytes < %zu needed", have, need);
     if (need && !ws) return fail(MRINV_E_WORKSPACE, "workspace is NULL");
@@ -631,6 +641,7 @@ static mrinv_status_t inverse_impl(mrinv_handle_t h, const double *src, int e0, 
     CHECK(check_dn(d, n));
     if (prec != MRINV_FP64 && prec != MRINV_MIXED_FP32) return fail(MRINV_E_ARG, "unknown precision %d", (int)prec);
     CHECK(check_ws(ws, wsb, ws_psi(d, n, prec)));
+    CHECK(check_seed(seed_len(h, n), d));
     const int64_t d2 = (int64_t)d * d;
     const int nl = nl_of(d2);
     const int lgN = std::max(1, ceil_log2(n));
@@ -839,7 +850,8 @@ extern "C" mrinv_status_t mrinv_autotune(mrinv_handle_t h, const double *q, int 
         mrinv_status_t st = time_inverse(h, q, d, n, precision, psi, ws, wsb, 3, &ms);
         if (st != MRINV_OK) {
             h->tune = best;   // a failed trial leaves the best tuning so far in the handle
-            return st;
+            // a candidate this problem cannot run (e.g. a seed too long for LDS) is skipped
+            return st == MRINV_E_UNSUPPORTED ? MRINV_OK : st;
         }
         if (ms < best_ms) { best_ms = ms; best = t; }
         return MRINV_OK;
@@ -962,27 +974,33 @@ extern "C" mrinv_status_t mrinv_scatter_block_add(mrinv_handle_t h, const double
 }
 
 // Device copies of small host vectors, placed in the handle scratch after the
-// first MRINV_MAX_N doubles (which the 1-lane scans use).
+// first MRINV_MAX_N doubles (which the 1-lane scans use).  They travel as
+// kernel arguments (put_small_vectors), so no host buffer has to outlive the
+// call and nothing waits for the stream.
 struct SmallVecs {
     int *ci, *di;
     double *alpha, *ones;
 };
 
-static mrinv_status_t put_small(mrinv_handle_t h, const std::vector<int> &ci, const std::vector<int> &di,
-                                const std::vector<double> &alpha, int nones, SmallVecs &sv) {
+static mrinv_status_t put_small(mrinv_handle_t h, const int *ci, int nci, const int *di, int ndi, const double *alpha,
+                                int nalpha, const double *ones, int nones, SmallVecs &sv) {
     char *base = (char *)(h->scratch + MRINV_MAX_N);
     sv.ci = (int *)base;
     sv.di = (int *)(base + 1024);
     sv.alpha = (double *)(base + 2048);
     sv.ones = (double *)(base + 2048 + 1024);
-    std::vector<double> ones(std::max(nones, 1), 1.0);
-    if (!ci.empty()) HIP_TRY(hipMemcpyAsync(sv.ci, ci.data(), ci.size() * sizeof(int), hipMemcpyHostToDevice, h->stream));
-    if (!di.empty()) HIP_TRY(hipMemcpyAsync(sv.di, di.data(), di.size() * sizeof(int), hipMemcpyHostToDevice, h->stream));
-    if (!alpha.empty())
-        HIP_TRY(hipMemcpyAsync(sv.alpha, alpha.data(), alpha.size() * sizeof(double), hipMemcpyHostToDevice, h->stream));
-    HIP_TRY(hipMemcpyAsync(sv.ones, ones.data(), ones.size() * sizeof(double), hipMemcpyHostToDevice, h->stream));
-    // The host vectors above are about to go out of scope.
-    HIP_TRY(hipStreamSynchronize(h->stream));
+    if (nci > SMALL_MAX || ndi > SMALL_MAX || nalpha > SMALL_MAX || nones > SMALL_MAX)
+        return fail(MRINV_E_UNSUPPORTED, "small vector longer than %d", SMALL_MAX);
+    SmallVecArgs v{};
+    v.nci = nci;
+    v.ndi = ndi;
+    v.nalpha = nalpha;
+    v.nones = nones;
+    for (int i = 0; i < nci; ++i) v.ci[i] = ci[i];
+    for (int i = 0; i < ndi; ++i) v.di[i] = di[i];
+    for (int i = 0; i < nalpha; ++i) v.alpha[i] = alpha[i];
+    for (int i = 0; i < nones; ++i) v.ones[i] = ones ? ones[i] : 1.0;
+    HIP_TRY(put_small_vectors(v, sv.ci, sv.di, sv.alpha, sv.ones, h->stream));
     return MRINV_OK;
 }
 
@@ -991,10 +1009,13 @@ static mrinv_status_t first_entrance_impl(mrinv_handle_t h, const double *q, int
                                           double offset, double scale, void *ws, size_t wsb) {
     if (!h || !q || !in_D || !alpha || !F) return fail(MRINV_E_ARG, "NULL handle or pointer");
     CHECK(check_dn(d, n));
-    std::vector<int> ci, di;
-    for (int i = 0; i < d; ++i) (in_D[i] ? di : ci).push_back(i);
-    if (di.empty()) return fail(MRINV_E_ARG, "target set D is empty");
-    const int nC = (int)ci.size(), nD = (int)di.size();
+    int ci[SMALL_MAX], di[SMALL_MAX];
+    int nC = 0, nD = 0;
+    for (int i = 0; i < d; ++i) {
+        if (in_D[i]) di[nD++] = i;
+        else ci[nC++] = i;
+    }
+    if (nD == 0) return fail(MRINV_E_ARG, "target set D is empty");
     CHECK(check_ws(ws, wsb, ws_first_entrance(d, n, nD, prec)));
     if (nC == 0) {
         // Already in D at time 0.
@@ -1005,10 +1026,10 @@ static mrinv_status_t first_entrance_impl(mrinv_handle_t h, const double *q, int
         }
         return MRINV_OK;
     }
-    std::vector<double> aC(nC);
+    double aC[SMALL_MAX];
     for (int a = 0; a < nC; ++a) aC[a] = alpha[ci[a]];
     SmallVecs sv;
-    CHECK(put_small(h, ci, di, aC, std::max(nD, nC), sv));
+    CHECK(put_small(h, ci, nC, di, nD, aC, nC, nullptr, std::max(nD, nC), sv));
     Carve cv(ws);
     double *qCC = cv.take<double>((size_t)n * nC * nC * 8);
     double *qCD = cv.take<double>((size_t)n * nC * nD * 8);
@@ -1045,9 +1066,9 @@ extern "C" mrinv_status_t mrinv_reliability(mrinv_handle_t h, const double *q, i
     TimerScope _ts(h);
     if (!up) return fail(MRINV_E_ARG, "NULL up mask");
     if (d < 1 || d > MRINV_MAX_D) return check_dn(d, n);
-    std::vector<int> down(d);
+    int down[MRINV_MAX_D];
     for (int i = 0; i < d; ++i) down[i] = up[i] ? 0 : 1;
-    return first_entrance_impl(h, q, d, n, down.data(), alpha, precision, nullptr, R, 1.0, -1.0, ws, wsb);
+    return first_entrance_impl(h, q, d, n, down, alpha, precision, nullptr, R, 1.0, -1.0, ws, wsb);
 }
 
 extern "C" mrinv_status_t mrinv_availability(mrinv_handle_t h, const double *P, int d, int64_t n, const int *up,
@@ -1055,12 +1076,10 @@ extern "C" mrinv_status_t mrinv_availability(mrinv_handle_t h, const double *P, 
     TimerScope _ts(h);
     if (!h || !P || !up || !alpha || !A) return fail(MRINV_E_ARG, "NULL handle or pointer");
     CHECK(check_dn(d, n));
-    std::vector<double> al(alpha, alpha + d), ind(d);
+    double ind[MRINV_MAX_D];
     for (int i = 0; i < d; ++i) ind[i] = up[i] ? 1.0 : 0.0;
     SmallVecs sv;
-    CHECK(put_small(h, {}, {}, al, d, sv));
-    HIP_TRY(hipMemcpyAsync(sv.ones, ind.data(), d * sizeof(double), hipMemcpyHostToDevice, h->stream));
-    HIP_TRY(hipStreamSynchronize(h->stream));
+    CHECK(put_small(h, nullptr, 0, nullptr, 0, alpha, d, ind, d, sv));
     HIP_TRY(contract(P, n, d, d, sv.alpha, sv.ones, 0, 0.0, 1.0, A, h->scratch + SCRATCH_SCAN_OFF, h->stream));
     return MRINV_OK;
 }
@@ -1210,15 +1229,15 @@ extern "C" mrinv_status_t mrinv_residual_norms(mrinv_handle_t h, const double *q
 // ---------------------------------------------------------------------------
 // Handle fields for the planner, which also runs without a handle to size
 // the workspace.
-static hipStream_t stream_of(mrinv_handle_t h) { return h ? h->stream : nullptr; }
 static unsigned int *status_of(mrinv_handle_t h) { return h ? h->status : nullptr; }
 
 constexpr size_t BATCH_SPEC_CAP = (size_t)24 << 30;
 
 struct BatchPlan {
     std::vector<unsigned char> table;        // host image of the device descriptor table
-    std::vector<std::function<hipError_t(char *)>> launches;   // each takes the device table base
+    std::vector<std::function<hipError_t(char *, hipStream_t)>> launches;   // device table base, stream
     size_t table_bytes = 0, x_off = 0, r_off = 0, spec_off = 0, spec_bytes = 0, total = 0;
+    char *ws = nullptr;                                       // workspace the table was uploaded to
     template <typename D> size_t put(const std::vector<D> &v) {
         const size_t off = align256(table.size());
         table.resize(off + v.size() * sizeof(D));
@@ -1246,8 +1265,7 @@ static void plan_fft(BatchPlan &bp, mrinv_handle_t h, int mode, const FftPlan &p
         const size_t off = bp.put(g);
         const int cnt = (int)g.size();
         const Twiddles<T> tw = tw_of<T>(h);
-        hipStream_t st = stream_of(h);
-        bp.launches.push_back([=](char *base) {
+        bp.launches.push_back([=](char *base, hipStream_t st) {
             return fft_pass_batched<T>(mode, p, pass, C, (const PassProblem<T> *)(base + off), cnt, total, bytes, tw, st);
         });
     }
@@ -1269,8 +1287,7 @@ static void plan_gemm(BatchPlan &bp, mrinv_handle_t h, const FftPlan &p, const s
         }
         const size_t off = bp.put(g);
         const int cnt = (int)g.size();
-        hipStream_t st = stream_of(h);
-        bp.launches.push_back([=](char *base) {
+        bp.launches.push_back([=](char *base, hipStream_t st) {
             return freq_gemm_batched<T>(p, cls, (const GemmProblem<T> *)(base + off), cnt, total, bytes, flops, st);
         });
     }
@@ -1394,8 +1411,7 @@ static void plan_newton(BatchPlan &bp, mrinv_handle_t h, std::vector<BatchProble
         if (!sp.empty()) {
             const size_t off = bp.put(sp);
             const int cnt = (int)sp.size();
-            hipStream_t st = stream_of(h);
-            bp.launches.push_back([=](char *base) {
+            bp.launches.push_back([=](char *base, hipStream_t st) {
                 return seed_recursion_batched<T>((const SeedProblem *)(base + off), cnt, cols, dmax, m0max, st);
             });
         }
@@ -1438,8 +1454,7 @@ static void plan_newton(BatchPlan &bp, mrinv_handle_t h, std::vector<BatchProble
                     const size_t off = bp.put(v);
                     const int cnt = (int)v.size();
                     const int lf = pass == 0 ? 1 : (dbl ? 1 : 0);
-                    hipStream_t st = stream_of(h);
-                    bp.launches.push_back([=](char *base) {
+                    bp.launches.push_back([=](char *base, hipStream_t st) {
                         return conv_direct_batched<T>(cls, lf, (const ConvDesc *)(base + off), cnt, total, flops, st);
                     });
                 }
@@ -1574,8 +1589,15 @@ static mrinv_status_t plan_batched(mrinv_handle_t h, int count, const double *co
     if (count < 1 || !d || !n) return fail(MRINV_E_ARG, "bad batch");
     if (prec != MRINV_FP64 && prec != MRINV_MIXED_FP32) return fail(MRINV_E_ARG, "unknown precision");
     std::vector<BatchProblem> P(count);
+    int64_t m0max = 1;
+    int dmax_all = 1;
     for (int b = 0; b < count; ++b) {
         CHECK(check_dn(d[b], n[b]));
+        m0max = std::max(m0max, seed_len(h, n[b]));
+        dmax_all = std::max(dmax_all, d[b]);
+    }
+    CHECK(check_seed(m0max, dmax_all));
+    for (int b = 0; b < count; ++b) {
         P[b].q = q_ptrs ? q_ptrs[b] : nullptr;
         P[b].psi = psi_ptrs ? psi_ptrs[b] : nullptr;
         P[b].d = d[b];
@@ -1615,9 +1637,8 @@ static mrinv_status_t plan_batched(mrinv_handle_t h, int count, const double *co
         const size_t goff = cur.put(gj);
         {
             unsigned int *status = status_of(h);
-            hipStream_t st = stream_of(h);
             const int cnt = count;
-            cur.launches.push_back([=](char *tb) {
+            cur.launches.push_back([=](char *tb, hipStream_t st) {
                 return gj_inverse_batched((const GjProblem *)(tb + goff), cnt, dmax, status, st);
             });
         }
@@ -1650,33 +1671,50 @@ extern "C" size_t mrinv_batched_workspace_size(mrinv_handle_t h, int count, cons
     return bp.total;
 }
 
-extern "C" mrinv_status_t mrinv_psi_inverse_batched(mrinv_handle_t h, int count, const double *const *q_ptrs,
-                                                    const int *d, const int64_t *n, mrinv_precision_t precision,
-                                                    double *const *psi_ptrs, void *ws, size_t wsb) {
-    TimerScope _ts(h);
+static void batch_plan_free(void *plan) { delete (BatchPlan *)plan; }
+
+extern "C" mrinv_status_t mrinv_psi_inverse_batched_prepare(mrinv_handle_t h, int count, const double *const *q_ptrs,
+                                                            const int *d, const int64_t *n,
+                                                            mrinv_precision_t precision, double *const *psi_ptrs,
+                                                            void *ws, size_t wsb) {
     if (!h || count < 1 || !q_ptrs || !d || !n || !psi_ptrs) return fail(MRINV_E_ARG, "NULL handle or pointer");
     for (int b = 0; b < count; ++b)
         if (!q_ptrs[b] || !psi_ptrs[b]) return fail(MRINV_E_ARG, "NULL problem pointer %d", b);
-    BatchPlan bp;
-    CHECK(plan_batched(h, count, q_ptrs, d, n, precision, psi_ptrs, (char *)ws, bp));
-    CHECK(check_ws(ws, wsb, bp.total));
-    // Stage the descriptor table through pinned host memory (reused across calls;
-    // the previous transfer is waited for before the buffer is rewritten).
-    if (h->pinned_bytes < bp.table.size()) {
-        if (h->pinned) {
-            (void)hipEventSynchronize(h->pinned_done);
-            (void)hipHostFree(h->pinned);
-        }
-        h->pinned = nullptr;
-        h->pinned_bytes = 0;
-        HIP_TRY(hipHostMalloc(&h->pinned, bp.table.size()));
-        h->pinned_bytes = bp.table.size();
-    } else if (h->pinned) {
-        HIP_TRY(hipEventSynchronize(h->pinned_done));
+    auto *bp = new (std::nothrow) BatchPlan();
+    if (!bp) return fail(MRINV_E_ARG, "out of host memory");
+    mrinv_status_t st = plan_batched(h, count, q_ptrs, d, n, precision, psi_ptrs, (char *)ws, *bp);
+    if (st == MRINV_OK) st = check_ws(ws, wsb, bp->total);
+    if (st != MRINV_OK) {
+        delete bp;
+        return st;
     }
-    memcpy(h->pinned, bp.table.data(), bp.table.size());
-    HIP_TRY(hipMemcpyAsync(ws, h->pinned, bp.table.size(), hipMemcpyHostToDevice, h->stream));
-    HIP_TRY(hipEventRecord(h->pinned_done, h->stream));
-    for (auto &launch : bp.launches) HIP_TRY(launch((char *)ws));
+    // The descriptor table goes into the head of the workspace from pageable
+    // host memory owned by the plan; the call waits for it, so the table is in
+    // place before any launch of the plan is enqueued.
+    bp->ws = (char *)ws;
+    hipError_t e = hipMemcpyAsync(ws, bp->table.data(), bp->table.size(), hipMemcpyHostToDevice, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) {
+        delete bp;
+        return fail(MRINV_E_HIP, "descriptor upload: %s", hipGetErrorString(e));
+    }
+    batch_plan_free(h->batch);
+    h->batch = bp;
     return MRINV_OK;
+}
+
+extern "C" mrinv_status_t mrinv_psi_inverse_batched_launch(mrinv_handle_t h) {
+    TimerScope _ts(h);
+    if (!h) return fail(MRINV_E_ARG, "NULL handle");
+    auto *bp = (BatchPlan *)h->batch;
+    if (!bp) return fail(MRINV_E_ARG, "no batched plan prepared on this handle");
+    for (auto &launch : bp->launches) HIP_TRY(launch(bp->ws, h->stream));
+    return MRINV_OK;
+}
+
+extern "C" mrinv_status_t mrinv_psi_inverse_batched(mrinv_handle_t h, int count, const double *const *q_ptrs,
+                                                    const int *d, const int64_t *n, mrinv_precision_t precision,
+                                                    double *const *psi_ptrs, void *ws, size_t wsb) {
+    CHECK(mrinv_psi_inverse_batched_prepare(h, count, q_ptrs, d, n, precision, psi_ptrs, ws, wsb));
+    return mrinv_psi_inverse_batched_launch(h);
 }

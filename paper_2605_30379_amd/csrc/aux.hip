@@ -205,7 +205,7 @@ __global__ void __launch_bounds__(SEED_THREADS) seed_recursion_batched_kernel(co
 template <typename T>
 hipError_t seed_recursion_batched(const SeedProblem *probs, int nprob, int total_cols, int dmax, int m0max,
                                   hipStream_t st) {
-    const size_t lds = ((size_t)m0max * dmax + (size_t)dmax * dmax + SEED_THREADS + dmax) * sizeof(double);
+    const size_t lds = seed_lds_bytes(m0max, dmax);
     launch_kernel(sizeof(T) == 8 ? "seed_recursion_batched_kernel<double>" : "seed_recursion_batched_kernel<float>",
                   0.0, 0.0, seed_recursion_batched_kernel<T>, dim3(total_cols), dim3(SEED_THREADS), lds, st, probs,
                   nprob);
@@ -214,9 +214,13 @@ hipError_t seed_recursion_batched(const SeedProblem *probs, int nprob, int total
 template hipError_t seed_recursion_batched<double>(const SeedProblem *, int, int, int, int, hipStream_t);
 template hipError_t seed_recursion_batched<float>(const SeedProblem *, int, int, int, int, hipStream_t);
 
+size_t seed_lds_bytes(int m0, int d) {
+    return ((size_t)m0 * d + (size_t)d * d + SEED_THREADS + d) * sizeof(double);
+}
+
 template <typename T>
 hipError_t seed_recursion(const double *A, int e0, int d, int m0, T *out, hipStream_t st) {
-    const size_t lds = ((size_t)m0 * d + (size_t)d * d + SEED_THREADS + d) * sizeof(double);
+    const size_t lds = seed_lds_bytes(m0, d);
     launch_kernel(sizeof(T) == 8 ? "seed_recursion_kernel<double>" : "seed_recursion_kernel<float>",
                   (double)m0 * d * d * 8.0 * 2, (double)m0 * m0 * d * d * d, seed_recursion_kernel<T>, dim3(d),
                   dim3(SEED_THREADS), lds, st, A, e0, d, m0, out);
@@ -469,6 +473,21 @@ hipError_t scatter_block_add(const double *Yb, int64_t n, int rows, int cols, co
     const int64_t total = n * nr * nc;
     hipLaunchKernelGGL(scatter_add_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, Yb, n, rows, cols,
                        ri, nr, ci, nc, Xb);
+    return hipGetLastError();
+}
+
+__global__ void put_small_kernel(SmallVecArgs v, int *ci, int *di, double *alpha, double *ones) {
+    const int t = threadIdx.x;
+    if (t < v.nci) ci[t] = v.ci[t];
+    if (t < v.ndi) di[t] = v.di[t];
+    if (t < v.nalpha) alpha[t] = v.alpha[t];
+    if (t < v.nones) ones[t] = v.ones[t];
+}
+
+hipError_t put_small_vectors(const SmallVecArgs &v, int *ci, int *di, double *alpha, double *ones, hipStream_t st) {
+    if (v.nci > SMALL_MAX || v.ndi > SMALL_MAX || v.nalpha > SMALL_MAX || v.nones > SMALL_MAX)
+        return hipErrorInvalidValue;
+    hipLaunchKernelGGL(put_small_kernel, dim3(1), dim3(SMALL_MAX), 0, st, v, ci, di, alpha, ones);
     return hipGetLastError();
 }
 

@@ -255,6 +255,21 @@ hipError_t scatter_block_add(const double *Yb, int64_t n, int rows, int cols, co
                              const int *ci, int nc, double *Xb, hipStream_t st);
 // q_bar(l)[i][j] += -sum_{k>=l} hb_bar(k)[i] for l >= 1.
 hipError_t survival_backward(const double *hbb, int d, int64_t n, double *qb, double *tmp, hipStream_t st);
+// Small host vectors of a functional (index lists, initial law, indicator),
+// passed by value as kernel arguments and written to device memory by one
+// small kernel, so the entry points neither wait for the stream nor keep
+// host buffers alive (and can be recorded into a HIP graph).
+constexpr int SMALL_MAX = 64;
+struct SmallVecArgs {
+    int nci, ndi, nalpha, nones;
+    int ci[SMALL_MAX];
+    int di[SMALL_MAX];
+    double alpha[SMALL_MAX];
+    double ones[SMALL_MAX];
+};
+hipError_t put_small_vectors(const SmallVecArgs &v, int *ci, int *di, double *alpha, double *ones, hipStream_t st);
+// LDS bytes of the recursion seed launch (m0 coefficients of a d x d problem).
+size_t seed_lds_bytes(int m0, int d);
 hipError_t fill_f64(double *p, int64_t count, double v, hipStream_t st);
 hipError_t fill_u32(unsigned int *p, int64_t count, unsigned int v, hipStream_t st);
 hipError_t residual_norms(const double *R_L, const double *R_R, int d, int64_t n, double *acc, hipStream_t st);
