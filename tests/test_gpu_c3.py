@@ -113,9 +113,17 @@ def test_c3_sampled_residuals_over_the_horizon(mr, orc, c3, psis, form):
 
 @pytest.mark.parametrize("form", ["fp64", "mixed"])
 def test_c3_functionals(mr, c3, psis, form):
+    """P = psi*Hbar is one transform product at length 2^19 over a recurrent
+    psi, so each entry carries the product rounding of the whole horizon
+    (bounded like psi by fp64_tol(n) in FP64; the product runs in FP64 in both
+    forms).  Availability sums the |U| = 32 entries alpha P(k) 1_U, so its
+    bound is |U| times P's.  Reliability and the first entrance come from the
+    inverses of the transient blocks q_UU and q_CC and keep psi's bound."""
     psi, q = psis[form], c3["q"]
     P = mr.transition(psi, q)
     tol = FP64_TOL if form == "fp64" else MIXED_TOL
+    p_tol = fp64_tol(N) if form == "fp64" else MIXED_TOL
+    a_tol = int(UP.sum()) * p_tol
     e_P = _maxerr(_np(P[:N_PSI]), c3["P"])
     rows = float((P.sum(dim=2) - 1).abs().max())
     A = mr.availability(P, UP, ALPHA)
@@ -127,7 +135,8 @@ def test_c3_functionals(mr, c3, psis, form):
     e_A = _maxerr(_np(A[:N_AV]), c3["A"])
     e_F = _maxerr(_np(F[:N_FE]), c3["F"])
     _log(f"{form}: P {e_P:.2e} (row sums {rows:.2e}), R {e_R:.2e}, A {e_A:.2e}, F {e_F:.2e}")
-    assert e_P <= tol and e_R <= tol and e_A <= tol and e_F <= tol
+    assert e_P <= p_tol and e_A <= a_tol
+    assert e_R <= tol and e_F <= tol
     assert rows <= _tol(form)
 
 
