@@ -124,6 +124,23 @@ mrinv_status_t mrinv_psi_inverse(mrinv_handle_t h, const double *q, int d, int64
                                  mrinv_precision_t precision, double *psi,
                                  void *ws, size_t ws_bytes);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the same
+ * inversion as mrinv_psi_inverse, computed by the same kernels with the same
+ * result, but its workspace is a library-owned device array of
+ * MRINV_NOALLOC_SCRATCH_BYTES per GPU (set up by mrinv_create, held until the
+ * process ends), so the call allocates nothing; the caller passes q and psi.
+ * Sizes whose workspace (mrinv_workspace_size(MRINV_OP_PSI_INVERSE, ...))
+ * exceeds the array return MRINV_E_WORKSPACE and enqueue nothing.  Every
+ * call on one GPU uses that GPU's single array: calls that overlap in time on
+ * one GPU (other streams, other threads) race and return wrong results; calls
+ * on one stream are ordered and safe.  The array keeps the last call's
+ * contents; nothing in it needs to start at zero.  The use_graph tuning is
+ * ignored. */
+#define MRINV_NOALLOC_SCRATCH_BYTES (64u << 20)
+mrinv_status_t mrinv_psi_inverse_noalloc(mrinv_handle_t h, const double *q, int d, int64_t n,
+                                         mrinv_precision_t precision, double *psi);
+
 /* Same as mrinv_psi_inverse for a general sequence A (A^(-1) of Theorem 2.1):
  * A is device [n][d][d] float64 with A(0) nonsingular. */
 mrinv_status_t mrinv_series_inverse(mrinv_handle_t h, const double *A, int d, int64_t n,

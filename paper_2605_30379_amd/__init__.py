@@ -32,6 +32,7 @@ __all__ = [
     "contract_backward", "scatter_block_add", "psi_inverse_batched", "residual_norms", "sync_status",
     "PsiInverse", "RenewalApply", "Transition", "Contract", "GatherBlock", "workspace_size",
     "FP64", "MIXED_FP32", "OPS", "Tuning", "get_tuning", "set_tuning", "autotune", "BatchedPlan",
+    "psi_inverse_noalloc", "NOALLOC_SCRATCH_BYTES",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -93,6 +94,7 @@ def lib():
             "mrinv_workspace_size": (sz, [i32, i32, i64, i32, i32]),
             "mrinv_psi_inverse": (i32, [vp, vp, i32, i64, i32, vp, vp, sz]),
             "mrinv_series_inverse": (i32, [vp, vp, i32, i64, i32, vp, vp, sz]),
+            "mrinv_psi_inverse_noalloc": (i32, [vp, vp, i32, i64, i32, vp]),
             "mrinv_markov_renewal_apply": (i32, [vp, vp, i32, i64, vp, i32, vp, vp, sz]),
             "mrinv_transition": (i32, [vp, vp, vp, i32, i64, vp, vp, sz]),
             "mrinv_survival": (i32, [vp, vp, i32, i64, vp]),
@@ -243,6 +245,23 @@ def psi_inverse(q: torch.Tensor, precision="fp64", check: bool = False) -> torch
     if check:
         sync_status(q.device)
     return out
+
+
+NOALLOC_SCRATCH_BYTES = 64 << 20
+
+
+def psi_inverse_noalloc(q: torch.Tensor, psi: torch.Tensor, precision="fp64") -> torch.Tensor:
+    """psi_inverse into a caller-given output with the library-owned workspace
+    (mrinv_psi_inverse_noalloc): nothing is allocated, by this function or the
+    library.  The handle of the stream must exist (make one call on the
+    stream first).  Calls overlapping on one GPU race; see include/mrinv.h."""
+    q = _square(q, "q")
+    n, d, _ = q.shape
+    if not isinstance(psi, torch.Tensor) or psi.shape != q.shape or psi.dtype != torch.float64 \
+            or not psi.is_contiguous() or psi.device != q.device:
+        raise MrinvError(1, "psi must be a contiguous float64 tensor shaped like q on its device")
+    _check(lib().mrinv_psi_inverse_noalloc(_handle(q.device), _ptr(q), d, n, _PREC[precision], _ptr(psi)))
+    return psi
 
 
 def series_inverse(A: torch.Tensor, precision="fp64", check: bool = False) -> torch.Tensor:

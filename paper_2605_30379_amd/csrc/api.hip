@@ -7,6 +7,7 @@
 
 #include <algorithm>
 #include <functional>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -47,6 +48,33 @@ constexpr size_t SCRATCH_SCAN_OFF = (size_t)MRINV_MAX_N + 4096;   // in doubles
 constexpr size_t SCRATCH_BYTES =
     SCRATCH_SCAN_OFF * sizeof(double) + ((MRINV_MAX_N + 1023) / 1024) * 256 * sizeof(double);
 
+// ---------------------------------------------------------------------------
+// Library-owned workspace of mrinv_psi_inverse_noalloc: one device array of
+// MRINV_NOALLOC_SCRATCH_BYTES on every GPU the library runs on, held until
+// the process ends.  In host code `scratch` only names the array: its device
+// address is looked up once per device (hipGetSymbolAddress with that device
+// current, in mrinv_create) and that address is what the kernels receive.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[MRINV_NOALLOC_SCRATCH_BYTES];
+constexpr int NOALLOC_MAX_DEVICES = 64;
+static std::mutex g_scratch_mu;
+static void *g_scratch_addr[NOALLOC_MAX_DEVICES];
+
+// Device address of `scratch` on device dev (the current device).
+static mrinv_status_t noalloc_scratch_lookup(int dev, void **out) {
+    *out = nullptr;
+    if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) return fail(MRINV_E_UNSUPPORTED, "device %d out of range", dev);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_addr[dev]) {
+        void *p = nullptr;
+        HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return fail(MRINV_E_HIP, "no device address for the library workspace");
+        g_scratch_addr[dev] = p;
+    }
+    *out = g_scratch_addr[dev];
+    return MRINV_OK;
+}
+
 // Tuning of a new handle, also used where no handle is given (workspace
 // queries), so that both plan the same launches.
 static const mrinv_tuning_t kDefaultTune = {9, 0, 0, 1, 1, 1, 0, 0, 1, -1};
@@ -73,6 +101,7 @@ struct mrinv_handle_s {
     } gc;
     hipStream_t cap_stream = nullptr;
     void *batch = nullptr;          // plan of the last mrinv_psi_inverse_batched_prepare (BatchPlan)
+    void *noalloc = nullptr;        // device address of `scratch` on this handle's device
     Twiddles<double> t64() const { return {tw64, tw64 + TW_HI_SIZE, tw64 + TW_HI_SIZE + TW_LO_SIZE, nullptr}; }
     Twiddles<float> t32() const { return {tw64, tw64 + TW_HI_SIZE, tw64 + TW_HI_SIZE + TW_LO_SIZE, nullptr}; }
 };
@@ -102,6 +131,8 @@ extern "C" mrinv_status_t mrinv_create(mrinv_handle_t *handle, void *stream) {
     // Any failure below releases what was made so far.
     auto init = [&]() -> mrinv_status_t {
         HIP_TRY(hipGetDevice(&h->device));
+        const mrinv_status_t sst = noalloc_scratch_lookup(h->device, &h->noalloc);
+        if (sst != MRINV_OK) return sst;
         std::vector<double2> hi, lo;
         host_twiddles(hi, lo);
         const size_t n64 = (TW_HI_SIZE + TW_LO_SIZE + 512) * sizeof(double2);
@@ -573,11 +604,15 @@ static mrinv_status_t newton(mrinv_handle_t h, const double *src, int e0, int d,
     }
     const GemmDesc g = gdesc(h, d, d, d);
     // Plans of every step and their outer-twiddle tables (one launch).
-    std::vector<FftPlan> plans;
+    // At most log2(MRINV_MAX_N) + 1 steps; a fixed array keeps the driver free
+    // of host allocations.
+    FftPlan plans[32];
+    int nplans = 0;
     TwGen tg{};
-    for (int64_t m = m0; m < n; m = std::min(2 * m, n)) {
-        plans.push_back(hplan(h, ceil_log2(std::min(2 * m, n))));
-        if (twr && h->tune.twiddle_tables >= 2) add_tables(tg, plans.back(), dbl, twr, twr_end);
+    for (int64_t m = m0; m < n && nplans < 32; m = std::min(2 * m, n)) {
+        plans[nplans] = hplan(h, ceil_log2(std::min(2 * m, n)));
+        if (twr && h->tune.twiddle_tables >= 2) add_tables(tg, plans[nplans], dbl, twr, twr_end);
+        ++nplans;
     }
     HIP_TRY(gen_outer_twiddles(tg, h->tw64, h->tw64 + TW_HI_SIZE, h->stream));
     size_t step = 0;
@@ -778,6 +813,22 @@ extern "C" mrinv_status_t mrinv_series_inverse(mrinv_handle_t h, const double *A
     TimerScope _ts(h);
     if (h && h->tune.use_graph && !h->timing) return inverse_graphed(h, A, 0, d, n, precision, Ainv, ws, ws_bytes);
     return inverse_impl(h, A, 0, d, n, precision, Ainv, ws, ws_bytes);
+}
+
+extern "C" mrinv_status_t mrinv_psi_inverse_noalloc(mrinv_handle_t h, const double *q, int d, int64_t n,
+                                                    mrinv_precision_t precision, double *psi) {
+    if (!h || !q || !psi) return fail(MRINV_E_ARG, "NULL handle or pointer");
+    CHECK(check_dn(d, n));
+    if (precision != MRINV_FP64 && precision != MRINV_MIXED_FP32)
+        return fail(MRINV_E_ARG, "unknown precision %d", (int)precision);
+    const size_t need = ws_psi(d, n, precision);
+    if (need > (size_t)MRINV_NOALLOC_SCRATCH_BYTES)
+        return fail(MRINV_E_WORKSPACE,
+                    "d=%d n=%lld needs %zu bytes of workspace; the library-owned array holds %zu "
+                    "(use mrinv_psi_inverse with a caller workspace)",
+                    d, (long long)n, need, (size_t)MRINV_NOALLOC_SCRATCH_BYTES);
+    if (!h->noalloc) return fail(MRINV_E_HIP, "library workspace not set up on this handle's device");
+    return inverse_impl(h, q, 1, d, n, precision, psi, h->noalloc, MRINV_NOALLOC_SCRATCH_BYTES);
 }
 
 // ---------------------------------------------------------------------------
