@@ -1338,8 +1338,9 @@ static void plan_gemm(BatchPlan &bp, mrinv_handle_t h, const FftPlan &p, const s
         }
         const size_t off = bp.put(g);
         const int cnt = (int)g.size();
+        const int mf = tune_of(h).mfma;
         bp.launches.push_back([=](char *base, hipStream_t st) {
-            return freq_gemm_batched<T>(p, cls, (const GemmProblem<T> *)(base + off), cnt, total, bytes, flops, st);
+            return freq_gemm_batched<T>(p, cls, mf, (const GemmProblem<T> *)(base + off), cnt, total, bytes, flops, st);
         });
     }
 }

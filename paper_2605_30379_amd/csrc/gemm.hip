@@ -398,7 +398,7 @@ __device__ __forceinline__ double lane_xor1(double x) {
 
 // TA / TB: operand stored transposed (A(i, t) at entry t d + i, B(t, j) at
 // entry j d + t), staged entry by entry.
-template <typename T, int DP, bool ODD, bool TA = false, bool TB = false>
+template <typename T, int DP, bool ODD, bool TA = false, bool TB = false, bool G3 = false>
 __device__ __forceinline__ void freq_gemm_mfma_body(const cplx<T> *__restrict__ ZA, const cplx<T> *__restrict__ ZB,
                                                     cplx<T> *__restrict__ ZC, const FftPlan &plan, int d,
                                                     int64_t blk) {
@@ -433,11 +433,20 @@ __device__ __forceinline__ void freq_gemm_mfma_body(const cplx<T> *__restrict__ 
     const int f = w / WPF, I = w - f * WPF;
     constexpr bool even = !ODD;               // C entries (i, j), (i, j^1) share a packed lane
     constexpr bool pairs = !ODD && !TA && !TB; // operands staged by packed lanes
-    V accR[WPF], accI[WPF];
+    // Four real products per complex product: accR = Re A Re B - Im A Im B,
+    // accI = Re A Im B + Im A Re B.  With G3 (three real products, Gauss's
+    // form of the complex product): accR = Re A Re B, accI = Im A Im B and
+    // acc3 = (Re A + Im A)(Re B + Im B), combined after the contraction into
+    // Re C = accR - accI and Im C = acc3 - accR - accI.
+    V accR[WPF], accI[WPF], acc3[G3 ? WPF : 1];
 #pragma unroll
     for (int J = 0; J < WPF; ++J)
 #pragma unroll
         for (int r = 0; r < 4; ++r) accR[J][r] = accI[J][r] = (T)0;
+#pragma unroll
+    for (int J = 0; J < (G3 ? WPF : 1); ++J)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) acc3[J][r] = (T)0;
 
     // Packed values of the current chunk in flight: rows k and L-k of the
     // lane holding each staged pair (even d) or entry (odd d).  Addresses of
@@ -556,18 +565,39 @@ __device__ __forceinline__ void freq_gemm_mfma_body(const cplx<T> *__restrict__ 
         for (int ks = 0; ks < KC / 4; ++ks) {
             const int t = 4 * ks + (l >> 4);
             const cplx<T> a = Af[t];
+            if constexpr (G3) {
+                const T as = a.x + a.y;
 #pragma unroll
-            for (int J = 0; J < WPF; ++J) {
-                const cplx<T> b = Bf[t * LDB + J * 16];
-                accR[J] = Op::mac(a.x, b.x, accR[J]);
-                accR[J] = Op::mac(-a.y, b.y, accR[J]);
-                accI[J] = Op::mac(a.x, b.y, accI[J]);
-                accI[J] = Op::mac(a.y, b.x, accI[J]);
+                for (int J = 0; J < WPF; ++J) {
+                    const cplx<T> b = Bf[t * LDB + J * 16];
+                    accR[J] = Op::mac(a.x, b.x, accR[J]);
+                    accI[J] = Op::mac(a.y, b.y, accI[J]);
+                    acc3[J] = Op::mac(as, b.x + b.y, acc3[J]);
+                }
+            } else {
+#pragma unroll
+                for (int J = 0; J < WPF; ++J) {
+                    const cplx<T> b = Bf[t * LDB + J * 16];
+                    accR[J] = Op::mac(a.x, b.x, accR[J]);
+                    accR[J] = Op::mac(-a.y, b.y, accR[J]);
+                    accI[J] = Op::mac(a.x, b.y, accI[J]);
+                    accI[J] = Op::mac(a.y, b.x, accI[J]);
+                }
             }
         }
         if (more) stage(kc + KC, cur ^ 1);
         __syncthreads();
         cur ^= 1;
+    }
+    if constexpr (G3) {
+#pragma unroll
+        for (int J = 0; J < WPF; ++J)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const T p1 = accR[J][r], p2 = accI[J][r];
+                accR[J][r] = p1 - p2;
+                accI[J][r] = acc3[J][r] - p1 - p2;
+            }
     }
 
     const bool fok = k0 + f < F;
@@ -615,15 +645,15 @@ __device__ __forceinline__ void freq_gemm_mfma_body(const cplx<T> *__restrict__ 
     }
 }
 
-template <typename T, int DP, bool ODD, bool TA, bool TB>
+template <typename T, int DP, bool ODD, bool TA, bool TB, bool G3>
 __global__ void __launch_bounds__((MfCfg<T, DP>::THREADS))
 __attribute__((amdgpu_waves_per_eu(MfCfg<T, DP>::WAVES)))
 freq_gemm_mfma_kernel(const cplx<T> *__restrict__ ZA, const cplx<T> *__restrict__ ZB, cplx<T> *__restrict__ ZC,
                       FftPlan plan, int d) {
-    freq_gemm_mfma_body<T, DP, ODD, TA, TB>(ZA, ZB, ZC, plan, d, blockIdx.x);
+    freq_gemm_mfma_body<T, DP, ODD, TA, TB, G3>(ZA, ZB, ZC, plan, d, blockIdx.x);
 }
 
-template <typename T, int DP, bool ODD>
+template <typename T, int DP, bool ODD, bool G3>
 __global__ void __launch_bounds__((MfCfg<T, DP>::THREADS))
 __attribute__((amdgpu_waves_per_eu(MfCfg<T, DP>::WAVES)))
 freq_gemm_mfma_batched_kernel(const GemmProblem<T> *probs, int nprob, FftPlan plan) {
@@ -635,15 +665,15 @@ freq_gemm_mfma_batched_kernel(const GemmProblem<T> *probs, int nprob, FftPlan pl
         else hi = mid - 1;
     }
     const GemmProblem<T> &pp = probs[lo];
-    freq_gemm_mfma_body<T, DP, ODD>(pp.A, pp.B, pp.C, plan, pp.d, bid - pp.wg_begin);
+    freq_gemm_mfma_body<T, DP, ODD, false, false, G3>(pp.A, pp.B, pp.C, plan, pp.d, bid - pp.wg_begin);
 }
 
-template <typename T, int DP, bool ODD, bool TA = false, bool TB = false>
-static hipError_t launch_gemm_mfma(const FftPlan &plan, int d, const cplx<T> *ZA, const cplx<T> *ZB, cplx<T> *ZC,
-                                   hipStream_t st) {
+template <typename T, int DP, bool ODD, bool TA = false, bool TB = false, bool G3 = false>
+static hipError_t launch_gemm_mfma_t(const FftPlan &plan, int d, const cplx<T> *ZA, const cplx<T> *ZB, cplx<T> *ZC,
+                                     hipStream_t st) {
     using Cfg = MfCfg<T, DP>;
     const size_t lds = mf_lds_bytes<T, DP>(ODD ? d : 0);
-    auto kern = freq_gemm_mfma_kernel<T, DP, ODD, TA, TB>;
+    auto kern = freq_gemm_mfma_kernel<T, DP, ODD, TA, TB, G3>;
     if (lds > 64 * 1024) {
         (void)hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         (void)hipGetLastError();
@@ -651,12 +681,8 @@ static hipError_t launch_gemm_mfma(const FftPlan &plan, int d, const cplx<T> *ZA
     const int64_t F = ((int64_t)1 << plan.lgL) / 2 + 1;
     const int64_t blocks = (F + Cfg::NF - 1) / Cfg::NF;
     char name[96];
-    if (TA || TB)
-        snprintf(name, sizeof name, "freq_gemm_mfma_kernel<%s, %d, %s, %s, %s>", sizeof(T) == 8 ? "double" : "float",
-                 DP, ODD ? "true" : "false", TA ? "true" : "false", TB ? "true" : "false");
-    else
-        snprintf(name, sizeof name, "freq_gemm_mfma_kernel<%s, %d, %s, false, false>",
-                 sizeof(T) == 8 ? "double" : "float", DP, ODD ? "true" : "false");
+    snprintf(name, sizeof name, "freq_gemm_mfma_kernel<%s, %d, %s, %s, %s, %s>", sizeof(T) == 8 ? "double" : "float",
+             DP, ODD ? "true" : "false", TA ? "true" : "false", TB ? "true" : "false", G3 ? "true" : "false");
     const double Lr = (double)((int64_t)1 << plan.lgL);
     const int nl = (d * d + 1) / 2;
     launch_kernel(name, Lr * 3.0 * nl * sizeof(cplx<T>), (double)F * 8.0 * d * d * d,
@@ -664,22 +690,41 @@ static hipError_t launch_gemm_mfma(const FftPlan &plan, int d, const cplx<T> *ZA
     return hipGetLastError();
 }
 
-template <typename T, int DP, bool ODD>
-static hipError_t launch_gemm_mfma_batched(const FftPlan &plan, const GemmProblem<T> *probs, int nprob,
-                                           int64_t total, double bytes, double flops, hipStream_t st) {
+// Three real products per complex product (Gauss's form) where the matrix
+// cores bound the product (padded d >= 48: intensity d/6 flop/B in FP64, near
+// or above the ridge); mfma == 2 keeps the four-product form everywhere.
+template <int DP> static bool use_g3(int mfma) { return mfma == 1 && DP >= 48; }
+
+template <typename T, int DP, bool ODD, bool TA = false, bool TB = false>
+static hipError_t launch_gemm_mfma(const FftPlan &plan, int d, int mfma, const cplx<T> *ZA, const cplx<T> *ZB,
+                                   cplx<T> *ZC, hipStream_t st) {
+    if (use_g3<DP>(mfma)) return launch_gemm_mfma_t<T, DP, ODD, TA, TB, true>(plan, d, ZA, ZB, ZC, st);
+    return launch_gemm_mfma_t<T, DP, ODD, TA, TB, false>(plan, d, ZA, ZB, ZC, st);
+}
+
+template <typename T, int DP, bool ODD, bool G3>
+static hipError_t launch_gemm_mfma_batched_t(const FftPlan &plan, const GemmProblem<T> *probs, int nprob,
+                                             int64_t total, double bytes, double flops, hipStream_t st) {
     using Cfg = MfCfg<T, DP>;
     const size_t lds = mf_lds_bytes<T, DP>(ODD ? DP - 1 : 0);
-    auto kern = freq_gemm_mfma_batched_kernel<T, DP, ODD>;
+    auto kern = freq_gemm_mfma_batched_kernel<T, DP, ODD, G3>;
     if (lds > 64 * 1024) {
         (void)hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         (void)hipGetLastError();
     }
     char name[96];
-    snprintf(name, sizeof name, "freq_gemm_mfma_batched_kernel<%s, %d, %s>", sizeof(T) == 8 ? "double" : "float",
-             DP, ODD ? "true" : "false");
+    snprintf(name, sizeof name, "freq_gemm_mfma_batched_kernel<%s, %d, %s, %s>", sizeof(T) == 8 ? "double" : "float",
+             DP, ODD ? "true" : "false", G3 ? "true" : "false");
     launch_kernel(name, bytes, flops,
                   kern, dim3((unsigned)total), dim3(Cfg::THREADS), lds, st, probs, nprob, plan);
     return hipGetLastError();
+}
+
+template <typename T, int DP, bool ODD>
+static hipError_t launch_gemm_mfma_batched(const FftPlan &plan, int mfma, const GemmProblem<T> *probs, int nprob,
+                                           int64_t total, double bytes, double flops, hipStream_t st) {
+    if (use_g3<DP>(mfma)) return launch_gemm_mfma_batched_t<T, DP, ODD, true>(plan, probs, nprob, total, bytes, flops, st);
+    return launch_gemm_mfma_batched_t<T, DP, ODD, false>(plan, probs, nprob, total, bytes, flops, st);
 }
 
 // ---------------------------------------------------------------------------
@@ -951,8 +996,8 @@ int64_t gemm_batch_layout(const FftPlan &plan, GemmProblem<T> *probs, int nprob,
 }
 
 template <typename T>
-hipError_t freq_gemm_batched(const FftPlan &plan, int dclass, const GemmProblem<T> *probs, int nprob, int64_t total,
-                             double bytes, double flops, hipStream_t st) {
+hipError_t freq_gemm_batched(const FftPlan &plan, int dclass, int mfma, const GemmProblem<T> *probs, int nprob,
+                             int64_t total, double bytes, double flops, hipStream_t st) {
     switch (dclass) {
         case 1: return launch_gemm_sq_batched<T, 8>(plan, probs, nprob, total, bytes, flops, st);
         case 2: return launch_gemm_sq_batched<T, 16>(plan, probs, nprob, total, bytes, flops, st);
@@ -962,23 +1007,23 @@ hipError_t freq_gemm_batched(const FftPlan &plan, int dclass, const GemmProblem<
         case 6: return launch_gemm_sq_batched<T, 48>(plan, probs, nprob, total, bytes, flops, st);
         case 7: return launch_gemm_sq_batched<T, 56>(plan, probs, nprob, total, bytes, flops, st);
         case 8: return launch_gemm_sq_batched<T, 64>(plan, probs, nprob, total, bytes, flops, st);
-        case 9: return launch_gemm_mfma_batched<T, 16, false>(plan, probs, nprob, total, bytes, flops, st);
-        case 10: return launch_gemm_mfma_batched<T, 32, false>(plan, probs, nprob, total, bytes, flops, st);
-        case 11: return launch_gemm_mfma_batched<T, 48, false>(plan, probs, nprob, total, bytes, flops, st);
-        case 12: return launch_gemm_mfma_batched<T, 64, false>(plan, probs, nprob, total, bytes, flops, st);
-        case 13: return launch_gemm_mfma_batched<T, 16, true>(plan, probs, nprob, total, bytes, flops, st);
-        case 14: return launch_gemm_mfma_batched<T, 32, true>(plan, probs, nprob, total, bytes, flops, st);
-        case 15: return launch_gemm_mfma_batched<T, 48, true>(plan, probs, nprob, total, bytes, flops, st);
-        default: return launch_gemm_mfma_batched<T, 64, true>(plan, probs, nprob, total, bytes, flops, st);
+        case 9: return launch_gemm_mfma_batched<T, 16, false>(plan, mfma, probs, nprob, total, bytes, flops, st);
+        case 10: return launch_gemm_mfma_batched<T, 32, false>(plan, mfma, probs, nprob, total, bytes, flops, st);
+        case 11: return launch_gemm_mfma_batched<T, 48, false>(plan, mfma, probs, nprob, total, bytes, flops, st);
+        case 12: return launch_gemm_mfma_batched<T, 64, false>(plan, mfma, probs, nprob, total, bytes, flops, st);
+        case 13: return launch_gemm_mfma_batched<T, 16, true>(plan, mfma, probs, nprob, total, bytes, flops, st);
+        case 14: return launch_gemm_mfma_batched<T, 32, true>(plan, mfma, probs, nprob, total, bytes, flops, st);
+        case 15: return launch_gemm_mfma_batched<T, 48, true>(plan, mfma, probs, nprob, total, bytes, flops, st);
+        default: return launch_gemm_mfma_batched<T, 64, true>(plan, mfma, probs, nprob, total, bytes, flops, st);
     }
 }
 
 template int64_t gemm_batch_layout<double>(const FftPlan &, GemmProblem<double> *, int, int);
 template int64_t gemm_batch_layout<float>(const FftPlan &, GemmProblem<float> *, int, int);
-template hipError_t freq_gemm_batched<double>(const FftPlan &, int, const GemmProblem<double> *, int, int64_t,
+template hipError_t freq_gemm_batched<double>(const FftPlan &, int, int, const GemmProblem<double> *, int, int64_t,
                                               double, double, hipStream_t);
-template hipError_t freq_gemm_batched<float>(const FftPlan &, int, const GemmProblem<float> *, int, int64_t, double,
-                                             double, hipStream_t);
+template hipError_t freq_gemm_batched<float>(const FftPlan &, int, int, const GemmProblem<float> *, int, int64_t,
+                                             double, double, hipStream_t);
 
 template <typename T, int DP>
 static hipError_t launch_gemm_sq(const FftPlan &plan, int d, const cplx<T> *ZA, const cplx<T> *ZB, cplx<T> *ZC,
@@ -1009,32 +1054,32 @@ static hipError_t gemm_sq(const FftPlan &plan, int d, int mfma, const cplx<T> *Z
         case 6: return launch_gemm_sq<T, 48>(plan, d, ZA, ZB, ZC, st);
         case 7: return launch_gemm_sq<T, 56>(plan, d, ZA, ZB, ZC, st);
         case 8: return launch_gemm_sq<T, 64>(plan, d, ZA, ZB, ZC, st);
-        case 9: return launch_gemm_mfma<T, 16, false>(plan, d, ZA, ZB, ZC, st);
-        case 10: return launch_gemm_mfma<T, 32, false>(plan, d, ZA, ZB, ZC, st);
-        case 11: return launch_gemm_mfma<T, 48, false>(plan, d, ZA, ZB, ZC, st);
-        case 12: return launch_gemm_mfma<T, 64, false>(plan, d, ZA, ZB, ZC, st);
-        case 13: return launch_gemm_mfma<T, 16, true>(plan, d, ZA, ZB, ZC, st);
-        case 14: return launch_gemm_mfma<T, 32, true>(plan, d, ZA, ZB, ZC, st);
-        case 15: return launch_gemm_mfma<T, 48, true>(plan, d, ZA, ZB, ZC, st);
-        default: return launch_gemm_mfma<T, 64, true>(plan, d, ZA, ZB, ZC, st);
+        case 9: return launch_gemm_mfma<T, 16, false>(plan, d, mfma, ZA, ZB, ZC, st);
+        case 10: return launch_gemm_mfma<T, 32, false>(plan, d, mfma, ZA, ZB, ZC, st);
+        case 11: return launch_gemm_mfma<T, 48, false>(plan, d, mfma, ZA, ZB, ZC, st);
+        case 12: return launch_gemm_mfma<T, 64, false>(plan, d, mfma, ZA, ZB, ZC, st);
+        case 13: return launch_gemm_mfma<T, 16, true>(plan, d, mfma, ZA, ZB, ZC, st);
+        case 14: return launch_gemm_mfma<T, 32, true>(plan, d, mfma, ZA, ZB, ZC, st);
+        case 15: return launch_gemm_mfma<T, 48, true>(plan, d, mfma, ZA, ZB, ZC, st);
+        default: return launch_gemm_mfma<T, 64, true>(plan, d, mfma, ZA, ZB, ZC, st);
     }
 }
 
 // Square products with one operand stored transposed (the adjoints), on the
 // matrix cores.
 template <typename T, bool TA, bool TB>
-static hipError_t gemm_sq_t(const FftPlan &plan, int d, const cplx<T> *ZA, const cplx<T> *ZB, cplx<T> *ZC,
+static hipError_t gemm_sq_t(const FftPlan &plan, int d, int mfma, const cplx<T> *ZA, const cplx<T> *ZB, cplx<T> *ZC,
                             hipStream_t st) {
     const bool odd = d & 1;
     switch ((d + 15) / 16) {
-        case 1: return odd ? launch_gemm_mfma<T, 16, true, TA, TB>(plan, d, ZA, ZB, ZC, st)
-                           : launch_gemm_mfma<T, 16, false, TA, TB>(plan, d, ZA, ZB, ZC, st);
-        case 2: return odd ? launch_gemm_mfma<T, 32, true, TA, TB>(plan, d, ZA, ZB, ZC, st)
-                           : launch_gemm_mfma<T, 32, false, TA, TB>(plan, d, ZA, ZB, ZC, st);
-        case 3: return odd ? launch_gemm_mfma<T, 48, true, TA, TB>(plan, d, ZA, ZB, ZC, st)
-                           : launch_gemm_mfma<T, 48, false, TA, TB>(plan, d, ZA, ZB, ZC, st);
-        default: return odd ? launch_gemm_mfma<T, 64, true, TA, TB>(plan, d, ZA, ZB, ZC, st)
-                            : launch_gemm_mfma<T, 64, false, TA, TB>(plan, d, ZA, ZB, ZC, st);
+        case 1: return odd ? launch_gemm_mfma<T, 16, true, TA, TB>(plan, d, mfma, ZA, ZB, ZC, st)
+                           : launch_gemm_mfma<T, 16, false, TA, TB>(plan, d, mfma, ZA, ZB, ZC, st);
+        case 2: return odd ? launch_gemm_mfma<T, 32, true, TA, TB>(plan, d, mfma, ZA, ZB, ZC, st)
+                           : launch_gemm_mfma<T, 32, false, TA, TB>(plan, d, mfma, ZA, ZB, ZC, st);
+        case 3: return odd ? launch_gemm_mfma<T, 48, true, TA, TB>(plan, d, mfma, ZA, ZB, ZC, st)
+                           : launch_gemm_mfma<T, 48, false, TA, TB>(plan, d, mfma, ZA, ZB, ZC, st);
+        default: return odd ? launch_gemm_mfma<T, 64, true, TA, TB>(plan, d, mfma, ZA, ZB, ZC, st)
+                            : launch_gemm_mfma<T, 64, false, TA, TB>(plan, d, mfma, ZA, ZB, ZC, st);
     }
 }
 
@@ -1045,8 +1090,8 @@ hipError_t freq_gemm(const FftPlan &plan, const GemmDesc &g, const cplx<T> *ZA, 
         return gemm_sq<T>(plan, g.ra, g.mfma, ZA, ZB, ZC, st);
     const bool sq = g.ra == g.m && g.m == g.cb && g.ra <= 64 && !(g.transA && g.transB);
     if (sq && gemm_sq_class(g.ra, g.mfma) >= 9) {
-        if (g.transA) return gemm_sq_t<T, true, false>(plan, g.ra, ZA, ZB, ZC, st);
-        return gemm_sq_t<T, false, true>(plan, g.ra, ZA, ZB, ZC, st);
+        if (g.transA) return gemm_sq_t<T, true, false>(plan, g.ra, g.mfma, ZA, ZB, ZC, st);
+        return gemm_sq_t<T, false, true>(plan, g.ra, g.mfma, ZA, ZB, ZC, st);
     }
     const int dmax = g.ra > g.cb ? g.ra : g.cb;
     // Thin products (a matrix times a vector, and its adjoints) take 1 x 1

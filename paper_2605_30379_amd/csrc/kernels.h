@@ -185,7 +185,8 @@ struct GemmDesc {
     int ra, m, cb;          // C[ra x cb] = A[ra x m] * B[m x cb]
     int transA, transB;     // operand stored transposed (A stored m x ra, B stored cb x m)
     int nlA, nlB, nlC;      // complex lanes of the stored sequences
-    int mfma;               // square products: 0 vector kernel, 1 matrix cores where the padding is small, 2 always
+    int mfma;               // square products: 0 vector kernel; 1 matrix cores, three real products per complex
+                            // product for padded d >= 48; 2 matrix cores, four real products
 };
 template <typename T>
 hipError_t freq_gemm(const FftPlan &plan, const GemmDesc &g, const cplx<T> *ZA, const cplx<T> *ZB, cplx<T> *ZC,
@@ -197,7 +198,7 @@ int gemm_sq_class(int d, int mfma);
 template <typename T>
 int64_t gemm_batch_layout(const FftPlan &plan, GemmProblem<T> *host_probs, int nprob, int mfma);
 template <typename T>
-hipError_t freq_gemm_batched(const FftPlan &plan, int dclass, const GemmProblem<T> *dev_probs, int nprob,
+hipError_t freq_gemm_batched(const FftPlan &plan, int dclass, int mfma, const GemmProblem<T> *dev_probs, int nprob,
                              int64_t total_wg, double bytes, double flops, hipStream_t st);
 // C = A * diag(h): A ra x cb, h has cb lanes.
 template <typename T>
