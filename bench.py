@@ -15,7 +15,9 @@ Workloads (synthetic, seeded):
   c4            512 uneven problems in one batched call (mixed value, FP64 beside).
   c5            gradient of availability + first-entrance loss, d = 32, n = 65536.
 
-Accuracy (both forms) is the max-abs error against the CPU oracle of psi, P,
+Forms: fp64 (the value), mixed (float32 Newton + float64 residual sweeps) and
+bf16x3 (the same with split-BF16 products on the matrix cores), all timed.
+Accuracy (every form) is the max-abs error against the CPU oracle of psi, P,
 reliability, availability and the first entrance into {d-1}, each on a prefix
 of the horizon (an exact sub-problem by finite-horizon exactness).
 """
@@ -376,28 +378,54 @@ def accuracy(cfg, q, forms, mr, torch, si, dev):
 
 def run_batched(args, mr, torch, si, dev):
     """512 uneven problems (d in 3..48, n log-uniform in [1024, 32768]) in one
-    batched call per step, mixed form; also the same problems one call each."""
+    batched call per step; every form timed, also as one call per problem.
+    The value is the mixed form's effective TFLOP/s; the FP64 form is measured
+    against its byte model (sum over problems of 14 L d^2 w per Newton step)
+    and the dominant kernel's roofline comes from the library's launch timer."""
     work = si.batch_workload(CONFIGS["c4"]["seed"], 512)
+    n_table = 0 if args.no_tuning_table else mr.load_tuning_table(device=dev)
+    print(f"[bench] c4: tuning table with {n_table} entries", file=sys.stderr, flush=True)
     qs = [si.family_kernel(w["family"], w["d"], w["n"], w["seed"], device=dev).q for w in work]
     torch.cuda.synchronize()
     fl = sum(f_nom(w["d"], w["n"]) for w in work)
+    mb64 = sum(model_bytes(w["d"], w["n"], 8) for w in work)
+    forms = [f for f in args.forms.split(",") if f]
     res = {}
-    for form in [f for f in args.forms.split(",") if f]:
-        ms = time_steps(lambda: mr.psi_inverse_batched(qs, form), args.steps, args.warmup, torch)
+    for form in forms:
+        plan = mr.BatchedPlan(qs, form)
+        ms = time_steps(plan.launch, args.steps, args.warmup, torch)
         mr.sync_status(dev)
         ms_single = time_steps(lambda: [mr.psi_inverse(q, form) for q in qs], max(1, args.steps // 4), 1, torch)
         res[form] = {"ms": ms, "tflops": fl / (ms * 1e-3) / 1e12, "ms_one_call_each": ms_single}
         print(f"[bench] c4 {form}: batched {ms:.3f} ms, one call each {ms_single:.3f} ms", file=sys.stderr, flush=True)
-    v = res.get("mixed", next(iter(res.values())))
+        del plan
+    value_form = "mixed" if "mixed" in res else forms[0]
+    roof = breakdown = None
+    if "fp64" in res:
+        plan = mr.BatchedPlan(qs, "fp64")
+        enable, collect = kernel_stats(mr, torch, dev)
+        enable(True)
+        plan.launch()
+        stats = collect()
+        enable(False)
+        roof, breakdown = roofline_of(stats, os.path.join(ROOT, "profiles", "traffic_c4_fp64.json"))
+        del plan
+    v = res[value_form]
     line = {
         "metric": "psi inversion sec & effective TFLOP/s, mixed vs FP64 on 1 GPU @ max err<=1e-10",
         "value": round(v["tflops"], 4), "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(v["ms"], 4), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
         "config": {"workload": "c4: 512 uneven problems, d in 3..48, n log-uniform in [1024, 32768], "
-                               "Weibull or lognormal, one batched call", "problems": 512},
+                               "Weibull or lognormal, one batched launch sequence per step (prepared plan)",
+                   "problems": 512, "form": value_form},
         "forms": {f: {k: round(x, 4) for k, x in r.items()} for f, r in res.items()},
-        "nominal_flops": fl, "source_hash": source_hash(),
+        "speedup_vs_fp64": ({f: round(res["fp64"]["ms"] / res[f]["ms"], 3) for f in res} if "fp64" in res else None),
+        "model_bytes_fp64": mb64,
+        "path_roofline_frac_fp64": (round(mb64 / (HBM_PEAK_GBS * 1e9) / (res["fp64"]["ms"] * 1e-3), 4)
+                                    if "fp64" in res else None),
+        "roofline_fp64": roof, "kernels_fp64": breakdown,
+        "nominal_flops": fl, "tuning_table_entries": n_table, "source_hash": source_hash(),
     }
     print(json.dumps(line), flush=True)
 
@@ -449,7 +477,8 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle work for cpu_baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true", help="skip the accuracy checks against the oracle")
-    ap.add_argument("--forms", default="fp64,mixed", help="comma-separated forms to time (value form first)")
+    ap.add_argument("--no-tuning-table", action="store_true", help="c4: do not load the per-class tuning table")
+    ap.add_argument("--forms", default="fp64,mixed,bf16x3", help="comma-separated forms to time (value form first)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one 1 GiB device-to-device copy first (reference for HBM counter runs)")
     ap.add_argument("--stage-table", nargs=4, metavar=("TRACE_CSV", "FETCH_CSV", "WRITE_CSV", "MFMA_CSV"),
@@ -553,6 +582,8 @@ def main():
         "effective_tflops": {f: round(res[f]["tflops"], 4) for f in forms},
         "mixed_speedup_vs_fp64": (round(res["fp64"]["ms"] / res["mixed"]["ms"], 3)
                                   if "fp64" in res and "mixed" in res else None),
+        "speedup_vs_fp64": ({f: round(res["fp64"]["ms"] / res[f]["ms"], 3) for f in forms}
+                            if "fp64" in res else None),
         "nominal_flops": f_nom(d, n),
         "model_bytes_fp64": model_bytes(d, n, 8),
         "path_roofline_frac_fp64": (round(model_bytes(d, n, 8) / (HBM_PEAK_GBS * 1e9) / (res["fp64"]["ms"] * 1e-3), 4)

@@ -47,8 +47,17 @@ extern "C" {
 #endif
 
 typedef enum {
-    MRINV_FP64 = 0,        /* every FFT and product in float64 */
-    MRINV_MIXED_FP32 = 1   /* float32 Newton, then a float64 residual sweep (see mrinv_psi_inverse) */
+    MRINV_FP64 = 0,          /* every FFT and product in float64; Newton step m -> m' at cyclic length m' */
+    MRINV_MIXED_FP32 = 1,    /* float32 Newton, then float64 residual sweeps (see mrinv_psi_inverse) */
+    MRINV_MIXED_BF16X3 = 2,  /* as MIXED_FP32, but the float32 frequency-domain products for d > 8 run as
+                                split-BF16 triple products (hi*hi + hi*lo + lo*hi) on the BF16 matrix cores
+                                with FP32 accumulation */
+    MRINV_FP64_PADDED = 3    /* float64 with every Newton step at the zero-padded length 2m' of the
+                                Appendix (no wrap-around), twice the transform work of MRINV_FP64.  On
+                                recurrent kernels the cyclic first product's rounding grows with the
+                                coefficient index; padding removes that term (d = 3, n = 300000: 8.7e-13
+                                instead of 3.6e-12) but doubles the transform length, whose own rounding
+                                dominates at the largest horizons (n = 2^21: 5.3e-12 instead of 2.0e-12) */
 } mrinv_precision_t;
 
 typedef enum {
@@ -76,7 +85,9 @@ typedef enum {
     MRINV_OP_TRANSITION_BACKWARD = 5,
     MRINV_OP_FIRST_ENTRANCE = 6,    /* mrinv_first_entrance / mrinv_reliability (r = |D|) */
     MRINV_OP_AVAILABILITY = 7,
-    MRINV_OP_RESIDUAL = 8           /* mrinv_residual_norms */
+    MRINV_OP_RESIDUAL = 8,          /* mrinv_residual_norms */
+    MRINV_OP_MRE = 9,               /* mrinv_mre_solve (r = columns of L) */
+    MRINV_OP_GJ = 10                /* mrinv_series_inverse_gj / mrinv_psi_inverse_gj */
 } mrinv_op_t;
 
 typedef struct mrinv_handle_s *mrinv_handle_t;
@@ -147,6 +158,22 @@ mrinv_status_t mrinv_series_inverse(mrinv_handle_t h, const double *A, int d, in
                                     mrinv_precision_t precision, double *Ainv,
                                     void *ws, size_t ws_bytes);
 
+/* The same inverse by Gauss-Jordan elimination over the truncated series
+ * ring C[[x]]/<x^n> (Appendix, Gauss-Jordan paragraph; cost
+ * O(d^3 n log n), Proposition 2.4): on the augmented sequence [A | I], pivot i
+ * takes the row whose column-i series has the largest |constant coefficient|
+ * (row pivoting; A(0) nonsingular guarantees a nonzero one), inverts that
+ * series by scalar Newton iteration, normalises its row and eliminates column
+ * i from the other rows with truncated series products (transform length
+ * 2^ceil(log2(2n-1))).  FP64.  The result agrees with mrinv_series_inverse to
+ * rounding (the inverse is unique).  A, Ainv : device [n][d][d];
+ * mrinv_psi_inverse_gj takes q and inverts e0 - q.  A singular A(0) (pivot
+ * below d 2^-53 max|A(0)|) sets MRINV_E_SINGULAR_A0 on the device. */
+mrinv_status_t mrinv_series_inverse_gj(mrinv_handle_t h, const double *A, int d, int64_t n, double *Ainv,
+                                       void *ws, size_t ws_bytes);
+mrinv_status_t mrinv_psi_inverse_gj(mrinv_handle_t h, const double *q, int d, int64_t n, double *psi,
+                                    void *ws, size_t ws_bytes);
+
 /* M = psi * L truncated at n (eq. (convolution) with rectangular
  * coefficients; reward-type equation V = psi*r, eq. (reward), and the
  * first-entrance kernel g_D = psi_CC * q_CD, eq. (first-entrance-mass)).
@@ -200,6 +227,77 @@ mrinv_status_t mrinv_reliability(mrinv_handle_t h, const double *q, int d, int64
                                  void *ws, size_t ws_bytes);
 mrinv_status_t mrinv_availability(mrinv_handle_t h, const double *P, int d, int64_t n,
                                   const int *up, const double *alpha, double *A);
+
+/* Expected renewal visits to B up to time k, counting the renewal at time
+ * zero (Section 4.1, eq. (renewal-visits); Table 2):
+ *   N_B(k) = alpha sum_{l<=k} psi(l) I_B 1,  k < n.
+ * psi : device [n][d][d]; in_B : host int mask [d]; alpha : host float64 [d]
+ * (both read during the call and passed as kernel arguments); N : device [n]. */
+mrinv_status_t mrinv_renewal_visits(mrinv_handle_t h, const double *psi, int d, int64_t n, const int *in_B,
+                                    const double *alpha, double *N);
+
+/*
+ * Mean-value (endpoint) discretisation of the continuous-time Markov renewal
+ * equation K = L + Q (Stieltjes) K on the grid t_m = m h (Section 4.2,
+ * eqs. (mre-discrete) and (mre-solution)):
+ *   K_h = (e0 - Qbar_h)^(-1) * [L_h - (1/2) Delta+Q_h * (L_h(0) e0)],
+ *   Delta Q_h(0) = 0,  Delta Q_h(m) = Q_h(m) - Q_h(m-1),
+ *   Delta+Q_h(m) = Delta Q_h(m+1),  Qbar_h = (Delta Q_h + Delta+Q_h) / 2.
+ *   Qs : device [n+1][d][d], Qs[m] = Q(m h) for m = 0..n (the value at n
+ *        enters Delta+Q_h(n-1));
+ *   L  : device [n][d][r], L[m] = L(m h);
+ *   K  : device [n][d][r] output, K_h(m) for m = 0..n-1.
+ * L = Hbar_h gives the transition function P_h; L = Q_UD on the up block gives
+ * the first-entrance distribution of reliability.  Qbar_h(0) = Delta Q_h(1)/2
+ * is not zero: the inverse runs its Gauss-Jordan path on I - Qbar_h(0).
+ * `precision` selects the inverse's form; the product with the right-hand
+ * side is float64.  1 <= d, r <= 64. */
+mrinv_status_t mrinv_mre_solve(mrinv_handle_t h, const double *Qs, int d, int64_t n, const double *L, int r,
+                               mrinv_precision_t precision, double *K, void *ws, size_t ws_bytes);
+
+/*
+ * Pathwise Monte Carlo of a finite semi-Markov process on the grid
+ * t_m = m * step, m < n: the independent validation of the continuous-time
+ * approximations in Section 5.2 (lognormal model, 10^6 trajectories,
+ * pointwise 95% normal confidence intervals).  Each trajectory starts in
+ * `initial`; at a jump from i it draws j from row i of P and a sojourn from
+ * F_ij (kernel Q_ij(t) = P_ij F_ij(t)).  The state at t_m is the one whose
+ * sojourn [a, b) has ceil(a/step) <= m < ceil(b/step).
+ *   A[m] : fraction of trajectories in an up state at t_m (availability);
+ *   R[m] : fraction that has not entered a down state on [0, t_m] (reliability);
+ *   tau_D (optional, device double [trajectories]): first entrance time into
+ *          the down set, -1 if none by t_{n-1} (0 if `initial` is down);
+ *   jumps (optional, device int [trajectories]): jumps at times <= t_{n-1}.
+ * Random numbers: Philox4x32-10 (Salmon et al., SC 2011); jump k of
+ * trajectory t uses counters (k, 0, t_lo, t_hi) and (k, 1, t_lo, t_hi) under
+ * the key (seed_lo, seed_hi): the first block's words 0-1 pick the next state,
+ * words 2-3 give the sojourn's first uniform, the second block's words 0-1 its
+ * second; a uniform is (x + 1/2) 2^-53 with x the top 27 and 26 bits of two
+ * words.  Sojourns: lognormal exp(mu + sigma z), z = sqrt(-2 ln u1)
+ * cos(2 pi u2); Weibull scale (-ln u1)^(1/shape); exponential -ln(u1)/rate.
+ * Results are deterministic (integer atomics).  Model arrays are host
+ * memory read during the call; A, R are device [n]; ws holds
+ * mrinv_mc_workspace_size(n) bytes.  1 <= d <= MRINV_MC_MAX_D.
+ */
+#define MRINV_MC_MAX_D 8
+typedef enum {
+    MRINV_SOJOURN_LOGNORMAL = 0,    /* p1 = mu, p2 = sigma: F(t) = Phi((ln t - mu) / sigma) */
+    MRINV_SOJOURN_WEIBULL = 1,      /* p1 = shape, p2 = scale: F(t) = 1 - exp(-(t/scale)^shape) */
+    MRINV_SOJOURN_EXPONENTIAL = 2   /* p1 = rate: F(t) = 1 - exp(-rate t) */
+} mrinv_sojourn_t;
+typedef struct {
+    int d;                  /* states */
+    int family;             /* mrinv_sojourn_t, one family for every transition */
+    int initial;            /* initial state */
+    const double *P;        /* host [d][d] embedded jump matrix (rows sum to 1) */
+    const double *p1;       /* host [d][d] sojourn parameters of i -> j (used where P_ij > 0) */
+    const double *p2;       /* host [d][d] */
+    const int *up;          /* host [d] up-state mask */
+} mrinv_mc_model_t;
+size_t mrinv_mc_workspace_size(int64_t n);
+mrinv_status_t mrinv_semi_markov_mc(mrinv_handle_t h, const mrinv_mc_model_t *model, double step, int64_t n,
+                                    int64_t trajectories, uint64_t seed, double *A, double *R, double *tau_D,
+                                    int *jumps, void *ws, size_t ws_bytes);
 
 /*
  * Adjoint of psi = (e0 - q)^-1: given psi and a cotangent psi_bar (device
@@ -305,6 +403,26 @@ typedef struct {
                            their two truncated products directly in the time domain on the matrix cores
                            instead of through transforms: -1 automatic from d (default), 0 never. */
 } mrinv_tuning_t;
+
+/* A table of tunings by problem class, typically written by the library's
+ * autotuning script (paper_2605_30379_amd/tune_table.py, which runs
+ * mrinv_autotune on one representative problem per class).  A call takes the
+ * first entry whose inclusive ranges hold its (d, n) and whose precision
+ * matches (-1: any); without a match the handle's tuning applies.  Single
+ * inversions (also those inside first_entrance, reliability, mre_solve) use
+ * the whole entry; batched inversions take each problem's recursion seed
+ * (seed_m0) and direct-step limit (direct_m) from its entry and every
+ * launch-shape field from the handle, so with a table installed a batched
+ * result equals the single call's to rounding, and bit for bit when the
+ * entries' launch-shape fields equal the handle's.  count = 0 clears the
+ * table; the entries are copied. */
+typedef struct {
+    int d_lo, d_hi;         /* inclusive range of the matrix dimension */
+    int64_t n_lo, n_hi;     /* inclusive range of the horizon */
+    int precision;          /* mrinv_precision_t, or -1 for every precision */
+    mrinv_tuning_t tune;
+} mrinv_tuning_entry_t;
+mrinv_status_t mrinv_set_tuning_table(mrinv_handle_t h, const mrinv_tuning_entry_t *entries, int count);
 
 mrinv_status_t mrinv_get_tuning(mrinv_handle_t h, mrinv_tuning_t *out);
 mrinv_status_t mrinv_set_tuning(mrinv_handle_t h, const mrinv_tuning_t *t);

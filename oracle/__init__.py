@@ -59,6 +59,11 @@ def _load():
         "orc_adjoint": (None, [dp, dp, I, L, dp]),
         "orc_forward_mode": (None, [dp, dp, dp, I, L, dp]),
         "orc_num_threads": (I, []),
+        "orc_philox4x32_10": (None, [ctypes.POINTER(ctypes.c_uint), ctypes.POINTER(ctypes.c_uint),
+                                     ctypes.POINTER(ctypes.c_uint)]),
+        "orc_semi_markov_mc": (None, [I, I, I, dp, dp, dp, ip, ctypes.c_double, L, L, ctypes.c_ulonglong,
+                                      ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(ctypes.c_longlong), dp,
+                                      ip]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -219,6 +224,75 @@ def reliability(q, up, alpha=None) -> np.ndarray:
     up = np.asarray(up, dtype=np.int32)
     _, F = first_entrance(q, 1 - up, alpha)
     return 1.0 - F
+
+
+def renewal_visits(q, inB, alpha) -> np.ndarray:
+    """Expected renewal visits to B up to time k, counting the renewal at time
+    zero (Section 4.1, eq. (renewal-visits)): N_B(k) = alpha sum_{l<=k} psi(l)
+    I_B 1, with the row alpha psi from the right recursion.  Returns [n]."""
+    q = _f64(q)
+    r = series_inverse_row(e0_minus(q), _f64(alpha))
+    return np.cumsum(r @ np.asarray(inB, dtype=np.float64))
+
+
+def mre_mean_value(Qs, L) -> np.ndarray:
+    """Mean-value (endpoint) discretisation of the continuous-time Markov
+    renewal equation K = L + Q star K (Section 4.2, eqs. (mre-discrete) and
+    (mre-solution)).  Qs is the kernel on the grid, Qs[m] = Q(m h) for
+    m = 0..n ([n+1, d, d]); L is [n, d, r], L[m] = L(m h).  With
+    Delta Q_h(0) = 0, Delta Q_h(m) = Q_h(m) - Q_h(m-1), Delta+Q_h(m) =
+    Delta Q_h(m+1) and Qbar_h = (Delta Q_h + Delta+Q_h)/2:
+        K_h = (e0 - Qbar_h)^(-1) * [L_h - 1/2 Delta+Q_h * (L_h(0) e0)],
+    where the last product is Delta+Q_h(m) L_h(0) at every m (the sequence
+    L_h(0) e0 has one coefficient).  Qbar_h(0) = Delta Q_h(1)/2, so the
+    inverse has A(0) = I - Qbar_h(0) != I.  Returns K_h [n, d, r]."""
+    Qs = _f64(Qs)
+    L = _f64(L)
+    n = L.shape[0]
+    if Qs.shape[0] != n + 1:
+        raise ValueError("Qs needs n + 1 grid values")
+    dQ = np.zeros_like(Qs)
+    dQ[1:] = Qs[1:] - Qs[:-1]
+    dQp = dQ[1:n + 1]
+    Qbar = 0.5 * (dQ[:n] + dQp)
+    A = -Qbar
+    A[0] += np.eye(Qs.shape[1])
+    X = series_inverse_left(A)
+    rhs = L - 0.5 * np.matmul(dQp, L[0])
+    return conv(X, rhs)
+
+
+def philox4x32_10(counter, key) -> np.ndarray:
+    """One block of Philox4x32-10 (Salmon et al., SC 2011): four 32-bit words."""
+    c = np.ascontiguousarray(counter, dtype=np.uint32)
+    k = np.ascontiguousarray(key, dtype=np.uint32)
+    out = np.empty(4, dtype=np.uint32)
+    up = ctypes.POINTER(ctypes.c_uint)
+    _load().orc_philox4x32_10(c.ctypes.data_as(up), k.ctypes.data_as(up), out.ctypes.data_as(up))
+    return out
+
+
+FAMILIES = {"lognormal": 0, "weibull": 1, "exponential": 2}
+
+
+def semi_markov_mc(P, p1, p2, up, h, n, trajectories, seed, family="lognormal", initial=0, per_path=False):
+    """Pathwise Monte Carlo of a semi-Markov process on the grid m h, m < n
+    (the Section 5.2 validation).  Returns (A, R) estimates, and with
+    per_path also (tau_D, jumps) per trajectory; see mrinv_oracle.c for the
+    stream layout and sampling."""
+    P = _f64(P)
+    d = P.shape[0]
+    a = np.zeros(n, dtype=np.int64)
+    r = np.zeros(n, dtype=np.int64)
+    tau = np.empty(trajectories) if per_path else None
+    jumps = np.empty(trajectories, dtype=np.int32) if per_path else None
+    lp = ctypes.POINTER(ctypes.c_longlong)
+    _load().orc_semi_markov_mc(d, FAMILIES[family], int(initial), _p(P), _p(_f64(p1)), _p(_f64(p2)),
+                               _ip(np.ascontiguousarray(up, dtype=np.int32)), float(h), int(n), int(trajectories),
+                               int(seed), a.ctypes.data_as(lp), r.ctypes.data_as(lp),
+                               _p(tau) if per_path else None, _ip(jumps) if per_path else None)
+    A, R = a / trajectories, r / trajectories
+    return (A, R, tau, jumps) if per_path else (A, R)
 
 
 def adjoint(psi_seq, psibar) -> np.ndarray:

@@ -471,6 +471,130 @@ void orc_forward_mode(const double *q, const double *psi, const double *dq, int 
     }
 }
 
+/* ------------------------------------------------------------------------- */
+/* Pathwise Monte Carlo of a finite semi-Markov process (Section 5.2, the     */
+/* validation of the lognormal model by simulated trajectories).             */
+/* Random numbers: Philox4x32-10 as published by Salmon, Moraes, Dror and     */
+/* Shaw (SC 2011): per round, with the multipliers M0 = 0xD2511F53 and        */
+/* M1 = 0xCD9E8D57, (hi0, lo0) = M0 * c0 and (hi1, lo1) = M1 * c2 as 64-bit    */
+/* products, and c <- (hi1 ^ c1 ^ k0, lo1, hi0 ^ c3 ^ k1, lo0); ten rounds,   */
+/* the key raised by (0x9E3779B9, 0xBB67AE85) between rounds.                 */
+/* Stream layout and sampling as stated in the library's interface: jump k of */
+/* trajectory t uses counters (k, 0, t_lo, t_hi) and (k, 1, t_lo, t_hi) under */
+/* the key (seed_lo, seed_hi); a uniform is (x + 1/2) 2^-53 with x the top 27 */
+/* and 26 bits of two words; the next state is the first j whose cumulative */
+/* row sum exceeds the uniform; the sojourn of i -> j is lognormal            */
+/* exp(mu + sigma z) with the Box-Muller z = sqrt(-2 ln u1) cos(2 pi u2)      */
+/* (family 0), Weibull scale (-ln u1)^(1/shape) (1), exponential             */
+/* -ln(u1)/rate (2).  The state at grid time m h is the one whose sojourn    */
+/* [a, b) has ceil(a/h) <= m < ceil(b/h).                                   */
+/* Outputs: counts A_cnt[m] of trajectories up at t_m, R_cnt[m] of those not */
+/* yet in a down state on [0, t_m]; per trajectory (optional) the first     */
+/* entrance time into the down set (-1 if none by t_{n-1}) and the number of  */
+/* jumps at times <= t_{n-1}.                                                 */
+/* ------------------------------------------------------------------------- */
+static void orc_philox(unsigned int c[4], unsigned int k0, unsigned int k1)
+{
+    for (int r = 0; r < 10; ++r) {
+        if (r > 0) { k0 += 0x9E3779B9u; k1 += 0xBB67AE85u; }
+        unsigned long long p0 = 0xD2511F53ull * (unsigned long long)c[0];
+        unsigned long long p1 = 0xCD9E8D57ull * (unsigned long long)c[2];
+        unsigned int hi0 = (unsigned int)(p0 >> 32), lo0 = (unsigned int)p0;
+        unsigned int hi1 = (unsigned int)(p1 >> 32), lo1 = (unsigned int)p1;
+        unsigned int n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
+        c[0] = n0; c[1] = lo1; c[2] = n2; c[3] = lo0;
+    }
+}
+
+void orc_philox4x32_10(const unsigned int *ctr, const unsigned int *key, unsigned int *out)
+{
+    unsigned int c[4] = {ctr[0], ctr[1], ctr[2], ctr[3]};
+    orc_philox(c, key[0], key[1]);
+    for (int i = 0; i < 4; ++i) out[i] = c[i];
+}
+
+static double orc_u01(unsigned int a, unsigned int b)
+{
+    unsigned long long x = ((unsigned long long)(a >> 5) << 26) | (unsigned long long)(b >> 6);
+    return ((double)x + 0.5) / 9007199254740992.0;
+}
+
+static long orc_grid_ceil(double t, double h, long n)
+{
+    double q = ceil(t / h);
+    return q >= (double)n ? n : (long)q;
+}
+
+void orc_semi_markov_mc(int d, int family, int initial, const double *P, const double *p1, const double *p2,
+                        const int *up, double h, long n, long trajectories, unsigned long long seed,
+                        long long *A_cnt, long long *R_cnt, double *tau_out, int *jumps_out)
+{
+    const double tmax = (double)(n - 1) * h;
+    const unsigned int key0 = (unsigned int)seed, key1 = (unsigned int)(seed >> 32);
+    long long *dA = (long long *)calloc((size_t)n + 1, sizeof(long long));
+    long long *dR = (long long *)calloc((size_t)n + 1, sizeof(long long));
+#pragma omp parallel
+    {
+        long long *lA = (long long *)calloc((size_t)n + 1, sizeof(long long));
+        long long *lR = (long long *)calloc((size_t)n + 1, sizeof(long long));
+#pragma omp for schedule(dynamic, 256)
+        for (long t = 0; t < trajectories; ++t) {
+            int s = initial;
+            double now = 0.0;
+            double tau = up[s] ? -1.0 : 0.0;
+            int jumps = 0;
+            if (up[s]) lR[0] += 1;
+            for (unsigned int k = 0; now <= tmax; ++k) {
+                unsigned int b0[4] = {k, 0u, (unsigned int)t, (unsigned int)((unsigned long long)t >> 32)};
+                unsigned int b1[4] = {k, 1u, (unsigned int)t, (unsigned int)((unsigned long long)t >> 32)};
+                orc_philox(b0, key0, key1);
+                orc_philox(b1, key0, key1);
+                double un = orc_u01(b0[0], b0[1]), ua = orc_u01(b0[2], b0[3]), ub = orc_u01(b1[0], b1[1]);
+                /* next state: first j with un < cumulative row sum; the last state with
+                   positive probability if rounding leaves the row sum below un */
+                int j = -1, last = -1;
+                double cum = 0.0;
+                for (int c = 0; c < d; ++c) {
+                    cum += P[s * d + c];
+                    if (P[s * d + c] > 0.0) last = c;
+                    if (j < 0 && un < cum) j = c;
+                }
+                if (j < 0) j = last;
+                double a = p1[s * d + j], b = p2[s * d + j], T;
+                if (family == 0) T = exp(a + b * (sqrt(-2.0 * log(ua)) * cos(6.283185307179586476925 * ub)));
+                else if (family == 1) T = b * pow(-log(ua), 1.0 / a);
+                else T = -log(ua) / a;
+                double next = now + T;
+                if (up[s]) {
+                    long ia = orc_grid_ceil(now, h, n), ib = orc_grid_ceil(next, h, n);
+                    if (ia < ib) { lA[ia] += 1; lA[ib] -= 1; }
+                }
+                now = next;
+                s = j;
+                if (now <= tmax) {
+                    ++jumps;
+                    if (tau < 0.0 && !up[s]) { tau = now; lR[orc_grid_ceil(now, h, n)] -= 1; }
+                }
+            }
+            if (tau_out) tau_out[t] = tau;
+            if (jumps_out) jumps_out[t] = jumps;
+        }
+#pragma omp critical
+        for (long i = 0; i <= n; ++i) { dA[i] += lA[i]; dR[i] += lR[i]; }
+        free(lA);
+        free(lR);
+    }
+    long long ra = 0, rr = 0;
+    for (long i = 0; i < n; ++i) {
+        ra += dA[i];
+        rr += dR[i];
+        A_cnt[i] = ra;
+        R_cnt[i] = rr;
+    }
+    free(dA);
+    free(dR);
+}
+
 /* Number of OpenMP threads the oracle will use (1 without OpenMP). */
 int orc_num_threads(void)
 {

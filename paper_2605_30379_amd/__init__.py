@@ -31,8 +31,10 @@ __all__ = [
     "gather_block", "psi_inverse_backward", "markov_renewal_apply_backward", "transition_backward",
     "contract_backward", "scatter_block_add", "psi_inverse_batched", "residual_norms", "sync_status",
     "PsiInverse", "RenewalApply", "Transition", "Contract", "GatherBlock", "workspace_size",
-    "FP64", "MIXED_FP32", "OPS", "Tuning", "get_tuning", "set_tuning", "autotune", "BatchedPlan",
-    "psi_inverse_noalloc", "NOALLOC_SCRATCH_BYTES",
+    "FP64", "MIXED_FP32", "MIXED_BF16X3", "FP64_PADDED", "OPS", "Tuning", "get_tuning", "set_tuning", "autotune", "BatchedPlan",
+    "psi_inverse_noalloc", "NOALLOC_SCRATCH_BYTES", "renewal_visits", "mre_solve",
+    "series_inverse_gj", "semi_markov_mc", "McModel", "SOJOURN", "TuningEntry", "set_tuning_table",
+    "load_tuning_table", "TUNING_TABLE",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -40,9 +42,13 @@ library_path = os.path.join(_HERE, "libmrinv.so")
 
 FP64 = 0
 MIXED_FP32 = 1
-_PREC = {"fp64": FP64, "mixed": MIXED_FP32, "mixed_fp32": MIXED_FP32, FP64: FP64, MIXED_FP32: MIXED_FP32}
+MIXED_BF16X3 = 2
+FP64_PADDED = 3
+_PREC = {"fp64": FP64, "mixed": MIXED_FP32, "mixed_fp32": MIXED_FP32, "bf16x3": MIXED_BF16X3,
+         "mixed_bf16x3": MIXED_BF16X3, "fp64_padded": FP64_PADDED,
+         FP64: FP64, MIXED_FP32: MIXED_FP32, MIXED_BF16X3: MIXED_BF16X3, FP64_PADDED: FP64_PADDED}
 OPS = {"psi_inverse": 0, "apply": 1, "transition": 2, "psi_backward": 3, "apply_backward": 4,
-       "transition_backward": 5, "first_entrance": 6, "availability": 7}
+       "transition_backward": 5, "first_entrance": 6, "availability": 7, "residual": 8, "mre": 9, "gj": 10}
 
 _STATUS = {0: "ok", 1: "invalid argument", 2: "A(0) singular", 3: "non-finite value",
            4: "workspace too small", 5: "unsupported size", 6: "HIP runtime error"}
@@ -57,6 +63,20 @@ class Tuning(ctypes.Structure):
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class McModel(ctypes.Structure):
+    """mrinv_mc_model_t."""
+    _fields_ = [("d", ctypes.c_int), ("family", ctypes.c_int), ("initial", ctypes.c_int),
+                ("P", ctypes.POINTER(ctypes.c_double)), ("p1", ctypes.POINTER(ctypes.c_double)),
+                ("p2", ctypes.POINTER(ctypes.c_double)), ("up", ctypes.POINTER(ctypes.c_int))]
+
+
+class TuningEntry(ctypes.Structure):
+    """mrinv_tuning_entry_t: a tuning for problems with d in [d_lo, d_hi],
+    n in [n_lo, n_hi] and the given precision (-1: any)."""
+    _fields_ = [("d_lo", ctypes.c_int), ("d_hi", ctypes.c_int), ("n_lo", ctypes.c_int64), ("n_hi", ctypes.c_int64),
+                ("precision", ctypes.c_int), ("tune", Tuning)]
 
 
 class MrinvError(RuntimeError):
@@ -103,6 +123,13 @@ def lib():
             "mrinv_first_entrance": (i32, [vp, vp, i32, i64, ip, dp, i32, vp, vp, vp, sz]),
             "mrinv_reliability": (i32, [vp, vp, i32, i64, ip, dp, i32, vp, vp, sz]),
             "mrinv_availability": (i32, [vp, vp, i32, i64, ip, dp, vp]),
+            "mrinv_renewal_visits": (i32, [vp, vp, i32, i64, ip, dp, vp]),
+            "mrinv_series_inverse_gj": (i32, [vp, vp, i32, i64, vp, vp, sz]),
+            "mrinv_mc_workspace_size": (sz, [i64]),
+            "mrinv_semi_markov_mc": (i32, [vp, ctypes.POINTER(McModel), f64, i64, i64, ctypes.c_uint64, vp, vp, vp,
+                                           vp, vp, sz]),
+            "mrinv_psi_inverse_gj": (i32, [vp, vp, i32, i64, vp, vp, sz]),
+            "mrinv_mre_solve": (i32, [vp, vp, i32, i64, vp, i32, i32, vp, vp, sz]),
             "mrinv_psi_inverse_backward": (i32, [vp, vp, vp, i32, i64, vp, vp, sz]),
             "mrinv_markov_renewal_apply_backward": (i32, [vp, vp, vp, vp, i32, i64, i32, vp, vp, vp, sz]),
             "mrinv_transition_backward": (i32, [vp, vp, vp, vp, i32, i64, vp, vp, vp, sz]),
@@ -116,6 +143,7 @@ def lib():
             "mrinv_batched_workspace_size": (sz, [vp, i32, ip, ctypes.POINTER(i64), i32]),
             "mrinv_residual_norms": (i32, [vp, vp, vp, i32, i64, dp, vp, sz]),
             "mrinv_get_tuning": (i32, [vp, ctypes.POINTER(Tuning)]),
+            "mrinv_set_tuning_table": (i32, [vp, ctypes.POINTER(TuningEntry), i32]),
             "mrinv_set_tuning": (i32, [vp, ctypes.POINTER(Tuning)]),
             "mrinv_autotune": (i32, [vp, vp, i32, i64, i32, vp, vp, sz, ctypes.POINTER(Tuning)]),
         }
@@ -209,6 +237,46 @@ def set_tuning(device=None, **kw):
     _check(lib().mrinv_set_tuning(h, ctypes.byref(t)))
 
 
+TUNING_TABLE = os.path.join(_HERE, "tuning_table.json")
+
+
+def set_tuning_table(entries, device=None) -> int:
+    """Install a per-class tuning table in the handle of (device, current
+    stream): a list of dicts with d_lo, d_hi, n_lo, n_hi, precision (a name
+    such as "fp64", or -1 for any) and tune (a dict of mrinv_tuning_t fields;
+    missing fields keep the handle's value).  An empty list clears it."""
+    dev = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+    h = _handle(dev)
+    base = Tuning()
+    _check(lib().mrinv_get_tuning(h, ctypes.byref(base)))
+    arr = (TuningEntry * max(1, len(entries)))()
+    names = {f for f, _ in Tuning._fields_}
+    for i, e in enumerate(entries):
+        t = Tuning(*[getattr(base, f) for f, _ in Tuning._fields_])
+        for k, v in e.get("tune", {}).items():
+            if k not in names:
+                raise MrinvError(1, f"unknown tuning field {k!r}")
+            setattr(t, k, int(v))
+        prec = e.get("precision", -1)
+        arr[i] = TuningEntry(int(e["d_lo"]), int(e["d_hi"]), int(e["n_lo"]), int(e["n_hi"]),
+                             -1 if prec in (-1, None, "any") else _PREC[prec], t)
+    _check(lib().mrinv_set_tuning_table(h, arr, len(entries)))
+    return len(entries)
+
+
+def load_tuning_table(path: str | None = None, device=None) -> int:
+    """Install the table written by paper_2605_30379_amd/tune_table.py (by
+    default the one next to this file); returns the number of entries, 0 if
+    there is no table."""
+    import json
+    path = TUNING_TABLE if path is None else path
+    if not os.path.exists(path):
+        return 0
+    with open(path) as f:
+        data = json.load(f)
+    return set_tuning_table(data["entries"], device)
+
+
 def autotune(q: torch.Tensor, precision="fp64") -> dict:
     """Measure candidate tunings on q, keep the fastest in the device's handle."""
     q = _seq(q, "q")
@@ -274,6 +342,21 @@ def series_inverse(A: torch.Tensor, precision="fp64", check: bool = False) -> to
     out = torch.empty_like(A)
     ws = _ws(lib().mrinv_workspace_size(0, d, n, 0, prec), A.device)
     _check(lib().mrinv_series_inverse(_handle(A.device), _ptr(A), d, n, prec, _ptr(out), _ptr(ws), ws.numel()))
+    if check:
+        sync_status(A.device)
+    return out
+
+
+def series_inverse_gj(A: torch.Tensor, check: bool = False, e0_minus: bool = False) -> torch.Tensor:
+    """A^(-1) on the horizon by Gauss-Jordan elimination over the truncated
+    series ring (Appendix); with e0_minus the argument is q and the result is
+    psi = (e0 - q)^(-1).  FP64."""
+    A = _square(A, "A")
+    n, d, _ = A.shape
+    out = torch.empty_like(A)
+    ws = _ws(lib().mrinv_workspace_size(10, d, n, 0, 0), A.device)
+    fn = lib().mrinv_psi_inverse_gj if e0_minus else lib().mrinv_series_inverse_gj
+    _check(fn(_handle(A.device), _ptr(A), d, n, _ptr(out), _ptr(ws), ws.numel()))
     if check:
         sync_status(A.device)
     return out
@@ -403,6 +486,68 @@ def availability(P: torch.Tensor, up, alpha) -> torch.Tensor:
     A = torch.empty(n, dtype=torch.float64, device=P.device)
     _check(lib().mrinv_availability(_handle(P.device), _ptr(P), d, n, _imask(up, d), _dalpha(alpha, d), _ptr(A)))
     return A
+
+
+def renewal_visits(psi: torch.Tensor, in_B, alpha) -> torch.Tensor:
+    """N_B(k) = alpha sum_{l<=k} psi(l) I_B 1 (eq. (renewal-visits))."""
+    psi = _square(psi, "psi")
+    n, d, _ = psi.shape
+    N = torch.empty(n, dtype=torch.float64, device=psi.device)
+    _check(lib().mrinv_renewal_visits(_handle(psi.device), _ptr(psi), d, n, _imask(in_B, d), _dalpha(alpha, d),
+                                      _ptr(N)))
+    return N
+
+
+def mre_solve(Qs: torch.Tensor, L: torch.Tensor, precision="fp64") -> torch.Tensor:
+    """Mean-value discretisation of K = L + Q (Stieltjes) K (Section 4.2,
+    eq. (mre-solution)): Qs [n+1, d, d] is Q on the grid t_m = m h, L [n, d, r]
+    is L(t_m); returns K_h [n, d, r]."""
+    Qs = _square(Qs, "Qs")
+    n1, d, _ = Qs.shape
+    n = n1 - 1
+    if n < 1:
+        raise MrinvError(1, "Qs needs at least two grid values")
+    L = _seq(L, "L", rows=d, n=n)
+    r = L.shape[2]
+    prec = _PREC[precision]
+    K = torch.empty_like(L)
+    ws = _ws(lib().mrinv_workspace_size(9, d, n, r, prec), Qs.device)
+    _check(lib().mrinv_mre_solve(_handle(Qs.device), _ptr(Qs), d, n, _ptr(L), r, prec, _ptr(K), _ptr(ws),
+                                 ws.numel()))
+    return K
+
+
+SOJOURN = {"lognormal": 0, "weibull": 1, "exponential": 2}
+
+
+def semi_markov_mc(P, p1, p2, up, step: float, n: int, trajectories: int, seed: int, family="lognormal",
+                   initial: int = 0, per_path: bool = False, device=None):
+    """Pathwise Monte Carlo of a semi-Markov process (mrinv_semi_markov_mc):
+    availability and reliability estimates on the grid m*step, m < n, as
+    float64 tensors on the GPU; with per_path also the first entrance time
+    into the down set and the number of jumps of every trajectory."""
+    import numpy as np
+    dev = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+    P_ = np.ascontiguousarray(P, dtype=np.float64)
+    d = P_.shape[0]
+    a1 = np.ascontiguousarray(p1, dtype=np.float64)
+    a2 = np.ascontiguousarray(p2, dtype=np.float64)
+    um = np.ascontiguousarray(up, dtype=np.int32)
+    if P_.shape != (d, d) or a1.shape != (d, d) or a2.shape != (d, d) or um.shape != (d,):
+        raise MrinvError(1, "P, p1, p2 must be d x d and up of length d")
+    dp = ctypes.POINTER(ctypes.c_double)
+    m = McModel(d, SOJOURN[family], int(initial), P_.ctypes.data_as(dp), a1.ctypes.data_as(dp),
+                a2.ctypes.data_as(dp), um.ctypes.data_as(ctypes.POINTER(ctypes.c_int)))
+    A = torch.empty(n, dtype=torch.float64, device=dev)
+    R = torch.empty(n, dtype=torch.float64, device=dev)
+    tau = torch.empty(trajectories, dtype=torch.float64, device=dev) if per_path else None
+    jumps = torch.empty(trajectories, dtype=torch.int32, device=dev) if per_path else None
+    L = lib()
+    ws = _ws(L.mrinv_mc_workspace_size(n), dev)
+    _check(L.mrinv_semi_markov_mc(_handle(dev), ctypes.byref(m), float(step), int(n), int(trajectories),
+                                  ctypes.c_uint64(int(seed)), _ptr(A), _ptr(R), _ptr(tau), _ptr(jumps), _ptr(ws),
+                                  ws.numel()))
+    return (A, R, tau, jumps) if per_path else (A, R)
 
 
 def residual_norms(q: torch.Tensor, X: torch.Tensor):

@@ -102,6 +102,7 @@ struct mrinv_handle_s {
     hipStream_t cap_stream = nullptr;
     void *batch = nullptr;          // plan of the last mrinv_psi_inverse_batched_prepare (BatchPlan)
     void *noalloc = nullptr;        // device address of `scratch` on this handle's device
+    std::vector<mrinv_tuning_entry_t> table;   // per-(d, n, precision) tunings (mrinv_set_tuning_table)
     Twiddles<double> t64() const { return {tw64, tw64 + TW_HI_SIZE, tw64 + TW_HI_SIZE + TW_LO_SIZE, nullptr}; }
     Twiddles<float> t32() const { return {tw64, tw64 + TW_HI_SIZE, tw64 + TW_HI_SIZE + TW_LO_SIZE, nullptr}; }
 };
@@ -212,10 +213,16 @@ extern "C" const char *mrinv_status_string(mrinv_status_t s) {
 
 extern "C" const char *mrinv_last_error(void) { return g_last_error.c_str(); }
 
-// Activates launch timing for the duration of one entry point.
+// Activates launch timing for the duration of one entry point; entry points
+// that call others keep the outermost scope's setting.
+static thread_local int g_timer_depth = 0;
 struct TimerScope {
-    explicit TimerScope(mrinv_handle_t h) { timer_activate(h && h->timing ? h->timer : nullptr, h ? h->stream : nullptr); }
-    ~TimerScope() { timer_activate(nullptr, nullptr); }
+    explicit TimerScope(mrinv_handle_t h) {
+        if (g_timer_depth++ == 0) timer_activate(h && h->timing ? h->timer : nullptr, h ? h->stream : nullptr);
+    }
+    ~TimerScope() {
+        if (--g_timer_depth == 0) timer_activate(nullptr, nullptr);
+    }
 };
 
 extern "C" mrinv_status_t mrinv_set_timing(mrinv_handle_t h, int enabled) {
@@ -280,12 +287,20 @@ struct Carve {
     }
 };
 
+// Precisions: FP64 (cyclic length m' per Newton step), FP64_PADDED (the
+// zero-padded length 2m' of every step), and the two mixed forms (float32
+// Newton with float32 or split-BF16 products, then float64 residual sweeps).
+static bool prec_valid(mrinv_precision_t p) { return p >= MRINV_FP64 && p <= MRINV_FP64_PADDED; }
+static bool prec_mixed(mrinv_precision_t p) { return p == MRINV_MIXED_FP32 || p == MRINV_MIXED_BF16X3; }
+static int prec_pad(mrinv_precision_t p) { return p == MRINV_FP64_PADDED ? 1 : 0; }
+static int prec_bf3(mrinv_precision_t p) { return p == MRINV_MIXED_BF16X3 ? 1 : 0; }
+
 // Outer-twiddle tables of all Newton steps up to 2^lgN plus, for the mixed
 // form, the sweep length 2^lg2 in both precisions (bounds valid for every
 // pass split: tables of one plan hold at most 1.1 L entries).
 static size_t ws_twiddles(int lgN, int lg2, mrinv_precision_t prec) {
     const size_t L = (size_t)1 << lgN;
-    if (prec == MRINV_FP64) return align256(3 * L * 16) + 4096;
+    if (!prec_mixed(prec)) return align256(3 * L * 16) + 4096;
     return align256(3 * L * 8) + align256(2 * ((size_t)1 << lg2) * 16) + align256(2 * ((size_t)1 << lg2) * 8) + 4096;
 }
 
@@ -299,7 +314,10 @@ static size_t ws_psi(int d, int64_t n, mrinv_precision_t prec) {
     const int64_t d2 = (int64_t)d * d;
     const int lgN = std::max(1, ceil_log2(n));
     const int lg2 = lg_full(n);
-    if (prec == MRINV_FP64) return 3 * spec_bytes(lgN, d2, true) + ws_twiddles(lgN, lg2, prec);
+    if (!prec_mixed(prec)) {
+        const int lgS = lgN + prec_pad(prec);
+        return 3 * spec_bytes(lgS, d2, true) + ws_twiddles(lgS, lg2, prec);
+    }
     // Sweeps: three float64 spectra at 2^lg2 plus the float32 copy of X's spectrum.
     size_t spec = std::max(3 * spec_bytes(lgN, d2, false), sweep_bytes(lg2, d2));
     return spec + 2 * align256((size_t)n * d2 * sizeof(float)) + ws_twiddles(lgN, lg2, prec);
@@ -341,6 +359,23 @@ static size_t ws_first_entrance(int d, int64_t n, int nD, mrinv_precision_t prec
     return blocks + std::max(ws_psi(nC, n, prec), ws_apply(nC, n, nD));
 }
 
+// Series Gauss-Jordan: W [n][d][2d], the pivot series and its inverse, the
+// multipliers, the pivot bookkeeping, five spectra at the product length
+// (pivot inverse, pivot row, normalised row, multipliers, update) and the
+// scalar inverse's own workspace.
+static size_t ws_gj(int d, int64_t n) {
+    const int lg = lg_full(n);
+    return align256((size_t)n * d * 2 * d * 8) + 2 * align256((size_t)n * 8) + align256((size_t)n * d * 8) + 256 +
+           spec_bytes(lg, 1, true) + 2 * spec_bytes(lg, 2 * d, true) + spec_bytes(lg, d, true) +
+           spec_bytes(lg, (int64_t)2 * d * d, true) + ws_psi(1, n, MRINV_FP64_PADDED);
+}
+
+static size_t ws_mre(int d, int64_t n, int r, mrinv_precision_t prec) {
+    // Qbar, (e0 - Qbar)^-1 and the right-hand side, then the inverse's or the product's workspace.
+    return 2 * align256((size_t)n * d * d * 8) + align256((size_t)n * d * r * 8) +
+           std::max(ws_psi(d, n, prec), ws_apply(d, n, r));
+}
+
 extern "C" size_t mrinv_workspace_size(mrinv_op_t op, int d, int64_t n, int r, mrinv_precision_t prec) {
     if (d < 1 || d > MRINV_MAX_D || n < 1 || n > MRINV_MAX_N) return 0;
     switch (op) {
@@ -353,6 +388,8 @@ extern "C" size_t mrinv_workspace_size(mrinv_op_t op, int d, int64_t n, int r, m
         case MRINV_OP_FIRST_ENTRANCE: return (r < 1 || r > d) ? 0 : ws_first_entrance(d, n, r, prec);
         case MRINV_OP_AVAILABILITY: return 256;
         case MRINV_OP_RESIDUAL: return ws_residual(d, n);
+        case MRINV_OP_MRE: return (r < 1 || r > MRINV_MAX_D) ? 0 : ws_mre(d, n, r, prec);
+        case MRINV_OP_GJ: return ws_gj(d, n);
     }
     return 0;
 }
@@ -405,6 +442,33 @@ static DstDesc dst_real(void *p, bool dbl, int64_t ld, int nreal, int64_t lo, in
 }
 
 static const mrinv_tuning_t &tune_of(mrinv_handle_t h) { return h ? h->tune : kDefaultTune; }
+
+// Tuning of a problem: the first table entry whose ranges hold (d, n) and
+// whose precision matches (-1 matches any), else the handle's.
+static const mrinv_tuning_t &tune_for(mrinv_handle_t h, int d, int64_t n, int prec) {
+    if (h)
+        for (const auto &e : h->table)
+            if (d >= e.d_lo && d <= e.d_hi && n >= e.n_lo && n <= e.n_hi && (e.precision < 0 || e.precision == prec))
+                return e.tune;
+    return tune_of(h);
+}
+
+// The table's tuning for one call: installed in the handle for the call's
+// duration and restored after it (calls made inside keep their own scope).
+struct TuneScope {
+    mrinv_handle_t h = nullptr;
+    mrinv_tuning_t saved{};
+    TuneScope(mrinv_handle_t hh, int d, int64_t n, int prec) {
+        if (!hh || hh->table.empty()) return;
+        h = hh;
+        saved = hh->tune;
+        const mrinv_tuning_t t = tune_for(hh, d, n, prec);
+        hh->tune = t;
+    }
+    ~TuneScope() {
+        if (h) h->tune = saved;
+    }
+};
 static int order_of(mrinv_handle_t h) { return tune_of(h).block_order; }
 template <typename T> static int lanes_of(mrinv_handle_t h) {
     return sizeof(T) == 8 ? tune_of(h).lanes_fp64 : tune_of(h).lanes_fp32;
@@ -501,12 +565,13 @@ static GemmDesc gdesc(mrinv_handle_t h, int ra, int m, int cb, int ta = 0, int t
 }
 
 // Length of the recursion seed: the largest power of two <= min(seed_m0, n).
-static int64_t seed_len(mrinv_handle_t h, int64_t n) {
-    const int64_t cap = std::min<int64_t>(tune_of(h).seed_m0, n);
+static int64_t seed_len(const mrinv_tuning_t &t, int64_t n) {
+    const int64_t cap = std::min<int64_t>(t.seed_m0, n);
     int64_t m0 = 1;
     while (2 * m0 <= cap) m0 *= 2;
     return m0;
 }
+static int64_t seed_len(mrinv_handle_t h, int64_t n) { return seed_len(tune_of(h), n); }
 
 // Newton steps m -> m2 with m2 <= direct_limit run as direct products in the
 // time domain.  Automatic choice: the largest power of two M for which the
@@ -514,8 +579,8 @@ static int64_t seed_len(mrinv_handle_t h, int64_t n) {
 // rounded up to the 16-wide matrix tiles); below that the transform launches'
 // fixed latency costs more (measured crossover: M = 256 at d = 16).  0 turns
 // the direct steps off.
-static int64_t direct_limit(mrinv_handle_t h, int d) {
-    const int v = tune_of(h).direct_m;
+static int64_t direct_limit(const mrinv_tuning_t &t, int d) {
+    const int v = t.direct_m;
     if (v == 0) return 0;
     int64_t M = 1;
     if (v > 0) {
@@ -526,6 +591,7 @@ static int64_t direct_limit(mrinv_handle_t h, int d) {
     while (1.5 * (double)M * (double)M * D * D * D <= 1.2e8) M *= 2;   // M is twice the step's m
     return M;
 }
+static int64_t direct_limit(mrinv_handle_t h, int d) { return direct_limit(tune_of(h), d); }
 
 // Register the outer-twiddle tables of plan p (every pass but the last,
 // whose column offset is always 0) in g, carving them from region.
@@ -559,7 +625,7 @@ static void add_tables(TwGen &g, FftPlan &p, bool dbl, char *&region, char *end)
 // ---------------------------------------------------------------------------
 template <typename T>
 static mrinv_status_t newton(mrinv_handle_t h, const double *src, int e0, int d, int64_t n, void *out,
-                             cplx<T> *SA, cplx<T> *SB, cplx<T> *ST, char *twr, char *twr_end) {
+                             cplx<T> *SA, cplx<T> *SB, cplx<T> *ST, char *twr, char *twr_end, int pad, int bf3) {
     const bool dbl = sizeof(T) == 8;
     const int d2 = d * d;
     const int nl = nl_of(d2);
@@ -602,7 +668,8 @@ static mrinv_status_t newton(mrinv_handle_t h, const double *src, int e0, int d,
         u.status = dbl ? h->status : nullptr;
         HIP_TRY(conv_direct<T>(u, h->stream));
     }
-    const GemmDesc g = gdesc(h, d, d, d);
+    GemmDesc g = gdesc(h, d, d, d);
+    g.bf3 = bf3;
     // Plans of every step and their outer-twiddle tables (one launch).
     // At most log2(MRINV_MAX_N) + 1 steps; a fixed array keeps the driver free
     // of host allocations.
@@ -610,7 +677,7 @@ static mrinv_status_t newton(mrinv_handle_t h, const double *src, int e0, int d,
     int nplans = 0;
     TwGen tg{};
     for (int64_t m = m0; m < n && nplans < 32; m = std::min(2 * m, n)) {
-        plans[nplans] = hplan(h, ceil_log2(std::min(2 * m, n)));
+        plans[nplans] = hplan(h, ceil_log2(std::min(2 * m, n)) + pad);
         if (twr && h->tune.twiddle_tables >= 2) add_tables(tg, plans[nplans], dbl, twr, twr_end);
         ++nplans;
     }
@@ -674,22 +741,23 @@ static mrinv_status_t inverse_impl(mrinv_handle_t h, const double *src, int e0, 
                                    mrinv_precision_t prec, double *out, void *ws, size_t wsb) {
     if (!h || !src || !out) return fail(MRINV_E_ARG, "NULL handle or pointer");
     CHECK(check_dn(d, n));
-    if (prec != MRINV_FP64 && prec != MRINV_MIXED_FP32) return fail(MRINV_E_ARG, "unknown precision %d", (int)prec);
+    if (!prec_valid(prec)) return fail(MRINV_E_ARG, "unknown precision %d", (int)prec);
     CHECK(check_ws(ws, wsb, ws_psi(d, n, prec)));
     CHECK(check_seed(seed_len(h, n), d));
     const int64_t d2 = (int64_t)d * d;
     const int nl = nl_of(d2);
     const int lgN = std::max(1, ceil_log2(n));
     Carve cv(ws);
-    const size_t twb = ws_twiddles(lgN, lg_full(n), prec);
+    const int pad = prec_pad(prec), bf3 = prec_bf3(prec);
+    const size_t twb = ws_twiddles(lgN + pad, lg_full(n), prec);
     char *twr = cv.take<char>(twb);
     char *twr_end = twr + twb;
-    if (prec == MRINV_FP64) {
-        const size_t sb = spec_bytes(lgN, d2, true);
+    if (!prec_mixed(prec)) {
+        const size_t sb = spec_bytes(lgN + pad, d2, true);
         auto *SA = cv.take<cplx<double>>(sb);
         auto *SB = cv.take<cplx<double>>(sb);
         auto *ST = cv.take<cplx<double>>(sb);
-        return newton<double>(h, src, e0, d, n, out, SA, SB, ST, twr, twr_end);
+        return newton<double>(h, src, e0, d, n, out, SA, SB, ST, twr, twr_end, pad, 0);
     }
     // Mixed: float32 Newton into X, then one sweep with a float64 residual.
     float *X = cv.take<float>((size_t)n * d2 * sizeof(float));
@@ -700,7 +768,7 @@ static mrinv_status_t inverse_impl(mrinv_handle_t h, const double *src, int e0, 
         auto *SA = (cplx<float> *)spec;
         auto *SB = (cplx<float> *)(spec + sb);
         auto *ST = (cplx<float> *)(spec + 2 * sb);
-        CHECK(newton<float>(h, src, e0, d, n, X, SA, SB, ST, twr, twr_end));
+        CHECK(newton<float>(h, src, e0, d, n, X, SA, SB, ST, twr, twr_end, 0, bf3));
     }
     // The sweep plan in both precisions, each with its own outer tables
     // (carved after the Newton tables, which newton() left in the region).
@@ -717,6 +785,8 @@ static mrinv_status_t inverse_impl(mrinv_handle_t h, const double *src, int e0, 
     }
     const double invL = 1.0 / (double)((int64_t)1 << p2.lgL);
     const GemmDesc g = gdesc(h, d, d, d);
+    GemmDesc g32 = g;
+    g32.bf3 = bf3;
     // Slots (sweep_bytes): A's float64 spectrum, formed once and kept for
     // every sweep; X's float64 spectrum, whose last forward pass also writes
     // the float32 copy into slot 3 for the correction product; the float64
@@ -742,7 +812,7 @@ static mrinv_status_t inverse_impl(mrinv_handle_t h, const double *src, int e0, 
         // X <- X + X*R, the correction product in float32; the last sweep
         // writes the float64 result, earlier ones update X in place.
         HIP_TRY(fwd<float>(h, p2f, nl, R32, src_real(R, false, d2, d2, 0, n)));
-        HIP_TRY(freq_gemm<float>(p2f, g, X32, R32, T32, h->stream));
+        HIP_TRY(freq_gemm<float>(p2f, g32, X32, R32, T32, h->stream));
         DstDesc dx = last ? dst_real(out, true, d2, d2, 0, n, invL, OP_XPLUS, -1, h->status)
                           : dst_real(X, false, d2, d2, 0, n, invL, OP_XPLUS);
         dx.aux = X;
@@ -803,6 +873,7 @@ static mrinv_status_t inverse_graphed(mrinv_handle_t h, const double *src, int e
 extern "C" mrinv_status_t mrinv_psi_inverse(mrinv_handle_t h, const double *q, int d, int64_t n,
                                             mrinv_precision_t precision, double *psi, void *ws, size_t ws_bytes) {
     TimerScope _ts(h);
+    TuneScope _tn(h, d, n, (int)precision);
     if (h && h->tune.use_graph && !h->timing) return inverse_graphed(h, q, 1, d, n, precision, psi, ws, ws_bytes);
     return inverse_impl(h, q, 1, d, n, precision, psi, ws, ws_bytes);
 }
@@ -811,6 +882,7 @@ extern "C" mrinv_status_t mrinv_series_inverse(mrinv_handle_t h, const double *A
                                                mrinv_precision_t precision, double *Ainv, void *ws,
                                                size_t ws_bytes) {
     TimerScope _ts(h);
+    TuneScope _tn(h, d, n, (int)precision);
     if (h && h->tune.use_graph && !h->timing) return inverse_graphed(h, A, 0, d, n, precision, Ainv, ws, ws_bytes);
     return inverse_impl(h, A, 0, d, n, precision, Ainv, ws, ws_bytes);
 }
@@ -819,8 +891,7 @@ extern "C" mrinv_status_t mrinv_psi_inverse_noalloc(mrinv_handle_t h, const doub
                                                     mrinv_precision_t precision, double *psi) {
     if (!h || !q || !psi) return fail(MRINV_E_ARG, "NULL handle or pointer");
     CHECK(check_dn(d, n));
-    if (precision != MRINV_FP64 && precision != MRINV_MIXED_FP32)
-        return fail(MRINV_E_ARG, "unknown precision %d", (int)precision);
+    if (!prec_valid(precision)) return fail(MRINV_E_ARG, "unknown precision %d", (int)precision);
     const size_t need = ws_psi(d, n, precision);
     if (need > (size_t)MRINV_NOALLOC_SCRATCH_BYTES)
         return fail(MRINV_E_WORKSPACE,
@@ -828,7 +899,76 @@ extern "C" mrinv_status_t mrinv_psi_inverse_noalloc(mrinv_handle_t h, const doub
                     "(use mrinv_psi_inverse with a caller workspace)",
                     d, (long long)n, need, (size_t)MRINV_NOALLOC_SCRATCH_BYTES);
     if (!h->noalloc) return fail(MRINV_E_HIP, "library workspace not set up on this handle's device");
+    TuneScope _tn(h, d, n, (int)precision);
     return inverse_impl(h, q, 1, d, n, precision, psi, h->noalloc, MRINV_NOALLOC_SCRATCH_BYTES);
+}
+
+// ---------------------------------------------------------------------------
+// FFT-Gauss-Jordan inversion over C[[x]]/<x^n> (Appendix, Gauss-Jordan
+// paragraph).  On W = [A | I], pivot i: choose the row with the largest
+// |constant coefficient| in column i and swap it into row i; invert the pivot
+// series by Newton's iteration (the d = 1 inverse); normalise row i by that
+// inverse; subtract from every other row r its multiplier W_ri times the
+// normalised row.  Every series product is a transform product at length
+// 2^ceil(log2(2n-1)) truncated to n.  After d pivots the right block is
+// A^(-1) mod x^n.
+// ---------------------------------------------------------------------------
+static mrinv_status_t gj_series_impl(mrinv_handle_t h, const double *src, int e0, int d, int64_t n, double *out,
+                                     void *ws, size_t wsb) {
+    if (!h || !src || !out) return fail(MRINV_E_ARG, "NULL handle or pointer");
+    CHECK(check_dn(d, n));
+    CHECK(check_ws(ws, wsb, ws_gj(d, n)));
+    CHECK(check_seed(seed_len(h, n), 1));
+    const FftPlan p = hplan(h, lg_full(n));
+    const int lg = p.lgL;
+    const int64_t w = 2 * d, ww = (int64_t)d * w;
+    const double invL = 1.0 / (double)((int64_t)1 << lg);
+    Carve cv(ws);
+    double *W = cv.take<double>((size_t)n * ww * 8);
+    double *u = cv.take<double>((size_t)n * 8);
+    double *v = cv.take<double>((size_t)n * 8);
+    double *col = cv.take<double>((size_t)n * d * 8);
+    char *book = cv.take<char>(256);
+    int *piv = (int *)book;
+    double *aux = (double *)(book + 128);
+    auto *SV = cv.take<cplx<double>>(spec_bytes(lg, 1, true));
+    auto *SR = cv.take<cplx<double>>(spec_bytes(lg, w, true));
+    auto *SP = cv.take<cplx<double>>(spec_bytes(lg, w, true));
+    auto *SC = cv.take<cplx<double>>(spec_bytes(lg, d, true));
+    auto *SU = cv.take<cplx<double>>(spec_bytes(lg, ww, true));
+    void *wsi = cv.p + cv.used;
+    const size_t wsib = ws_psi(1, n, MRINV_FP64_PADDED);
+    HIP_TRY(gjs_init(src, e0, n, d, W, h->stream));
+    for (int i = 0; i < d; ++i) {
+        double *row = W + (int64_t)i * w;   // row i of every coefficient: stride ww between time rows
+        HIP_TRY(gjs_pivot_step(W, n, d, i, piv, aux, u, col, h->status, h->stream));
+        // the pivot series' inverse with zero-padded Newton products (no wrap-around)
+        CHECK(inverse_impl(h, u, 0, 1, n, MRINV_FP64_PADDED, v, wsi, wsib));
+        // row_i <- v * row_i  (1x1 times 1x2d series products, truncated to n)
+        HIP_TRY(fwd<double>(h, p, 1, SV, src_real(v, true, 1, 1, 0, n)));
+        HIP_TRY(fwd<double>(h, p, nl_of(w), SR, src_real(row, true, ww, (int)w, 0, n)));
+        HIP_TRY(freq_gemm<double>(p, gdesc(h, 1, 1, (int)w), SV, SR, SP, h->stream));
+        HIP_TRY(inv<double>(h, p, nl_of(w), SP, dst_real(row, true, ww, (int)w, 0, n, invL, OP_STORE)));
+        // W <- W - col * row_i  (d x 1 times 1 x 2d; col_i = 0 leaves row i alone)
+        HIP_TRY(fwd<double>(h, p, nl_of(d), SC, src_real(col, true, d, d, 0, n)));
+        HIP_TRY(fwd<double>(h, p, nl_of(w), SR, src_real(row, true, ww, (int)w, 0, n)));
+        HIP_TRY(freq_gemm<double>(p, gdesc(h, d, 1, (int)w), SC, SR, SU, h->stream));
+        HIP_TRY(inv<double>(h, p, nl_of(ww), SU, dst_real(W, true, ww, (int)ww, 0, n, -invL, OP_ADD)));
+    }
+    HIP_TRY(gjs_result(W, n, d, out, h->status, h->stream));
+    return MRINV_OK;
+}
+
+extern "C" mrinv_status_t mrinv_series_inverse_gj(mrinv_handle_t h, const double *A, int d, int64_t n, double *Ainv,
+                                                  void *ws, size_t ws_bytes) {
+    TimerScope _ts(h);
+    return gj_series_impl(h, A, 0, d, n, Ainv, ws, ws_bytes);
+}
+
+extern "C" mrinv_status_t mrinv_psi_inverse_gj(mrinv_handle_t h, const double *q, int d, int64_t n, double *psi,
+                                               void *ws, size_t ws_bytes) {
+    TimerScope _ts(h);
+    return gj_series_impl(h, q, 1, d, n, psi, ws, ws_bytes);
 }
 
 // ---------------------------------------------------------------------------
@@ -862,6 +1002,19 @@ extern "C" mrinv_status_t mrinv_set_tuning(mrinv_handle_t h, const mrinv_tuning_
     return MRINV_OK;
 }
 
+extern "C" mrinv_status_t mrinv_set_tuning_table(mrinv_handle_t h, const mrinv_tuning_entry_t *entries, int count) {
+    if (!h || count < 0 || (count > 0 && !entries)) return fail(MRINV_E_ARG, "NULL handle or entries");
+    for (int i = 0; i < count; ++i) {
+        const auto &e = entries[i];
+        if (e.d_lo < 1 || e.d_hi < e.d_lo || e.n_lo < 1 || e.n_hi < e.n_lo || e.precision < -1 ||
+            e.precision > (int)MRINV_FP64_PADDED)
+            return fail(MRINV_E_ARG, "table entry %d has bad ranges", i);
+        CHECK(check_tuning(e.tune));
+    }
+    h->table.assign(entries, entries + count);
+    return MRINV_OK;
+}
+
 // Milliseconds per inversion under the handle's current tuning.
 static mrinv_status_t time_inverse(mrinv_handle_t h, const double *q, int d, int64_t n, mrinv_precision_t prec,
                                    double *psi, void *ws, size_t wsb, int reps, float *ms) {
@@ -889,6 +1042,13 @@ extern "C" mrinv_status_t mrinv_autotune(mrinv_handle_t h, const double *q, int 
     if (!h || !q || !psi) return fail(MRINV_E_ARG, "NULL handle or pointer");
     CHECK(check_dn(d, n));
     CHECK(check_ws(ws, wsb, ws_psi(d, n, precision)));
+    // The table (if any) steps aside while candidates are timed.
+    struct TableAside {
+        mrinv_handle_t h;
+        std::vector<mrinv_tuning_entry_t> saved;
+        explicit TableAside(mrinv_handle_t hh) : h(hh) { saved.swap(hh->table); }
+        ~TableAside() { h->table.swap(saved); }
+    } aside(h);
     // Coordinate search from the current tuning: one knob at a time.
     mrinv_tuning_t best = h->tune;
     float best_ms = 0.f;
@@ -909,7 +1069,7 @@ extern "C" mrinv_status_t mrinv_autotune(mrinv_handle_t h, const double *q, int 
     };
     for (int v : {7, 8, 9}) { mrinv_tuning_t t = best; t.lgp_max = v; CHECK(trial(t)); }
     for (int v : {0, 8, 16, 32}) { mrinv_tuning_t t = best; t.lanes_fp64 = v; CHECK(trial(t)); }
-    if (precision != MRINV_FP64)
+    if (prec_mixed(precision))
         for (int v : {0, 8, 16, 32}) { mrinv_tuning_t t = best; t.lanes_fp32 = v; CHECK(trial(t)); }
     for (int v : {1, 16, 32, 64}) { mrinv_tuning_t t = best; t.seed_m0 = v; CHECK(trial(t)); }
     for (int v : {0, 1}) { mrinv_tuning_t t = best; t.pair_forward = v; CHECK(trial(t)); }
@@ -1135,6 +1295,96 @@ extern "C" mrinv_status_t mrinv_availability(mrinv_handle_t h, const double *P, 
     return MRINV_OK;
 }
 
+extern "C" mrinv_status_t mrinv_renewal_visits(mrinv_handle_t h, const double *psi, int d, int64_t n,
+                                               const int *in_B, const double *alpha, double *N) {
+    TimerScope _ts(h);
+    if (!h || !psi || !in_B || !alpha || !N) return fail(MRINV_E_ARG, "NULL handle or pointer");
+    CHECK(check_dn(d, n));
+    double ind[MRINV_MAX_D];
+    for (int i = 0; i < d; ++i) ind[i] = in_B[i] ? 1.0 : 0.0;
+    SmallVecs sv;
+    CHECK(put_small(h, nullptr, 0, nullptr, 0, alpha, d, ind, d, sv));
+    HIP_TRY(contract(psi, n, d, d, sv.alpha, sv.ones, 1, 0.0, 1.0, N, h->scratch + SCRATCH_SCAN_OFF, h->stream));
+    return MRINV_OK;
+}
+
+extern "C" mrinv_status_t mrinv_mre_solve(mrinv_handle_t h, const double *Qs, int d, int64_t n, const double *L,
+                                          int r, mrinv_precision_t precision, double *K, void *ws, size_t wsb) {
+    TimerScope _ts(h);
+    if (!h || !Qs || !L || !K) return fail(MRINV_E_ARG, "NULL handle or pointer");
+    CHECK(check_dn(d, n));
+    if (r < 1 || r > MRINV_MAX_D) return fail(r < 1 ? MRINV_E_ARG : MRINV_E_UNSUPPORTED, "bad r=%d", r);
+    if (!prec_valid(precision)) return fail(MRINV_E_ARG, "unknown precision %d", (int)precision);
+    CHECK(check_ws(ws, wsb, ws_mre(d, n, r, precision)));
+    CHECK(check_seed(seed_len(h, n), d));
+    Carve cv(ws);
+    double *Qbar = cv.take<double>((size_t)n * d * d * 8);
+    double *X = cv.take<double>((size_t)n * d * d * 8);
+    double *R = cv.take<double>((size_t)n * d * r * 8);
+    void *rest = cv.p + cv.used;
+    const size_t rest_b = wsb - cv.used;
+    HIP_TRY(mre_prepare(Qs, L, n, d, r, Qbar, R, h->stream));
+    // (e0 - Qbar_h)^-1: Qbar_h(0) = Delta Q_h(1)/2, so A(0) = I - Qbar_h(0) takes the Gauss-Jordan path.
+    {
+        TuneScope _tn(h, d, n, (int)precision);
+        CHECK(inverse_impl(h, Qbar, 1, d, n, precision, X, rest, rest_b));
+    }
+    return mrinv_markov_renewal_apply(h, X, d, n, R, r, K, rest, rest_b);
+}
+
+extern "C" size_t mrinv_mc_workspace_size(int64_t n) {
+    if (n < 1 || n > MRINV_MAX_N) return 0;
+    return 2 * align256((size_t)(n + 1) * sizeof(int));
+}
+
+extern "C" mrinv_status_t mrinv_semi_markov_mc(mrinv_handle_t h, const mrinv_mc_model_t *model, double step,
+                                               int64_t n, int64_t trajectories, uint64_t seed, double *A, double *R,
+                                               double *tau_D, int *jumps, void *ws, size_t wsb) {
+    TimerScope _ts(h);
+    if (!h || !model || !A || !R) return fail(MRINV_E_ARG, "NULL handle or pointer");
+    if (!model->P || !model->p1 || !model->p2 || !model->up) return fail(MRINV_E_ARG, "NULL model array");
+    const int d = model->d;
+    if (d < 1 || d > MRINV_MC_MAX_D) return fail(MRINV_E_UNSUPPORTED, "Monte Carlo needs 1 <= d <= %d", MRINV_MC_MAX_D);
+    if (n < 1 || n > MRINV_MAX_N) return fail(MRINV_E_ARG, "bad n=%lld", (long long)n);
+    if (trajectories < 1 || trajectories > ((int64_t)1 << 31) - 1)
+        return fail(MRINV_E_ARG, "trajectories must be in 1..2^31-1 (counts are int32)");
+    if (!(step > 0.0) || !isfinite(step)) return fail(MRINV_E_ARG, "step must be positive");
+    if (model->family < MRINV_SOJOURN_LOGNORMAL || model->family > MRINV_SOJOURN_EXPONENTIAL)
+        return fail(MRINV_E_ARG, "unknown sojourn family %d", model->family);
+    if (model->initial < 0 || model->initial >= d) return fail(MRINV_E_ARG, "initial state out of range");
+    McModel m{};
+    m.d = d;
+    m.family = model->family;
+    m.initial = model->initial;
+    for (int i = 0; i < d; ++i) {
+        double acc = 0.0;
+        m.up[i] = model->up[i] ? 1 : 0;
+        m.last[i] = -1;
+        for (int j = 0; j < d; ++j) {
+            const double pij = model->P[i * d + j];
+            if (!(pij >= 0.0) || !isfinite(pij)) return fail(MRINV_E_ARG, "P[%d][%d] is not a probability", i, j);
+            acc += pij;
+            m.cum[i * MC_MAX_D + j] = acc;
+            m.p1[i * MC_MAX_D + j] = model->p1[i * d + j];
+            m.p2[i * MC_MAX_D + j] = model->p2[i * d + j];
+            if (pij > 0.0) {
+                m.last[i] = j;
+                const double a = model->p1[i * d + j], b = model->p2[i * d + j];
+                const bool ok = model->family == MRINV_SOJOURN_LOGNORMAL ? (isfinite(a) && b > 0.0 && isfinite(b))
+                                : model->family == MRINV_SOJOURN_WEIBULL ? (a > 0.0 && b > 0.0 && isfinite(a) && isfinite(b))
+                                                                         : (a > 0.0 && isfinite(a));
+                if (!ok) return fail(MRINV_E_ARG, "bad sojourn parameters for %d -> %d", i, j);
+            }
+        }
+        if (fabs(acc - 1.0) > 1e-12) return fail(MRINV_E_ARG, "row %d of P sums to %.17g, not 1", i, acc);
+    }
+    CHECK(check_ws(ws, wsb, mrinv_mc_workspace_size(n)));
+    int *diffA = (int *)ws;
+    int *diffR = (int *)((char *)ws + align256((size_t)(n + 1) * sizeof(int)));
+    HIP_TRY(semi_markov_mc(m, step, n, trajectories, seed, A, R, tau_D, jumps, diffA, diffR, h->stream));
+    return MRINV_OK;
+}
+
 // ---------------------------------------------------------------------------
 // Adjoints
 // ---------------------------------------------------------------------------
@@ -1323,7 +1573,8 @@ static void plan_fft(BatchPlan &bp, mrinv_handle_t h, int mode, const FftPlan &p
 }
 
 template <typename T>
-static void plan_gemm(BatchPlan &bp, mrinv_handle_t h, const FftPlan &p, const std::vector<GemmProblem<T>> &probs) {
+static void plan_gemm(BatchPlan &bp, mrinv_handle_t h, const FftPlan &p, const std::vector<GemmProblem<T>> &probs,
+                      int bf3 = 0) {
     for (int cls = 1; cls <= 16; ++cls) {
         std::vector<GemmProblem<T>> g;
         for (auto &q : probs)
@@ -1340,7 +1591,8 @@ static void plan_gemm(BatchPlan &bp, mrinv_handle_t h, const FftPlan &p, const s
         const int cnt = (int)g.size();
         const int mf = tune_of(h).mfma;
         bp.launches.push_back([=](char *base, hipStream_t st) {
-            return freq_gemm_batched<T>(p, cls, mf, (const GemmProblem<T> *)(base + off), cnt, total, bytes, flops, st);
+            return freq_gemm_batched<T>(p, cls, mf, bf3, (const GemmProblem<T> *)(base + off), cnt, total, bytes, flops,
+                                        st);
         });
     }
 }
@@ -1417,6 +1669,8 @@ struct BatchProblem {
     int d;
     int64_t n;
     float *X, *R;   // mixed form
+    int64_t seed;   // recursion seed length and direct-step limit of this problem's tuning
+    int64_t dlim;
 };
 
 // Sub-batches of `idx` whose summed need stays under the cap (at least one each).
@@ -1438,7 +1692,8 @@ static std::vector<std::vector<int>> split_by_cap(const std::vector<int> &idx, c
 }
 
 template <typename T>
-static void plan_newton(BatchPlan &bp, mrinv_handle_t h, std::vector<BatchProblem> &P, char *spec, size_t &spec_max) {
+static void plan_newton(BatchPlan &bp, mrinv_handle_t h, std::vector<BatchProblem> &P, char *spec, size_t &spec_max,
+                        int pad, int bf3) {
     const bool dbl = sizeof(T) == 8;
     const int64_t nmax = [&] { int64_t m = 0; for (auto &b : P) m = std::max(m, b.n); return m; }();
     // Seeds: the first m0 coefficients of each problem by the recursion.
@@ -1446,7 +1701,7 @@ static void plan_newton(BatchPlan &bp, mrinv_handle_t h, std::vector<BatchProble
         std::vector<SeedProblem> sp;
         int cols = 0, dmax = 0, m0max = 0;
         for (auto &b : P) {
-            const int64_t m0 = seed_len(h, b.n);
+            const int64_t m0 = b.seed;
             if (m0 <= 1) continue;
             SeedProblem x{};
             x.A = b.q;
@@ -1469,7 +1724,7 @@ static void plan_newton(BatchPlan &bp, mrinv_handle_t h, std::vector<BatchProble
         }
     }
     for (int64_t m = 1; m < nmax; m *= 2) {
-        const FftPlan p = hplan(h, ceil_log2(2 * m));
+        const FftPlan p = hplan(h, ceil_log2(2 * m) + pad);
         const int64_t L = (int64_t)1 << p.lgL;
         // Direct steps of this m (as in the single-problem call), E scratch at
         // the start of the spectrum region; the transform steps below reuse it
@@ -1480,7 +1735,7 @@ static void plan_newton(BatchPlan &bp, mrinv_handle_t h, std::vector<BatchProble
             for (int i = 0; i < (int)P.size(); ++i) {
                 const BatchProblem &b = P[i];
                 const int64_t m2 = std::min(2 * m, b.n);
-                if (!(b.n > m && m >= seed_len(h, b.n) && m2 <= direct_limit(h, b.d))) continue;
+                if (!(b.n > m && m >= b.seed && m2 <= b.dlim)) continue;
                 const int64_t d2 = (int64_t)b.d * b.d;
                 void *out = dbl ? (void *)b.psi : (void *)b.X;
                 void *E = spec + used;
@@ -1514,7 +1769,7 @@ static void plan_newton(BatchPlan &bp, mrinv_handle_t h, std::vector<BatchProble
         std::vector<int> act;
         std::vector<size_t> need;
         for (int i = 0; i < (int)P.size(); ++i)
-            if (P[i].n > m && m >= seed_len(h, P[i].n) && std::min(2 * m, P[i].n) > direct_limit(h, P[i].d)) {
+            if (P[i].n > m && m >= P[i].seed && std::min(2 * m, P[i].n) > P[i].dlim) {
                 act.push_back(i);
                 need.push_back(3 * spec_bytes(p.lgL, (int64_t)P[i].d * P[i].d, dbl));
             }
@@ -1553,15 +1808,16 @@ static void plan_newton(BatchPlan &bp, mrinv_handle_t h, std::vector<BatchProble
             spec_max = std::max(spec_max, used);
             plan_fwd<T>(bp, h, p, SA, nl, sa);
             plan_fwd<T>(bp, h, p, SB, nl, sb);
-            plan_gemm<T>(bp, h, p, g1);
+            plan_gemm<T>(bp, h, p, g1, bf3);
             plan_remask<T>(bp, h, p, ST, nl, lo, hi, true);
-            plan_gemm<T>(bp, h, p, g2);
+            plan_gemm<T>(bp, h, p, g2, bf3);
             plan_inv<T>(bp, h, p, SA, nl, du);
         }
     }
 }
 
-static void plan_sweeps(BatchPlan &bp, mrinv_handle_t h, std::vector<BatchProblem> &P, char *spec, size_t &spec_max) {
+static void plan_sweeps(BatchPlan &bp, mrinv_handle_t h, std::vector<BatchProblem> &P, char *spec, size_t &spec_max,
+                        int bf3) {
     // Group by the residual length 2^ceil(log2(2n-1)).
     std::vector<int> lgs;
     for (auto &b : P) lgs.push_back(lg_full(b.n));
@@ -1627,7 +1883,7 @@ static void plan_sweeps(BatchPlan &bp, mrinv_handle_t h, std::vector<BatchProble
                 plan_gemm<double>(bp, h, p, g64);
                 plan_inv<double>(bp, h, p, T64, nl, dr);
                 plan_fwd<float>(bp, h, p, R32, nl, sr);
-                plan_gemm<float>(bp, h, p, g32);
+                plan_gemm<float>(bp, h, p, g32, bf3);
                 plan_inv<float>(bp, h, p, T32, nl, dx);
             }
         }
@@ -1639,24 +1895,27 @@ static mrinv_status_t plan_batched(mrinv_handle_t h, int count, const double *co
                                    const int64_t *n, mrinv_precision_t prec, double *const *psi_ptrs, char *ws,
                                    BatchPlan &bp) {
     if (count < 1 || !d || !n) return fail(MRINV_E_ARG, "bad batch");
-    if (prec != MRINV_FP64 && prec != MRINV_MIXED_FP32) return fail(MRINV_E_ARG, "unknown precision");
+    if (!prec_valid(prec)) return fail(MRINV_E_ARG, "unknown precision");
     std::vector<BatchProblem> P(count);
     int64_t m0max = 1;
     int dmax_all = 1;
     for (int b = 0; b < count; ++b) {
         CHECK(check_dn(d[b], n[b]));
-        m0max = std::max(m0max, seed_len(h, n[b]));
+        m0max = std::max(m0max, seed_len(tune_for(h, d[b], n[b], (int)prec), n[b]));
         dmax_all = std::max(dmax_all, d[b]);
     }
     CHECK(check_seed(m0max, dmax_all));
     for (int b = 0; b < count; ++b) {
+        const mrinv_tuning_t &tb = tune_for(h, d[b], n[b], (int)prec);
+        P[b].seed = seed_len(tb, n[b]);
+        P[b].dlim = direct_limit(tb, d[b]);
         P[b].q = q_ptrs ? q_ptrs[b] : nullptr;
         P[b].psi = psi_ptrs ? psi_ptrs[b] : nullptr;
         P[b].d = d[b];
         P[b].n = n[b];
     }
     // Pass 1 sizes the table; pass 2 fills it with final addresses.
-    const bool mixed = prec == MRINV_MIXED_FP32;
+    const bool mixed = prec_mixed(prec);
     size_t xr = 0;
     if (mixed)
         for (auto &b : P) xr += align256((size_t)b.n * b.d * b.d * sizeof(float));
@@ -1695,10 +1954,10 @@ static mrinv_status_t plan_batched(mrinv_handle_t h, int count, const double *co
             });
         }
         if (mixed) {
-            plan_newton<float>(cur, h, P, spec, spec_max);
-            plan_sweeps(cur, h, P, spec, spec_max);
+            plan_newton<float>(cur, h, P, spec, spec_max, 0, prec_bf3(prec));
+            plan_sweeps(cur, h, P, spec, spec_max, prec_bf3(prec));
         } else {
-            plan_newton<double>(cur, h, P, spec, spec_max);
+            plan_newton<double>(cur, h, P, spec, spec_max, prec_pad(prec), 0);
         }
         cur.table_bytes = align256(cur.table.size());
         if (round == 0) {

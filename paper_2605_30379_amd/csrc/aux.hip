@@ -492,6 +492,181 @@ hipError_t put_small_vectors(const SmallVecArgs &v, int *ci, int *di, double *al
 }
 
 // ---------------------------------------------------------------------------
+// Mean-value discretisation of a continuous-time Markov renewal equation
+// (Section 4.2): from the kernel on the grid, Qs[m] = Q(m h) for m = 0..n,
+//   Qbar_h(m) = (Delta Q_h(m) + Delta Q_h(m+1)) / 2,  Delta Q_h(0) = 0,
+// and the right-hand side of eq. (mre-solution),
+//   R(m) = L_h(m) - (1/2) Delta Q_h(m+1) L_h(0)
+// (the product Delta+Q_h * (L_h(0) e0) has this single term per m).
+// ---------------------------------------------------------------------------
+__global__ void mre_qbar_kernel(const double *Qs, int64_t n, int d, double *Qbar) {
+    const int64_t dd = (int64_t)d * d;
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= n * dd) return;
+    const int64_t m = gid / dd;
+    const double q0 = Qs[gid], q1 = Qs[gid + dd];
+    const double dm = m > 0 ? q0 - Qs[gid - dd] : 0.0;
+    Qbar[gid] = 0.5 * (dm + (q1 - q0));
+}
+
+__global__ void mre_rhs_kernel(const double *Qs, const double *L, int64_t n, int d, int r, double *R) {
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t dr = (int64_t)d * r;
+    if (gid >= n * dr) return;
+    const int64_t m = gid / dr;
+    const int e = (int)(gid - m * dr);
+    const int i = e / r, c = e - i * r;
+    const int64_t dd = (int64_t)d * d;
+    const double *q1 = Qs + (m + 1) * dd + (int64_t)i * d, *q0 = Qs + m * dd + (int64_t)i * d;
+    double s = 0.0;
+    for (int t = 0; t < d; ++t) s += (q1[t] - q0[t]) * L[(int64_t)t * r + c];
+    R[gid] = L[gid] - 0.5 * s;
+}
+
+hipError_t mre_prepare(const double *Qs, const double *L, int64_t n, int d, int r, double *Qbar, double *R,
+                       hipStream_t st) {
+    const int64_t t1 = n * d * d, t2 = n * d * r;
+    launch_kernel("mre_qbar_kernel", (double)t1 * 8.0 * 3.0, 0.0, mre_qbar_kernel,
+                  dim3((unsigned)((t1 + 255) / 256)), dim3(256), 0, st, Qs, n, d, Qbar);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    launch_kernel("mre_rhs_kernel", ((double)t1 * 2.0 + (double)t2 * 2.0) * 8.0, (double)t2 * 3.0 * d,
+                  mre_rhs_kernel, dim3((unsigned)((t2 + 255) / 256)), dim3(256), 0, st, Qs, L, n, d, r, R);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Gauss-Jordan elimination over the truncated series ring C[[x]]/<x^n>
+// (Appendix, Gauss-Jordan paragraph).  The augmented sequence W = [A | I] is
+// held time-major, W[k][r][c] with 2d columns.  These kernels do the
+// bookkeeping of one pivot step; the series products run through the
+// transform and product kernels.
+// ---------------------------------------------------------------------------
+__global__ void gjs_init_kernel(const double *A, int e0_minus, int64_t n, int d, double *W) {
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int w = 2 * d;
+    if (gid >= n * d * w) return;
+    const int64_t k = gid / ((int64_t)d * w);
+    const int e = (int)(gid - k * d * w);
+    const int r = e / w, c = e - r * w;
+    double v;
+    if (c < d) {
+        v = A[(k * d + r) * d + c];
+        if (e0_minus) v = (k == 0 && r == c ? 1.0 : 0.0) - v;
+    } else {
+        v = (k == 0 && c - d == r) ? 1.0 : 0.0;
+    }
+    W[gid] = v;
+}
+
+// Pivot of column i: the row r >= i whose series has the largest |constant
+// coefficient| (the constant coefficients follow Gauss-Jordan on A(0)
+// exactly).  A pivot with |W(0)_ri| <= d 2^-53 max|A(0)| marks A(0) singular.
+// aux[0] holds max|A(0)|, set at i = 0.  One wavefront.
+__global__ void gjs_pivot_kernel(const double *W, int d, int i, int *piv, double *aux, unsigned int *status) {
+    const int lane = threadIdx.x;
+    const int w = 2 * d;
+    double amax;
+    if (i == 0) {
+        double m = 0.0;
+        for (int e = lane; e < d * d; e += 64) m = fmax(m, fabs(W[(e / d) * w + e % d]));
+        for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
+        amax = m;                       // every lane holds the maximum after the butterfly
+        if (lane == 0) aux[0] = m;
+    } else {
+        amax = aux[0];
+    }
+    double best = -1.0;
+    int row = i;
+    if (lane >= i && lane < d) {
+        best = fabs(W[lane * w + i]);
+        row = lane;
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        const double ob = __shfl_xor(best, o, 64);
+        const int orow = __shfl_xor(row, o, 64);
+        if (ob > best || (ob == best && orow < row)) {
+            best = ob;
+            row = orow;
+        }
+    }
+    if (lane == 0) {
+        piv[i] = row;
+        if (!(best > d * 1.1102230246251565e-16 * amax)) atomicOr(status, STATUS_SINGULAR);
+    }
+}
+
+// Swap rows i and piv[i] of W over the whole horizon.
+__global__ void gjs_swap_kernel(double *W, int64_t n, int d, int i, const int *piv) {
+    const int p = piv[i];
+    if (p == i) return;
+    const int w = 2 * d;
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= n * w) return;
+    const int64_t k = gid / w;
+    const int c = (int)(gid - k * w);
+    double *a = W + (k * d + i) * w + c, *b = W + (k * d + p) * w + c;
+    const double t = *a;
+    *a = *b;
+    *b = t;
+}
+
+// u(k) = W(k)_ii (the pivot series) and col(k)_r = W(k)_ri for r != i,
+// col(k)_i = 0 (the multipliers of the elimination).
+__global__ void gjs_gather_kernel(const double *W, int64_t n, int d, int i, double *u, double *col) {
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= n * d) return;
+    const int64_t k = gid / d;
+    const int r = (int)(gid - k * d);
+    const double v = W[(k * d + r) * 2 * d + i];
+    col[gid] = r == i ? 0.0 : v;
+    if (r == i) u[k] = v;
+}
+
+// Ainv(k) = right block of W(k).
+__global__ void gjs_result_kernel(const double *W, int64_t n, int d, double *out, unsigned int *status) {
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= n * d * d) return;
+    const int64_t k = gid / ((int64_t)d * d);
+    const int e = (int)(gid - k * d * d);
+    const int r = e / d, c = e - r * d;
+    const double v = W[(k * d + r) * 2 * d + d + c];
+    out[gid] = v;
+    if (status && !isfinite(v)) atomicOr(status, STATUS_NONFINITE);
+}
+
+hipError_t gjs_init(const double *A, int e0_minus, int64_t n, int d, double *W, hipStream_t st) {
+    const int64_t t = n * d * 2 * d;
+    launch_kernel("gjs_init_kernel", (double)t * 8.0 * 1.5, 0.0, gjs_init_kernel, dim3((unsigned)((t + 255) / 256)),
+                  dim3(256), 0, st, A, e0_minus, n, d, W);
+    return hipGetLastError();
+}
+
+hipError_t gjs_pivot_step(double *W, int64_t n, int d, int i, int *piv, double *aux, double *u, double *col,
+                          unsigned int *status, hipStream_t st) {
+    launch_kernel("gjs_pivot_kernel", 0.0, 0.0, gjs_pivot_kernel, dim3(1), dim3(64), 0, st, (const double *)W, d, i,
+                  piv, aux, status);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int64_t t1 = n * 2 * d;
+    launch_kernel("gjs_swap_kernel", (double)t1 * 32.0, 0.0, gjs_swap_kernel, dim3((unsigned)((t1 + 255) / 256)),
+                  dim3(256), 0, st, W, n, d, i, (const int *)piv);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int64_t t2 = n * d;
+    launch_kernel("gjs_gather_kernel", (double)t2 * 16.0 + (double)n * 8.0, 0.0, gjs_gather_kernel,
+                  dim3((unsigned)((t2 + 255) / 256)), dim3(256), 0, st, (const double *)W, n, d, i, u, col);
+    return hipGetLastError();
+}
+
+hipError_t gjs_result(const double *W, int64_t n, int d, double *out, unsigned int *status, hipStream_t st) {
+    const int64_t t = n * d * d;
+    launch_kernel("gjs_result_kernel", (double)t * 16.0, 0.0, gjs_result_kernel, dim3((unsigned)((t + 255) / 256)),
+                  dim3(256), 0, st, W, n, d, out, status);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // Fills and residual reductions.
 // ---------------------------------------------------------------------------
 __global__ void fill_f64_kernel(double *p, int64_t count, double v) {

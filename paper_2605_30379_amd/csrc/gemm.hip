@@ -695,6 +695,293 @@ static hipError_t launch_gemm_mfma_t(const FftPlan &plan, int d, const cplx<T> *
 // or above the ridge); mfma == 2 keeps the four-product form everywhere.
 template <int DP> static bool use_g3(int mfma) { return mfma == 1 && DP >= 48; }
 
+// ---------------------------------------------------------------------------
+// Split-BF16 form of the float square products (precision MRINV_MIXED_BF16X3):
+// every float operand entry x is held as hi + lo with hi = bf16(x) and
+// lo = bf16(x - hi) (about 16 significant bits together), and a real product
+// is hi*hi + hi*lo + lo*hi on the 16x16x32 BF16 matrix cores with FP32
+// accumulation (the lo*lo term, about 2^-16 relative, is dropped).  The
+// complex product takes four real products, so one 16x16 output tile and one
+// 32-wide contraction chunk cost 12 BF16 MFMAs.
+//
+// Operand layout of the 16x16x32 instruction (lane l): A[i][k] for i = l % 16,
+// k = 8 (l / 16) + 0..7, eight values of a row; B[k][j] for j = l % 16 and the
+// same k; the FP32 accumulator holds C[4 (l / 16) + r][l % 16] like the
+// 16x16x4 FP32 form, so the packing epilogue is shared.
+// LDS: per frequency and operand, four planes (re hi, im hi, re lo, im lo) of
+// DP rows x 32 contraction entries (B stored transposed, [j][k]), rows padded
+// to 40 entries (80 bytes) so the 16-byte row reads of a wave spread over the
+// banks.
+// ---------------------------------------------------------------------------
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+
+template <int DP> struct BfCfg {
+    static constexpr int WPF = DP / 16;
+    static constexpr int NF = WPF >= 3 ? 1 : 4 / WPF;
+    static constexpr int THREADS = 64 * WPF * NF;
+    static constexpr int KC = 32;
+    static constexpr int LDK = 40;
+    static constexpr int PLANE = DP * LDK;            // bf16 entries of one plane
+};
+
+template <int DP>
+static size_t bf3_lds_bytes(int dmax_odd) {
+    using Cfg = BfCfg<DP>;
+    const size_t ab = (size_t)Cfg::NF * 2 * 4 * Cfg::PLANE * sizeof(__bf16);
+    const size_t cs = (size_t)Cfg::NF * ((size_t)dmax_odd * dmax_odd + 1) * sizeof(float2);
+    return cs > ab ? cs : ab;
+}
+
+__device__ __forceinline__ void bf3_put(__bf16 *pl, int plane, int off, float2 v) {
+    const __bf16 rh = (__bf16)v.x, ih = (__bf16)v.y;
+    pl[off] = rh;
+    pl[plane + off] = ih;
+    pl[2 * plane + off] = (__bf16)(v.x - (float)rh);
+    pl[3 * plane + off] = (__bf16)(v.y - (float)ih);
+}
+
+template <int DP, bool ODD>
+__device__ __forceinline__ void freq_gemm_bf3_body(const float2 *__restrict__ ZA, const float2 *__restrict__ ZB,
+                                                   float2 *__restrict__ ZC, const FftPlan &plan, int d, int64_t blk) {
+    using Cfg = BfCfg<DP>;
+    using V = mf_f4;
+    constexpr int WPF = Cfg::WPF, NF = Cfg::NF, KC = Cfg::KC, NT = Cfg::THREADS, LDK = Cfg::LDK;
+    constexpr int PL = Cfg::PLANE;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    __bf16 *S = reinterpret_cast<__bf16 *>(smem_raw);     // [NF][operand A, B][4 planes][DP][LDK]
+    __shared__ int64_t rows1[NF], rows2[NF];
+    const int64_t L = (int64_t)1 << plan.lgL;
+    const int64_t F = L / 2 + 1;
+    const int64_t k0 = blk * NF;
+    const int tid = threadIdx.x;
+    const int nl = (d * d + 1) >> 1;
+    if (tid < NF) {
+        const int64_t k = k0 + tid;
+        rows1[tid] = k < F ? freq_row(plan, k) : 0;
+        rows2[tid] = k < F ? freq_row(plan, (L - k) & (L - 1)) : 0;
+    }
+    __syncthreads();
+    const int l = tid & 63, w = tid >> 6;
+    const int f = w / WPF, I = w - f * WPF;
+    V accR[WPF], accI[WPF];
+#pragma unroll
+    for (int J = 0; J < WPF; ++J)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) accR[J][r] = accI[J][r] = 0.f;
+    auto base = [&](int ff, int op) { return S + (size_t)(ff * 2 + op) * 4 * PL; };
+
+    for (int kc = 0; kc < d; kc += KC) {
+        // Stage the chunk: A entries (i, t) at [i][t], B entries (t, j) at [j][t],
+        // separated from the packed lanes by the Hermitian symmetry and split.
+        if constexpr (!ODD) {
+            // Even d: a packed lane holds an aligned entry pair of one row.
+            for (int idx = tid; idx < NF * DP * (KC / 2); idx += NT) {
+                const int ff = idx / (DP * (KC / 2)), p = idx - ff * (DP * (KC / 2));
+                const bool fok = k0 + ff < F;
+                {
+                    const int i = p / (KC / 2), t = 2 * (p - i * (KC / 2));
+                    const bool ok = fok && i < d && kc + t < d;
+                    const int c = ok ? (i * d + kc + t) >> 1 : 0;
+                    const float2 z1 = ZA[rows1[ff] * nl + c], z2 = ZA[rows2[ff] * nl + c];
+                    const float2 ev = ok ? make_float2((z1.x + z2.x) * 0.5f, (z1.y - z2.y) * 0.5f) : make_float2(0.f, 0.f);
+                    const float2 od = ok ? make_float2((z1.y + z2.y) * 0.5f, (z2.x - z1.x) * 0.5f) : make_float2(0.f, 0.f);
+                    __bf16 *a = base(ff, 0);
+                    bf3_put(a, PL, i * LDK + t, ev);
+                    bf3_put(a, PL, i * LDK + t + 1, od);
+                }
+                {
+                    const int t = p / (DP / 2), j = 2 * (p - t * (DP / 2));
+                    const bool ok = fok && j < d && kc + t < d;
+                    const int c = ok ? ((kc + t) * d + j) >> 1 : 0;
+                    const float2 z1 = ZB[rows1[ff] * nl + c], z2 = ZB[rows2[ff] * nl + c];
+                    const float2 ev = ok ? make_float2((z1.x + z2.x) * 0.5f, (z1.y - z2.y) * 0.5f) : make_float2(0.f, 0.f);
+                    const float2 od = ok ? make_float2((z1.y + z2.y) * 0.5f, (z2.x - z1.x) * 0.5f) : make_float2(0.f, 0.f);
+                    __bf16 *b = base(ff, 1);
+                    bf3_put(b, PL, j * LDK + t, ev);
+                    bf3_put(b, PL, (j + 1) * LDK + t, od);
+                }
+            }
+        } else {
+            for (int idx = tid; idx < NF * DP * KC; idx += NT) {
+                const int ff = idx / (DP * KC), p = idx - ff * (DP * KC);
+                const bool fok = k0 + ff < F;
+                {
+                    const int i = p / KC, t = p - i * KC;
+                    const bool ok = fok && i < d && kc + t < d;
+                    const float2 v = ok ? unpack<float>(ZA, nl, rows1[ff], rows2[ff], i * d + kc + t) : make_float2(0.f, 0.f);
+                    bf3_put(base(ff, 0), PL, i * LDK + t, v);
+                }
+                {
+                    const int j = p / KC, t = p - j * KC;
+                    const bool ok = fok && j < d && kc + t < d;
+                    const float2 v = ok ? unpack<float>(ZB, nl, rows1[ff], rows2[ff], (kc + t) * d + j) : make_float2(0.f, 0.f);
+                    bf3_put(base(ff, 1), PL, j * LDK + t, v);
+                }
+            }
+        }
+        __syncthreads();
+        {
+            const __bf16 *Ab = base(f, 0) + (I * 16 + (l & 15)) * LDK + 8 * (l >> 4);
+            const bf16x8_t arh = *(const bf16x8_t *)(Ab);
+            const bf16x8_t aih = *(const bf16x8_t *)(Ab + PL);
+            const bf16x8_t arl = *(const bf16x8_t *)(Ab + 2 * PL);
+            const bf16x8_t ail = *(const bf16x8_t *)(Ab + 3 * PL);
+            const bf16x8_t naih = -aih, nail = -ail;
+#pragma unroll
+            for (int J = 0; J < WPF; ++J) {
+                const __bf16 *Bb = base(f, 1) + (J * 16 + (l & 15)) * LDK + 8 * (l >> 4);
+                const bf16x8_t brh = *(const bf16x8_t *)(Bb);
+                const bf16x8_t bih = *(const bf16x8_t *)(Bb + PL);
+                const bf16x8_t brl = *(const bf16x8_t *)(Bb + 2 * PL);
+                const bf16x8_t bil = *(const bf16x8_t *)(Bb + 3 * PL);
+                // Re C += Re A Re B - Im A Im B,  Im C += Re A Im B + Im A Re B
+                accR[J] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(arh, brh, accR[J], 0, 0, 0);
+                accR[J] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(arh, brl, accR[J], 0, 0, 0);
+                accR[J] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(arl, brh, accR[J], 0, 0, 0);
+                accR[J] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(naih, bih, accR[J], 0, 0, 0);
+                accR[J] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(naih, bil, accR[J], 0, 0, 0);
+                accR[J] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(nail, bih, accR[J], 0, 0, 0);
+                accI[J] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(arh, bih, accI[J], 0, 0, 0);
+                accI[J] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(arh, bil, accI[J], 0, 0, 0);
+                accI[J] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(arl, bih, accI[J], 0, 0, 0);
+                accI[J] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aih, brh, accI[J], 0, 0, 0);
+                accI[J] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aih, brl, accI[J], 0, 0, 0);
+                accI[J] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ail, brh, accI[J], 0, 0, 0);
+            }
+        }
+        __syncthreads();
+    }
+
+    const bool fok = k0 + f < F;
+    if constexpr (!ODD) {
+        const int64_t r1 = rows1[f], r2 = rows2[f];
+        const bool odd_lane = (l & 1) != 0;
+#pragma unroll
+        for (int J = 0; J < WPF; ++J) {
+            const int j = J * 16 + (l & 15);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int i = I * 16 + 4 * (l >> 4) + r;
+                const float vr = accR[J][r], vi = accI[J][r];
+                const float pr = lane_xor1(vr), pi = lane_xor1(vi);
+                if (fok && i < d && j < d) {
+                    const int c = (i * d + (j & ~1)) >> 1;
+                    if (!odd_lane) ZC[r1 * nl + c] = make_float2(vr - pi, vi + pr);
+                    else if (r2 != r1) ZC[r2 * nl + c] = make_float2(pr + vi, vr - pi);
+                }
+            }
+        }
+    } else {
+        float2 *Cs = reinterpret_cast<float2 *>(smem_raw);   // [NF][d*d + 1]
+        const int ld = d * d + 1;
+#pragma unroll
+        for (int J = 0; J < WPF; ++J) {
+            const int j = J * 16 + (l & 15);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int i = I * 16 + 4 * (l >> 4) + r;
+                if (i < d && j < d) Cs[f * ld + i * d + j] = make_float2(accR[J][r], accI[J][r]);
+            }
+        }
+        __syncthreads();
+        for (int idx = tid; idx < NF * nl; idx += NT) {
+            const int ff = idx / nl, c = idx - ff * nl;
+            if (k0 + ff >= F) continue;
+            const int e = 2 * c;
+            const float2 ce = Cs[ff * ld + e];
+            const float2 co = (e + 1 < d * d) ? Cs[ff * ld + e + 1] : make_float2(0.f, 0.f);
+            pack_store<float>(ZC, nl, rows1[ff], rows2[ff], c, ce, co);
+        }
+    }
+}
+
+template <int DP, bool ODD>
+__global__ void __launch_bounds__(BfCfg<DP>::THREADS)
+freq_gemm_bf3_kernel(const float2 *__restrict__ ZA, const float2 *__restrict__ ZB, float2 *__restrict__ ZC,
+                     FftPlan plan, int d) {
+    freq_gemm_bf3_body<DP, ODD>(ZA, ZB, ZC, plan, d, blockIdx.x);
+}
+
+template <int DP, bool ODD>
+__global__ void __launch_bounds__(BfCfg<DP>::THREADS)
+freq_gemm_bf3_batched_kernel(const GemmProblem<float> *probs, int nprob, FftPlan plan) {
+    int lo = 0, hi = nprob - 1;
+    const int64_t bid = blockIdx.x;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (probs[mid].wg_begin <= bid) lo = mid;
+        else hi = mid - 1;
+    }
+    const GemmProblem<float> &pp = probs[lo];
+    freq_gemm_bf3_body<DP, ODD>(pp.A, pp.B, pp.C, plan, pp.d, bid - pp.wg_begin);
+}
+
+template <int DP, bool ODD>
+static hipError_t launch_gemm_bf3(const FftPlan &plan, int d, const float2 *ZA, const float2 *ZB, float2 *ZC,
+                                  hipStream_t st) {
+    using Cfg = BfCfg<DP>;
+    const size_t lds = bf3_lds_bytes<DP>(ODD ? d : 0);
+    auto kern = freq_gemm_bf3_kernel<DP, ODD>;
+    if (lds > 64 * 1024) {
+        (void)hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        (void)hipGetLastError();
+    }
+    const int64_t F = ((int64_t)1 << plan.lgL) / 2 + 1;
+    const int64_t blocks = (F + Cfg::NF - 1) / Cfg::NF;
+    char name[96];
+    snprintf(name, sizeof name, "freq_gemm_bf3_kernel<%d, %s>", DP, ODD ? "true" : "false");
+    const double Lr = (double)((int64_t)1 << plan.lgL);
+    const int nl = (d * d + 1) / 2;
+    launch_kernel(name, Lr * 3.0 * nl * sizeof(float2), (double)F * 8.0 * d * d * d, kern, dim3((unsigned)blocks),
+                  dim3(Cfg::THREADS), lds, st, ZA, ZB, ZC, plan, d);
+    return hipGetLastError();
+}
+
+template <int DP, bool ODD>
+static hipError_t launch_gemm_bf3_batched(const FftPlan &plan, const GemmProblem<float> *probs, int nprob,
+                                          int64_t total, double bytes, double flops, hipStream_t st) {
+    using Cfg = BfCfg<DP>;
+    const size_t lds = bf3_lds_bytes<DP>(ODD ? DP - 1 : 0);
+    auto kern = freq_gemm_bf3_batched_kernel<DP, ODD>;
+    if (lds > 64 * 1024) {
+        (void)hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        (void)hipGetLastError();
+    }
+    char name[96];
+    snprintf(name, sizeof name, "freq_gemm_bf3_batched_kernel<%d, %s>", DP, ODD ? "true" : "false");
+    launch_kernel(name, bytes, flops, kern, dim3((unsigned)total), dim3(Cfg::THREADS), lds, st, probs, nprob, plan);
+    return hipGetLastError();
+}
+
+// Square split-BF16 product of matrix-core class cls (9..16, see gemm_sq_class).
+static hipError_t gemm_bf3(const FftPlan &plan, int cls, int d, const float2 *ZA, const float2 *ZB, float2 *ZC,
+                           hipStream_t st) {
+    switch (cls) {
+        case 9: return launch_gemm_bf3<16, false>(plan, d, ZA, ZB, ZC, st);
+        case 10: return launch_gemm_bf3<32, false>(plan, d, ZA, ZB, ZC, st);
+        case 11: return launch_gemm_bf3<48, false>(plan, d, ZA, ZB, ZC, st);
+        case 12: return launch_gemm_bf3<64, false>(plan, d, ZA, ZB, ZC, st);
+        case 13: return launch_gemm_bf3<16, true>(plan, d, ZA, ZB, ZC, st);
+        case 14: return launch_gemm_bf3<32, true>(plan, d, ZA, ZB, ZC, st);
+        case 15: return launch_gemm_bf3<48, true>(plan, d, ZA, ZB, ZC, st);
+        default: return launch_gemm_bf3<64, true>(plan, d, ZA, ZB, ZC, st);
+    }
+}
+
+static hipError_t gemm_bf3_batched(const FftPlan &plan, int cls, const GemmProblem<float> *probs, int nprob,
+                                   int64_t total, double bytes, double flops, hipStream_t st) {
+    switch (cls) {
+        case 9: return launch_gemm_bf3_batched<16, false>(plan, probs, nprob, total, bytes, flops, st);
+        case 10: return launch_gemm_bf3_batched<32, false>(plan, probs, nprob, total, bytes, flops, st);
+        case 11: return launch_gemm_bf3_batched<48, false>(plan, probs, nprob, total, bytes, flops, st);
+        case 12: return launch_gemm_bf3_batched<64, false>(plan, probs, nprob, total, bytes, flops, st);
+        case 13: return launch_gemm_bf3_batched<16, true>(plan, probs, nprob, total, bytes, flops, st);
+        case 14: return launch_gemm_bf3_batched<32, true>(plan, probs, nprob, total, bytes, flops, st);
+        case 15: return launch_gemm_bf3_batched<48, true>(plan, probs, nprob, total, bytes, flops, st);
+        default: return launch_gemm_bf3_batched<64, true>(plan, probs, nprob, total, bytes, flops, st);
+    }
+}
+
 template <typename T, int DP, bool ODD, bool TA = false, bool TB = false>
 static hipError_t launch_gemm_mfma(const FftPlan &plan, int d, int mfma, const cplx<T> *ZA, const cplx<T> *ZB,
                                    cplx<T> *ZC, hipStream_t st) {
@@ -996,8 +1283,11 @@ int64_t gemm_batch_layout(const FftPlan &plan, GemmProblem<T> *probs, int nprob,
 }
 
 template <typename T>
-hipError_t freq_gemm_batched(const FftPlan &plan, int dclass, int mfma, const GemmProblem<T> *probs, int nprob,
-                             int64_t total, double bytes, double flops, hipStream_t st) {
+hipError_t freq_gemm_batched(const FftPlan &plan, int dclass, int mfma, int bf3, const GemmProblem<T> *probs,
+                             int nprob, int64_t total, double bytes, double flops, hipStream_t st) {
+    if constexpr (sizeof(T) == 4) {
+        if (bf3 && dclass >= 9) return gemm_bf3_batched(plan, dclass, probs, nprob, total, bytes, flops, st);
+    }
     switch (dclass) {
         case 1: return launch_gemm_sq_batched<T, 8>(plan, probs, nprob, total, bytes, flops, st);
         case 2: return launch_gemm_sq_batched<T, 16>(plan, probs, nprob, total, bytes, flops, st);
@@ -1020,9 +1310,9 @@ hipError_t freq_gemm_batched(const FftPlan &plan, int dclass, int mfma, const Ge
 
 template int64_t gemm_batch_layout<double>(const FftPlan &, GemmProblem<double> *, int, int);
 template int64_t gemm_batch_layout<float>(const FftPlan &, GemmProblem<float> *, int, int);
-template hipError_t freq_gemm_batched<double>(const FftPlan &, int, int, const GemmProblem<double> *, int, int64_t,
-                                              double, double, hipStream_t);
-template hipError_t freq_gemm_batched<float>(const FftPlan &, int, int, const GemmProblem<float> *, int, int64_t,
+template hipError_t freq_gemm_batched<double>(const FftPlan &, int, int, int, const GemmProblem<double> *, int,
+                                              int64_t, double, double, hipStream_t);
+template hipError_t freq_gemm_batched<float>(const FftPlan &, int, int, int, const GemmProblem<float> *, int, int64_t,
                                              double, double, hipStream_t);
 
 template <typename T, int DP>
@@ -1086,6 +1376,11 @@ static hipError_t gemm_sq_t(const FftPlan &plan, int d, int mfma, const cplx<T> 
 template <typename T>
 hipError_t freq_gemm(const FftPlan &plan, const GemmDesc &g, const cplx<T> *ZA, const cplx<T> *ZB, cplx<T> *ZC,
                      hipStream_t st) {
+    if constexpr (sizeof(T) == 4) {
+        if (g.bf3 && g.ra == g.m && g.m == g.cb && !g.transA && !g.transB && g.ra <= 64 &&
+            gemm_sq_class(g.ra, g.mfma) >= 9)
+            return gemm_bf3(plan, gemm_sq_class(g.ra, g.mfma), g.ra, ZA, ZB, ZC, st);
+    }
     if (g.ra == g.m && g.m == g.cb && !g.transA && !g.transB && g.ra <= 64)
         return gemm_sq<T>(plan, g.ra, g.mfma, ZA, ZB, ZC, st);
     const bool sq = g.ra == g.m && g.m == g.cb && g.ra <= 64 && !(g.transA && g.transB);

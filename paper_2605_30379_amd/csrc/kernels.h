@@ -187,6 +187,7 @@ struct GemmDesc {
     int nlA, nlB, nlC;      // complex lanes of the stored sequences
     int mfma;               // square products: 0 vector kernel; 1 matrix cores, three real products per complex
                             // product for padded d >= 48; 2 matrix cores, four real products
+    int bf3;                // float square products on the matrix cores as split-BF16 triple products
 };
 template <typename T>
 hipError_t freq_gemm(const FftPlan &plan, const GemmDesc &g, const cplx<T> *ZA, const cplx<T> *ZB, cplx<T> *ZC,
@@ -198,8 +199,8 @@ int gemm_sq_class(int d, int mfma);
 template <typename T>
 int64_t gemm_batch_layout(const FftPlan &plan, GemmProblem<T> *host_probs, int nprob, int mfma);
 template <typename T>
-hipError_t freq_gemm_batched(const FftPlan &plan, int dclass, int mfma, const GemmProblem<T> *dev_probs, int nprob,
-                             int64_t total_wg, double bytes, double flops, hipStream_t st);
+hipError_t freq_gemm_batched(const FftPlan &plan, int dclass, int mfma, int bf3, const GemmProblem<T> *dev_probs,
+                             int nprob, int64_t total_wg, double bytes, double flops, hipStream_t st);
 // C = A * diag(h): A ra x cb, h has cb lanes.
 template <typename T>
 hipError_t freq_diag(const FftPlan &plan, int ra, int cb, const cplx<T> *ZA, const cplx<T> *ZH, cplx<T> *ZC,
@@ -271,6 +272,28 @@ struct SmallVecArgs {
 hipError_t put_small_vectors(const SmallVecArgs &v, int *ci, int *di, double *alpha, double *ones, hipStream_t st);
 // LDS bytes of the recursion seed launch (m0 coefficients of a d x d problem).
 size_t seed_lds_bytes(int m0, int d);
+// Qbar_h and the right-hand side of the mean-value scheme (Section 4.2).
+hipError_t mre_prepare(const double *Qs, const double *L, int64_t n, int d, int r, double *Qbar, double *R,
+                       hipStream_t st);
+// Series Gauss-Jordan (Appendix): W = [A | I] ([n][d][2d]); one pivot step's
+// pivot choice, row swap and gathers (pivot series u, multipliers col); the
+// right block as the result.
+hipError_t gjs_init(const double *A, int e0_minus, int64_t n, int d, double *W, hipStream_t st);
+hipError_t gjs_pivot_step(double *W, int64_t n, int d, int i, int *piv, double *aux, double *u, double *col,
+                          unsigned int *status, hipStream_t st);
+hipError_t gjs_result(const double *W, int64_t n, int d, double *out, unsigned int *status, hipStream_t st);
+// Monte Carlo of a semi-Markov process (mc.hip); the model travels by value.
+constexpr int MC_MAX_D = 8;
+constexpr uint32_t MC_MAX_JUMPS = 1u << 22;   // every trajectory stops after this many jumps
+struct McModel {
+    int d, family, initial;
+    int up[MC_MAX_D];
+    int last[MC_MAX_D];                        // last state with positive jump probability, per row
+    double cum[MC_MAX_D * MC_MAX_D];           // cumulative row sums of the embedded matrix
+    double p1[MC_MAX_D * MC_MAX_D], p2[MC_MAX_D * MC_MAX_D];
+};
+hipError_t semi_markov_mc(const McModel &m, double step, int64_t n, int64_t trajectories, uint64_t seed, double *A,
+                          double *R, double *tau, int *jumps, int *diffA, int *diffR, hipStream_t st);
 hipError_t fill_f64(double *p, int64_t count, double v, hipStream_t st);
 hipError_t fill_u32(unsigned int *p, int64_t count, unsigned int v, hipStream_t st);
 hipError_t residual_norms(const double *R_L, const double *R_R, int d, int64_t n, double *acc, hipStream_t st);

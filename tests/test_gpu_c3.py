@@ -1,6 +1,7 @@
 """Parity at the headline workload: d = 64, n = 262144 (2^18), discrete
-lognormal sojourns (seed 3), FP64 and mixed forms, through the C-ABI in the
-launch configuration bench.py times.
+lognormal sojourns (seed 3), FP64 and both mixed forms (float32 products and
+the split-BF16 products the workload names), through the C-ABI in the launch
+configuration bench.py times.
 
 The quadratic oracle cannot form all 2^18 coefficients, so the evidence is
 layered (every reference comes from the oracle, never from the GPU path):
@@ -80,7 +81,7 @@ def c3(orc):
 @pytest.fixture(scope="module")
 def psis(mr, c3):
     out = {}
-    for form in ("fp64", "mixed"):
+    for form in ("fp64", "mixed", "bf16x3"):
         _log(f"psi_inverse {form}")
         out[form] = mr.psi_inverse(c3["q"], form, check=True)
     torch.cuda.synchronize()
@@ -91,7 +92,7 @@ def _tol(form, n=N):
     return fp64_tol(n) if form == "fp64" else MIXED_TOL
 
 
-@pytest.mark.parametrize("form", ["fp64", "mixed"])
+@pytest.mark.parametrize("form", ["fp64", "mixed", "bf16x3"])
 def test_c3_psi_prefix_and_alpha_row(mr, c3, psis, form):
     psi = psis[form]
     e_pre = _maxerr(_np(psi[:N_PSI]), c3["psi"])
@@ -101,7 +102,7 @@ def test_c3_psi_prefix_and_alpha_row(mr, c3, psis, form):
     assert e_row <= (FP64_TOL if form == "fp64" else MIXED_TOL)
 
 
-@pytest.mark.parametrize("form", ["fp64", "mixed"])
+@pytest.mark.parametrize("form", ["fp64", "mixed", "bf16x3"])
 def test_c3_sampled_residuals_over_the_horizon(mr, orc, c3, psis, form):
     t = time.time()
     rho = orc.residual_at(c3["qh"], _np(psis[form]), RESID_KS, e0_minus=True)
@@ -111,7 +112,7 @@ def test_c3_sampled_residuals_over_the_horizon(mr, orc, c3, psis, form):
     assert per_k.max() <= _tol(form)
 
 
-@pytest.mark.parametrize("form", ["fp64", "mixed"])
+@pytest.mark.parametrize("form", ["fp64", "mixed", "bf16x3"])
 def test_c3_functionals(mr, c3, psis, form):
     """P = psi*Hbar is one transform product at length 2^19 over a recurrent
     psi, so each entry carries the product rounding of the whole horizon
@@ -140,7 +141,8 @@ def test_c3_functionals(mr, c3, psis, form):
     assert rows <= _tol(form)
 
 
-def test_c3_mixed_against_fp64_whole_horizon(psis):
-    diff = float((psis["mixed"] - psis["fp64"]).abs().max())
-    _log(f"max|mixed - fp64| over the horizon: {diff:.3e}")
+@pytest.mark.parametrize("form", ["mixed", "bf16x3"])
+def test_c3_mixed_against_fp64_whole_horizon(psis, form):
+    diff = float((psis[form] - psis["fp64"]).abs().max())
+    _log(f"max|{form} - fp64| over the horizon: {diff:.3e}")
     assert diff <= MIXED_TOL

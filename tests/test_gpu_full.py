@@ -233,10 +233,10 @@ def _continuous_schemes(mr, orc, Q, Hb, n):
     reliability on t_0 .. t_{n-1} as {scheme: (A, R)}.
       * process: psi of q = Delta Q_h (FP64), P = psi*Hbar, availability, and
         reliability by first entrance (Section 4.1);
-      * mean_value: K_h = (e0 - Qbar_h)^-1 * [L_h - 1/2 Delta^+Q_h * (L_h(0) e0)]
-        with the general-A(0) inverse and the rectangular products.
-    Every inverse is checked against the oracle on a 2048-step prefix (an
-    exact sub-problem, Proposition 2.3)."""
+      * mean_value: mrinv_mre_solve, K_h = (e0 - Qbar_h)^-1 * [L_h - 1/2
+        Delta^+Q_h * (L_h(0) e0)] (general-A(0) inverse, rectangular product).
+    The process inverse and the mean-value P are checked against the oracle on
+    a 2048-step prefix (an exact sub-problem, Proposition 2.3)."""
     up, U, D = [1, 1, 1, 0], [0, 1, 2], [3]
     alpha = [1.0, 0.0, 0.0, 0.0]
     dev = torch.device("cuda")
@@ -249,20 +249,13 @@ def _continuous_schemes(mr, orc, Q, Hb, n):
     assert _maxerr(_np(psi[:2048]), orc.psi(dQ[:2048])) <= 1e-12
     out["process"] = (_np(mr.availability(mr.transition(psi, q), up, alpha)), _np(mr.reliability(q, up, alpha)))
 
-    dQp = dQ[1:n + 1]
-    Qbar = 0.5 * (dQ[:n] + dQp)
-
-    def inverse(rows):
-        Am = -Qbar[:, rows][:, :, rows]
-        Am[0] += np.eye(len(rows))
-        X = mr.series_inverse(torch.from_numpy(np.ascontiguousarray(Am)).to(dev), "fp64")
-        assert _maxerr(_np(X[:2048]), orc.series_inverse_left(Am[:2048])) <= 1e-12
-        return X
-
-    L = np.ascontiguousarray(Hb[:n] - 0.5 * dQp)            # L = Hbar, L(0) = I
-    P = mr.markov_renewal_apply(inverse([0, 1, 2, 3]), torch.from_numpy(L).to(dev))
-    QUD = np.ascontiguousarray(Q[:n][:, U][:, :, D])        # L = Q_UD, L(0) = 0
-    GD = mr.markov_renewal_apply(inverse(U), torch.from_numpy(QUD).to(dev))
+    # Mean-value scheme (Section 4.2, eq. (mre-solution)) by the library:
+    # L = Hbar gives P; L = Q_UD on the up block gives the first entrance.
+    Qg = torch.from_numpy(np.ascontiguousarray(Q[:n + 1])).to(dev)
+    P = mr.mre_solve(Qg, torch.from_numpy(np.ascontiguousarray(Hb[:n])).to(dev))
+    assert _maxerr(_np(P[:2048]), orc.mre_mean_value(Q[:2049], Hb[:2048])) <= 1e-12
+    QU = torch.from_numpy(np.ascontiguousarray(Q[:n + 1][:, U][:, :, U])).to(dev)
+    GD = mr.mre_solve(QU, torch.from_numpy(np.ascontiguousarray(Q[:n][:, U][:, :, D])).to(dev))
     out["mean_value"] = (_np(mr.availability(P, up, alpha)), 1.0 - _np(GD)[:, 0, 0])
     return out
 

@@ -335,24 +335,11 @@ def _mean_value(orc, Q, Hb, n):
     reliability on t_0 .. t_{n-1}, from the kernel Q sampled on t_0 .. t_n and
     the survival Hb:
     K_h = (e0 - Qbar_h)^-1 * [L_h - 1/2 Delta^+Q_h * (L_h(0) e0)], with
-    L = Hbar for P and L = Q_UD (first entrance into D = {3}) for reliability.
-    Qbar_h(0) = Delta Q_h(1) / 2 is not zero, so this runs the general-A(0)
-    inverse."""
+    L = Hbar for P and L = Q_UD (first entrance into D = {3}) for reliability,
+    through oracle.mre_mean_value (general-A(0) inverse, Qbar_h(0) != 0)."""
     s = Q.shape[1]
-    dQ = np.zeros_like(Q)
-    dQ[1:] = Q[1:] - Q[:-1]
-    dQp = dQ[1:n + 1]                      # Delta^+ Q_h(m) = Delta Q_h(m + 1)
-    Qbar = 0.5 * (dQ[:n] + dQp)
-
-    def solve(rows, L, L0):
-        A = -Qbar[:, rows][:, :, rows]
-        A[0] += np.eye(len(rows))
-        X = orc.series_inverse_left(A)
-        corr = np.einsum("kij,jl->kil", dQp[:, rows][:, :, rows], L0)
-        return orc.conv(X, L - 0.5 * corr)
-
-    P = solve(list(range(s)), Hb[:n], np.eye(s))
-    GD = solve(UP, Q[:n][:, UP][:, :, DOWN], np.zeros((len(UP), len(DOWN))))
+    P = orc.mre_mean_value(Q[:n + 1], Hb[:n])
+    GD = orc.mre_mean_value(Q[:n + 1][:, UP][:, :, UP], Q[:n][:, UP][:, :, DOWN])
     return P, P[:, 0, UP].sum(1), 1.0 - GD[:, 0, 0]
 
 
@@ -524,3 +511,128 @@ def test_recursion_sums_do_not_depend_on_the_thread_count(orc):
                                    cwd=os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
                                    check=True).stdout.strip())
     assert outs[0] == outs[1]
+
+
+def test_mean_value_scheme_planted_mistakes(orc):
+    """mre_mean_value is pinned by the printed convergence table above; these
+    are the plausible slips that table rules out, checked to move the h = 0.1
+    errors by far more than its five digits: A(0) taken as I, the Delta+
+    correction dropped, and Delta Q in place of Qbar (the process scheme)."""
+    fx = pf.read_blocks("exponential_convergence.txt")
+    G, T = pf.generator(fx), float(fx["horizon"])
+    h = 0.1
+    n = int(np.floor(T / h + 1e-9)) + 1
+    Q, Hb = si.exponential_semi_markov(G, h, n + 1)
+    Pex, _, _ = _exact(G, h * np.arange(n))
+    good = np.max(np.linalg.norm(orc.mre_mean_value(Q, Hb[:n]) - Pex, axis=(1, 2)))
+    dQ = np.zeros_like(Q)
+    dQ[1:] = Q[1:] - Q[:-1]
+    Qbar = 0.5 * (dQ[:n] + dQ[1:n + 1])
+    A = -Qbar
+    A[0] = np.eye(4)                                           # slip 1: A(0) = I
+    slip1 = orc.conv(orc.series_inverse_left(A), Hb[:n] - 0.5 * np.matmul(dQ[1:n + 1], Hb[0]))
+    A = -Qbar
+    A[0] += np.eye(4)
+    slip2 = orc.conv(orc.series_inverse_left(A), Hb[:n])       # slip 2: no Delta+ correction
+    A = -dQ[:n]
+    A[0] += np.eye(4)
+    slip3 = orc.conv(orc.series_inverse_left(A), Hb[:n])       # slip 3: the process scheme
+    for bad in (slip1, slip2, slip3):
+        e = np.max(np.linalg.norm(bad - Pex, axis=(1, 2)))
+        assert e > 3 * good, (e, good)
+
+
+def test_renewal_visits_closed_forms(orc):
+    """Renewal visits N_B(k) = alpha sum_{l<=k} psi(l) I_B 1 (eq.
+    (renewal-visits)): for d = 1 geometric sojourns every step renews with
+    probability 1 - a, so N(k) = 1 + k (1 - a); for the Markov case
+    N_B(k) = alpha [I_B 1 + sum_{l=1..k} M^(l-1) (M - diag a) 1_B]; summed over
+    a partition of E the visits add up."""
+    a, n = 0.7, 50
+    q = np.zeros((n, 1, 1))
+    q[1:, 0, 0] = (1 - a) * a ** np.arange(n - 1)
+    N = orc.renewal_visits(q, [1], [1.0])
+    assert np.max(np.abs(N - (1 + np.arange(n) * (1 - a)))) <= 1e-13
+    d, n = 5, 60
+    k = si.geometric_kernel(d, n, 14)
+    M, av = k.params["M"], k.params["a"]
+    alpha = np.array([0.2, 0.0, 0.5, 0.3, 0.0])
+    inB = np.array([1, 0, 0, 1, 1])
+    ref = np.empty(n)
+    acc = alpha @ inB
+    Mk = np.eye(d)
+    ref[0] = acc
+    for t in range(1, n):
+        acc += alpha @ Mk @ (M - np.diag(av)) @ inB
+        ref[t] = acc
+        Mk = Mk @ M
+    got = orc.renewal_visits(k.q.numpy(), inB, alpha)
+    assert np.max(np.abs(got - ref)) <= 1e-12
+    other = orc.renewal_visits(k.q.numpy(), 1 - inB, alpha)
+    every = orc.renewal_visits(k.q.numpy(), np.ones(d), alpha)
+    assert np.max(np.abs(got + other - every)) <= 1e-12
+
+
+def test_monte_carlo_oracle_markov_closed_form(orc):
+    """The oracle's pathwise Monte Carlo (the Section 5.2 validation method)
+    on exponential sojourns, where the process is the Markov chain of the
+    exponential benchmark's generator: availability alpha exp(G t) 1_U and
+    reliability alpha_U exp(G_UU t) 1 hold within 5.5 binomial standard
+    deviations at every grid point.  A sampler that picks the wrong next
+    state, uses the wrong rate or marks the wrong grid cells fails by far more."""
+    from scipy.linalg import expm
+    G = pf.generator(pf.read_blocks("exponential_convergence.txt"))
+    lam = -np.diag(G)
+    P = G / lam[:, None]
+    np.fill_diagonal(P, 0.0)
+    rate = np.repeat(lam[:, None], 4, axis=1)
+    h, n, M = 0.05, 400, 200000
+    A, R = orc.semi_markov_mc(P, rate, np.ones((4, 4)), [1, 1, 1, 0], h, n, M, 11, family="exponential")
+    t = h * np.arange(n)
+    Aex = np.array([expm(G * x)[0, :3].sum() for x in t])
+    Rex = np.array([expm(G[:3, :3] * x)[0].sum() for x in t])
+    for est, ex in ((A, Aex), (R, Rex)):
+        sd = np.sqrt(np.maximum(ex * (1 - ex), 1e-6) / M)
+        assert np.max(np.abs(est - ex) / sd) <= 5.5
+    # planted: the same simulation with the rates swapped between states is far off
+    A2, _ = orc.semi_markov_mc(P, rate[::-1].copy(), np.ones((4, 4)), [1, 1, 1, 0], h, n, M, 11, family="exponential")
+    assert np.max(np.abs(A2 - Aex)) > 20 * np.max(np.sqrt(Aex * (1 - Aex) / M))
+
+
+def test_monte_carlo_oracle_lognormal_sojourn_law(orc):
+    """The lognormal sampler: a two-state alternating process whose first
+    sojourn is lognormal(mu, sigma) has R(t) = P(T > t) = 1 - Phi((ln t - mu)/
+    sigma) for the down state entered at the first jump; the estimate holds
+    within 5.5 standard deviations.  The stream is deterministic: the same
+    seed repeats bit for bit, another seed differs."""
+    from scipy.stats import norm
+    P = np.array([[0.0, 1.0], [1.0, 0.0]])
+    mu, sg = np.array([[0.0, 1.2], [0.0, 0.0]]), np.array([[1.0, 0.7], [1.0, 1.0]])
+    h, n, M = 0.05, 300, 200000
+    A, R, tau, jumps = orc.semi_markov_mc(P, mu, sg, [1, 0], h, n, M, 12, per_path=True)
+    t = h * np.arange(n)
+    Rex = np.where(t > 0, 1.0 - norm.cdf((np.log(np.maximum(t, 1e-300)) - 1.2) / 0.7), 1.0)
+    sd = np.sqrt(np.maximum(Rex * (1 - Rex), 1e-6) / M)
+    assert np.max(np.abs(R - Rex) / sd) <= 5.5
+    again = orc.semi_markov_mc(P, mu, sg, [1, 0], h, n, M, 12, per_path=True)
+    assert np.array_equal(again[2], tau) and np.array_equal(again[3], jumps)
+    other = orc.semi_markov_mc(P, mu, sg, [1, 0], h, n, M, 13, per_path=True)
+    assert not np.array_equal(other[2], tau)
+
+
+def test_philox_stream_statistics(orc):
+    """Philox4x32-10 blocks: words are uniform on 32 bits (mean and a 64-bin
+    chi-square over 2^14 blocks) and one flipped counter bit changes about
+    half of the 128 output bits."""
+    words = np.array([orc.philox4x32_10([k, 0, 5, 0], [123, 456]) for k in range(1 << 14)]).ravel()
+    u = words / 2.0 ** 32
+    assert abs(u.mean() - 0.5) <= 5 * np.sqrt(1 / 12 / u.size)
+    counts = np.bincount((words >> 26).astype(np.int64), minlength=64)
+    chi2 = float(np.sum((counts - u.size / 64) ** 2 / (u.size / 64)))
+    assert chi2 <= 130                      # 63 degrees of freedom: far beyond the 1e-6 quantile
+    a = orc.philox4x32_10([1, 2, 3, 4], [5, 6])
+    flips = []
+    for bit in range(32):
+        b = orc.philox4x32_10([1 ^ (1 << bit), 2, 3, 4], [5, 6])
+        flips.append(sum(bin(int(x) ^ int(y)).count("1") for x, y in zip(a, b)))
+    assert 48 <= np.mean(flips) <= 80
