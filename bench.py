@@ -175,6 +175,30 @@ def roofline_of(stats, traffic_file=None):
     return roof, breakdown
 
 
+def hbm_measured(mr, torch, dev, roof):
+    """Measured HBM ceilings (mrinv_hbm_probe, best of 3 event-timed launches
+    over an 8 GiB buffer): a plain copy, and in-place reads and writes with the
+    addressing of the first and the last 512-row FFT pass at 8, 16 and 32
+    lanes per workgroup over 2^18 rows of 2048 complex doubles (the d=64,
+    n=262144 spectra).  The dominant kernel's algorithmic bandwidth is set
+    against the copy rate."""
+    buf = torch.empty(1 << 30, dtype=torch.float64, device=dev)
+    rates = {"copy": round(mr.hbm_probe(buf, "copy", reps=3), 1)}
+    for pattern in ("pass_first", "pass_last"):
+        for lanes in (8, 16, 32):
+            rates[f"{pattern}_{lanes}"] = round(mr.hbm_probe(buf, pattern, lanes=lanes, reps=3), 1)
+    del buf
+    torch.cuda.empty_cache()
+    out = {"unit": "GB/s", "rates": rates, "buffer_bytes": 1 << 33,
+           "note": "best of 3 launches; bytes read + written over event-timed duration"}
+    if roof:
+        gbps = roof["algorithmic_bytes_per_launch"] / (roof["avg_us"] * 1e-6) / 1e9
+        out["dominant_kernel_GBps"] = round(gbps, 1)
+        out["dominant_kernel_frac_of_copy"] = round(gbps / rates["copy"], 4)
+    print(f"[bench] hbm measured {json.dumps(out)}", file=sys.stderr, flush=True)
+    return out
+
+
 def write_traffic(args, kernel: str, fetch_csv: str, write_csv: str) -> None:
     """HBM traffic of one launch of `kernel` from rocprofv3 counter runs.
 
@@ -455,7 +479,8 @@ def run_gradient(args, mr, torch, si, dev):
         return ps
 
     ms = time_steps(step, args.steps, args.warmup, torch)
-    fwd_ms = time_steps(lambda: mr.psi_inverse(si.weibull_kernel(d, n, 5, device=dev).q), args.steps, 1, torch)
+    q5 = si.weibull_kernel(d, n, CONFIGS["c5"]["seed"], device=dev).q
+    fwd_ms = time_steps(lambda: mr.psi_inverse(q5), args.steps, 1, torch)
     line = {
         "metric": "psi inversion sec & effective TFLOP/s, mixed vs FP64 on 1 GPU @ max err<=1e-10",
         "value": round(2 * f_nom(d, n) / (ms * 1e-3) / 1e12, 4), "unit": "TFLOP/s", "n_gpus": 1,
@@ -478,6 +503,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true", help="skip the accuracy checks against the oracle")
     ap.add_argument("--no-tuning-table", action="store_true", help="c4: do not load the per-class tuning table")
+    ap.add_argument("--no-hbm-probe", action="store_true", help="skip the measured HBM ceilings")
     ap.add_argument("--forms", default="fp64,mixed,bf16x3", help="comma-separated forms to time (value form first)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one 1 GiB device-to-device copy first (reference for HBM counter runs)")
@@ -547,6 +573,7 @@ def main():
     traffic_file = os.path.join(ROOT, "profiles", f"traffic_{args.config}_{value_form}.json")
     roof, breakdown = roofline_of(stats, traffic_file)
     path_ms = sum(s["total_ms"] for s in stats) / max(1, min(args.steps, 5))
+    hbm = None if args.no_hbm_probe else hbm_measured(mr, torch, dev, roof)
 
     # Accuracy of both forms against the oracle (prefixes: exact sub-problems by
     # finite-horizon exactness), the mixed form against FP64 over the whole
@@ -591,6 +618,7 @@ def main():
         "kernel_time_ms_per_step": round(path_ms, 4),
         "accuracy": acc,
         "roofline": roof,
+        "hbm_measured": hbm,
         "kernels": breakdown,
         "cpu_baseline": cpu,
         "source_hash": source_hash(),

@@ -23,8 +23,8 @@
  *   bytes (256-byte aligned).
  * - Calls only enqueue work on the handle's HIP stream and return, with these
  *   exceptions, each stated at its declaration: mrinv_sync_status,
- *   mrinv_residual_norms, mrinv_autotune, mrinv_kernel_stats and
- *   mrinv_psi_inverse_batched_prepare (hence mrinv_psi_inverse_batched) wait
+ *   mrinv_residual_norms, mrinv_autotune, mrinv_kernel_stats, mrinv_hbm_probe
+ *   and mrinv_psi_inverse_batched_prepare (hence mrinv_psi_inverse_batched) wait
  *   for the stream.  Calls that only enqueue can be recorded into a HIP graph
  *   (stream capture) and replayed; the mrinv_create of the handle must come
  *   before the capture.
@@ -454,6 +454,26 @@ mrinv_status_t mrinv_set_timing(mrinv_handle_t h, int enabled);
 /* Synchronises the stream; fills up to max_out entries, returns the number of
  * distinct kernels recorded (or -1 on error). */
 int mrinv_kernel_stats(mrinv_handle_t h, mrinv_kernel_stat_t *out, int max_out);
+
+/* Measurement utility, not an operation of the paper: the rate at which this
+ * GPU reads and writes HBM for one access pattern, the practical ceiling for
+ * the transform and product kernels above (whose published peak, 8 TB/s, no
+ * kernel reaches).  buf: caller-owned device memory of `bytes` bytes; its
+ * contents are overwritten.  pattern:
+ *   MRINV_HBM_COPY: the first half of buf is copied to the second half, one
+ *     16-byte element per thread (bytes >= 2 MiB);
+ *   MRINV_HBM_PASS_FIRST, MRINV_HBM_PASS_LAST: every element of an array of
+ *     L rows x 2048 complex doubles (L the largest power of two that fits,
+ *     bytes >= 32 MiB) is read and written in place with the addressing of the
+ *     first (rows m + (L/512) i) or the last (rows 512 m + i) 512-row FFT
+ *     pass, `lanes` (8, 16 or 32) consecutive lanes per workgroup, and its
+ *     real part increased by 1 (so each launch visits every element once).
+ * Runs `reps` (1..100) launches on the handle's stream, waits for each, and
+ * writes the best rate in GB/s (bytes read + bytes written, over the
+ * launch's event-timed duration) to *gbps.  Allocates nothing. */
+typedef enum { MRINV_HBM_COPY = 0, MRINV_HBM_PASS_FIRST = 1, MRINV_HBM_PASS_LAST = 2 } mrinv_hbm_pattern_t;
+mrinv_status_t mrinv_hbm_probe(mrinv_handle_t h, void *buf, size_t bytes, int pattern, int lanes, int reps,
+                               double *gbps);
 
 #ifdef __cplusplus
 }

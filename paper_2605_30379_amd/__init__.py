@@ -146,6 +146,7 @@ def lib():
             "mrinv_set_tuning_table": (i32, [vp, ctypes.POINTER(TuningEntry), i32]),
             "mrinv_set_tuning": (i32, [vp, ctypes.POINTER(Tuning)]),
             "mrinv_autotune": (i32, [vp, vp, i32, i64, i32, vp, vp, sz, ctypes.POINTER(Tuning)]),
+            "mrinv_hbm_probe": (i32, [vp, vp, sz, i32, i32, i32, dp]),
         }
         for name, (res, args) in sigs.items():
             fn = getattr(L, name)
@@ -288,6 +289,20 @@ def autotune(q: torch.Tensor, precision="fp64") -> dict:
     _check(lib().mrinv_autotune(_handle(q.device), _ptr(q), d, n, prec, _ptr(out), _ptr(ws), ws.numel(),
                                 ctypes.byref(t)))
     return t.as_dict()
+
+
+HBM_PATTERNS = {"copy": 0, "pass_first": 1, "pass_last": 2}
+
+
+def hbm_probe(buf: torch.Tensor, pattern="copy", lanes: int = 16, reps: int = 5) -> float:
+    """Best read + write rate (GB/s) of one access pattern over the device
+    buffer `buf` (contents overwritten; mrinv_hbm_probe)."""
+    if not buf.is_cuda or not buf.is_contiguous():
+        raise MrinvError(1, "buf must be a contiguous device tensor")
+    out = ctypes.c_double(0.0)
+    _check(lib().mrinv_hbm_probe(_handle(buf.device), _ptr(buf), buf.numel() * buf.element_size(),
+                                 HBM_PATTERNS[pattern], int(lanes), int(reps), ctypes.byref(out)))
+    return out.value
 
 
 def sync_status(device=None):

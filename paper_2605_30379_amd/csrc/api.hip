@@ -243,6 +243,29 @@ extern "C" int mrinv_kernel_stats(mrinv_handle_t h, mrinv_kernel_stat_t *out, in
     return timer_stats(h->timer, h->stream, out, max_out);
 }
 
+namespace mrinv {
+size_t hbm_probe_min_bytes();
+hipError_t hbm_probe(hipStream_t st, void *buf, size_t bytes, int pattern, int lanes, int reps, double *gbps);
+}
+
+extern "C" mrinv_status_t mrinv_hbm_probe(mrinv_handle_t h, void *buf, size_t bytes, int pattern, int lanes,
+                                          int reps, double *gbps) {
+    if (!h || !buf || !gbps) return fail(MRINV_E_ARG, "NULL handle or pointer");
+    if (pattern < MRINV_HBM_COPY || pattern > MRINV_HBM_PASS_LAST) return fail(MRINV_E_ARG, "unknown pattern %d", pattern);
+    if (reps < 1 || reps > 100) return fail(MRINV_E_ARG, "reps %d not in 1..100", reps);
+    if (((uintptr_t)buf & 15) != 0) return fail(MRINV_E_ARG, "buffer not 16-byte aligned");
+    if (pattern == MRINV_HBM_COPY) {
+        if (bytes < ((size_t)2 << 20)) return fail(MRINV_E_ARG, "copy probe needs at least 2 MiB");
+    } else {
+        if (lanes != 8 && lanes != 16 && lanes != 32) return fail(MRINV_E_ARG, "lanes %d not 8, 16 or 32", lanes);
+        if (bytes < hbm_probe_min_bytes())
+            return fail(MRINV_E_ARG, "pass probe needs at least %zu bytes", hbm_probe_min_bytes());
+    }
+    *gbps = 0.0;
+    HIP_TRY(hbm_probe(h->stream, buf, bytes, pattern, lanes, reps, gbps));
+    return MRINV_OK;
+}
+
 // ---------------------------------------------------------------------------
 // Plans and workspace
 // ---------------------------------------------------------------------------
