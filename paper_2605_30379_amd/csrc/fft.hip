@@ -690,6 +690,10 @@ hipError_t fft_pass(int mode, const FftPlan &plan, int pass, int nl, cplx<T> *z,
     if (C == 32 && (lgP > 8 || nl <= 16)) C = 16;
     C = fewer_lanes_when_small(C, g.L >> lgP, nl, 0);
     g.nchunks = (nl + C - 1) / C;
+    // The fused pass at 8 lanes (128-byte row segments, the first pass's
+    // strided rows) runs about 7% faster with consecutive workgroups on
+    // different columns, unless the tuning fixes the order.
+    if (mode == 2 && C == 8 && order == 0) g.col_fastest = 1;
     Twiddles<T> t = tw;
     t.outer = plan.outer[pass];
     switch (mode) {
