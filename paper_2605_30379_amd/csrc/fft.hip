@@ -104,6 +104,18 @@ __device__ __forceinline__ void wg_fft(cplx<T> *lds, int lds_stride, int c, int 
     }
 }
 
+// A wave-uniform 64-bit value passed through readfirstlane: the same number,
+// which the compiler can no longer prove equal to its source.  The stores of
+// a pass use it for their row stride, so their addresses are formed anew
+// instead of keeping the first stage's load addresses (the same rows in the
+// 512-row passes) alive across the transform: without it the 512-row inverse
+// pass spills 44 bytes per lane at its 64-register budget.
+__device__ __forceinline__ int64_t uniform_copy(int64_t x) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)x);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)((uint64_t)x >> 32));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
 __device__ __forceinline__ bool is_diag_lane(int e, int e0_d) {
     return e < e0_d * e0_d && (e % (e0_d + 1)) == 0;
 }
@@ -267,8 +279,9 @@ __device__ __forceinline__ void fft_pass_body(cplx<T> *z, const PassGeom &g, int
     };
     auto z_store_all = [&](int b0, int lgs, auto &v) {
         if (!lane_ok) return;
-        cplx<T> *q = zc + (int64_t)b0 * rs;
-        const int64_t step = rs << lgs;
+        const int64_t rsu = uniform_copy(rs);    // rs is the same in every lane
+        cplx<T> *q = zc + (int64_t)b0 * rsu;
+        const int64_t step = rsu << lgs;
 #pragma unroll
         for (int r = 0; r < MR_RADIX(v); ++r) {
             *q = v[r];
