@@ -360,15 +360,24 @@ template <> struct MfmaOp<float> {
     __device__ static __forceinline__ int row(int l, int r) { return 4 * (l >> 4) + r; }
 };
 
-template <typename T, int DP> struct MfCfg {
-    static constexpr int WPF = DP / 16;                  // waves per frequency
-    static constexpr int NF = WPF >= 3 ? 1 : 4 / WPF;    // frequencies per workgroup
-    static constexpr int THREADS = 64 * WPF * NF;
+// JS (column split): two waves per 16-row strip, each owning half of the
+// strip's column tiles, so a wave holds half the accumulators.  Used by the
+// three-product FP64 form at d = 64, whose 3 x 4 accumulator tiles (96
+// registers) would otherwise hold it at 148 registers and 3 waves per SIMD.
+template <typename T, int DP, bool JS = false> struct MfCfg {
+    static constexpr int WPF = DP / 16;                  // 16-row strips per frequency
+    static constexpr int JSPLIT = JS ? 2 : 1;            // waves per strip
+    static constexpr int WPFX = WPF * JSPLIT;            // waves per frequency
+    static constexpr int JW = WPF / JSPLIT;              // 16-column tiles per wave
+    static constexpr int NF = WPFX >= 3 ? 1 : 4 / WPFX;  // frequencies per workgroup
+    static constexpr int THREADS = 64 * WPFX * NF;
     // Contraction chunk and register budget.  FP64 products with d > 16 take
     // 8-wide chunks (half the LDS of 16-wide ones) and a register budget of
     // 4 (d <= 32) or 3 (d <= 64) waves per SIMD, so more workgroups share a CU.
-    static constexpr int WAVES = sizeof(T) == 8 && DP >= 32 ? (DP == 32 ? 4 : 3) : 1;
-    static constexpr int KC = WAVES > 1 ? 8 : 16;
+    // The column split takes 16-wide chunks (one A pair and one B pair per
+    // thread) and 4 waves per SIMD: two 512-thread workgroups per CU.
+    static constexpr int WAVES = JS ? 4 : (sizeof(T) == 8 && DP >= 32 ? (DP == 32 ? 4 : 3) : 1);
+    static constexpr int KC = JS ? 16 : (WAVES > 1 ? 8 : 16);
     static constexpr int LDA = KC + 1;                   // As[f][i][t], i < DP, t < KC
     static constexpr int LDB = DP + 1;                   // Bs[f][t][j]
     static constexpr int AS = DP * LDA;
@@ -377,9 +386,9 @@ template <typename T, int DP> struct MfCfg {
 };
 
 // LDS bytes of one workgroup; odd d stages C (d*d complex per frequency).
-template <typename T, int DP>
+template <typename T, int DP, bool JS = false>
 static size_t mf_lds_bytes(int dmax_odd) {
-    using Cfg = MfCfg<T, DP>;
+    using Cfg = MfCfg<T, DP, JS>;
     const size_t ab = (size_t)Cfg::NBUF * Cfg::NF * (Cfg::AS + Cfg::BS) * sizeof(cplx<T>);
     const size_t cs = (size_t)Cfg::NF * ((size_t)dmax_odd * dmax_odd + 1) * sizeof(cplx<T>);
     return cs > ab ? cs : ab;
@@ -398,14 +407,17 @@ __device__ __forceinline__ double lane_xor1(double x) {
 
 // TA / TB: operand stored transposed (A(i, t) at entry t d + i, B(t, j) at
 // entry j d + t), staged entry by entry.
+template <typename T, int DP, bool G3>
+__host__ __device__ constexpr bool mf_js() { return G3 && sizeof(T) == 8 && DP == 64; }
+
 template <typename T, int DP, bool ODD, bool TA = false, bool TB = false, bool G3 = false>
 __device__ __forceinline__ void freq_gemm_mfma_body(const cplx<T> *__restrict__ ZA, const cplx<T> *__restrict__ ZB,
                                                     cplx<T> *__restrict__ ZC, const FftPlan &plan, int d,
                                                     int64_t blk) {
-    using Cfg = MfCfg<T, DP>;
+    using Cfg = MfCfg<T, DP, mf_js<T, DP, G3>()>;
     using Op = MfmaOp<T>;
     using V = typename Op::V;
-    constexpr int WPF = Cfg::WPF, NF = Cfg::NF, KC = Cfg::KC, NT = Cfg::THREADS;
+    constexpr int WPF = Cfg::WPF, WPFX = Cfg::WPFX, JW = Cfg::JW, NF = Cfg::NF, KC = Cfg::KC, NT = Cfg::THREADS;
     constexpr int LDA = Cfg::LDA, LDB = Cfg::LDB;
     // Staging work per thread and chunk: entry pairs (even d) or entries
     // (odd d) of A and of B; NT = 4 DP NF makes both counts exact.
@@ -430,7 +442,8 @@ __device__ __forceinline__ void freq_gemm_mfma_body(const cplx<T> *__restrict__ 
     }
     __syncthreads();
     const int l = tid & 63, w = tid >> 6;
-    const int f = w / WPF, I = w - f * WPF;
+    const int f = w / WPFX, wr = w - f * WPFX;
+    const int I = wr % WPF, J0 = (wr / WPF) * JW;   // row strip, first column tile
     constexpr bool even = !ODD;               // C entries (i, j), (i, j^1) share a packed lane
     constexpr bool pairs = !ODD && !TA && !TB; // operands staged by packed lanes
     // Four real products per complex product: accR = Re A Re B - Im A Im B,
@@ -438,13 +451,13 @@ __device__ __forceinline__ void freq_gemm_mfma_body(const cplx<T> *__restrict__ 
     // form of the complex product): accR = Re A Re B, accI = Im A Im B and
     // acc3 = (Re A + Im A)(Re B + Im B), combined after the contraction into
     // Re C = accR - accI and Im C = acc3 - accR - accI.
-    V accR[WPF], accI[WPF], acc3[G3 ? WPF : 1];
+    V accR[JW], accI[JW], acc3[G3 ? JW : 1];
 #pragma unroll
-    for (int J = 0; J < WPF; ++J)
+    for (int J = 0; J < JW; ++J)
 #pragma unroll
         for (int r = 0; r < 4; ++r) accR[J][r] = accI[J][r] = (T)0;
 #pragma unroll
-    for (int J = 0; J < (G3 ? WPF : 1); ++J)
+    for (int J = 0; J < (G3 ? JW : 1); ++J)
 #pragma unroll
         for (int r = 0; r < 4; ++r) acc3[J][r] = (T)0;
 
@@ -568,16 +581,16 @@ __device__ __forceinline__ void freq_gemm_mfma_body(const cplx<T> *__restrict__ 
             if constexpr (G3) {
                 const T as = a.x + a.y;
 #pragma unroll
-                for (int J = 0; J < WPF; ++J) {
-                    const cplx<T> b = Bf[t * LDB + J * 16];
+                for (int J = 0; J < JW; ++J) {
+                    const cplx<T> b = Bf[t * LDB + (J0 + J) * 16];
                     accR[J] = Op::mac(a.x, b.x, accR[J]);
                     accI[J] = Op::mac(a.y, b.y, accI[J]);
                     acc3[J] = Op::mac(as, b.x + b.y, acc3[J]);
                 }
             } else {
 #pragma unroll
-                for (int J = 0; J < WPF; ++J) {
-                    const cplx<T> b = Bf[t * LDB + J * 16];
+                for (int J = 0; J < JW; ++J) {
+                    const cplx<T> b = Bf[t * LDB + (J0 + J) * 16];
                     accR[J] = Op::mac(a.x, b.x, accR[J]);
                     accR[J] = Op::mac(-a.y, b.y, accR[J]);
                     accI[J] = Op::mac(a.x, b.y, accI[J]);
@@ -591,7 +604,7 @@ __device__ __forceinline__ void freq_gemm_mfma_body(const cplx<T> *__restrict__ 
     }
     if constexpr (G3) {
 #pragma unroll
-        for (int J = 0; J < WPF; ++J)
+        for (int J = 0; J < JW; ++J)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const T p1 = accR[J][r], p2 = accI[J][r];
@@ -607,8 +620,8 @@ __device__ __forceinline__ void freq_gemm_mfma_body(const cplx<T> *__restrict__ 
         const int64_t r1 = rows1[f], r2 = rows2[f];
         const bool odd_lane = (l & 1) != 0;
 #pragma unroll
-        for (int J = 0; J < WPF; ++J) {
-            const int j = J * 16 + (l & 15);
+        for (int J = 0; J < JW; ++J) {
+            const int j = (J0 + J) * 16 + (l & 15);
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int i = I * 16 + Op::row(l, r);
@@ -625,8 +638,8 @@ __device__ __forceinline__ void freq_gemm_mfma_body(const cplx<T> *__restrict__ 
         cplx<T> *Cs = As;   // [NF][d*d + 1]
         const int ld = d * d + 1;
 #pragma unroll
-        for (int J = 0; J < WPF; ++J) {
-            const int j = J * 16 + (l & 15);
+        for (int J = 0; J < JW; ++J) {
+            const int j = (J0 + J) * 16 + (l & 15);
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int i = I * 16 + Op::row(l, r);
@@ -646,16 +659,16 @@ __device__ __forceinline__ void freq_gemm_mfma_body(const cplx<T> *__restrict__ 
 }
 
 template <typename T, int DP, bool ODD, bool TA, bool TB, bool G3>
-__global__ void __launch_bounds__((MfCfg<T, DP>::THREADS))
-__attribute__((amdgpu_waves_per_eu(MfCfg<T, DP>::WAVES)))
+__global__ void __launch_bounds__((MfCfg<T, DP, mf_js<T, DP, G3>()>::THREADS))
+__attribute__((amdgpu_waves_per_eu(MfCfg<T, DP, mf_js<T, DP, G3>()>::WAVES)))
 freq_gemm_mfma_kernel(const cplx<T> *__restrict__ ZA, const cplx<T> *__restrict__ ZB, cplx<T> *__restrict__ ZC,
                       FftPlan plan, int d) {
     freq_gemm_mfma_body<T, DP, ODD, TA, TB, G3>(ZA, ZB, ZC, plan, d, blockIdx.x);
 }
 
 template <typename T, int DP, bool ODD, bool G3>
-__global__ void __launch_bounds__((MfCfg<T, DP>::THREADS))
-__attribute__((amdgpu_waves_per_eu(MfCfg<T, DP>::WAVES)))
+__global__ void __launch_bounds__((MfCfg<T, DP, mf_js<T, DP, G3>()>::THREADS))
+__attribute__((amdgpu_waves_per_eu(MfCfg<T, DP, mf_js<T, DP, G3>()>::WAVES)))
 freq_gemm_mfma_batched_kernel(const GemmProblem<T> *probs, int nprob, FftPlan plan) {
     int lo = 0, hi = nprob - 1;
     const int64_t bid = blockIdx.x;
@@ -671,8 +684,8 @@ freq_gemm_mfma_batched_kernel(const GemmProblem<T> *probs, int nprob, FftPlan pl
 template <typename T, int DP, bool ODD, bool TA = false, bool TB = false, bool G3 = false>
 static hipError_t launch_gemm_mfma_t(const FftPlan &plan, int d, const cplx<T> *ZA, const cplx<T> *ZB, cplx<T> *ZC,
                                      hipStream_t st) {
-    using Cfg = MfCfg<T, DP>;
-    const size_t lds = mf_lds_bytes<T, DP>(ODD ? d : 0);
+    using Cfg = MfCfg<T, DP, mf_js<T, DP, G3>()>;
+    const size_t lds = mf_lds_bytes<T, DP, mf_js<T, DP, G3>()>(ODD ? d : 0);
     auto kern = freq_gemm_mfma_kernel<T, DP, ODD, TA, TB, G3>;
     if (lds > 64 * 1024) {
         (void)hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -992,8 +1005,8 @@ static hipError_t launch_gemm_mfma(const FftPlan &plan, int d, int mfma, const c
 template <typename T, int DP, bool ODD, bool G3>
 static hipError_t launch_gemm_mfma_batched_t(const FftPlan &plan, const GemmProblem<T> *probs, int nprob,
                                              int64_t total, double bytes, double flops, hipStream_t st) {
-    using Cfg = MfCfg<T, DP>;
-    const size_t lds = mf_lds_bytes<T, DP>(ODD ? DP - 1 : 0);
+    using Cfg = MfCfg<T, DP, mf_js<T, DP, G3>()>;
+    const size_t lds = mf_lds_bytes<T, DP, mf_js<T, DP, G3>()>(ODD ? DP - 1 : 0);
     auto kern = freq_gemm_mfma_batched_kernel<T, DP, ODD, G3>;
     if (lds > 64 * 1024) {
         (void)hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
