@@ -1575,13 +1575,21 @@ static void plan_fft(BatchPlan &bp, mrinv_handle_t h, int mode, const FftPlan &p
                      const std::vector<PassProblem<T>> &probs) {
     if (probs.empty()) return;
     const bool dbl = sizeof(T) == 8;
-    // Group by lanes per workgroup: the handle's choice (at most 16 here), 2
-    // for problems of at most 2 lanes.
-    const int lanes = lanes_of<T>(h) == 0 ? 16 : std::min(16, lanes_of<T>(h));
-    for (int C : {2, 8, 16}) {
+    // Group by lanes per workgroup, chosen per problem as for a single
+    // transform: the handle's choice, else the automatic rule (32 lanes for
+    // small-tile passes of wide rows, 8 for the fused 512-row float64 pass,
+    // 16 otherwise); 2 for problems of at most 2 lanes.
+    const int lgP = p.lgP[pass];
+    auto lanes_for = [&](const PassProblem<T> &q) {
+        if (q.nl <= 2) return 2;
+        int C = lanes_of<T>(h) ? lanes_of<T>(h) : fft_lanes_per_block(dbl, q.nl, lgP, mode);
+        if (C == 32 && (lgP > 8 || q.nl <= 16)) C = 16;
+        return C;
+    };
+    for (int C : {2, 8, 16, 32}) {
         std::vector<PassProblem<T>> g;
         for (auto &q : probs)
-            if ((q.nl <= 2 ? 2 : lanes) == C) g.push_back(q);
+            if (lanes_for(q) == C) g.push_back(q);
         if (g.empty()) continue;
         const int64_t total = fft_batch_layout<T>(p, pass, g.data(), (int)g.size(), C);
         double bytes = 0;

@@ -791,6 +791,23 @@ static hipError_t launch_batched_c(int lgP, const PassProblem<T> *probs, int npr
     }
 }
 
+// 32 lanes per workgroup only up to 256-row passes (LDS).
+template <typename T, int MODE>
+static hipError_t launch_batched_c32(int lgP, const PassProblem<T> *probs, int nprob, int64_t total,
+                                     const PassGeom &g, double bytes, const Twiddles<T> &tw, hipStream_t st) {
+    switch (lgP) {
+        case 1: return launch_batched_t<T, 1, 32, MODE>(probs, nprob, total, g, bytes, tw, st);
+        case 2: return launch_batched_t<T, 2, 32, MODE>(probs, nprob, total, g, bytes, tw, st);
+        case 3: return launch_batched_t<T, 3, 32, MODE>(probs, nprob, total, g, bytes, tw, st);
+        case 4: return launch_batched_t<T, 4, 32, MODE>(probs, nprob, total, g, bytes, tw, st);
+        case 5: return launch_batched_t<T, 5, 32, MODE>(probs, nprob, total, g, bytes, tw, st);
+        case 6: return launch_batched_t<T, 6, 32, MODE>(probs, nprob, total, g, bytes, tw, st);
+        case 7: return launch_batched_t<T, 7, 32, MODE>(probs, nprob, total, g, bytes, tw, st);
+        case 8: return launch_batched_t<T, 8, 32, MODE>(probs, nprob, total, g, bytes, tw, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
 static PassGeom pass_geom(const FftPlan &plan, int pass) {
     PassGeom g{};
     g.L = (int64_t)1 << plan.lgL;
@@ -830,6 +847,9 @@ hipError_t fft_pass_batched(int mode, const FftPlan &plan, int pass, int C, cons
         case 202: return launch_batched_c<T, 2, 2>(lgP, probs, nprob, total, g, bytes, tw, st);
         case 208: return launch_batched_c<T, 8, 2>(lgP, probs, nprob, total, g, bytes, tw, st);
         case 216: return launch_batched_c<T, 16, 2>(lgP, probs, nprob, total, g, bytes, tw, st);
+        case 32: return launch_batched_c32<T, 0>(lgP, probs, nprob, total, g, bytes, tw, st);
+        case 132: return launch_batched_c32<T, 1>(lgP, probs, nprob, total, g, bytes, tw, st);
+        case 232: return launch_batched_c32<T, 2>(lgP, probs, nprob, total, g, bytes, tw, st);
         default: return hipErrorInvalidValue;
     }
 }
