@@ -446,6 +446,26 @@ def test_batched_matches_single_calls_and_oracle(mr, orc, precision):
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_batched_wide_problems_match_single_calls_and_oracle(mr, orc, precision):
+    """Problems with padded d = 64 (even and odd d) in one batch, long enough
+    for transform steps: the batched products take the same three-product,
+    two-waves-per-strip kernels as the single calls (bitwise equal), and both
+    match the oracle on a prefix."""
+    specs = [(64, 1500), (57, 1100), (50, 700), (20, 1500)]
+    qs = [si.family_kernel("lognormal" if i % 2 else "weibull", d, n, 900 + i).q.cuda()
+          for i, (d, n) in enumerate(specs)]
+    outs = mr.psi_inverse_batched(qs, precision)
+    mr.sync_status()
+    tol = FP64_TOL if precision == "fp64" else MIXED_TOL
+    for (d, n), q, o in zip(specs, qs, outs):
+        single = mr.psi_inverse(q, precision)
+        torch.cuda.synchronize()
+        assert torch.equal(o, single), (d, n)
+        ref = orc.psi(q[:300].cpu().numpy())
+        assert _maxerr(_np(o[:300]), ref) <= tol, (d, n)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_graph_replays_match_eager(mr, precision):
     """With graph recording on, repeated calls with the same pointers replay
     one HIP graph.  Every replay, with eager work and new input values in
