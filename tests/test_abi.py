@@ -58,6 +58,12 @@ def test_argument_validation_without_gpu(L):
     assert st == 1
     assert b"NULL" in L.mrinv_last_error()
     assert L.mrinv_status_string(2) == b"A(0) singular"
+    # The HBM probe checks its handle and pointers before any launch too.
+    gbps = ctypes.c_double(-1.0)
+    L.mrinv_hbm_probe.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int, ctypes.c_int,
+                                  ctypes.c_int, ctypes.POINTER(ctypes.c_double)]
+    assert L.mrinv_hbm_probe(None, None, 1 << 30, 0, 16, 3, ctypes.byref(gbps)) == 1
+    assert gbps.value == -1.0
 
 
 def test_product_path_has_no_cpu_fallback():
