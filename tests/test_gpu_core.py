@@ -81,6 +81,26 @@ def test_psi_three_pass_geometric_closed_form(mr, orc):
     assert _maxerr(_np(got[torch.as_tensor(ks).cuda()]), ref) <= fp64_tol(n)
 
 
+def test_psi_largest_d64_problem_closed_form(mr, orc):
+    """The largest d = 64 FP64 inversion that fits one GPU with room to spare:
+    a ragged horizon n = 2^20 - 4321 (last Newton step truncated, three-pass
+    transforms at L = 2^20, about 171 GB of q, psi and workspace).  The Markov
+    closed form at sampled k across the whole horizon, within the long-horizon
+    FP64 bound."""
+    d, n = 64, (1 << 20) - 4321
+    torch.cuda.empty_cache()
+    k = si.geometric_kernel(d, n, 37, device="cuda")
+    got = mr.psi_inverse(k.q, check=True)
+    ks = np.unique(np.concatenate([[0, 1, 2, 3, 4095, 4096, 65535, 524287, 524288, n - 2, n - 1],
+                                   np.linspace(0, n - 1, 24).astype(int)]))
+    ref = orc.geometric_psi(k.params["M"], k.params["a"], ks)
+    e = _maxerr(_np(got[torch.as_tensor(ks).cuda()]), ref)
+    print(f"[max] d={d} n={n}: {e:.3e}", flush=True)
+    del got, k
+    torch.cuda.empty_cache()
+    assert e <= fp64_tol(n)
+
+
 def test_padded_newton_meets_the_fp64_target_at_long_horizons(mr, orc):
     """The zero-padded Newton length (MRINV_FP64_PADDED) removes the
     wrap-around of the cyclic first product, whose rounding grows along a
