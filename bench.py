@@ -240,8 +240,11 @@ def write_traffic(args, kernel: str, fetch_csv: str, write_csv: str) -> None:
 def stage_table(trace_csv: str, fetch_csv: str, write_csv: str, mfma_csv: str) -> None:
     """Per-stage counter evidence from four rocprofv3 runs of one bench
     command: a kernel trace (durations), FETCH_SIZE, WRITE_SIZE, and MfmaUtil
-    with SQ_INSTS_VALU_MFMA_MOPS_F64 / _F32.  Dispatches are grouped by kernel
-    and grid size (one group per launch shape); for each group it prints the
+    with SQ_INSTS_VALU_MFMA_MOPS_F64 / _F32.  Dispatches are grouped by kernel,
+    grid size and position in a run of adjacent dispatches of that same shape
+    (the passes of one transform can share a kernel and a grid while reading
+    different windows, so each pass keeps a row of its own); for each group it
+    prints the
     mean duration, the scaled HBM bytes (FETCH and WRITE calibrated on the
     1 GiB copy of --calibrate-copy, as for --traffic), the achieved HBM
     bandwidth and its fraction of the 8 TB/s peak, the MFMA busy percentage
@@ -256,18 +259,35 @@ def stage_table(trace_csv: str, fetch_csv: str, write_csv: str, mfma_csv: str) -
     def keep(name):
         return "copyBuffer" not in name and "mrinv" in name
 
+    def run_keys(shapes):
+        """(kernel, grid, position in the run of adjacent equal shapes) for
+        each dispatch of a list in dispatch order."""
+        keys, prev, pos = [], None, 0
+        for sh in shapes:
+            pos = pos + 1 if sh == prev else 0
+            keys.append((sh[0], sh[1], pos))
+            prev = sh
+        return keys
+
     dur = collections.defaultdict(list)
-    for r in csv.DictReader(open(trace_csv)):
+    trace = sorted(csv.DictReader(open(trace_csv)), key=lambda r: int(r["Dispatch_Id"]))
+    shapes = [(short(r["Kernel_Name"]), int(r["Grid_Size_X"]) * int(r["Grid_Size_Y"]) * int(r["Grid_Size_Z"]))
+              for r in trace]
+    for r, k in zip(trace, run_keys(shapes)):
         if keep(r["Kernel_Name"]):
-            g = int(r["Grid_Size_X"]) * int(r["Grid_Size_Y"]) * int(r["Grid_Size_Z"])
-            dur[(short(r["Kernel_Name"]), g)].append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-9)
+            dur[k].append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-9)
 
     def counters(path, names):
         out = collections.defaultdict(lambda: collections.defaultdict(list))
         rows = list(csv.DictReader(open(path)))
+        first = {}
+        for r in rows:
+            first.setdefault(int(r["Dispatch_Id"]), r)
+        ids = sorted(first)
+        key = dict(zip(ids, run_keys([(short(first[i]["Kernel_Name"]), int(first[i]["Grid_Size"])) for i in ids])))
         for r in rows:
             if r["Counter_Name"] in names and keep(r["Kernel_Name"]):
-                out[(short(r["Kernel_Name"]), int(r["Grid_Size"]))][r["Counter_Name"]].append(float(r["Counter_Value"]))
+                out[key[int(r["Dispatch_Id"])]][r["Counter_Name"]].append(float(r["Counter_Value"]))
         return rows, out
 
     scaled = {}
@@ -284,9 +304,9 @@ def stage_table(trace_csv: str, fetch_csv: str, write_csv: str, mfma_csv: str) -
         return sum(xs) / len(xs) if xs else 0.0
 
     total = sum(sum(v) for v in dur.values())
-    print("| kernel | grid | dispatches | avg us | share of kernel time | FETCH MB | WRITE MB | HBM GB/s | of 8 TB/s "
+    print("| kernel | grid | run pos | dispatches | avg us | share of kernel time | FETCH MB | WRITE MB | HBM GB/s | of 8 TB/s "
           "| MFMA busy % | MFMA TFLOP/s |")
-    print("|---|---|---|---|---|---|---|---|---|---|---|")
+    print("|---|---|---|---|---|---|---|---|---|---|---|---|")
     for k in sorted(dur, key=lambda k: -sum(dur[k])):
         t = sum(dur[k]) / len(dur[k])
         share = sum(dur[k]) / total
@@ -302,7 +322,7 @@ def stage_table(trace_csv: str, fetch_csv: str, write_csv: str, mfma_csv: str) -
 
         def fmt(x, spec):
             return "—" if x is None else format(x, spec)
-        print(f"| `{k[0]}` | {k[1]} | {len(dur[k])} | {t * 1e6:.2f} | {share:.3f} | {fmt(f and f / 1e6, '.2f')} "
+        print(f"| `{k[0]}` | {k[1]} | {k[2]} | {len(dur[k])} | {t * 1e6:.2f} | {share:.3f} | {fmt(f and f / 1e6, '.2f')} "
               f"| {fmt(w and w / 1e6, '.2f')} | {fmt(bw, '.0f')} | {fmt(bw and bw / 8000.0, '.3f')} "
               f"| {fmt(util, '.1f')} | {fmt(tf, '.2f')} |")
     print(f"\nKernel time over the trace: {total * 1e3:.3f} ms in {sum(len(v) for v in dur.values())} dispatches; "

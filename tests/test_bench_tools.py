@@ -1,6 +1,7 @@
 """The counter summarizer of bench.py (--stage-table) on small synthetic
 rocprofv3-shaped files: calibration on the copy dispatch, grouping by launch
-shape, bandwidth and matrix-core rate arithmetic.  No GPU needed."""
+shape and position in a run of adjacent equal shapes, bandwidth and
+matrix-core rate arithmetic.  No GPU needed."""
 import csv
 import os
 import sys
@@ -11,9 +12,10 @@ sys.path.insert(0, ROOT)
 import bench  # noqa: E402
 
 KERNEL = "void mrinv::freq_gemm_mfma_kernel<double, 16, false, false, false>(mrinv::GemmArgs<double>)"
+OTHER = "void mrinv::fft_pass_kernel<double, 8, 16, 1>(mrinv::PassGeom)"
 COPY = "__amd_rocclr_copyBuffer"
 
-TRACE_COLS = ["Kind", "Kernel_Name", "Start_Timestamp", "End_Timestamp", "Grid_Size_X", "Grid_Size_Y", "Grid_Size_Z"]
+TRACE_COLS = ["Kind", "Dispatch_Id", "Kernel_Name", "Start_Timestamp", "End_Timestamp", "Grid_Size_X", "Grid_Size_Y", "Grid_Size_Z"]
 PMC_COLS = ["Dispatch_Id", "Kernel_Name", "Grid_Size", "Counter_Name", "Counter_Value"]
 
 
@@ -26,31 +28,35 @@ def _write(path, cols, rows):
 
 
 def test_stage_table_arithmetic(tmp_path, capsys):
-    # Two launches of one shape, 10 us and 30 us (mean 20 us).
-    trace = [
-        {"Kind": "KERNEL_DISPATCH", "Kernel_Name": COPY, "Start_Timestamp": 0, "End_Timestamp": 1000,
-         "Grid_Size_X": 512, "Grid_Size_Y": 1, "Grid_Size_Z": 1},
-        {"Kind": "KERNEL_DISPATCH", "Kernel_Name": KERNEL, "Start_Timestamp": 2000, "End_Timestamp": 12000,
-         "Grid_Size_X": 4096, "Grid_Size_Y": 1, "Grid_Size_Z": 1},
-        {"Kind": "KERNEL_DISPATCH", "Kernel_Name": KERNEL, "Start_Timestamp": 20000, "End_Timestamp": 50000,
-         "Grid_Size_X": 4096, "Grid_Size_Y": 1, "Grid_Size_Z": 1},
-    ]
+    # Dispatch order: copy, KERNEL (10 us), OTHER, KERNEL (30 us), KERNEL (5 us).
+    # The first two KERNEL launches are both first in their run (mean 20 us);
+    # the third directly follows a launch of its own shape and gets a row of
+    # its own (run position 1), as the second pass of a transform does.
+    def launch(i, name, t0, t1, grid):
+        return {"Kind": "KERNEL_DISPATCH", "Dispatch_Id": i, "Kernel_Name": name, "Start_Timestamp": t0,
+                "End_Timestamp": t1, "Grid_Size_X": grid, "Grid_Size_Y": 1, "Grid_Size_Z": 1}
+    trace = [launch(1, COPY, 0, 1000, 512), launch(2, KERNEL, 2000, 12000, 4096),
+             launch(3, OTHER, 13000, 14000, 4096), launch(4, KERNEL, 20000, 50000, 4096),
+             launch(5, KERNEL, 51000, 56000, 4096)]
     # The copy reads 1 GiB with FETCH_SIZE counting half of it and writes
     # 1 GiB with WRITE_SIZE exact, as measured on the device: scales 2 and 1.
     gib_kib = float(1 << 20)
 
-    def pmc(counter, copy_kib, kern_kib):
-        return [{"Dispatch_Id": 1, "Kernel_Name": COPY, "Grid_Size": 512, "Counter_Name": counter,
-                 "Counter_Value": copy_kib}] + [
-            {"Dispatch_Id": i, "Kernel_Name": KERNEL, "Grid_Size": 4096, "Counter_Name": counter,
-             "Counter_Value": kern_kib} for i in (2, 3)]
+    def pmc(counter, copy_kib, kern_kib, last_kib):
+        return ([{"Dispatch_Id": 1, "Kernel_Name": COPY, "Grid_Size": 512, "Counter_Name": counter,
+                  "Counter_Value": copy_kib},
+                 {"Dispatch_Id": 3, "Kernel_Name": OTHER, "Grid_Size": 4096, "Counter_Name": counter,
+                  "Counter_Value": 1.0}] +
+                [{"Dispatch_Id": i, "Kernel_Name": KERNEL, "Grid_Size": 4096, "Counter_Name": counter,
+                  "Counter_Value": v} for i, v in ((2, kern_kib), (4, kern_kib), (5, last_kib))])
 
-    # Per launch: 50 MB fetched (25 MB counted), 30 MB written.
-    fetch = pmc("FETCH_SIZE", gib_kib / 2, 25e6 / 1024)
-    write = pmc("WRITE_SIZE", gib_kib, 30e6 / 1024)
+    # Per launch in run position 0: 50 MB fetched (25 MB counted), 30 MB
+    # written; in run position 1: 10 MB fetched, 5 MB written.
+    fetch = pmc("FETCH_SIZE", gib_kib / 2, 25e6 / 1024, 5e6 / 1024)
+    write = pmc("WRITE_SIZE", gib_kib, 30e6 / 1024, 5e6 / 1024)
     # MFMA: 40% busy; 2e6 MOPS x 512 flops = 1.024 GFLOP per launch.
     mfma = [{"Dispatch_Id": i, "Kernel_Name": KERNEL, "Grid_Size": 4096, "Counter_Name": n, "Counter_Value": v}
-            for i in (2, 3) for n, v in (("MfmaUtil", 40.0), ("SQ_INSTS_VALU_MFMA_MOPS_F64", 2e6))]
+            for i in (2, 4, 5) for n, v in (("MfmaUtil", 40.0), ("SQ_INSTS_VALU_MFMA_MOPS_F64", 2e6))]
     paths = [str(tmp_path / n) for n in ("trace.csv", "fetch.csv", "write.csv", "mfma.csv")]
     _write(paths[0], TRACE_COLS, trace)
     _write(paths[1], PMC_COLS, fetch)
@@ -59,18 +65,23 @@ def test_stage_table_arithmetic(tmp_path, capsys):
 
     bench.stage_table(*paths)
     out = capsys.readouterr().out
-    row = [ln for ln in out.splitlines() if "freq_gemm_mfma_kernel<double, 16, false, false, false>" in ln]
-    assert len(row) == 1, out
-    cells = [c.strip() for c in row[0].strip("|").split("|")]
-    # kernel, grid, dispatches, avg us, share, FETCH MB, WRITE MB, GB/s, frac, busy, TFLOP/s
-    assert cells[1] == "4096" and cells[2] == "2"
-    assert float(cells[3]) == 20.0
-    assert float(cells[4]) == 1.0                       # the copy is not part of the path
-    assert abs(float(cells[5]) - 50.0) < 1e-6 and abs(float(cells[6]) - 30.0) < 1e-6
-    assert abs(float(cells[7]) - 80e6 / 20e-6 / 1e9) < 0.5          # 4000 GB/s
-    assert abs(float(cells[8]) - 0.5) < 1e-3
-    assert float(cells[9]) == 40.0
-    assert abs(float(cells[10]) - 1.024e9 / 20e-6 / 1e12) < 0.01    # 51.2 TFLOP/s
+    rows = [[c.strip() for c in ln.strip().strip("|").split("|")]
+            for ln in out.splitlines() if "freq_gemm_mfma_kernel<double, 16, false, false, false>" in ln]
+    assert len(rows) == 2, out
+    by_pos = {r[2]: r for r in rows}
+    # kernel, grid, run pos, dispatches, avg us, share, FETCH MB, WRITE MB, GB/s, frac, busy, TFLOP/s
+    cells = by_pos["0"]
+    assert cells[1] == "4096" and cells[3] == "2"
+    assert float(cells[4]) == 20.0
+    assert abs(float(cells[5]) - 40.0 / 46.0) < 1e-3    # the copy is not part of the path
+    assert abs(float(cells[6]) - 50.0) < 1e-6 and abs(float(cells[7]) - 30.0) < 1e-6
+    assert abs(float(cells[8]) - 80e6 / 20e-6 / 1e9) < 0.5          # 4000 GB/s
+    assert abs(float(cells[9]) - 0.5) < 1e-3
+    assert float(cells[10]) == 40.0
+    assert abs(float(cells[11]) - 1.024e9 / 20e-6 / 1e12) < 0.01    # 51.2 TFLOP/s
+    last = by_pos["1"]
+    assert last[3] == "1" and float(last[4]) == 5.0
+    assert abs(float(last[6]) - 10.0) < 1e-6 and abs(float(last[7]) - 5.0) < 1e-6
 
 
 def test_write_traffic_scaling_and_hash(tmp_path, monkeypatch):
