@@ -13,6 +13,9 @@
 // (the value at L-k is the conjugate by the same symmetry).
 #include <stdio.h>
 
+#include <algorithm>
+#include <mutex>
+
 #include "common.h"
 #include "kernels.h"
 
@@ -658,6 +661,218 @@ __device__ __forceinline__ void freq_gemm_mfma_body(const cplx<T> *__restrict__ 
     }
 }
 
+// Streamed form of the even-d, untransposed product with one frequency per
+// workgroup (padded d >= 48): a grid of resident workgroups walks the
+// frequencies k = blockIdx.x, blockIdx.x + gridDim.x, ... < F.  While a
+// workgroup multiplies the last contraction chunk of frequency k it loads and
+// stages the first chunk of its next frequency, so neither its first loads
+// nor its epilogue stores leave the matrix cores and the memory idle.  The
+// arithmetic per frequency is that of freq_gemm_mfma_body (same chunks, same
+// order, same bits).
+template <typename T, int DP, bool G3>
+__device__ __forceinline__ void freq_gemm_mfma_stream_body(const cplx<T> *__restrict__ ZA,
+                                                           const cplx<T> *__restrict__ ZB, cplx<T> *__restrict__ ZC,
+                                                           const FftPlan &plan, int d) {
+    using Cfg = MfCfg<T, DP, mf_js<T, DP, G3>()>;
+    using Op = MfmaOp<T>;
+    using V = typename Op::V;
+    static_assert(Cfg::NF == 1 && Cfg::NBUF == 2, "one frequency per workgroup, double-buffered chunks");
+    constexpr int WPF = Cfg::WPF, JW = Cfg::JW, KC = Cfg::KC, NT = Cfg::THREADS;
+    constexpr int LDA = Cfg::LDA, LDB = Cfg::LDB;
+    constexpr int PA = DP * (KC / 2), PB = KC * (DP / 2);
+    constexpr int NPR = PA / NT;                      // pairs of A (and of B) per thread
+    static_assert(PA == NPR * NT && PB == NPR * NT, "staging split");
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    cplx<T> *As = reinterpret_cast<cplx<T> *>(smem_raw);
+    constexpr int BUF = Cfg::AS + Cfg::BS;
+    const int64_t L = (int64_t)1 << plan.lgL;
+    const int64_t F = L / 2 + 1;
+    const int tid = threadIdx.x;
+    const int nl = (d * d + 1) >> 1;
+    const int l = tid & 63, w = tid >> 6;
+    const int I = w % WPF, J0 = (w / WPF) * JW;      // row strip, first column tile
+
+    cplx<T> xa1[NPR], xa2[NPR], xb1[NPR], xb2[NPR];
+    // Packed values of chunk kc of the frequency in rows r1 (k) and r2 (L-k);
+    // addresses of entries outside the d x d block are clamped to lane 0.
+    auto fetch = [&](int64_t r1, int64_t r2, int kc) {
+#pragma unroll
+        for (int u = 0; u < NPR; ++u) {
+            const int p = tid + u * NT;
+            const int i = p / (KC / 2), t = 2 * (p - i * (KC / 2));
+            const int c = (i < d && kc + t < d) ? (i * d + kc + t) >> 1 : 0;
+            xa1[u] = ZA[r1 * nl + c];
+            xa2[u] = ZA[r2 * nl + c];
+            const int t2 = p / (DP / 2), jb = 2 * (p - t2 * (DP / 2));
+            const int cb = (jb < d && kc + t2 < d) ? ((kc + t2) * d + jb) >> 1 : 0;
+            xb1[u] = ZB[r1 * nl + cb];
+            xb2[u] = ZB[r2 * nl + cb];
+        }
+    };
+    // Separate the two real sequences of each packed lane and write the
+    // chunk to LDS buffer buf, zero outside the d x d block.
+    auto stage = [&](int kc, int buf) {
+        cplx<T> *Ab = As + buf * BUF;
+        cplx<T> *Bb = Ab + Cfg::AS;
+#pragma unroll
+        for (int u = 0; u < NPR; ++u) {
+            const int p = tid + u * NT;
+            {
+                const int i = p / (KC / 2), t = 2 * (p - i * (KC / 2));
+                const bool ok = i < d && kc + t < d;
+                const cplx<T> z1 = xa1[u], z2 = xa2[u];
+                const cplx<T> ev = ok ? mk<T>((z1.x + z2.x) * (T)0.5, (z1.y - z2.y) * (T)0.5) : mk<T>(0, 0);
+                const cplx<T> od = ok ? mk<T>((z1.y + z2.y) * (T)0.5, (z2.x - z1.x) * (T)0.5) : mk<T>(0, 0);
+                cplx<T> *dst = Ab + i * LDA + t;
+                dst[0] = ev;
+                dst[1] = od;
+            }
+            {
+                const int t = p / (DP / 2), j = 2 * (p - t * (DP / 2));
+                const bool ok = j < d && kc + t < d;
+                const cplx<T> z1 = xb1[u], z2 = xb2[u];
+                const cplx<T> ev = ok ? mk<T>((z1.x + z2.x) * (T)0.5, (z1.y - z2.y) * (T)0.5) : mk<T>(0, 0);
+                const cplx<T> od = ok ? mk<T>((z1.y + z2.y) * (T)0.5, (z2.x - z1.x) * (T)0.5) : mk<T>(0, 0);
+                cplx<T> *dst = Bb + t * LDB + j;
+                dst[0] = ev;
+                dst[1] = od;
+            }
+        }
+    };
+
+    int64_t k = blockIdx.x;
+    if (k >= F) return;                               // the whole workgroup leaves together
+    int64_t r1 = freq_row(plan, k), r2 = freq_row(plan, (L - k) & (L - 1));
+    fetch(r1, r2, 0);
+    stage(0, 0);
+    __syncthreads();
+    int cur = 0;
+    for (;;) {
+        const int64_t kn = k + gridDim.x;
+        const bool next = kn < F;
+        const int64_t n1 = next ? freq_row(plan, kn) : 0, n2 = next ? freq_row(plan, (L - kn) & (L - 1)) : 0;
+        V accR[JW], accI[JW], acc3[G3 ? JW : 1];
+#pragma unroll
+        for (int J = 0; J < JW; ++J)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) accR[J][r] = accI[J][r] = (T)0;
+#pragma unroll
+        for (int J = 0; J < (G3 ? JW : 1); ++J)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) acc3[J][r] = (T)0;
+        // Chunk kc is read from buffer cur while the following chunk (the
+        // next frequency's first after the last) is fetched and staged into
+        // the other buffer; one barrier per chunk.
+        for (int kc = 0; kc < d; kc += KC) {
+            const bool more = kc + KC < d;
+            if (more) fetch(r1, r2, kc + KC);
+            else if (next) fetch(n1, n2, 0);
+            const cplx<T> *Af = As + cur * BUF + (I * 16 + (l & 15)) * LDA;
+            const cplx<T> *Bf = As + cur * BUF + Cfg::AS + (l & 15);
+#pragma unroll
+            for (int ks = 0; ks < KC / 4; ++ks) {
+                const int t = 4 * ks + (l >> 4);
+                const cplx<T> a = Af[t];
+                if constexpr (G3) {
+                    const T as = a.x + a.y;
+#pragma unroll
+                    for (int J = 0; J < JW; ++J) {
+                        const cplx<T> b = Bf[t * LDB + (J0 + J) * 16];
+                        accR[J] = Op::mac(a.x, b.x, accR[J]);
+                        accI[J] = Op::mac(a.y, b.y, accI[J]);
+                        acc3[J] = Op::mac(as, b.x + b.y, acc3[J]);
+                    }
+                } else {
+#pragma unroll
+                    for (int J = 0; J < JW; ++J) {
+                        const cplx<T> b = Bf[t * LDB + (J0 + J) * 16];
+                        accR[J] = Op::mac(a.x, b.x, accR[J]);
+                        accR[J] = Op::mac(-a.y, b.y, accR[J]);
+                        accI[J] = Op::mac(a.x, b.y, accI[J]);
+                        accI[J] = Op::mac(a.y, b.x, accI[J]);
+                    }
+                }
+            }
+            if (more) stage(kc + KC, cur ^ 1);
+            else if (next) stage(0, cur ^ 1);
+            __syncthreads();
+            cur ^= 1;
+        }
+        if constexpr (G3) {
+#pragma unroll
+            for (int J = 0; J < JW; ++J)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const T p1 = accR[J][r], p2 = accI[J][r];
+                    accR[J][r] = p1 - p2;
+                    accI[J][r] = acc3[J][r] - p1 - p2;
+                }
+        }
+        // Entries (i, j) and (i, j^1) sit in lanes l and l^1 of the same
+        // accumulator element: the even lane writes row k, the odd lane row L-k.
+        const bool odd_lane = (l & 1) != 0;
+#pragma unroll
+        for (int J = 0; J < JW; ++J) {
+            const int j = (J0 + J) * 16 + (l & 15);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int i = I * 16 + Op::row(l, r);
+                const T vr = accR[J][r], vi = accI[J][r];
+                const T pr = lane_xor1(vr), pi = lane_xor1(vi);
+                if (i < d && j < d) {
+                    const int c = (i * d + (j & ~1)) >> 1;
+                    if (!odd_lane) ZC[r1 * nl + c] = mk<T>(vr - pi, vi + pr);
+                    else if (r2 != r1) ZC[r2 * nl + c] = mk<T>(pr + vi, vr - pi);
+                }
+            }
+        }
+        if (!next) break;
+        k = kn;
+        r1 = n1;
+        r2 = n2;
+    }
+}
+
+template <typename T, int DP, bool G3>
+__global__ void __launch_bounds__((MfCfg<T, DP, mf_js<T, DP, G3>()>::THREADS))
+__attribute__((amdgpu_waves_per_eu(MfCfg<T, DP, mf_js<T, DP, G3>()>::WAVES)))
+freq_gemm_mfma_stream_kernel(const cplx<T> *__restrict__ ZA, const cplx<T> *__restrict__ ZB,
+                             cplx<T> *__restrict__ ZC, FftPlan plan, int d) {
+    freq_gemm_mfma_stream_body<T, DP, G3>(ZA, ZB, ZC, plan, d);
+}
+
+// Streamed products (freq_gemm_mfma_stream_body) are used for the
+// column-split FP64 d = 64 product only: there the streamed kernel keeps its
+// two workgroups per CU (120 registers) and is 2-3% faster per C3 inversion
+// (20.9-21.4 against 21.7-21.8 ms, alternating runs on one GPU).  The FP32
+// d = 64 product grows from 60 to 132 registers when streamed, halves its
+// resident workgroups and slows down by 9%, so it stays one frequency per
+// workgroup.
+constexpr bool MF_STREAM = true;
+
+// Workgroups of `kern` resident on the current device at once (occupancy per
+// CU times the CU count), queried once per kernel and device.
+static int64_t resident_workgroups(const void *kern, int threads, size_t lds) {
+    struct Entry { const void *k; int dev; int64_t n; };
+    static Entry cache[64];
+    static int used = 0;
+    static std::mutex mu;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    std::lock_guard<std::mutex> lock(mu);
+    for (int i = 0; i < used; ++i)
+        if (cache[i].k == kern && cache[i].dev == dev) return cache[i].n;
+    int per_cu = 0, cus = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, threads, lds) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
+        (void)hipGetLastError();
+        return 0;
+    }
+    const int64_t n = (int64_t)per_cu * cus;
+    if (used < 64) cache[used++] = Entry{kern, dev, n};
+    return n;
+}
+
 template <typename T, int DP, bool ODD, bool TA, bool TB, bool G3>
 __global__ void __launch_bounds__((MfCfg<T, DP, mf_js<T, DP, G3>()>::THREADS))
 __attribute__((amdgpu_waves_per_eu(MfCfg<T, DP, mf_js<T, DP, G3>()>::WAVES)))
@@ -686,18 +901,35 @@ static hipError_t launch_gemm_mfma_t(const FftPlan &plan, int d, const cplx<T> *
                                      hipStream_t st) {
     using Cfg = MfCfg<T, DP, mf_js<T, DP, G3>()>;
     const size_t lds = mf_lds_bytes<T, DP, mf_js<T, DP, G3>()>(ODD ? d : 0);
+    const int64_t F = ((int64_t)1 << plan.lgL) / 2 + 1;
+    const double Lr = (double)((int64_t)1 << plan.lgL);
+    const int nl = (d * d + 1) / 2;
+    if constexpr (MF_STREAM && !ODD && !TA && !TB && mf_js<T, DP, G3>()) {
+        auto skern = freq_gemm_mfma_stream_kernel<T, DP, G3>;
+        if (lds > 64 * 1024) {
+            (void)hipFuncSetAttribute((const void *)skern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+            (void)hipGetLastError();
+        }
+        const int64_t res = resident_workgroups((const void *)skern, Cfg::THREADS, lds);
+        if (res > 0) {
+            const int64_t blocks = std::min<int64_t>(F, res);
+            char name[96];
+            snprintf(name, sizeof name, "freq_gemm_mfma_stream_kernel<%s, %d, %s>",
+                     sizeof(T) == 8 ? "double" : "float", DP, G3 ? "true" : "false");
+            launch_kernel(name, Lr * 3.0 * nl * sizeof(cplx<T>), (double)F * 8.0 * d * d * d, skern,
+                          dim3((unsigned)blocks), dim3(Cfg::THREADS), lds, st, ZA, ZB, ZC, plan, d);
+            return hipGetLastError();
+        }
+    }
     auto kern = freq_gemm_mfma_kernel<T, DP, ODD, TA, TB, G3>;
     if (lds > 64 * 1024) {
         (void)hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         (void)hipGetLastError();
     }
-    const int64_t F = ((int64_t)1 << plan.lgL) / 2 + 1;
     const int64_t blocks = (F + Cfg::NF - 1) / Cfg::NF;
     char name[96];
     snprintf(name, sizeof name, "freq_gemm_mfma_kernel<%s, %d, %s, %s, %s, %s>", sizeof(T) == 8 ? "double" : "float",
              DP, ODD ? "true" : "false", TA ? "true" : "false", TB ? "true" : "false", G3 ? "true" : "false");
-    const double Lr = (double)((int64_t)1 << plan.lgL);
-    const int nl = (d * d + 1) / 2;
     launch_kernel(name, Lr * 3.0 * nl * sizeof(cplx<T>), (double)F * 8.0 * d * d * d,
                   kern, dim3((unsigned)blocks), dim3(Cfg::THREADS), lds, st, ZA, ZB, ZC, plan, d);
     return hipGetLastError();
