@@ -243,14 +243,19 @@ def stage_table(trace_csv: str, fetch_csv: str, write_csv: str, mfma_csv: str) -
     with SQ_INSTS_VALU_MFMA_MOPS_F64 / _F32.  Dispatches are grouped by kernel,
     grid size and position in a run of adjacent dispatches of that same shape
     (the passes of one transform can share a kernel and a grid while reading
-    different windows, so each pass keeps a row of its own); for each group it
-    prints the
+    different windows, so each pass keeps a row of its own), and then by the
+    dispatch's FETCH bytes to a quarter octave (a kernel whose grid is the
+    number of resident workgroups has the same grid at every transform
+    length).  One command dispatches the same sequence in every profiler run,
+    so the i-th dispatch of a shape is the same launch in all four files.  For
+    each group it prints the
     mean duration, the scaled HBM bytes (FETCH and WRITE calibrated on the
     1 GiB copy of --calibrate-copy, as for --traffic), the achieved HBM
     bandwidth and its fraction of the 8 TB/s peak, the MFMA busy percentage
     and the matrix-core flop rate (MOPS x 512 flops).  Prints markdown."""
     import collections
     import csv
+    import math
     import re
 
     def short(name):
@@ -269,25 +274,51 @@ def stage_table(trace_csv: str, fetch_csv: str, write_csv: str, mfma_csv: str) -
             prev = sh
         return keys
 
-    dur = collections.defaultdict(list)
-    trace = sorted(csv.DictReader(open(trace_csv)), key=lambda r: int(r["Dispatch_Id"]))
-    shapes = [(short(r["Kernel_Name"]), int(r["Grid_Size_X"]) * int(r["Grid_Size_Y"]) * int(r["Grid_Size_Z"]))
-              for r in trace]
-    for r, k in zip(trace, run_keys(shapes)):
-        if keep(r["Kernel_Name"]):
-            dur[k].append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-9)
-
-    def counters(path, names):
-        out = collections.defaultdict(lambda: collections.defaultdict(list))
+    def counter_keys(path):
+        """Rows of a counter file and the shape key of each dispatch id, with
+        the dispatch's index among the dispatches of its key."""
         rows = list(csv.DictReader(open(path)))
         first = {}
         for r in rows:
             first.setdefault(int(r["Dispatch_Id"]), r)
         ids = sorted(first)
-        key = dict(zip(ids, run_keys([(short(first[i]["Kernel_Name"]), int(first[i]["Grid_Size"])) for i in ids])))
+        keys = run_keys([(short(first[i]["Kernel_Name"]), int(first[i]["Grid_Size"])) for i in ids])
+        seen = collections.Counter()
+        key = {}
+        for i, k in zip(ids, keys):
+            key[i] = (k, seen[k])
+            seen[k] += 1
+        return rows, key
+
+    # Size class of each dispatch: log2 of its FETCH counter to a quarter
+    # octave, by shape key and index.
+    frows, fkey = counter_keys(fetch_csv)
+    fclass = {}
+    for r in frows:
+        if r["Counter_Name"] == "FETCH_SIZE":
+            v = float(r["Counter_Value"])
+            fclass[fkey[int(r["Dispatch_Id"])]] = round(4 * math.log2(v)) if v > 0 else -1
+
+    def group(k, idx):
+        return k + (fclass.get((k, idx), -1),)
+
+    dur = collections.defaultdict(list)
+    trace = sorted(csv.DictReader(open(trace_csv)), key=lambda r: int(r["Dispatch_Id"]))
+    shapes = [(short(r["Kernel_Name"]), int(r["Grid_Size_X"]) * int(r["Grid_Size_Y"]) * int(r["Grid_Size_Z"]))
+              for r in trace]
+    seen = collections.Counter()
+    for r, k in zip(trace, run_keys(shapes)):
+        if keep(r["Kernel_Name"]):
+            dur[group(k, seen[k])].append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-9)
+        seen[k] += 1
+
+    def counters(path, names):
+        out = collections.defaultdict(lambda: collections.defaultdict(list))
+        rows, key = counter_keys(path)
         for r in rows:
             if r["Counter_Name"] in names and keep(r["Kernel_Name"]):
-                out[key[int(r["Dispatch_Id"])]][r["Counter_Name"]].append(float(r["Counter_Value"]))
+                k, idx = key[int(r["Dispatch_Id"])]
+                out[group(k, idx)][r["Counter_Name"]].append(float(r["Counter_Value"]))
         return rows, out
 
     scaled = {}
