@@ -280,7 +280,12 @@ __device__ __forceinline__ void fft_pass_body(cplx<T> *z, const PassGeom &g, int
     auto z_store_all = [&](int b0, int lgs, auto &v) {
         if (!lane_ok) return;
         const int64_t rsu = uniform_copy(rs);    // rs is the same in every lane
-        cplx<T> *q = zc + (int64_t)b0 * rsu;
+        // The lane's address is formed again from the thread index (hidden
+        // from the optimiser), so the 64-bit load address zc need not stay
+        // live through the stages.
+        int tx = (int)threadIdx.x;
+        asm volatile("" : "+v"(tx));
+        cplx<T> *q = z + base * nl + (chunk * C + tx % C) + (int64_t)b0 * rsu;
         const int64_t step = rsu << lgs;
 #pragma unroll
         for (int r = 0; r < MR_RADIX(v); ++r) {
@@ -501,6 +506,16 @@ __device__ __forceinline__ void fft_pass_body(cplx<T> *z, const PassGeom &g, int
         }
     } else {
         const T sc = dst.op == OP_NEG ? -(T)dst.scale : (T)dst.scale;
+        // The column's rows base + idx * S rise with idx, so the window
+        // [lo, hi) is the index range [ilo, ihi) (S = 2^(lgB - LGP)); both
+        // bounds are the same for the whole workgroup.
+        const int lgS = g.lgB - LGP;
+        auto first_idx = [&](int64_t x) {
+            if (x <= base) return 0;
+            const int64_t q = (x - base + S - 1) >> lgS;
+            return q >= P ? P : (int)q;
+        };
+        const int ilo = first_idx(dst.lo), ihi = first_idx(dst.hi);
         start_inverse();
         if constexpr (SPLIT == 2) {
             cplx<T> v[1 << LGR];
@@ -508,9 +523,8 @@ __device__ __forceinline__ void fft_pass_body(cplx<T> *z, const PassGeom &g, int
             split_stages<T, LGP, true, C / 2>(lds, half, ch, jb, v, roots);
 #pragma unroll
             for (int r = 0; r < (1 << LGR); ++r) {
-                const int64_t t = base + (int64_t)(bl + (r << LGL)) * S;
-                const bool keep = t >= dst.lo && t < dst.hi;
-                v[r] = keep ? cscale<T>(v[r], sc) : mk<T>(0, 0);
+                const int idx = bl + (r << LGL);
+                v[r] = idx >= ilo && idx < ihi ? cscale<T>(v[r], sc) : mk<T>(0, 0);
             }
             split_exchange<T, 1 << LGR, C / 2>(lds, half, ch, bl, LGL, jb, LGP - LGR, v);
             split_stages<T, LGP, false, C / 2>(lds, half, ch, jb, v, roots);
@@ -521,9 +535,7 @@ __device__ __forceinline__ void fft_pass_body(cplx<T> *z, const PassGeom &g, int
 #pragma unroll
             for (int r = 0; r < MR_RADIX(v); ++r) {
                 const int idx = b0 + (r << lgs);
-                const int64_t t = base + idx * S;
-                const bool keep = t >= dst.lo && t < dst.hi;
-                lds[idx * LDS_STRIDE + c] = keep ? cscale<T>(v[r], sc) : mk<T>(0, 0);
+                lds[idx * LDS_STRIDE + c] = idx >= ilo && idx < ihi ? cscale<T>(v[r], sc) : mk<T>(0, 0);
             }
         };
         wg_fft<T, LGP, true>(lds, LDS_STRIDE, c, grp, pre_inv_load, mask_store_all, false, true, roots);
@@ -680,10 +692,6 @@ static int fewer_lanes_when_small(int C, int64_t cols, int nl_a, int nl_b) {
 // 16 otherwise.
 int fft_lanes_per_block(bool dbl, int nl, int lgP, int mode) {
     if (nl <= 2) return 2;
-    // The fused 512-row float64 pass (inverse, mask, forward) runs at 8 lanes:
-    // 512 threads and a 48 KB half-lane tile, three workgroups per CU with 80
-    // registers instead of two with 64 (no spills).
-    if (dbl && lgP == 9 && mode == 2) return 8;
     return nl >= 512 && lgP <= (dbl ? 7 : 8) ? 32 : 16;
 }
 
