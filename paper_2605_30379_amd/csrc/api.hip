@@ -278,14 +278,27 @@ static int ceil_log2(int64_t x) {
 // Transform length of a product truncated at n whose operands have n terms.
 static int lg_full(int64_t n) { return std::max(1, ceil_log2(2 * n - 1)); }
 
+// Radices of a transform of length 2^lgL, each at most 2^lgp_max.  One or two
+// passes split the length evenly (the larger radix first).  Three or more
+// passes give the last, contiguous pass the largest radix and split the rest
+// evenly: the first pass then visits few rows of a zero-padded window.  At
+// L = 2^19 (the mixed form's sweeps at d = 64) 5/5/9 beats the even 7/6/6
+// by 4.5% per inversion (alternating runs on one GPU); the same rule for two
+// passes (8/9 at 2^17, 7/9 at 2^16) was 1-2% slower.
 static FftPlan make_plan(int lgL, int lgp_max = LGP_MAX) {
     FftPlan p{};
     p.lgL = lgL;
     p.npass = (lgL + lgp_max - 1) / lgp_max;
     if (p.npass < 1) p.npass = 1;
     int rem = lgL;
-    for (int j = 0; j < p.npass; ++j) {
-        const int left = p.npass - j;
+    int even = p.npass;                   // passes split evenly
+    if (p.npass >= 3) {
+        p.lgP[p.npass - 1] = lgp_max;
+        rem -= lgp_max;
+        even = p.npass - 1;
+    }
+    for (int j = 0; j < even; ++j) {
+        const int left = even - j;
         p.lgP[j] = (rem + left - 1) / left;
         rem -= p.lgP[j];
     }
