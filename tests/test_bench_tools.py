@@ -113,3 +113,45 @@ def test_write_traffic_scaling_and_hash(tmp_path, monkeypatch):
     assert abs(out["bytes_per_launch"] - 50e6) < 1
     assert out["source_hash"] == bench.kernel_source_hash(name)
     assert bench.kernel_source_hash(name) != bench.kernel_source_hash("fft_pass_kernel<double, 8, 16, 0>")
+
+
+def test_stage_table_splits_one_shape_by_fetch_bytes(tmp_path, capsys):
+    """A kernel launched with the same grid at two transform lengths (the
+    resident-grid product) keeps one row per length: dispatches of one shape
+    are grouped by their FETCH bytes to a quarter octave, and each row's
+    duration comes from the matching dispatches of the trace run."""
+    other = OTHER
+    grid = 262144
+    # KERNEL at 4 GB, OTHER, KERNEL at 1 GB, OTHER, KERNEL at 4.1 GB (same class as 4 GB).
+    spec = [(2, KERNEL, 40.0, 4e9), (3, other, 1.0, 1e6), (4, KERNEL, 10.0, 1e9), (5, other, 1.0, 1e6),
+            (6, KERNEL, 44.0, 4.1e9)]
+    trace = [{"Kind": "KERNEL_DISPATCH", "Dispatch_Id": 1, "Kernel_Name": COPY, "Start_Timestamp": 0,
+              "End_Timestamp": 1000, "Grid_Size_X": 512, "Grid_Size_Y": 1, "Grid_Size_Z": 1}]
+    t = 2000
+    for i, name, us, _ in spec:
+        trace.append({"Kind": "KERNEL_DISPATCH", "Dispatch_Id": i, "Kernel_Name": name, "Start_Timestamp": t,
+                      "End_Timestamp": t + int(us * 1000), "Grid_Size_X": grid, "Grid_Size_Y": 1,
+                      "Grid_Size_Z": 1})
+        t += int(us * 1000) + 500
+    gib_kib = float(1 << 20)
+
+    def pmc(counter, copy_kib, scale):
+        return [{"Dispatch_Id": 1, "Kernel_Name": COPY, "Grid_Size": 512, "Counter_Name": counter,
+                 "Counter_Value": copy_kib}] + [
+            {"Dispatch_Id": i, "Kernel_Name": name, "Grid_Size": grid, "Counter_Name": counter,
+             "Counter_Value": b / scale / 1024} for i, name, _, b in spec]
+    paths = [str(tmp_path / n) for n in ("trace.csv", "fetch.csv", "write.csv", "mfma.csv")]
+    _write(paths[0], TRACE_COLS, trace)
+    _write(paths[1], PMC_COLS, pmc("FETCH_SIZE", gib_kib / 2, 2.0))
+    _write(paths[2], PMC_COLS, pmc("WRITE_SIZE", gib_kib, 2.0))
+    _write(paths[3], PMC_COLS, [])
+    bench.stage_table(*paths)
+    out = capsys.readouterr().out
+    rows = [[c.strip() for c in ln.strip().strip("|").split("|")]
+            for ln in out.splitlines() if "freq_gemm_mfma_kernel<double, 16, false, false, false>" in ln]
+    assert len(rows) == 2, out
+    big = [r for r in rows if float(r[6]) > 3000][0]
+    small = [r for r in rows if float(r[6]) < 3000][0]
+    assert big[3] == "2" and abs(float(big[4]) - 42.0) < 1e-6          # mean of 40 and 44 us
+    assert abs(float(big[6]) - 4050.0) < 1e-6                          # mean of 4000 and 4100 MB
+    assert small[3] == "1" and abs(float(small[4]) - 10.0) < 1e-6 and abs(float(small[6]) - 1000.0) < 1e-6
