@@ -486,12 +486,14 @@ def test_batched_wide_problems_match_single_calls_and_oracle(mr, orc, precision)
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
-def test_graph_replays_match_eager(mr, precision):
+@pytest.mark.parametrize("d", [6, 64])
+def test_graph_replays_match_eager(mr, precision, d):
     """With graph recording on, repeated calls with the same pointers replay
     one HIP graph.  Every replay, with eager work and new input values in
-    between, must equal the eager (unrecorded) result bitwise."""
+    between, must equal the eager (unrecorded) result bitwise.  At d = 64 the
+    FP64 products are the streamed kernel (a grid of resident workgroups)."""
     import ctypes
-    d, n = 6, 3000
+    n = 3000
     prec = mr._PREC[precision]
     q = si.weibull_kernel(d, n, 61).q.cuda()
     q2 = si.lognormal_kernel(d, n, 62).q.cuda()
