@@ -144,4 +144,41 @@ __host__ __device__ constexpr int min_stage_lg(int lgP) {
     return lgP <= 4 ? lgP : lgP <= 8 ? lgP / 2 : lgP / 3;
 }
 
+// Index of the problem that owns workgroup bid in a batched launch of NT
+// threads per workgroup: the last i with probs[i].wg_begin <= bid (the begins
+// ascend from 0).  With whole waves (NT a multiple of 64) each wave finds it
+// on its own: its 64 lanes test 64 evenly spaced begins at once, the ballot
+// of the hits (a prefix, the begins being sorted) picks the span that holds
+// the answer, and the next round tests that span; one round for up to 64
+// problems, two for up to 4096, where a serial search waits for log2(nprob)
+// dependent loads before the workgroup touches its data.  The ballots keep
+// the result wave-uniform, so the descriptor loads stay scalar.  Workgroups
+// with a partial wave search serially.
+template <int NT, typename P>
+__device__ __forceinline__ int owner_of(const P *probs, int nprob, int64_t bid) {
+    int lo = 0;
+    if constexpr (NT % 64 != 0) {
+        int hi = nprob - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (probs[mid].wg_begin <= bid) lo = mid;
+            else hi = mid - 1;
+        }
+        return lo;
+    } else {
+        if (nprob <= 1) return 0;
+        const int lane = (int)(threadIdx.x & 63);
+        int span = nprob;                     // the answer lies in [lo, lo + span)
+        for (;;) {
+            const int stride = (span + 63) >> 6;
+            const int j = lo + lane * stride;
+            const bool hit = lane * stride < span && probs[j].wg_begin <= bid;
+            const int k = __popcll(__ballot(hit)) - 1;   // >= 0 while probs[lo].wg_begin <= bid
+            lo += (k > 0 ? k : 0) * stride;
+            if (stride == 1) return lo;
+            span = stride < nprob - lo ? stride : nprob - lo;
+        }
+    }
+}
+
 }  // namespace mrinv

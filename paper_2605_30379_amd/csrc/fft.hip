@@ -571,14 +571,8 @@ template <typename T, int LGP, int C, int MODE>
 __global__ void __launch_bounds__(C << (LGP - min_stage_lg(LGP)))
 __attribute__((amdgpu_waves_per_eu(pass_waves<T, LGP, C, MODE>())))
 fft_pass_batched_kernel(const PassProblem<T> *probs, int nprob, PassGeom g, Twiddles<T> tw) {
-    int lo = 0, hi = nprob - 1;
     const int64_t bid = blockIdx.x;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (probs[mid].wg_begin <= bid) lo = mid;
-        else hi = mid - 1;
-    }
-    const PassProblem<T> &pp = probs[lo];
+    const PassProblem<T> &pp = probs[owner_of<(C << (LGP - min_stage_lg(LGP)))>(probs, nprob, bid)];
     fft_pass_body<T, LGP, C, MODE>(pp.z, g, pp.nl, pp.nchunks, bid - pp.wg_begin, pp.src, pp.dst, tw);
 }
 

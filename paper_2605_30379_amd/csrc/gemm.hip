@@ -319,13 +319,8 @@ freq_gemm_sq_kernel(const cplx<T> *__restrict__ ZA, const cplx<T> *__restrict__ 
 template <typename T, int DP>
 __global__ void __launch_bounds__(SqCfg<DP>::THREADS)
 freq_gemm_sq_batched_kernel(const GemmProblem<T> *probs, int nprob, FftPlan plan) {
-    int lo = 0, hi = nprob - 1;
     const int64_t bid = blockIdx.x;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (probs[mid].wg_begin <= bid) lo = mid;
-        else hi = mid - 1;
-    }
+    const int lo = owner_of<SqCfg<DP>::THREADS>(probs, nprob, bid);
     const GemmProblem<T> &pp = probs[lo];
     freq_gemm_sq_body<T, DP>(pp.A, pp.B, pp.C, plan, pp.d, bid - pp.wg_begin);
 }
@@ -885,13 +880,8 @@ template <typename T, int DP, bool ODD, bool G3>
 __global__ void __launch_bounds__((MfCfg<T, DP, mf_js<T, DP, G3>()>::THREADS))
 __attribute__((amdgpu_waves_per_eu(MfCfg<T, DP, mf_js<T, DP, G3>()>::WAVES)))
 freq_gemm_mfma_batched_kernel(const GemmProblem<T> *probs, int nprob, FftPlan plan) {
-    int lo = 0, hi = nprob - 1;
     const int64_t bid = blockIdx.x;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (probs[mid].wg_begin <= bid) lo = mid;
-        else hi = mid - 1;
-    }
+    const int lo = owner_of<MfCfg<T, DP, mf_js<T, DP, G3>()>::THREADS>(probs, nprob, bid);
     const GemmProblem<T> &pp = probs[lo];
     freq_gemm_mfma_body<T, DP, ODD, false, false, G3>(pp.A, pp.B, pp.C, plan, pp.d, bid - pp.wg_begin);
 }
@@ -1150,13 +1140,8 @@ freq_gemm_bf3_kernel(const float2 *__restrict__ ZA, const float2 *__restrict__ Z
 template <int DP, bool ODD>
 __global__ void __launch_bounds__(BfCfg<DP>::THREADS)
 freq_gemm_bf3_batched_kernel(const GemmProblem<float> *probs, int nprob, FftPlan plan) {
-    int lo = 0, hi = nprob - 1;
     const int64_t bid = blockIdx.x;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (probs[mid].wg_begin <= bid) lo = mid;
-        else hi = mid - 1;
-    }
+    const int lo = owner_of<BfCfg<DP>::THREADS>(probs, nprob, bid);
     const GemmProblem<float> &pp = probs[lo];
     freq_gemm_bf3_body<DP, ODD>(pp.A, pp.B, pp.C, plan, pp.d, bid - pp.wg_begin);
 }
@@ -1373,6 +1358,8 @@ __global__ void __launch_bounds__(CONV_THREADS) conv_direct_kernel(ConvDesc c) {
 
 template <typename T, typename TL, int DP>
 __global__ void __launch_bounds__(CONV_THREADS) conv_direct_batched_kernel(const ConvDesc *cs, int n) {
+    // Few, long workgroups: the serial search costs nothing here, and the
+    // wave-level lookup would add registers to a kernel that already spills.
     int lo = 0, hi = n - 1;
     const int64_t bid = blockIdx.x;
     while (lo < hi) {
